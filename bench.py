@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Benchmark of the SDP-BSREM hot path on one MI355X.
+
+Workload: the 2D 256x256 reconstruction (300 mm FOV, 288 angles x 367 bins,
+24 interleaved subsets, SDP-P2 with the Table II high-count row, seeded
+12-ellipse phantom with hot lesions, 5e6 counts, 20 % background).
+One step = one full iteration: 24 subiterations (forward projection +
+ratio, back-projection + RDP/smoothness stencil, preconditioned update)
+followed by the FP64 objective.  Inputs are resident in HBM before timing.
+
+Prints ONE JSON line (metric, value = subiterations/s, roofline of the
+dominant kernel from HIP events, CPU oracle baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNELS = {0: "k_fp (forward projection + Poisson ratio)",
+           1: "k_bp (back-projection + RDP gradient + mu)",
+           2: "k_update (nu, S, relaxed step, P_t)"}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "raygeom.h"):
+        with open(os.path.join(ROOT, "paper_2111_07886_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(kernel, nnz_sub, rays_sub, q):
+    """Bytes one launch must move (A is computed on the fly, never stored):
+    forward: 4 B image gather per nonzero + read y, r and write w per ray;
+    back: 4 B w gather per nonzero + stage w once per ray + read f, write G, mu;
+    update: read f, G, mu, p and write f per voxel."""
+    if kernel == 0:
+        return 4.0 * nnz_sub + 12.0 * rays_sub
+    if kernel == 1:
+        return 4.0 * nnz_sub + 4.0 * rays_sub + 12.0 * q
+    return 20.0 * q
+
+
+def cpu_baseline(w, p, budget_s=12.0):
+    """The FP64 oracle, as it stands, on the same workload: subiterations from
+    f0 with the objective after every full iteration, until ~budget_s of CPU
+    work is done."""
+    import oracle
+    oracle.build(force=False)
+    g = oracle.geom(w.desc)
+    rec = oracle.Recon(g, oracle.params(p), w.f0, w.y_f32, w.r_f32)
+    M = w.desc["n_subsets"]
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and n < 50 * M:
+        rec.subiteration()
+        n += 1
+        if n % M == 0:
+            rec.objective()
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt, 3), "unit": "subiterations/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {n} subiterations (objective after each of the {n // M} full iterations) "
+                      f"of the same 256x256 / 288x367 / 24-subset P2 workload from f0, FP64 C oracle, "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (for PMC byte-counter scaling)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU sharding is "
+                                   "described in DESIGN.md and is not measured", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2111_07886_amd as pet
+    from synth import configs
+
+    w, p, _ = configs.c2()
+    p = dict(p, objective_every=1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    f = torch.tensor(w.f0, dtype=torch.float32, device=dev).contiguous()
+    y = torch.tensor(w.y, dtype=torch.float32, device=dev).contiguous()
+    r = torch.tensor(w.r, dtype=torch.float32, device=dev).contiguous()
+    w.y_f32 = y.cpu().double().numpy()
+    w.r_f32 = r.cpu().double().numpy()
+    geom = pet.Geometry(w.desc)
+    M = w.desc["n_subsets"]
+    state = pet.State(geom, p)
+
+    if args.calibrate_copy:
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    # warm-up, then exactly `steps` timed iterations bracketed by synchronisation
+    state.run(f, y, r, args.warmup, want_objective=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    obj = state.run(f, y, r, args.steps, want_objective=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sub_per_s = args.steps * M / elapsed
+
+    # per-kernel device time: HIP events on the launch stream around every
+    # launch of one kernel, over a pass of the same steps (kept out of the
+    # timed region above so that the events do not perturb it)
+    nnz_sub = geom.nnz(0) / M
+    rays_sub = geom.n_bins / M
+    q = geom.n_voxels
+    per_kernel = {}
+    if not args.no_profile:
+        for k in (0, 1, 2):
+            state.profile(k)
+            state.run(f, y, r, min(args.steps, 10), want_objective=True)
+            ms, n = state.profile_read()
+            state.profile(-1)
+            per_kernel[k] = dict(avg_us=1e3 * ms / max(n, 1), launches=n,
+                                 bytes=algorithmic_bytes(k, nnz_sub, rays_sub, q))
+    roofline = None
+    if per_kernel:
+        dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"])
+        K = per_kernel[dom]
+        achieved = K["bytes"] / (K["avg_us"] * 1e-6) / 1e9
+        traffic = None
+        tpath = os.path.join(ROOT, "profiles", "traffic_c2.json")
+        if os.path.exists(tpath):
+            t = json.load(open(tpath))
+            if t.get("kernel_source") == kernel_source_hash() and str(dom) in t.get("bytes_per_launch", {}):
+                traffic = t["bytes_per_launch"][str(dom)]
+        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                    "kernel": KERNELS[dom], "avg_launch_us": round(K["avg_us"], 3),
+                    "algorithmic_bytes_per_launch": int(K["bytes"]),
+                    "per_kernel_us": {KERNELS[k].split()[0]: round(v["avg_us"], 3) for k, v in per_kernel.items()}}
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(w, p)
+
+    out = {
+        "metric": "subiterations/s",
+        "value": round(sub_per_s, 2),
+        "unit": "subiterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2D SDP-P2, 256x256 image (1.171875 mm), 288 angles x 367 bins, "
+                               "24 subsets, 5e6 counts, 20% background; step = 1 iteration "
+                               "(24 subiterations) + FP64 objective",
+                   "subsets": M, "nnz_per_subset": int(nnz_sub), "rays_per_subset": int(rays_sub),
+                   "voxels": q, "objective_last": obj[-1] if obj else None},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

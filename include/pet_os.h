@@ -1,0 +1,202 @@
+/*
+ * pet_os.h -- C ABI of the MI355X ordered-subsets PET reconstruction library.
+ *
+ * Implements SDP-BSREM (Guo et al., "A Fast Convergent Ordered-Subsets
+ * Algorithm with Subiteration-Dependent Preconditioners for PET Image
+ * Reconstruction", arXiv 2111.07886): minimise
+ *     Phi(f) = <Af,1> - <ln(Af+gamma), g> + beta R(f)          (eq:ObjectiveFunction)
+ * with the relative difference prior R (eq:RDP) over the box
+ * B = {0 <= f_j <= U} (eq:BoundedSet) by the iteration of Table I
+ * (tab:SDPBSREM):
+ *     f~ = f - lambda_k diag(alpha_{k,i} nu^{k,i}) S(f) grad Phi_i(f),   f <- P_t(f~)
+ * with S from eq:preconditioner/eq:pj, P_t from eq:OperatorPt, lambda_k =
+ * lambda0/(a k + 1), alpha_{k,i} from preconditioner:Nesterov (M1, P1) or
+ * preconditioner:KM (M2, P2) and nu^{k,i} from eq:nuki (P1, P2).
+ *
+ * Notation: the paper's g (counts), gamma (background mean) and f (image) are
+ * the arguments y, r and f below.
+ *
+ * Conventions shared by every call
+ *   - Images are FP32, contiguous [nz][ny][nx] (x fastest); nz = 1 in 2D.
+ *     Pixel centres at ((i - (n-1)/2) * v); cells are half-open.
+ *   - Sinograms are FP32, contiguous [plane][angle][bin] (bins fastest); one
+ *     plane in 2D.  Angle a is theta_a = a*pi/n_angles; bin b sits at
+ *     s_b = (b - (n_radial-1)/2) * ds; ray (a,b) is x cos + y sin = s_b.
+ *     3D: rings at slice centres (n_rings == nz, ring_pitch == vz); the LOR of
+ *     rings (r1, r2) climbs linearly from z_r1 to z_r2 between the two points
+ *     where the transaxial line meets the detector circle of radius
+ *     det_radius; span-1 plane order is ring difference d = 0,+1,-1,...,+D,-D
+ *     with ascending r1 inside each d.
+ *   - Subset i (1..M) is every angle a with a mod M == i-1 (interleaved).
+ *   - Pointers named f, y, r, q, w, out are DEVICE pointers owned by the
+ *     caller (e.g. torch tensors); they must stay valid until the work queued
+ *     on `stream` has finished.  `stream` is a hipStream_t (NULL: default).
+ *   - Handles (pet_os_geom, pet_os_state) are owned by the library.
+ *   - Every call returns PET_OS_OK (0) or a negative PET_OS_ERR_* code and sets
+ *     a thread-local message readable with pet_os_last_error().  Arguments are
+ *     validated before anything is queued: a failing call changes nothing.
+ *   - Calls are asynchronous on `stream` unless stated otherwise.
+ */
+#ifndef PET_OS_H
+#define PET_OS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PET_OS_OK 0
+#define PET_OS_ERR_INVALID_ARG (-1)
+#define PET_OS_ERR_OUT_OF_MEMORY (-2)
+#define PET_OS_ERR_DEVICE (-3)
+#define PET_OS_ERR_BUDGET (-4)
+#define PET_OS_ERR_NUMERIC (-5)
+#define PET_OS_ERR_TIMEOUT (-6)
+#define PET_OS_ERR_STATE_MISMATCH (-7)
+
+/* preconditioner variants of Sec. III-B: BSREM (alpha = nu = 1), M1/P1
+ * (Nesterov alpha), M2/P2 (KM alpha); P* also use the smoothness vector nu. */
+#define PET_OS_BSREM 0
+#define PET_OS_M1 1
+#define PET_OS_M2 2
+#define PET_OS_P1 3
+#define PET_OS_P2 4
+
+typedef struct pet_os_geom pet_os_geom;
+typedef struct pet_os_state pet_os_state;
+typedef void* pet_os_stream; /* hipStream_t */
+
+/* Scanner / image geometry (system model of Sec. IV-A, one line per bin). */
+typedef struct {
+    int32_t dim;              /* 2 or 3 */
+    int32_t nx, ny, nz;       /* image size; nz ignored (1) in 2D */
+    double vx, vy, vz;        /* voxel size [mm] */
+    int32_t n_angles;         /* angles over [0, pi) */
+    int32_t n_radial;         /* radial bins */
+    double ds;                /* bin spacing [mm] */
+    int32_t n_rings;          /* 3D: == nz */
+    int32_t max_ring_diff;    /* 3D: D, span 1 */
+    double ring_pitch;        /* 3D: == vz */
+    double det_radius;        /* 3D: detector ring radius [mm], > image half-diagonal */
+    int32_t n_subsets;        /* M, 1 <= M <= n_angles */
+} pet_os_geom_desc;
+
+/* Algorithm parameters (Sec. II, III-B, IV-A). */
+typedef struct {
+    int32_t mode;             /* PET_OS_BSREM .. PET_OS_P2 */
+    double beta;              /* >= 0, eq:ObjectiveFunction */
+    double gamma_R;           /* >= 0, eq:RDP */
+    double eps;               /* > 0, eq:RDP */
+    double t_clip;            /* t of eq:OperatorPt, 0 < t < U */
+    double U;                 /* box bound of eq:BoundedSet, > 0 */
+    double lambda0, a;        /* lambda_k = lambda0/(a k + 1), both > 0 */
+    double rho, delta1, delta2;  /* KM sequence, > 0 */
+    double nu1, nu2;          /* clamp of nu, 0 < nu1 < nu2 */
+    int64_t J0, J1;           /* 0 <= J0 <= J1, eq:nuki */
+    int32_t objective_every;  /* reconstruct: objective each this many iterations (>= 1) */
+} pet_os_params;
+
+/* Human-readable message of the last failing call on this thread. */
+const char* pet_os_last_error(void);
+
+/* Library version string. */
+const char* pet_os_version(void);
+
+/* Geometry: validates the descriptor (Sec. IV-A conventions above), builds the
+ * FP64 angle/bin/plane tables on the device and computes the sensitivity
+ * s = A^T 1 and the normaliser p_j = s_j/M (or 1/M where s_j = 0) of eq:pj.
+ * Synchronous.  The library owns *out until pet_os_destroy_geometry. */
+int pet_os_create_geometry(const pet_os_geom_desc* desc, pet_os_geom** out);
+int pet_os_destroy_geometry(pet_os_geom* geom);
+
+/* Sizes: voxels, bins (planes*angles*radial), planes. Any pointer may be NULL. */
+int pet_os_geometry_info(const pet_os_geom* geom, int64_t* n_voxels, int64_t* n_bins,
+                         int32_t* n_planes);
+
+/* Copy of the sensitivity A^T 1 (eq:pj numerator) into out[n_voxels] (device). */
+int pet_os_sensitivity(const pet_os_geom* geom, float* out, pet_os_stream stream);
+
+/* q = A_i f: forward projection (sec. II-B) of the rays of subset `subset`
+ * (1..M), or of every ray when subset == 0.  q is natural layout; entries of
+ * other subsets are not written.  f: n_voxels floats, q: n_bins floats. */
+int pet_os_forward(const pet_os_geom* geom, const float* f, int32_t subset, float* q,
+                   pet_os_stream stream);
+
+/* out = A_i^T w: back-projection of the rays of `subset` (0 = all), w in
+ * natural layout (entries of other subsets ignored).  Voxel-driven gather,
+ * no atomics, deterministic. */
+int pet_os_back(const pet_os_geom* geom, const float* w, int32_t subset, float* out,
+                pet_os_stream stream);
+
+/* Objective Phi(f) of eq:ObjectiveFunction (fidelity eq:FidelityTerm with
+ * FP64 log and sums, plus beta R(f)).  Synchronous: *phi is a host double. */
+int pet_os_objective(const pet_os_geom* geom, const pet_os_params* params, const float* f,
+                     const float* y, const float* r, double* phi, pet_os_stream stream);
+
+/* Default box bound (the paper only proves U exists, eq:BoundedSet):
+ * U = 1e3 * max(max_j f0_j, (sum y - sum r)_+ / sum_j s_j).  Synchronous. */
+int pet_os_default_U(const pet_os_geom* geom, const float* f0, const float* y, const float* r,
+                     double* U, pet_os_stream stream);
+
+/* Per-reconstruction state: position (k, i) of the next subiteration, the
+ * Nesterov t (FP64), the frozen nu of eq:nuki, and device scratch.  `params`
+ * is copied and validated.  The geometry must outlive the state. */
+int pet_os_state_create(const pet_os_geom* geom, const pet_os_params* params,
+                        pet_os_state** out);
+int pet_os_state_destroy(pet_os_state* state);
+
+/* Position of the next subiteration: k (0-based iteration), i (1-based subset). */
+int pet_os_state_position(const pet_os_state* state, int64_t* k, int32_t* i);
+
+/* One subiteration of Table I on f (in place, n_voxels floats, device):
+ *   q = A_i f; w = 1 - y_i/(q + r_i); b = A_i^T w;  grad Phi_i = b + (beta/M) grad R(f)
+ *   f~ = f - lambda_k alpha_{k,i} nu^{k,i} S(f) grad Phi_i;  f = P_t(f~)
+ * then advances (k, i).  nu^{k,i} is computed from the iterate entering the
+ * subiteration.  y, r: n_bins floats (natural layout, r > 0).  Asynchronous;
+ * the FP64 scalars lambda_k, alpha_{k,i} are evaluated on the host. */
+int pet_os_subiteration(pet_os_state* state, float* f, const float* y, const float* r,
+                        pet_os_stream stream);
+
+/* n_iter iterations (n_iter * M subiterations) of SDP-BSREM from f (in/out).
+ * obj: NULL, or a HOST array of n_iter+1 doubles receiving Phi(f^k) for
+ * k = 0, objective_every, 2*objective_every, ... (other entries NaN); the
+ * call then blocks at the end.  With obj == NULL it is asynchronous. */
+int pet_os_reconstruct(const pet_os_geom* geom, const pet_os_params* params, float* f,
+                       const float* y, const float* r, int32_t n_iter, double* obj,
+                       pet_os_stream stream);
+
+/* n_iter further iterations (n_iter * M subiterations) on an existing state,
+ * from its current position, on f (in/out).  Uses only the state's scratch
+ * (no allocation).  obj: NULL, or a HOST array of n_iter doubles receiving
+ * Phi after iteration j+1 when (j+1) % objective_every == 0 or j+1 == n_iter
+ * (NaN otherwise); the call then blocks at the end.  Asynchronous otherwise. */
+int pet_os_run(pet_os_state* state, float* f, const float* y, const float* r, int32_t n_iter,
+               double* obj, pet_os_stream stream);
+
+/* Kernel timing with HIP events on the state's stream (tracing, Sec. IV
+ * reports CPU time; this reports device time).  kernel: 0 = forward
+ * projection + ratio, 1 = back-projection + RDP/mu stencil, 2 = update,
+ * -1 = off.  Events bracket every launch of that kernel until switched off.
+ * read: synchronises, returns the summed milliseconds and launch count since
+ * the last read, and resets them. */
+int pet_os_state_profile(pet_os_state* state, int32_t kernel);
+int pet_os_state_profile_read(pet_os_state* state, double* total_ms, int64_t* launches);
+
+/* Number of nonzero a_ij of subset `subset` (0 = all rays): the work of one
+ * projection in the system model.  Synchronous. */
+int pet_os_nnz(const pet_os_geom* geom, int32_t subset, int64_t* nnz);
+
+/* Checkpoint of a state: (k, i, t, params, geometry descriptor, frozen nu).
+ * export: buf == NULL queries the size into *len; otherwise *len must be at
+ * least that size.  Synchronous (copies the frozen nu to the host).
+ * import: the target state must have the same geometry descriptor and mode,
+ * else PET_OS_ERR_STATE_MISMATCH. */
+int pet_os_state_export(const pet_os_state* state, void* buf, size_t* len);
+int pet_os_state_import(pet_os_state* state, const void* buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PET_OS_H */

@@ -1,0 +1,289 @@
+"""Python binding of the pet_os C ABI (``include/pet_os.h``).
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+kernels of ``libpet_os.so``.  Tensors are torch CUDA (HIP) float32 contiguous
+tensors; pointers and ``torch.cuda.current_stream()`` are passed through.
+There is no CPU fallback: without the built library every call raises.
+
+torch is imported before the library is loaded so that both share one HIP
+runtime in the process.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpet_os.so")
+
+MODES = {"BSREM": 0, "M1": 1, "M2": 2, "P1": 3, "P2": 4}
+ERRORS = {-1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "DEVICE", -4: "BUDGET", -5: "NUMERIC",
+          -6: "TIMEOUT", -7: "STATE_MISMATCH"}
+
+# every symbol declared in include/pet_os.h
+EXPORTS = ["pet_os_last_error", "pet_os_version", "pet_os_create_geometry", "pet_os_destroy_geometry",
+           "pet_os_geometry_info", "pet_os_sensitivity", "pet_os_forward", "pet_os_back",
+           "pet_os_objective", "pet_os_default_U", "pet_os_state_create", "pet_os_state_destroy",
+           "pet_os_state_position", "pet_os_subiteration", "pet_os_reconstruct",
+           "pet_os_state_export", "pet_os_state_import", "pet_os_run", "pet_os_state_profile",
+           "pet_os_state_profile_read", "pet_os_nnz"]
+
+
+class PetOSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pet_os error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class GeomDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("vx", C.c_double), ("vy", C.c_double), ("vz", C.c_double),
+                ("n_angles", C.c_int32), ("n_radial", C.c_int32), ("ds", C.c_double),
+                ("n_rings", C.c_int32), ("max_ring_diff", C.c_int32),
+                ("ring_pitch", C.c_double), ("det_radius", C.c_double), ("n_subsets", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("beta", C.c_double), ("gamma_R", C.c_double),
+                ("eps", C.c_double), ("t_clip", C.c_double), ("U", C.c_double),
+                ("lambda0", C.c_double), ("a", C.c_double), ("rho", C.c_double),
+                ("delta1", C.c_double), ("delta2", C.c_double), ("nu1", C.c_double),
+                ("nu2", C.c_double), ("J0", C.c_int64), ("J1", C.c_int64),
+                ("objective_every", C.c_int32)]
+
+
+_lib = None
+_P = C.c_void_p
+
+
+def lib():
+    """Load libpet_os.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2111_07886_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        i32, i64 = C.c_int32, C.c_int64
+        sig = {
+            "pet_os_last_error": (C.c_char_p, []),
+            "pet_os_version": (C.c_char_p, []),
+            "pet_os_create_geometry": (C.c_int, [C.POINTER(GeomDesc), C.POINTER(_P)]),
+            "pet_os_destroy_geometry": (C.c_int, [_P]),
+            "pet_os_geometry_info": (C.c_int, [_P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]),
+            "pet_os_sensitivity": (C.c_int, [_P, _P, _P]),
+            "pet_os_forward": (C.c_int, [_P, _P, i32, _P, _P]),
+            "pet_os_back": (C.c_int, [_P, _P, i32, _P, _P]),
+            "pet_os_objective": (C.c_int, [_P, C.POINTER(Params), _P, _P, _P, C.POINTER(C.c_double), _P]),
+            "pet_os_default_U": (C.c_int, [_P, _P, _P, _P, C.POINTER(C.c_double), _P]),
+            "pet_os_state_create": (C.c_int, [_P, C.POINTER(Params), C.POINTER(_P)]),
+            "pet_os_state_destroy": (C.c_int, [_P]),
+            "pet_os_state_position": (C.c_int, [_P, C.POINTER(i64), C.POINTER(i32)]),
+            "pet_os_subiteration": (C.c_int, [_P, _P, _P, _P, _P]),
+            "pet_os_reconstruct": (C.c_int, [_P, C.POINTER(Params), _P, _P, _P, i32,
+                                             C.POINTER(C.c_double), _P]),
+            "pet_os_state_export": (C.c_int, [_P, _P, C.POINTER(C.c_size_t)]),
+            "pet_os_state_import": (C.c_int, [_P, _P, C.c_size_t]),
+            "pet_os_run": (C.c_int, [_P, _P, _P, _P, i32, C.POINTER(C.c_double), _P]),
+            "pet_os_state_profile": (C.c_int, [_P, i32]),
+            "pet_os_state_profile_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(i64)]),
+            "pet_os_nnz": (C.c_int, [_P, i32, C.POINTER(i64)]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().pet_os_last_error().decode()
+
+
+def _check(rc):
+    if rc != 0:
+        raise PetOSError(rc, last_error())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev(t: torch.Tensor, n: int | None = None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return C.c_void_p(t.data_ptr())
+
+
+def desc_struct(d: dict) -> GeomDesc:
+    g = GeomDesc()
+    g.dim = int(d["dim"])
+    g.nx, g.ny, g.nz = int(d["nx"]), int(d["ny"]), int(d.get("nz", 1))
+    g.vx, g.vy, g.vz = float(d["vx"]), float(d["vy"]), float(d.get("vz", 1.0))
+    g.n_angles, g.n_radial, g.ds = int(d["n_angles"]), int(d["n_radial"]), float(d["ds"])
+    g.n_rings, g.max_ring_diff = int(d.get("n_rings", 1)), int(d.get("max_ring_diff", 0))
+    g.ring_pitch, g.det_radius = float(d.get("ring_pitch", 1.0)), float(d.get("det_radius", 0.0))
+    g.n_subsets = int(d["n_subsets"])
+    return g
+
+
+def params_struct(p: dict) -> Params:
+    q = Params()
+    q.mode = MODES[p["mode"]] if isinstance(p["mode"], str) else int(p["mode"])
+    for k in ("beta", "gamma_R", "eps", "t_clip", "U", "lambda0", "a", "rho", "delta1", "delta2",
+              "nu1", "nu2"):
+        setattr(q, k, float(p[k]))
+    q.J0, q.J1 = int(p["J0"]), int(p["J1"])
+    q.objective_every = int(p.get("objective_every", 1))
+    return q
+
+
+class Geometry:
+    """Handle of pet_os_create_geometry (sensitivity and p computed on creation)."""
+
+    def __init__(self, desc: dict):
+        self.desc = dict(desc)
+        self._d = desc_struct(desc)
+        h = _P()
+        _check(lib().pet_os_create_geometry(C.byref(self._d), C.byref(h)))
+        self.handle = h
+        nv, nb, npl = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(lib().pet_os_geometry_info(h, C.byref(nv), C.byref(nb), C.byref(npl)))
+        self.n_voxels, self.n_bins, self.n_planes = nv.value, nb.value, npl.value
+
+    @property
+    def img_shape(self):
+        d = self.desc
+        return (d["nz"], d["ny"], d["nx"]) if d["dim"] == 3 else (d["ny"], d["nx"])
+
+    @property
+    def sino_shape(self):
+        return (self.n_planes, self.desc["n_angles"], self.desc["n_radial"])
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pet_os_destroy_geometry(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sensitivity(self, stream=None):
+        out = torch.empty(self.img_shape, device="cuda", dtype=torch.float32)
+        _check(lib().pet_os_sensitivity(self.handle, _dev(out), _stream(stream)))
+        return out
+
+    def forward(self, f, subset=0, out=None, stream=None):
+        if out is None:
+            out = torch.zeros(self.sino_shape, device="cuda", dtype=torch.float32)
+        _check(lib().pet_os_forward(self.handle, _dev(f, self.n_voxels, "f"), int(subset),
+                                    _dev(out, self.n_bins, "q"), _stream(stream)))
+        return out
+
+    def back(self, w, subset=0, out=None, stream=None):
+        if out is None:
+            out = torch.empty(self.img_shape, device="cuda", dtype=torch.float32)
+        _check(lib().pet_os_back(self.handle, _dev(w, self.n_bins, "w"), int(subset),
+                                 _dev(out, self.n_voxels, "out"), _stream(stream)))
+        return out
+
+    def objective(self, params: dict, f, y, r, stream=None) -> float:
+        p = params_struct(params)
+        phi = C.c_double()
+        _check(lib().pet_os_objective(self.handle, C.byref(p), _dev(f, self.n_voxels, "f"),
+                                      _dev(y, self.n_bins, "y"), _dev(r, self.n_bins, "r"),
+                                      C.byref(phi), _stream(stream)))
+        return phi.value
+
+    def nnz(self, subset=0) -> int:
+        n = C.c_int64()
+        _check(lib().pet_os_nnz(self.handle, int(subset), C.byref(n)))
+        return n.value
+
+    def default_U(self, f0, y, r, stream=None) -> float:
+        U = C.c_double()
+        _check(lib().pet_os_default_U(self.handle, _dev(f0, self.n_voxels, "f0"), _dev(y, self.n_bins, "y"),
+                                      _dev(r, self.n_bins, "r"), C.byref(U), _stream(stream)))
+        return U.value
+
+
+class State:
+    """Handle of pet_os_state_create: one reconstruction advanced subiteration by subiteration."""
+
+    def __init__(self, geom: Geometry, params: dict):
+        self.geom = geom
+        self._p = params_struct(params)
+        h = _P()
+        _check(lib().pet_os_state_create(geom.handle, C.byref(self._p), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pet_os_state_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def subiteration(self, f, y, r, stream=None):
+        g = self.geom
+        _check(lib().pet_os_subiteration(self.handle, _dev(f, g.n_voxels, "f"), _dev(y, g.n_bins, "y"),
+                                         _dev(r, g.n_bins, "r"), _stream(stream)))
+
+    def run(self, f, y, r, n_iter, want_objective=False, stream=None):
+        """pet_os_run: n_iter iterations from the current position; returns the
+        objective after each iteration (NaN where not evaluated) or None."""
+        g = self.geom
+        obj = (C.c_double * max(1, n_iter))() if want_objective else None
+        _check(lib().pet_os_run(self.handle, _dev(f, g.n_voxels, "f"), _dev(y, g.n_bins, "y"),
+                                _dev(r, g.n_bins, "r"), int(n_iter), obj, _stream(stream)))
+        return list(obj)[:n_iter] if want_objective else None
+
+    def profile(self, kernel: int):
+        """Bracket every launch of kernel 0 (forward+ratio), 1 (back+stencil) or
+        2 (update) with HIP events; -1 switches off."""
+        _check(lib().pet_os_state_profile(self.handle, int(kernel)))
+
+    def profile_read(self):
+        ms, n = C.c_double(), C.c_int64()
+        _check(lib().pet_os_state_profile_read(self.handle, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def position(self):
+        k, i = C.c_int64(), C.c_int32()
+        _check(lib().pet_os_state_position(self.handle, C.byref(k), C.byref(i)))
+        return k.value, i.value
+
+    def export(self) -> bytes:
+        n = C.c_size_t()
+        _check(lib().pet_os_state_export(self.handle, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().pet_os_state_export(self.handle, buf, C.byref(n)))
+        return buf.raw[: n.value]
+
+    def import_(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(lib().pet_os_state_import(self.handle, buf, len(blob)))
+
+
+def reconstruct(geom: Geometry, params: dict, f, y, r, n_iter: int, want_objective=False, stream=None):
+    """pet_os_reconstruct: n_iter iterations in place on f; returns the objective
+    trace (list of n_iter+1 floats, NaN where not evaluated) or None."""
+    p = params_struct(params)
+    obj = (C.c_double * (n_iter + 1))() if want_objective else None
+    _check(lib().pet_os_reconstruct(geom.handle, C.byref(p), _dev(f, geom.n_voxels, "f"),
+                                    _dev(y, geom.n_bins, "y"), _dev(r, geom.n_bins, "r"), int(n_iter),
+                                    obj, _stream(stream)))
+    return list(obj) if want_objective else None

@@ -1,0 +1,914 @@
+// capi.cpp -- C ABI of the pet_os library: geometry tables, per-request state,
+// the plain subiteration / reconstruct drivers, objective, checkpoints.
+//
+// Host side of SDP-BSREM (Table I): the FP64 scalar schedule (lambda_k of
+// thm:SpecificSDPs, alpha_{k,i} of preconditioner:Nesterov / preconditioner:KM,
+// the J-mode of eq:nuki) is evaluated here and handed to the kernels; every
+// per-voxel and per-bin step runs on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace petos {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+    set_error(msg);
+    return code;
+}
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// ---------------------------------------------------------------- geometry validation
+
+static int validate_desc(const pet_os_geom_desc* d) {
+    if (!d) return fail(PET_OS_ERR_INVALID_ARG, "desc is NULL");
+    if (d->dim != 2 && d->dim != 3) return fail(PET_OS_ERR_INVALID_ARG, "dim must be 2 or 3");
+    if (d->nx < 1 || d->ny < 1) return fail(PET_OS_ERR_INVALID_ARG, "nx, ny must be >= 1");
+    if (!finite_pos(d->vx) || !finite_pos(d->vy) || !finite_pos(d->ds))
+        return fail(PET_OS_ERR_INVALID_ARG, "vx, vy, ds must be finite and > 0");
+    if (d->n_angles < 1 || d->n_radial < 1) return fail(PET_OS_ERR_INVALID_ARG, "n_angles, n_radial must be >= 1");
+    if (d->n_subsets < 1 || d->n_subsets > d->n_angles)
+        return fail(PET_OS_ERR_INVALID_ARG, "n_subsets must be in [1, n_angles]");
+    if ((int64_t)d->nx * d->ny * (d->dim == 3 ? d->nz : 1) > (int64_t)1 << 30)
+        return fail(PET_OS_ERR_INVALID_ARG, "image too large");
+    if (d->dim == 3) {
+        if (d->nz < 1 || !finite_pos(d->vz)) return fail(PET_OS_ERR_INVALID_ARG, "nz >= 1 and vz > 0 required");
+        if (d->n_rings != d->nz || d->ring_pitch != d->vz)
+            return fail(PET_OS_ERR_INVALID_ARG, "rings must sit at slice centres: n_rings == nz, ring_pitch == vz");
+        if (d->max_ring_diff < 0 || d->max_ring_diff > std::min(d->nz - 1, 31))
+            return fail(PET_OS_ERR_INVALID_ARG, "max_ring_diff must be in [0, min(nz-1, 31)]");
+        double half_diag = 0.5 * std::sqrt((double)d->nx * d->nx * d->vx * d->vx + (double)d->ny * d->ny * d->vy * d->vy);
+        double smax = 0.5 * (d->n_radial - 1) * d->ds;
+        if (!finite_pos(d->det_radius) || d->det_radius <= half_diag || d->det_radius <= smax)
+            return fail(PET_OS_ERR_INVALID_ARG, "det_radius must exceed the image half-diagonal and the largest |s_b|");
+        double hmin = std::sqrt(d->det_radius * d->det_radius - smax * smax);
+        double step = std::sqrt(d->vx * d->vx + d->vy * d->vy);
+        if (d->max_ring_diff * step / (2.0 * hmin) >= 1.0)
+            return fail(PET_OS_ERR_INVALID_ARG, "LORs too oblique: more than one slice per transaxial voxel");
+    }
+    return PET_OS_OK;
+}
+
+static int n_planes_of(const pet_os_geom_desc* d) {
+    if (d->dim == 2) return 1;
+    int n = d->n_rings;
+    for (int k = 1; k <= d->max_ring_diff; ++k) n += 2 * (d->n_rings - k);
+    return n;
+}
+
+// exact grid position of an axis-parallel ray on an axis with n cells of size v
+static double axis_pos(const pet_os_geom_desc* d, int b, int n, double v) {
+    if (d->ds == v) return (double)(2L * b - (d->n_radial - 1) + n) / 2.0;
+    double sb = ((double)b - 0.5 * (double)(d->n_radial - 1)) * d->ds;
+    return (sb + 0.5 * n * v) / v;
+}
+
+static void build_angles(const pet_os_geom_desc* d, std::vector<AngleK>& out) {
+    const double h0 = 0.5 * (double)(d->n_radial - 1);
+    out.resize(d->n_angles);
+    for (int a = 0; a < d->n_angles; ++a) {
+        AngleK K{};
+        double c, s;
+        if (a == 0) { c = 1.0; s = 0.0; }
+        else if (2 * a == d->n_angles) { c = 0.0; s = 1.0; }
+        else {
+            double th = (double)a * M_PI / (double)d->n_angles;
+            c = std::cos(th);
+            s = std::sin(th);
+        }
+        K.c = c;
+        K.s = s;
+        K.row_major = (std::fabs(c) * d->vx >= std::fabs(s) * d->vy) ? 1 : 0;
+        if (K.row_major) {
+            if (s == 0.0) {
+                K.Q = 0.0; K.invQ = 0.0; K.icv = 0.0; K.K = 0.0;
+                K.wslope = d->ds / d->vx;
+                K.wC = 0.5 * d->nx - h0 * d->ds / d->vx;
+            } else {
+                double t = s / c;
+                K.Q = -t * (d->vy / d->vx);
+                K.invQ = 1.0 / K.Q;
+                K.icv = 1.0 / (c * d->vx);
+                K.K = 0.5 * d->nx + t * (d->vy / d->vx) * (0.5 * d->ny);
+                K.wslope = d->ds * K.icv;
+                K.wC = K.K - h0 * d->ds * K.icv;
+            }
+            K.L = d->vy / std::fabs(c);
+            K.Au = -s / c;
+            K.Bu = -0.5 * d->ny * d->vy / c;
+            K.du = d->vy / c;
+        } else {
+            if (c == 0.0) {
+                K.Q = 0.0; K.invQ = 0.0; K.icv = 0.0; K.K = 0.0;
+                K.wslope = d->ds / d->vy;
+                K.wC = 0.5 * d->ny - h0 * d->ds / d->vy;
+            } else {
+                double t = c / s;
+                K.Q = -t * (d->vx / d->vy);
+                K.invQ = 1.0 / K.Q;
+                K.icv = 1.0 / (s * d->vy);
+                K.K = 0.5 * d->ny + t * (d->vx / d->vy) * (0.5 * d->nx);
+                K.wslope = d->ds * K.icv;
+                K.wC = K.K - h0 * d->ds * K.icv;
+            }
+            K.L = d->vx / std::fabs(s);
+            K.Au = c / s;
+            K.Bu = 0.5 * d->nx * d->vx / s;
+            K.du = -d->vx / s;
+        }
+        out[a] = K;
+    }
+}
+
+}  // namespace petos
+
+using namespace petos;
+
+std::vector<int> pet_os_geom::subset_angles(int subset) const {
+    std::vector<int> v;
+    for (int a = 0; a < d.n_angles; ++a)
+        if (subset == 0 || a % d.n_subsets == subset - 1) v.push_back(a);
+    return v;
+}
+
+// device block layout helper
+namespace {
+struct Carver {
+    size_t off = 0;
+    template <typename T>
+    size_t take(size_t n) {
+        off = (off + 255) & ~(size_t)255;
+        size_t at = off;
+        off += n * sizeof(T);
+        return at;
+    }
+};
+}  // namespace
+
+struct GeomExtra {
+    int* all_angles;     // [n_angles] 0..Na-1
+    int* subset_lists;   // [M][max_sub]
+    std::vector<int> subset_count;
+};
+
+// The subset lists live inside dev_block right after the tables; keep their
+// offsets in a side table keyed by the geometry.
+#include <map>
+#include <mutex>
+static std::mutex g_geo_mu;
+static std::map<const pet_os_geom*, GeomExtra> g_geo_extra;
+
+static GeomExtra* extra_of(const pet_os_geom* g) {
+    std::lock_guard<std::mutex> lk(g_geo_mu);
+    auto it = g_geo_extra.find(g);
+    return it == g_geo_extra.end() ? nullptr : &it->second;
+}
+
+
+extern "C" {
+
+const char* pet_os_last_error(void) { return g_last_error.c_str(); }
+
+const char* pet_os_version(void) { return "pet_os 0.1 (gfx950)"; }
+
+int pet_os_create_geometry(const pet_os_geom_desc* desc, pet_os_geom** out) {
+    if (!out) return fail(PET_OS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = validate_desc(desc);
+    if (rc) return rc;
+    pet_os_geom_desc d = *desc;
+    if (d.dim == 2) {
+        d.nz = 1; d.vz = 1.0; d.n_rings = 1; d.max_ring_diff = 0; d.ring_pitch = 1.0;
+    }
+    auto* G = new pet_os_geom();
+    G->d = d;
+    G->n_planes = n_planes_of(&d);
+    G->n_vox = (int64_t)d.nx * d.ny * d.nz;
+    G->n_bins = (int64_t)G->n_planes * d.n_angles * d.n_radial;
+    PETOS_HIP(hipGetDevice(&G->device));
+
+    // host tables (FP64)
+    std::vector<AngleK> ang;
+    build_angles(&d, ang);
+    std::vector<BinK> bins(d.n_radial);
+    const int D = d.max_ring_diff, ND = 2 * D + 1;
+    std::vector<double> kappa((size_t)d.n_radial * ND);
+    for (int b = 0; b < d.n_radial; ++b) {
+        BinK& B = bins[b];
+        B.sb = ((double)b - 0.5 * (double)(d.n_radial - 1)) * d.ds;
+        if (d.dim == 3) {
+            B.h = std::sqrt(d.det_radius * d.det_radius - B.sb * B.sb);
+            B.inv2h = 1.0 / (2.0 * B.h);
+        } else {
+            B.h = 1.0;
+            B.inv2h = 0.5;
+        }
+        B.axis_pos_x = axis_pos(&d, b, d.nx, d.vx);
+        B.axis_pos_y = axis_pos(&d, b, d.ny, d.vy);
+        for (int k = -D; k <= D; ++k) {
+            double mz = (double)k * d.ring_pitch / (2.0 * B.h);
+            kappa[(size_t)b * ND + k + D] = (d.dim == 3) ? std::sqrt(1.0 + mz * mz) : 1.0;
+        }
+    }
+    std::vector<int2> planes;
+    std::vector<int> plane_base(ND);
+    std::vector<double> inv_d(ND);
+    for (int m = 0; m <= 2 * D; ++m) {
+        int dd = (m == 0) ? 0 : ((m % 2) ? (m + 1) / 2 : -(m / 2));
+        int lo = dd < 0 ? -dd : 0, hi = dd < 0 ? d.n_rings - 1 : d.n_rings - 1 - dd;
+        plane_base[dd + D] = (int)planes.size();
+        for (int r1 = lo; r1 <= hi; ++r1) planes.push_back(make_int2(r1, dd));
+    }
+    if (d.dim == 2) planes.assign(1, make_int2(0, 0));
+    for (int k = -D; k <= D; ++k) inv_d[k + D] = (k == 0) ? 0.0 : 1.0 / (double)k;
+
+    const int M = d.n_subsets;
+    int max_sub = 0;
+    std::vector<int> counts(M);
+    for (int i = 1; i <= M; ++i) {
+        counts[i - 1] = (int)G->subset_angles(i).size();
+        max_sub = std::max(max_sub, counts[i - 1]);
+    }
+    G->max_sub_angles = max_sub;
+    std::vector<int> lists((size_t)M * max_sub, 0);
+    for (int i = 1; i <= M; ++i) {
+        auto v = G->subset_angles(i);
+        std::copy(v.begin(), v.end(), lists.begin() + (size_t)(i - 1) * max_sub);
+    }
+    std::vector<int> all(d.n_angles);
+    for (int a = 0; a < d.n_angles; ++a) all[a] = a;
+
+    Carver cv;
+    size_t o_ang = cv.take<AngleK>(ang.size());
+    size_t o_bin = cv.take<BinK>(bins.size());
+    size_t o_pl = cv.take<int2>(planes.size());
+    size_t o_kap = cv.take<double>(kappa.size());
+    size_t o_pb = cv.take<int>(plane_base.size());
+    size_t o_id = cv.take<double>(inv_d.size());
+    size_t o_all = cv.take<int>(all.size());
+    size_t o_lst = cv.take<int>(lists.size());
+    size_t o_pn = cv.take<float>((size_t)G->n_vox);
+    size_t o_sn = cv.take<float>((size_t)G->n_vox);
+    size_t total = cv.off;
+    char* blk = nullptr;
+    if (hipMalloc(&blk, total) != hipSuccess) {
+        delete G;
+        return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc of geometry tables failed");
+    }
+    G->dev_block = blk;
+    auto up = [&](size_t off, const void* src, size_t bytes) {
+        return hipMemcpy(blk + off, src, bytes, hipMemcpyHostToDevice);
+    };
+    if (up(o_ang, ang.data(), ang.size() * sizeof(AngleK)) != hipSuccess ||
+        up(o_bin, bins.data(), bins.size() * sizeof(BinK)) != hipSuccess ||
+        up(o_pl, planes.data(), planes.size() * sizeof(int2)) != hipSuccess ||
+        up(o_kap, kappa.data(), kappa.size() * sizeof(double)) != hipSuccess ||
+        up(o_pb, plane_base.data(), plane_base.size() * sizeof(int)) != hipSuccess ||
+        up(o_id, inv_d.data(), inv_d.size() * sizeof(double)) != hipSuccess ||
+        up(o_all, all.data(), all.size() * sizeof(int)) != hipSuccess ||
+        up(o_lst, lists.data(), lists.size() * sizeof(int)) != hipSuccess) {
+        (void)hipFree(blk);
+        delete G;
+        return fail(PET_OS_ERR_DEVICE, "upload of geometry tables failed");
+    }
+    GeoK& k = G->k;
+    k.dim = d.dim; k.nx = d.nx; k.ny = d.ny; k.nz = d.nz;
+    k.n_angles = d.n_angles; k.n_radial = d.n_radial; k.n_subsets = M; k.n_planes = G->n_planes;
+    k.n_rings = d.n_rings; k.max_rd = D; k.nvox = (int)G->n_vox;
+    k.vx = d.vx; k.vy = d.vy; k.vz = d.vz; k.ds = d.ds; k.det_radius = d.det_radius;
+    k.ang = (const AngleK*)(blk + o_ang);
+    k.bin = (const BinK*)(blk + o_bin);
+    k.planes = (const int2*)(blk + o_pl);
+    k.kappa = (const double*)(blk + o_kap);
+    k.plane_base = (const int*)(blk + o_pb);
+    k.inv_d = (const double*)(blk + o_id);
+    G->pnorm = (float*)(blk + o_pn);
+    G->sens = (float*)(blk + o_sn);
+    {
+        std::lock_guard<std::mutex> lk(g_geo_mu);
+        GeomExtra& e = g_geo_extra[G];
+        e.all_angles = (int*)(blk + o_all);
+        e.subset_lists = (int*)(blk + o_lst);
+        e.subset_count = counts;
+    }
+
+    // a0: sensitivity A^T 1 and p of eq:pj
+    BPLaunch L{};
+    L.w = nullptr;
+    L.angles = (const int*)(blk + o_all);
+    L.n_al = d.n_angles;
+    L.out = G->sens;
+    rc = launch_bp(G, L, nullptr);
+    if (rc) { pet_os_destroy_geometry(G); return rc; }
+    std::vector<float> s((size_t)G->n_vox);
+    if (hipMemcpy(s.data(), G->sens, s.size() * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) {
+        pet_os_destroy_geometry(G);
+        return fail(PET_OS_ERR_DEVICE, "sensitivity read-back failed");
+    }
+    std::vector<float> p(s.size());
+    double ssum = 0.0;
+    for (size_t j = 0; j < s.size(); ++j) {
+        ssum += s[j];
+        p[j] = (s[j] > 0.0f) ? (float)((double)s[j] / (double)M) : (float)(1.0 / (double)M);
+    }
+    G->sens_sum = ssum;
+    if (hipMemcpy(G->pnorm, p.data(), p.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+        pet_os_destroy_geometry(G);
+        return fail(PET_OS_ERR_DEVICE, "upload of p failed");
+    }
+    *out = G;
+    return PET_OS_OK;
+}
+
+int pet_os_destroy_geometry(pet_os_geom* geom) {
+    if (!geom) return fail(PET_OS_ERR_INVALID_ARG, "geom is NULL");
+    {
+        std::lock_guard<std::mutex> lk(g_geo_mu);
+        g_geo_extra.erase(geom);
+    }
+    if (geom->dev_block) (void)hipFree(geom->dev_block);
+    delete geom;
+    return PET_OS_OK;
+}
+
+int pet_os_geometry_info(const pet_os_geom* g, int64_t* nv, int64_t* nb, int32_t* np) {
+    if (!g) return fail(PET_OS_ERR_INVALID_ARG, "geom is NULL");
+    if (nv) *nv = g->n_vox;
+    if (nb) *nb = g->n_bins;
+    if (np) *np = g->n_planes;
+    return PET_OS_OK;
+}
+
+int pet_os_sensitivity(const pet_os_geom* g, float* out, pet_os_stream stream) {
+    if (!g || !out) return fail(PET_OS_ERR_INVALID_ARG, "NULL argument");
+    PETOS_HIP(hipMemcpyAsync(out, g->sens, (size_t)g->n_vox * sizeof(float), hipMemcpyDeviceToDevice,
+                             (hipStream_t)stream));
+    return PET_OS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- work buffers
+
+namespace petos {
+
+int work_alloc(const pet_os_geom* g, bool need_nu, Work* w) {
+    *w = Work{};
+    Carver cv;
+    size_t nv = (size_t)g->n_vox;
+    size_t o_w = cv.take<float>((size_t)g->max_sub_angles * g->n_planes * g->d.n_radial);
+    size_t o_G = cv.take<float>(nv);
+    size_t o_mu = cv.take<float>(nv);
+    size_t o_nu = need_nu ? cv.take<float>(nv) : 0;
+    int caps[RED_COUNT];
+    caps[RED_SUMF] = elem_grid(g->n_vox);
+    caps[RED_SUMMU] = bp_grid(g);
+    caps[RED_FID] = fp_grid(g, g->d.n_angles);
+    caps[RED_RDP] = elem_grid(g->n_vox);
+    caps[RED_SUMY] = elem_grid(g->n_bins);
+    caps[RED_SUMR] = elem_grid(g->n_bins);
+    caps[RED_SUMS] = 1;
+    size_t o_red[RED_COUNT];
+    for (int r = 0; r < RED_COUNT; ++r) o_red[r] = cv.take<double>((size_t)caps[r]);
+    size_t o_tot = cv.take<double>(RED_COUNT);
+    size_t o_tk = cv.take<unsigned>(RED_COUNT);
+    char* blk = nullptr;
+    if (hipMalloc(&blk, cv.off) != hipSuccess) return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc of scratch failed");
+    w->bytes = cv.off;
+    w->red_block = (double*)blk;
+    w->w = (float*)(blk + o_w);
+    w->G = (float*)(blk + o_G);
+    w->mu = (float*)(blk + o_mu);
+    w->nu_frozen = need_nu ? (float*)(blk + o_nu) : nullptr;
+    for (int r = 0; r < RED_COUNT; ++r) {
+        w->red[r].part = (double*)(blk + o_red[r]);
+        w->red[r].total = (double*)(blk + o_tot) + r;
+        w->red[r].ticket = (unsigned*)(blk + o_tk) + r;
+        w->red[r].cap = caps[r];
+    }
+    if (hipMemset(blk + o_tot, 0, RED_COUNT * sizeof(double)) != hipSuccess ||
+        hipMemset(blk + o_tk, 0, RED_COUNT * sizeof(unsigned)) != hipSuccess) {
+        (void)hipFree(blk);
+        return fail(PET_OS_ERR_DEVICE, "scratch init failed");
+    }
+    return PET_OS_OK;
+}
+
+void work_free(Work* w) {
+    if (w->red_block) (void)hipFree(w->red_block);
+    *w = Work{};
+}
+
+}  // namespace petos
+
+// ---------------------------------------------------------------- state
+
+struct pet_os_state {
+    const pet_os_geom* g;
+    pet_os_params p;
+    int64_t k;
+    int32_t i;
+    double t_nest;
+    int have_frozen;
+    Work w;
+    double* obj_dev = nullptr;          // (fid, R) pairs of queued objective evaluations
+    int obj_cap = 0;
+    int prof_kernel = -1;               // kernel bracketed by events, -1 = none
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+    size_t prof_used = 0;
+};
+
+namespace petos {
+
+static int validate_params(const pet_os_params* p, const pet_os_geom* g) {
+    if (!p) return fail(PET_OS_ERR_INVALID_ARG, "params is NULL");
+    if (p->mode < PET_OS_BSREM || p->mode > PET_OS_P2) return fail(PET_OS_ERR_INVALID_ARG, "unknown mode");
+    if (!(std::isfinite(p->beta) && p->beta >= 0.0)) return fail(PET_OS_ERR_INVALID_ARG, "beta must be >= 0");
+    if (!(std::isfinite(p->gamma_R) && p->gamma_R >= 0.0)) return fail(PET_OS_ERR_INVALID_ARG, "gamma_R must be >= 0");
+    if (!finite_pos(p->eps)) return fail(PET_OS_ERR_INVALID_ARG, "eps must be > 0");
+    if (!finite_pos(p->U)) return fail(PET_OS_ERR_INVALID_ARG, "U must be > 0");
+    if (!(std::isfinite(p->t_clip) && p->t_clip > 0.0 && p->t_clip < p->U))
+        return fail(PET_OS_ERR_INVALID_ARG, "t_clip must be in (0, U)");
+    if (!finite_pos(p->lambda0) || !finite_pos(p->a)) return fail(PET_OS_ERR_INVALID_ARG, "lambda0, a must be > 0");
+    if (p->mode == PET_OS_M2 || p->mode == PET_OS_P2) {
+        if (!finite_pos(p->rho) || !finite_pos(p->delta1) || !finite_pos(p->delta2))
+            return fail(PET_OS_ERR_INVALID_ARG, "rho, delta1, delta2 must be > 0");
+    }
+    if (p->mode == PET_OS_P1 || p->mode == PET_OS_P2) {
+        if (!(finite_pos(p->nu1) && std::isfinite(p->nu2) && p->nu1 < p->nu2))
+            return fail(PET_OS_ERR_INVALID_ARG, "need 0 < nu1 < nu2");
+        if (p->J0 < 0 || p->J1 < p->J0) return fail(PET_OS_ERR_INVALID_ARG, "need 0 <= J0 <= J1");
+    }
+    (void)g;
+    return PET_OS_OK;
+}
+
+// FP64 scalar schedule of subiteration (k, i); advances the Nesterov t.
+struct Sched {
+    double lam, alpha;
+    int nu_mode;
+};
+
+static Sched schedule_step(pet_os_state* st) {
+    const pet_os_params& p = st->p;
+    const int M = st->g->d.n_subsets;
+    const int64_t J = st->k * (int64_t)M + st->i;
+    Sched s;
+    s.lam = p.lambda0 / (p.a * (double)st->k + 1.0);
+    s.alpha = 1.0;
+    if (p.mode == PET_OS_M1 || p.mode == PET_OS_P1) {
+        double t = st->t_nest;
+        double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+        s.alpha = 1.0 + (t - 1.0) / tn;
+        st->t_nest = tn;
+    } else if (p.mode == PET_OS_M2 || p.mode == PET_OS_P2) {
+        double n = (double)(J - 1);
+        s.alpha = (p.rho * n + p.delta2) / (n + p.delta1);
+    }
+    s.nu_mode = NU_ONE;
+    if (p.mode == PET_OS_P1 || p.mode == PET_OS_P2) {
+        if (J <= p.J0) s.nu_mode = NU_ONE;
+        else if (J < p.J1) s.nu_mode = NU_COMPUTE;
+        else if (J == p.J1) s.nu_mode = NU_COMPUTE_FREEZE;
+        else s.nu_mode = st->have_frozen ? NU_FROZEN : NU_ONE;
+    }
+    return s;
+}
+
+// events around launches of the profiled kernel
+static int prof_begin(pet_os_state* st, int kernel, hipStream_t s, hipEvent_t* end) {
+    *end = nullptr;
+    if (st->prof_kernel != kernel) return PET_OS_OK;
+    if (st->prof_used == st->prof_ev.size()) {
+        hipEvent_t a, b;
+        PETOS_HIP(hipEventCreate(&a));
+        PETOS_HIP(hipEventCreate(&b));
+        st->prof_ev.emplace_back(a, b);
+    }
+    auto& pr = st->prof_ev[st->prof_used++];
+    PETOS_HIP(hipEventRecord(pr.first, s));
+    *end = pr.second;
+    return PET_OS_OK;
+}
+
+static int prof_end(hipEvent_t end, hipStream_t s) {
+    if (end) PETOS_HIP(hipEventRecord(end, s));
+    return PET_OS_OK;
+}
+
+static int run_subiteration(pet_os_state* st, float* f, const float* y, const float* r, hipStream_t s,
+                            bool sumf_current) {
+    const pet_os_geom* g = st->g;
+    GeomExtra* ex = extra_of(g);
+    if (!ex) return fail(PET_OS_ERR_INVALID_ARG, "geometry was destroyed");
+    const int M = g->d.n_subsets;
+    Sched sc = schedule_step(st);
+    const bool want_mu = sc.nu_mode == NU_COMPUTE || sc.nu_mode == NU_COMPUTE_FREEZE;
+    int rc;
+    if (want_mu && !sumf_current) {
+        rc = launch_sum(f, g->n_vox, st->w.red[RED_SUMF], s);
+        if (rc) return rc;
+    }
+    const int* angles = ex->subset_lists + (size_t)(st->i - 1) * g->max_sub_angles;
+    const int n_al = ex->subset_count[st->i - 1];
+    FPLaunch F{};
+    F.f = f; F.y = y; F.r = r; F.out = st->w.w; F.angles = angles; F.n_al = n_al; F.mode = FP_RATIO;
+    hipEvent_t ev;
+    if ((rc = prof_begin(st, 0, s, &ev))) return rc;
+    rc = launch_fp(g, F, s);
+    if (rc || (rc = prof_end(ev, s))) return rc;
+    BPLaunch B{};
+    B.w = st->w.w; B.w_natural = 0; B.angles = angles; B.n_al = n_al; B.out = st->w.G;
+    B.f = f; B.mu = st->w.mu; B.want_mu = want_mu ? 1 : 0;
+    B.beta_over_M = (float)(st->p.beta / (double)M);
+    B.gamma_R = (float)st->p.gamma_R;
+    B.eps = (float)st->p.eps;
+    B.total_f = st->w.red[RED_SUMF].total;
+    B.red_mu = st->w.red[RED_SUMMU];
+    if ((rc = prof_begin(st, 1, s, &ev))) return rc;
+    rc = launch_bp(g, B, s);
+    if (rc || (rc = prof_end(ev, s))) return rc;
+    UpdLaunch U{};
+    U.f = f; U.G = st->w.G; U.mu = st->w.mu; U.pnorm = g->pnorm; U.nu_frozen = st->w.nu_frozen;
+    U.nu_mode = sc.nu_mode;
+    U.step = (float)(sc.lam * sc.alpha);
+    U.nu1 = (float)st->p.nu1; U.nu2 = (float)st->p.nu2;
+    U.U = (float)st->p.U; U.t_clip = (float)st->p.t_clip;
+    U.total_mu = st->w.red[RED_SUMMU].total;
+    U.red_f = st->w.red[RED_SUMF];
+    if ((rc = prof_begin(st, 2, s, &ev))) return rc;
+    rc = launch_update(g, U, s);
+    if (rc || (rc = prof_end(ev, s))) return rc;
+    if (sc.nu_mode == NU_COMPUTE_FREEZE) st->have_frozen = 1;
+    st->i += 1;
+    if (st->i > M) { st->i = 1; st->k += 1; }
+    return PET_OS_OK;
+}
+
+// queue Phi(f) = fidelity + beta R into two device doubles (fid, R) at dst
+static int queue_objective(const pet_os_geom* g, const pet_os_params* p, Work* w, const float* f,
+                           const float* y, const float* r, double* dst, hipStream_t s) {
+    GeomExtra* ex = extra_of(g);
+    FPLaunch F{};
+    F.f = f; F.y = y; F.r = r; F.out = nullptr; F.angles = ex->all_angles; F.n_al = g->d.n_angles;
+    F.mode = FP_OBJECTIVE; F.red = w->red[RED_FID];
+    int rc = launch_fp(g, F, s);
+    if (rc) return rc;
+    rc = launch_rdp_value(g, f, (float)p->gamma_R, (float)p->eps, w->red[RED_RDP], s);
+    if (rc) return rc;
+    PETOS_HIP(hipMemcpyAsync(dst, w->red[RED_FID].total, sizeof(double), hipMemcpyDeviceToDevice, s));
+    PETOS_HIP(hipMemcpyAsync(dst + 1, w->red[RED_RDP].total, sizeof(double), hipMemcpyDeviceToDevice, s));
+    return PET_OS_OK;
+}
+
+}  // namespace petos
+
+extern "C" {
+
+int pet_os_state_create(const pet_os_geom* g, const pet_os_params* p, pet_os_state** out) {
+    if (!out) return fail(PET_OS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!g || !extra_of(g)) return fail(PET_OS_ERR_INVALID_ARG, "invalid geometry");
+    int rc = validate_params(p, g);
+    if (rc) return rc;
+    auto* st = new pet_os_state();
+    st->g = g;
+    st->p = *p;
+    st->k = 0;
+    st->i = 1;
+    st->t_nest = 1.0;
+    st->have_frozen = 0;
+    const bool need_nu = p->mode == PET_OS_P1 || p->mode == PET_OS_P2;
+    rc = work_alloc(g, need_nu, &st->w);
+    if (rc) { delete st; return rc; }
+    *out = st;
+    return PET_OS_OK;
+}
+
+int pet_os_state_destroy(pet_os_state* st) {
+    if (!st) return fail(PET_OS_ERR_INVALID_ARG, "state is NULL");
+    work_free(&st->w);
+    if (st->obj_dev) (void)hipFree(st->obj_dev);
+    for (auto& pr : st->prof_ev) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    delete st;
+    return PET_OS_OK;
+}
+
+int pet_os_state_position(const pet_os_state* st, int64_t* k, int32_t* i) {
+    if (!st) return fail(PET_OS_ERR_INVALID_ARG, "state is NULL");
+    if (k) *k = st->k;
+    if (i) *i = st->i;
+    return PET_OS_OK;
+}
+
+int pet_os_subiteration(pet_os_state* st, float* f, const float* y, const float* r, pet_os_stream stream) {
+    if (!st || !f || !y || !r) return fail(PET_OS_ERR_INVALID_ARG, "NULL argument");
+    return run_subiteration(st, f, y, r, (hipStream_t)stream, false);
+}
+
+int pet_os_forward(const pet_os_geom* g, const float* f, int32_t subset, float* q, pet_os_stream stream) {
+    if (!g || !f || !q) return fail(PET_OS_ERR_INVALID_ARG, "NULL argument");
+    GeomExtra* ex = extra_of(g);
+    if (!ex) return fail(PET_OS_ERR_INVALID_ARG, "invalid geometry");
+    if (subset < 0 || subset > g->d.n_subsets) return fail(PET_OS_ERR_INVALID_ARG, "subset out of range");
+    FPLaunch F{};
+    F.f = f; F.out = q; F.mode = FP_PLAIN;
+    F.angles = subset == 0 ? ex->all_angles : ex->subset_lists + (size_t)(subset - 1) * g->max_sub_angles;
+    F.n_al = subset == 0 ? g->d.n_angles : ex->subset_count[subset - 1];
+    return launch_fp(g, F, (hipStream_t)stream);
+}
+
+int pet_os_back(const pet_os_geom* g, const float* w, int32_t subset, float* out, pet_os_stream stream) {
+    if (!g || !w || !out) return fail(PET_OS_ERR_INVALID_ARG, "NULL argument");
+    GeomExtra* ex = extra_of(g);
+    if (!ex) return fail(PET_OS_ERR_INVALID_ARG, "invalid geometry");
+    if (subset < 0 || subset > g->d.n_subsets) return fail(PET_OS_ERR_INVALID_ARG, "subset out of range");
+    BPLaunch B{};
+    B.w = w; B.w_natural = 1; B.out = out;
+    B.angles = subset == 0 ? ex->all_angles : ex->subset_lists + (size_t)(subset - 1) * g->max_sub_angles;
+    B.n_al = subset == 0 ? g->d.n_angles : ex->subset_count[subset - 1];
+    return launch_bp(g, B, (hipStream_t)stream);
+}
+
+int pet_os_objective(const pet_os_geom* g, const pet_os_params* p, const float* f, const float* y,
+                     const float* r, double* phi, pet_os_stream stream) {
+    if (!g || !p || !f || !y || !r || !phi) return fail(PET_OS_ERR_INVALID_ARG, "NULL argument");
+    if (!extra_of(g)) return fail(PET_OS_ERR_INVALID_ARG, "invalid geometry");
+    Work w;
+    int rc = work_alloc(g, false, &w);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    double* dst = nullptr;
+    if (hipMalloc(&dst, 2 * sizeof(double)) != hipSuccess) {
+        work_free(&w);
+        return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc failed");
+    }
+    rc = queue_objective(g, p, &w, f, y, r, dst, s);
+    double h[2] = {0, 0};
+    if (!rc) {
+        if (hipMemcpyAsync(h, dst, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            rc = fail(PET_OS_ERR_DEVICE, "objective read-back failed");
+    }
+    (void)hipFree(dst);
+    work_free(&w);
+    if (rc) return rc;
+    *phi = h[0] + p->beta * h[1];
+    if (!std::isfinite(*phi)) return fail(PET_OS_ERR_NUMERIC, "objective is not finite");
+    return PET_OS_OK;
+}
+
+int pet_os_default_U(const pet_os_geom* g, const float* f0, const float* y, const float* r, double* U,
+                     pet_os_stream stream) {
+    if (!g || !f0 || !y || !r || !U) return fail(PET_OS_ERR_INVALID_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    Work w;
+    int rc = work_alloc(g, false, &w);
+    if (rc) return rc;
+    rc = launch_sum(y, g->n_bins, w.red[RED_SUMY], s);
+    if (!rc) rc = launch_sum(r, g->n_bins, w.red[RED_SUMR], s);
+    double sy = 0, sr = 0;
+    std::vector<float> fh((size_t)g->n_vox);
+    if (!rc) {
+        if (hipMemcpyAsync(&sy, w.red[RED_SUMY].total, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&sr, w.red[RED_SUMR].total, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(fh.data(), f0, fh.size() * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            rc = fail(PET_OS_ERR_DEVICE, "default_U read-back failed");
+    }
+    work_free(&w);
+    if (rc) return rc;
+    double fmax = 0.0;
+    for (float v : fh) fmax = std::max(fmax, (double)v);
+    double chat = (sy - sr > 0.0 && g->sens_sum > 0.0) ? (sy - sr) / g->sens_sum : 0.0;
+    *U = 1e3 * std::max(fmax, chat);
+    return PET_OS_OK;
+}
+
+// n_iter iterations on a state; objective pairs (fid, R) after iteration j+1
+// go to obj_dev[2 * (slot0 + j + 1)] when wanted.
+static int run_iterations(pet_os_state* st, float* f, const float* y, const float* r, int n_iter, bool want_obj,
+                          int every, int slot0, hipStream_t s, std::vector<char>& have) {
+    const int M = st->g->d.n_subsets;
+    bool sumf_current = false;
+    int rc = PET_OS_OK;
+    for (int j = 0; j < n_iter && !rc; ++j) {
+        for (int i = 0; i < M && !rc; ++i) {
+            rc = run_subiteration(st, f, y, r, s, sumf_current);
+            sumf_current = true;     // the update kernel leaves sum(f) of the new iterate
+        }
+        if (!rc && want_obj && ((j + 1) % every == 0 || j + 1 == n_iter)) {
+            rc = queue_objective(st->g, &st->p, &st->w, f, y, r, st->obj_dev + 2 * (size_t)(slot0 + j + 1), s);
+            have[slot0 + j + 1] = 1;
+        }
+    }
+    return rc;
+}
+
+static int ensure_obj(pet_os_state* st, int n) {
+    if (st->obj_cap >= n) return PET_OS_OK;
+    if (st->obj_dev) {
+        PETOS_HIP(hipDeviceSynchronize());
+        (void)hipFree(st->obj_dev);
+        st->obj_dev = nullptr;
+        st->obj_cap = 0;
+    }
+    if (hipMalloc(&st->obj_dev, 2 * sizeof(double) * (size_t)n) != hipSuccess)
+        return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc of objective slots failed");
+    st->obj_cap = n;
+    return PET_OS_OK;
+}
+
+static int read_objectives(pet_os_state* st, int n, const std::vector<char>& have, double* out, int first,
+                           hipStream_t s) {
+    std::vector<double> h(2 * (size_t)n);
+    PETOS_HIP(hipMemcpyAsync(h.data(), st->obj_dev, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    PETOS_HIP(hipStreamSynchronize(s));
+    for (int k = first; k < n; ++k)
+        out[k - first] = have[k] ? h[2 * k] + st->p.beta * h[2 * k + 1] : std::numeric_limits<double>::quiet_NaN();
+    return PET_OS_OK;
+}
+
+int pet_os_run(pet_os_state* st, float* f, const float* y, const float* r, int32_t n_iter, double* obj,
+               pet_os_stream stream) {
+    if (!st || !f || !y || !r) return fail(PET_OS_ERR_INVALID_ARG, "NULL argument");
+    if (n_iter < 0) return fail(PET_OS_ERR_INVALID_ARG, "n_iter must be >= 0");
+    if (obj && st->p.objective_every < 1) return fail(PET_OS_ERR_INVALID_ARG, "objective_every must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    if (obj && (rc = ensure_obj(st, n_iter + 1))) return rc;
+    std::vector<char> have((size_t)n_iter + 1, 0);
+    rc = run_iterations(st, f, y, r, n_iter, obj != nullptr, std::max(1, st->p.objective_every), 0, s, have);
+    if (rc) return rc;
+    if (obj) {
+        std::vector<double> tmp((size_t)n_iter + 1);
+        if ((rc = read_objectives(st, n_iter + 1, have, tmp.data(), 0, s))) return rc;
+        for (int j = 0; j < n_iter; ++j) obj[j] = tmp[j + 1];
+        if (n_iter > 0 && !std::isfinite(obj[n_iter - 1])) return fail(PET_OS_ERR_NUMERIC, "objective is not finite");
+    }
+    return PET_OS_OK;
+}
+
+int pet_os_reconstruct(const pet_os_geom* g, const pet_os_params* p, float* f, const float* y, const float* r,
+                       int32_t n_iter, double* obj, pet_os_stream stream) {
+    if (!g || !p || !f || !y || !r) return fail(PET_OS_ERR_INVALID_ARG, "NULL argument");
+    if (n_iter < 0) return fail(PET_OS_ERR_INVALID_ARG, "n_iter must be >= 0");
+    if (obj && p->objective_every < 1) return fail(PET_OS_ERR_INVALID_ARG, "objective_every must be >= 1");
+    pet_os_state* st = nullptr;
+    int rc = pet_os_state_create(g, p, &st);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<char> have((size_t)n_iter + 1, 0);
+    if (obj) {
+        rc = ensure_obj(st, n_iter + 1);
+        if (!rc) rc = queue_objective(g, p, &st->w, f, y, r, st->obj_dev, s);
+        have[0] = 1;
+    }
+    if (!rc) rc = run_iterations(st, f, y, r, n_iter, obj != nullptr, p->objective_every, 0, s, have);
+    if (!rc && obj) {
+        rc = read_objectives(st, n_iter + 1, have, obj, 0, s);
+        if (!rc && !std::isfinite(obj[n_iter])) rc = fail(PET_OS_ERR_NUMERIC, "objective is not finite");
+    }
+    // the state's scratch is released below: wait for the queued work first
+    if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = fail(PET_OS_ERR_DEVICE, "stream synchronize failed");
+    pet_os_state_destroy(st);
+    return rc;
+}
+
+int pet_os_state_profile(pet_os_state* st, int32_t kernel) {
+    if (!st) return fail(PET_OS_ERR_INVALID_ARG, "state is NULL");
+    if (kernel < -1 || kernel > 2) return fail(PET_OS_ERR_INVALID_ARG, "kernel must be -1..2");
+    st->prof_kernel = kernel;
+    return PET_OS_OK;
+}
+
+int pet_os_state_profile_read(pet_os_state* st, double* total_ms, int64_t* launches) {
+    if (!st) return fail(PET_OS_ERR_INVALID_ARG, "state is NULL");
+    double tot = 0.0;
+    for (size_t k = 0; k < st->prof_used; ++k) {
+        PETOS_HIP(hipEventSynchronize(st->prof_ev[k].second));
+        float ms = 0.0f;
+        PETOS_HIP(hipEventElapsedTime(&ms, st->prof_ev[k].first, st->prof_ev[k].second));
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (int64_t)st->prof_used;
+    st->prof_used = 0;
+    return PET_OS_OK;
+}
+
+int pet_os_nnz(const pet_os_geom* g, int32_t subset, int64_t* nnz) {
+    if (!g || !nnz) return fail(PET_OS_ERR_INVALID_ARG, "NULL argument");
+    GeomExtra* ex = extra_of(g);
+    if (!ex) return fail(PET_OS_ERR_INVALID_ARG, "invalid geometry");
+    if (subset < 0 || subset > g->d.n_subsets) return fail(PET_OS_ERR_INVALID_ARG, "subset out of range");
+    const int n_al = subset == 0 ? g->d.n_angles : ex->subset_count[subset - 1];
+    const int64_t n = (int64_t)n_al * g->n_planes * g->d.n_radial;
+    Work w;
+    int rc = work_alloc(g, false, &w);
+    if (rc) return rc;
+    float* cnt = nullptr;
+    if (hipMalloc(&cnt, (size_t)n * sizeof(float)) != hipSuccess) {
+        work_free(&w);
+        return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc failed");
+    }
+    Reduction red = w.red[RED_SUMY];
+    FPLaunch F{};
+    F.out = cnt; F.mode = FP_COUNT; F.n_al = n_al;
+    F.angles = subset == 0 ? ex->all_angles : ex->subset_lists + (size_t)(subset - 1) * g->max_sub_angles;
+    rc = launch_fp(g, F, nullptr);
+    if (!rc) rc = launch_sum(cnt, n, red, nullptr);
+    double tot = 0.0;
+    if (!rc && (hipMemcpy(&tot, red.total, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess))
+        rc = fail(PET_OS_ERR_DEVICE, "read-back failed");
+    (void)hipDeviceSynchronize();
+    (void)hipFree(cnt);
+    work_free(&w);
+    if (rc) return rc;
+    *nnz = (int64_t)std::llround(tot);
+    return PET_OS_OK;
+}
+
+// ---------------------------------------------------------------- checkpoints
+
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t have_frozen;
+    pet_os_geom_desc desc;
+    pet_os_params params;
+    int64_t k;
+    int32_t i;
+    int32_t pad;
+    double t_nest;
+    int64_t n_vox;
+};
+
+int pet_os_state_export(const pet_os_state* st, void* buf, size_t* len) {
+    if (!st || !len) return fail(PET_OS_ERR_INVALID_ARG, "NULL argument");
+    const size_t nv = (size_t)st->g->n_vox;
+    const size_t need = sizeof(CkptHeader) + (st->w.nu_frozen ? nv * sizeof(float) : 0);
+    if (!buf) { *len = need; return PET_OS_OK; }
+    if (*len < need) return fail(PET_OS_ERR_INVALID_ARG, "buffer too small");
+    CkptHeader h{};
+    std::memcpy(h.magic, "PETOSCK1", 8);
+    h.version = 1;
+    h.have_frozen = (uint32_t)st->have_frozen;
+    h.desc = st->g->d;
+    h.params = st->p;
+    h.k = st->k;
+    h.i = st->i;
+    h.t_nest = st->t_nest;
+    h.n_vox = (int64_t)nv;
+    std::memcpy(buf, &h, sizeof(h));
+    if (st->w.nu_frozen) {
+        PETOS_HIP(hipDeviceSynchronize());
+        PETOS_HIP(hipMemcpy((char*)buf + sizeof(h), st->w.nu_frozen, nv * sizeof(float), hipMemcpyDeviceToHost));
+    }
+    *len = need;
+    return PET_OS_OK;
+}
+
+int pet_os_state_import(pet_os_state* st, const void* buf, size_t len) {
+    if (!st || !buf) return fail(PET_OS_ERR_INVALID_ARG, "NULL argument");
+    if (len < sizeof(CkptHeader)) return fail(PET_OS_ERR_INVALID_ARG, "checkpoint too short");
+    CkptHeader h;
+    std::memcpy(&h, buf, sizeof(h));
+    if (std::memcmp(h.magic, "PETOSCK1", 8) != 0 || h.version != 1)
+        return fail(PET_OS_ERR_INVALID_ARG, "not a pet_os checkpoint");
+    if (std::memcmp(&h.desc, &st->g->d, sizeof(pet_os_geom_desc)) != 0 || h.params.mode != st->p.mode ||
+        h.n_vox != st->g->n_vox)
+        return fail(PET_OS_ERR_STATE_MISMATCH, "checkpoint geometry or mode differs from the state");
+    const size_t nv = (size_t)st->g->n_vox;
+    const bool has_nu = st->w.nu_frozen != nullptr;
+    if (len < sizeof(CkptHeader) + (has_nu ? nv * sizeof(float) : 0))
+        return fail(PET_OS_ERR_INVALID_ARG, "checkpoint too short");
+    if (h.i < 1 || h.i > st->g->d.n_subsets || h.k < 0) return fail(PET_OS_ERR_INVALID_ARG, "bad position");
+    if (has_nu) {
+        PETOS_HIP(hipDeviceSynchronize());
+        PETOS_HIP(hipMemcpy(st->w.nu_frozen, (const char*)buf + sizeof(h), nv * sizeof(float),
+                            hipMemcpyHostToDevice));
+    }
+    st->p = h.params;
+    st->k = h.k;
+    st->i = h.i;
+    st->t_nest = h.t_nest;
+    st->have_frozen = (int)h.have_frozen;
+    return PET_OS_OK;
+}
+
+}  // extern "C"

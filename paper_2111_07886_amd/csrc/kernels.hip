@@ -1,0 +1,764 @@
+// kernels.hip -- gfx950 kernels of one SDP-BSREM subiteration.
+//
+//   k_fp      ray-driven forward projection of a subset, fused with the
+//             Poisson ratio w = 1 - y/(q + r) (or plain q, or the FP64
+//             log-likelihood partials of eq:FidelityTerm)
+//   k_bp      voxel-driven gather back-projection with the subset's sinogram
+//             footprint staged in LDS (no atomics), fused with the RDP gradient
+//             (eqn:gradRD), the smoothness measure mu (Sec. III-B) and
+//             G = A_i^T w + (beta/M) grad R
+//   k_update  nu of eq:nuki, S of eq:preconditioner, the relaxed step and
+//             P_t of eq:OperatorPt, plus the FP64 sum of the new iterate
+//   k_rdp     FP64 partials of R(f) (eq:RDP) for the objective
+//
+// FP64 sums are deterministic: fixed-order block trees, then the last block
+// adds the per-block partials in index order (see Reduction).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace petos {
+
+constexpr int NT = 256;   // threads per block everywhere
+
+// ------------------------------------------------------------------ reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum of v over the block in a fixed order; valid in thread 0.
+__device__ double block_sum(double v, double* sh /* >= NT/64 */) {
+    v = wave_sum(v);
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+// Writes this block's partial; the last block to arrive sums all partials in
+// index order into *R.total and re-arms the ticket.  Every thread must call.
+__device__ void reduce_finish(double v, Reduction R, double* sh) {
+    __shared__ unsigned s_last;
+    double bs = block_sum(v, sh);
+    int nblk = gridDim.x;
+    if (threadIdx.x == 0) {
+        R.part[blockIdx.x] = bs;
+        __threadfence();
+        unsigned t = atomicAdd(R.ticket, 1u);
+        s_last = (t == (unsigned)(nblk - 1)) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (s_last) {
+        __threadfence();
+        double acc = 0.0;
+        const volatile double* part = R.part;
+        for (int i = threadIdx.x; i < nblk; i += blockDim.x) acc += part[i];
+        double tot = block_sum(acc, sh);
+        if (threadIdx.x == 0) {
+            *R.total = tot;
+            *R.ticket = 0u;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ forward projection
+
+struct FPArgs {
+    const float* f;
+    const float* y;
+    const float* r;
+    float* out;
+    const int* angles;
+    int n_al;
+    int mode;
+    Reduction red;
+};
+
+// One ray per (thread-row of the block); SEG threads split its major cells.
+template <int DIM, int SEG>
+__global__ __launch_bounds__(NT) void k_fp(GeoK g, FPArgs A) {
+    constexpr int RPB = NT / SEG;
+    __shared__ float s_part[SEG][RPB];
+    __shared__ double s_red[NT / 64];
+    const int lr = threadIdx.x % RPB;
+    const int seg = threadIdx.x / RPB;
+    const int P = g.n_planes, Nr = g.n_radial;
+    const long long nrays = (long long)A.n_al * P * Nr;
+    const long long ray = (long long)blockIdx.x * RPB + lr;
+    const bool valid = ray < nrays;
+
+    float acc = 0.0f;
+    int b = 0, plane = 0, al = 0, a = 0;
+    if (valid) {
+        b = (int)(ray % Nr);
+        long long t = ray / Nr;
+        plane = (int)(t % P);
+        al = (int)(t / P);
+        a = A.angles[al];
+        const AngleK& AK = g.ang[a];
+        TxRay tx = tx_ray(g, AK, b);
+        int n_major = tx.row_major ? g.ny : g.nx;
+        int n_minor = tx.row_major ? g.nx : g.ny;
+        int m0, m1;
+        major_range(tx, n_major, n_minor, m0, m1);
+        int cnt = m1 - m0 + 1;
+        int per = (cnt + SEG - 1) / SEG;
+        int s0 = m0 + seg * per;
+        int s1 = min(m1, s0 + per - 1);
+        const int sx = tx.row_major ? 1 : g.nx;       // stride along the minor cell index
+        const int sm = tx.row_major ? g.nx : 1;       // stride along the major index
+        int qstep = (tx.Q > 0.0) ? 1 : -1;
+        if (DIM == 2) {
+            for (int m = s0; m <= s1; ++m) {
+                double gm = __fma_rn(tx.Q, (double)m, tx.P);
+                int c0 = (int)floor(gm);
+                #pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    if (k == 1 && tx.Q == 0.0) break;
+                    int c = c0 + k * qstep;
+                    if (c < 0 || c >= n_minor) continue;
+                    double lo, hi;
+                    cell_interval(gm, tx.Q, tx.invQ, c, lo, hi);
+                    if (hi > lo) {
+                        if (A.mode == FP_COUNT) { acc += 1.0f; continue; }
+                        float aij = (float)(tx.L * (hi - lo));
+                        acc = fmaf(aij, A.f[(long long)m * sm + (long long)c * sx], acc);
+                    }
+                }
+            }
+        } else {
+            int2 pl = g.planes[plane];
+            ZBin zb = z_bin(g, AK, b);
+            ZRay z = z_ray(g, zb, b, pl.x, pl.y);
+            double Lk = tx.L * z.kap;
+            int zstep = (z.Qz > 0.0) ? 1 : -1;
+            const long long slab = (long long)g.nx * g.ny;
+            for (int m = s0; m <= s1; ++m) {
+                double gm = __fma_rn(tx.Q, (double)m, tx.P);
+                double zm = __fma_rn(z.Qz, (double)m, z.Pz);
+                int c0 = (int)floor(gm);
+                int k0 = (int)floor(zm);
+                #pragma unroll
+                for (int kx = 0; kx < 2; ++kx) {
+                    if (kx == 1 && tx.Q == 0.0) break;
+                    int c = c0 + kx * qstep;
+                    if (c < 0 || c >= n_minor) continue;
+                    double lx, hx;
+                    cell_interval(gm, tx.Q, tx.invQ, c, lx, hx);
+                    if (!(hx > lx)) continue;
+                    #pragma unroll
+                    for (int kz = 0; kz < 2; ++kz) {
+                        if (kz == 1 && z.Qz == 0.0) break;
+                        int kk = k0 + kz * zstep;
+                        if (kk < 0 || kk >= g.nz) continue;
+                        double lz, hz;
+                        cell_interval(zm, z.Qz, z.invQz, kk, lz, hz);
+                        double len = fmin(hx, hz) - fmax(lx, lz);
+                        if (len > 0.0) {
+                            if (A.mode == FP_COUNT) { acc += 1.0f; continue; }
+                            float aij = (float)(Lk * len);
+                            acc = fmaf(aij, A.f[kk * slab + (long long)m * sm + (long long)c * sx], acc);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (SEG > 1) {
+        s_part[seg][lr] = acc;
+        __syncthreads();
+        if (seg == 0) {
+            float t = 0.0f;
+            #pragma unroll
+            for (int k = 0; k < SEG; ++k) t += s_part[k][lr];
+            acc = t;
+        }
+    }
+    double term = 0.0;
+    if (seg == 0 && valid) {
+        long long nat = ((long long)plane * g.n_angles + a) * Nr + b;
+        if (A.mode == FP_RATIO) {
+            float q = acc;
+            A.out[ray] = 1.0f - A.y[nat] / (q + A.r[nat]);
+        } else if (A.mode == FP_COUNT) {
+            A.out[ray] = acc;
+        } else if (A.mode == FP_PLAIN) {
+            A.out[nat] = acc;
+        } else {
+            double q = (double)acc;
+            term = q - (double)A.y[nat] * log(q + (double)A.r[nat]);
+        }
+    }
+    if (A.mode == FP_OBJECTIVE) reduce_finish(term, A.red, s_red);
+}
+
+// ------------------------------------------------------------------ back projection
+
+struct BPArgs {
+    const float* w;          // null => unit weights (sensitivity)
+    long long w_sp, w_sa;    // w index = plane * w_sp + angle_index * w_sa + b
+    int w_natural;           // angle_index = natural angle (1) or position in the list (0)
+    const int* angles;
+    int n_al;
+    float* out;
+    const float* f;          // non-null => fused stencil, out = G
+    float* mu;
+    int want_mu;
+    float beta_over_M, gamma_R, eps;
+    const double* total_f;
+    Reduction red_mu;
+    int nb_max;              // staged bins per row
+    int rows_max;            // staged rows (planes) per angle
+    int chunk;               // angles staged together
+};
+
+template <int DIM>
+struct Tile;
+template <>
+struct Tile<2> { static constexpr int X = 16, Y = 16, Z = 1; };
+template <>
+struct Tile<3> { static constexpr int X = 8, Y = 8, Z = 4; };
+
+constexpr int MAXD2 = 63;    // ring differences -31..31
+constexpr int MAXCH = 16;    // angles per staging chunk
+constexpr int MAXROWS = 2048;
+
+// RDP gradient (eqn:gradRD; in-image 8/26 neighbours, unit weights) and the
+// Matlab-style gradient magnitude of Sec. III-B at one voxel of the halo tile.
+template <int DIM>
+__device__ __forceinline__ void stencil_at(const float* sf, int HX, int HY, int hx, int hy, int hz, int ix,
+                                           int iy, int iz, const GeoK& g, float gR, float eps, float& gradR,
+                                           float& gmag) {
+    auto at = [&](int dx, int dy, int dz) -> float {
+        return sf[((hz + dz) * HY + (hy + dy)) * HX + (hx + dx)];
+    };
+    const float fj = at(0, 0, 0);
+    float acc = 0.0f;
+    const int zr = (DIM == 3) ? 1 : 0;
+    for (int dz = -zr; dz <= zr; ++dz) {
+        const int z = iz + dz;
+        if (z < 0 || z >= g.nz) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int y = iy + dy;
+            if (y < 0 || y >= g.ny) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int x = ix + dx;
+                if ((dx | dy | dz) == 0 || x < 0 || x >= g.nx) continue;
+                const float fk = at(dx, dy, dz);
+                const float d = fj - fk;
+                const float ad = fabsf(d);
+                const float den = fj + fk + gR * ad + eps;
+                const float num = d * (gR * ad + fj + 3.0f * fk + 2.0f * eps);
+                acc += num / (den * den);
+            }
+        }
+    }
+    gradR = 2.0f * acc;
+    auto der = [&](int i, int n, int dx, int dy, int dz) -> float {
+        if (n < 2) return 0.0f;
+        if (i == 0) return at(dx, dy, dz) - fj;
+        if (i == n - 1) return fj - at(-dx, -dy, -dz);
+        return 0.5f * (at(dx, dy, dz) - at(-dx, -dy, -dz));
+    };
+    const float gx = der(ix, g.nx, 1, 0, 0);
+    const float gy = der(iy, g.ny, 0, 1, 0);
+    const float gz = (DIM == 3) ? der(iz, g.nz, 0, 0, 1) : 0.0f;
+    gmag = sqrtf(gx * gx + gy * gy + gz * gz);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(NT) void k_bp(GeoK g, BPArgs A) {
+    using T = Tile<DIM>;
+    constexpr int HX = T::X + 2, HY = T::Y + 2, HZ = (DIM == 3) ? T::Z + 2 : 1;
+    constexpr int ND = (DIM == 3) ? MAXD2 : 1;
+    extern __shared__ float s_w[];
+    __shared__ float s_f[HX * HY * HZ];
+    __shared__ int s_blo[MAXCH], s_nb[MAXCH], s_row0[MAXCH];
+    __shared__ double s_tau[MAXCH][2];
+    __shared__ short s_r1lo[MAXCH][ND], s_nrow[MAXCH][ND], s_rowb[MAXCH][ND];
+    constexpr int NROWS = (DIM == 3) ? MAXROWS : MAXCH;
+    __shared__ long long s_src[NROWS];
+    __shared__ int s_ncol[NROWS];
+    __shared__ int s_rows_total;
+    __shared__ double s_red[NT / 64];
+
+    const int tiles_x = (g.nx + T::X - 1) / T::X;
+    const int tiles_y = (g.ny + T::Y - 1) / T::Y;
+    int t = blockIdx.x;
+    const int tx0 = (t % tiles_x) * T::X;
+    t /= tiles_x;
+    const int ty0 = (t % tiles_y) * T::Y;
+    const int tz0 = (t / tiles_y) * T::Z;
+    const int lx = threadIdx.x % T::X;
+    const int ly = (threadIdx.x / T::X) % T::Y;
+    const int lz = threadIdx.x / (T::X * T::Y);
+    const int ix = tx0 + lx, iy = ty0 + ly, iz = tz0 + lz;
+    const int nzv = (DIM == 3) ? g.nz : 1;
+    const bool inside = ix < g.nx && iy < g.ny && iz < nzv;
+    const int P = g.n_planes, Nr = g.n_radial, D = g.max_rd, R = g.n_rings;
+    const double h0 = 0.5 * (double)(Nr - 1);
+    const int nb_max = A.nb_max;
+
+    // tile box in mm
+    const double X0 = ((double)tx0 - 0.5 * g.nx) * g.vx, X1 = X0 + T::X * g.vx;
+    const double Y0 = ((double)ty0 - 0.5 * g.ny) * g.vy, Y1 = Y0 + T::Y * g.vy;
+
+    float acc = 0.0f;
+    for (int c0 = 0; c0 < A.n_al; c0 += A.chunk) {
+        const int nch = min(A.chunk, A.n_al - c0);
+        if (A.w != nullptr) {
+            // (1) per-angle bin footprint of the tile (+1 bin margin) and tau range
+            if (threadIdx.x < nch) {
+                const int j = threadIdx.x;
+                const AngleK& AK = g.ang[A.angles[c0 + j]];
+                double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+                for (int k = 0; k < 4; ++k) {
+                    const double x = (k & 1) ? X1 : X0, y = (k & 2) ? Y1 : Y0;
+                    const double u = x * AK.c + y * AK.s;     // radial position
+                    const double v = -x * AK.s + y * AK.c;    // position along the ray
+                    umin = fmin(umin, u); umax = fmax(umax, u);
+                    vmin = fmin(vmin, v); vmax = fmax(vmax, v);
+                }
+                int blo = (int)floor(umin / g.ds + h0) - 1;
+                int bhi = (int)ceil(umax / g.ds + h0) + 1;
+                blo = max(blo, 0);
+                bhi = min(bhi, Nr - 1);
+                int nb = bhi - blo + 1;
+                if (nb > nb_max) nb = nb_max;
+                if (nb < 0) nb = 0;
+                s_blo[j] = blo;
+                s_nb[j] = nb;
+                if (DIM == 3 && nb > 0) {
+                    double hmin = fmin(g.bin[blo].h, g.bin[blo + nb - 1].h);
+                    double hmax = (blo <= h0 && blo + nb - 1 >= h0) ? g.det_radius
+                                                                      : fmax(g.bin[blo].h, g.bin[blo + nb - 1].h);
+                    s_tau[j][0] = 0.5 + vmin / (2.0 * (vmin < 0.0 ? hmin : hmax)) - 1e-9;
+                    s_tau[j][1] = 0.5 + vmax / (2.0 * (vmax > 0.0 ? hmin : hmax)) + 1e-9;
+                }
+            }
+            __syncthreads();
+            // (2) rows (planes) per ring difference
+            if (DIM == 3) {
+                for (int e = threadIdx.x; e < nch * (2 * D + 1); e += NT) {
+                    const int j = e / (2 * D + 1), di = e % (2 * D + 1), d = di - D;
+                    const double tlo = s_tau[j][0], thi = s_tau[j][1];
+                    const double a0 = d * tlo, a1 = d * thi;
+                    int lo = (int)floor((double)tz0 - 0.5 - fmax(a0, a1)) - 1;
+                    int hi = (int)ceil((double)(tz0 + T::Z) - 0.5 - fmin(a0, a1)) + 1;
+                    lo = max(lo, max(0, -d));
+                    hi = min(hi, min(R - 1, R - 1 - d));
+                    s_r1lo[j][di] = (short)lo;
+                    s_nrow[j][di] = (short)max(0, hi - lo + 1);
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    int tot = 0;
+                    for (int j = 0; j < nch; ++j) {
+                        s_row0[j] = tot;
+                        int rb = 0;
+                        for (int di = 0; di <= 2 * D; ++di) {
+                            int n = s_nrow[j][di];
+                            if (rb + n > A.rows_max) n = max(0, A.rows_max - rb);
+                            if (s_nb[j] == 0) n = 0;
+                            s_nrow[j][di] = (short)n;
+                            s_rowb[j][di] = (short)rb;
+                            rb += n;
+                        }
+                        tot += rb;
+                    }
+                    s_rows_total = tot;
+                }
+                __syncthreads();
+                for (int e = threadIdx.x; e < nch * (2 * D + 1); e += NT) {
+                    const int j = e / (2 * D + 1), di = e % (2 * D + 1), d = di - D;
+                    const int al = c0 + j;
+                    const int aidx = A.w_natural ? A.angles[al] : al;
+                    const int pb = g.plane_base[di] - max(0, -d);
+                    for (int k = 0; k < s_nrow[j][di]; ++k) {
+                        const int row = s_row0[j] + s_rowb[j][di] + k;
+                        const int plane = pb + s_r1lo[j][di] + k;
+                        s_src[row] = (long long)plane * A.w_sp + (long long)aidx * A.w_sa + s_blo[j];
+                        s_ncol[row] = s_nb[j];
+                    }
+                }
+            } else {
+                if (threadIdx.x < nch) {
+                    const int j = threadIdx.x, al = c0 + j;
+                    const int aidx = A.w_natural ? A.angles[al] : al;
+                    s_row0[j] = j;
+                    s_r1lo[j][0] = 0;
+                    s_nrow[j][0] = (short)(s_nb[j] > 0 ? 1 : 0);
+                    s_rowb[j][0] = 0;
+                    s_src[j] = (long long)aidx * A.w_sa + s_blo[j];
+                    s_ncol[j] = s_nb[j];
+                }
+                if (threadIdx.x == 0) s_rows_total = nch;
+            }
+            __syncthreads();
+            // (3) stage the footprint rows into LDS
+            const int nel = s_rows_total * nb_max;
+            for (int e = threadIdx.x; e < nel; e += NT) {
+                const int row = e / nb_max, col = e - row * nb_max;
+                if (col < s_ncol[row]) s_w[e] = A.w[s_src[row] + col];
+            }
+            __syncthreads();
+        }
+
+        // (4) gather: every bin (and plane) whose LOR crosses this voxel
+        if (inside) {
+            for (int j = 0; j < nch; ++j) {
+                const int al = c0 + j;
+                const int a = A.angles[al];
+                const AngleK& AK = g.ang[a];
+                const int m = AK.row_major ? iy : ix;
+                const int mc = AK.row_major ? ix : iy;
+                // g(m) in [mc - max(Q,0), mc + 1 - min(Q,0)] selects the bins
+                const double base = __fma_rn(AK.Q, (double)m, AK.wC);
+                const double glo = (double)mc - fmax(AK.Q, 0.0) - 1e-7;
+                const double ghi = (double)mc + 1.0 - fmin(AK.Q, 0.0) + 1e-7;
+                const double bA = (glo - base) / AK.wslope, bB = (ghi - base) / AK.wslope;
+                const int b0 = (int)fmax(floor(fmin(bA, bB)), 0.0);
+                const int b1 = (int)fmin(ceil(fmax(bA, bB)), (double)(Nr - 1));
+                const int aidx = A.w_natural ? a : al;
+                for (int b = b0; b <= b1; ++b) {
+                    const TxRay tx = tx_ray(g, AK, b);
+                    const double gm = __fma_rn(tx.Q, (double)m, tx.P);
+                    double ax, bx;
+                    cell_interval(gm, tx.Q, tx.invQ, mc, ax, bx);
+                    if (!(bx > ax)) continue;
+                    const int bcol = b - s_blo[j];
+                    const bool bin_staged = A.w != nullptr && bcol >= 0 && bcol < s_nb[j];
+                    if (DIM == 2) {
+                        float wv = 1.0f;
+                        if (A.w != nullptr)
+                            wv = bin_staged ? s_w[s_row0[j] * nb_max + bcol] : A.w[(long long)aidx * A.w_sa + b];
+                        const float aij = (float)(tx.L * (bx - ax));
+                        acc = fmaf(aij, wv, acc);
+                    } else {
+                        const ZBin zb = z_bin(g, AK, b);
+                        for (int d = -D; d <= D; ++d) {
+                            const double dd = (double)d;
+                            const double bza = 0.5 + dd * (zb.tau0 + zb.tauQ * ((double)m + ax));
+                            const double bzb = 0.5 + dd * (zb.tau0 + zb.tauQ * ((double)m + bx));
+                            int r1a = (int)ceil((double)iz - fmax(bza, bzb) - 1e-9);
+                            int r1b = (int)floor((double)iz + 1.0 - fmin(bza, bzb) + 1e-9);
+                            r1a = max(r1a, max(0, -d));
+                            r1b = min(r1b, min(R - 1, R - 1 - d));
+                            for (int r1 = r1a; r1 <= r1b; ++r1) {
+                                const ZRay z = z_ray(g, zb, b, r1, d);
+                                const double zm = __fma_rn(z.Qz, (double)m, z.Pz);
+                                double az, bzz;
+                                cell_interval(zm, z.Qz, z.invQz, iz, az, bzz);
+                                const double len = fmin(bx, bzz) - fmax(ax, az);
+                                if (!(len > 0.0)) continue;
+                                float wv = 1.0f;
+                                if (A.w != nullptr) {
+                                    const int di = d + D;
+                                    const int rr = r1 - s_r1lo[j][di];
+                                    if (bin_staged && rr >= 0 && rr < s_nrow[j][di]) {
+                                        wv = s_w[(s_row0[j] + s_rowb[j][di] + rr) * nb_max + bcol];
+                                    } else {
+                                        const int plane = g.plane_base[di] - max(0, -d) + r1;
+                                        wv = A.w[(long long)plane * A.w_sp + (long long)aidx * A.w_sa + b];
+                                    }
+                                }
+                                const double Lk = tx.L * z.kap;
+                                const float aij = (float)(Lk * len);
+                                acc = fmaf(aij, wv, acc);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    (void)P;
+
+    if (A.f == nullptr) {
+        if (inside) A.out[((long long)iz * g.ny + iy) * g.nx + ix] = acc;
+        return;
+    }
+
+    // (5) fused image-space part: grad R, mu, G = A_i^T w + (beta/M) grad R
+    for (int e = threadIdx.x; e < HX * HY * HZ; e += NT) {
+        const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
+        const int gx = tx0 - 1 + hx, gy = ty0 - 1 + hy, gz = (DIM == 3) ? tz0 - 1 + hz : 0;
+        float v = 0.0f;
+        if (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < nzv)
+            v = A.f[((long long)gz * g.ny + gy) * g.nx + gx];
+        s_f[e] = v;
+    }
+    __syncthreads();
+    double mu_part = 0.0;
+    if (inside) {
+        float gradR, gmag;
+        stencil_at<DIM>(s_f, HX, HY, lx + 1, ly + 1, (DIM == 3) ? lz + 1 : 0, ix, iy, iz, g, A.gamma_R, A.eps,
+                        gradR, gmag);
+        const long long j = ((long long)iz * g.ny + iy) * g.nx + ix;
+        A.out[j] = fmaf(A.beta_over_M, gradR, acc);
+        if (A.want_mu) {
+            const float meanf = (float)(*A.total_f / (double)g.nvox);
+            const float mu = fmaxf(0.01f, gmag / meanf);
+            A.mu[j] = mu;
+            mu_part = (double)mu;
+        }
+    }
+    if (A.want_mu) reduce_finish(mu_part, A.red_mu, s_red);
+}
+
+// ------------------------------------------------------------------ update
+
+struct UpdArgs {
+    float* f;
+    const float* G;
+    const float* mu;
+    const float* pnorm;
+    float* nu_frozen;
+    int nu_mode;
+    float step, nu1, nu2, U, t_clip;
+    const double* total_mu;
+    Reduction red_f;
+    long long n;
+};
+
+__global__ __launch_bounds__(NT) void k_update(UpdArgs A) {
+    __shared__ double s_red[NT / 64];
+    const long long j = (long long)blockIdx.x * NT + threadIdx.x;
+    double part = 0.0;
+    if (j < A.n) {
+        float nu = 1.0f;
+        if (A.nu_mode == NU_COMPUTE || A.nu_mode == NU_COMPUTE_FREEZE) {
+            const float meanmu = (float)(*A.total_mu / (double)A.n);
+            nu = fminf(A.nu2, fmaxf(A.nu1, meanmu / A.mu[j]));
+            if (A.nu_mode == NU_COMPUTE_FREEZE) A.nu_frozen[j] = nu;
+        } else if (A.nu_mode == NU_FROZEN) {
+            nu = A.nu_frozen[j];
+        }
+        const float fj = A.f[j];
+        const float S = (fj < 0.5f * A.U) ? fj / A.pnorm[j] : (A.U - fj) / A.pnorm[j];
+        const float ft = fj - A.step * nu * S * A.G[j];
+        const float fn = (ft <= 0.0f) ? A.t_clip : ((ft >= A.U) ? A.U - A.t_clip : ft);
+        A.f[j] = fn;
+        part = (double)fn;
+    }
+    reduce_finish(part, A.red_f, s_red);
+}
+
+__global__ __launch_bounds__(NT) void k_sum(const float* x, long long n, Reduction R) {
+    __shared__ double s_red[NT / 64];
+    const long long j = (long long)blockIdx.x * NT + threadIdx.x;
+    reduce_finish(j < n ? (double)x[j] : 0.0, R, s_red);
+}
+
+__global__ __launch_bounds__(NT) void k_fill(float* x, long long n, float v) {
+    const long long j = (long long)blockIdx.x * NT + threadIdx.x;
+    if (j < n) x[j] = v;
+}
+
+// R(f) of eq:RDP, FP64 per voxel and per block
+template <int DIM>
+__global__ __launch_bounds__(NT) void k_rdp(GeoK g, const float* f, float gR, float eps, Reduction R) {
+    __shared__ double s_red[NT / 64];
+    const long long j = (long long)blockIdx.x * NT + threadIdx.x;
+    double v = 0.0;
+    if (j < g.nvox) {
+        const int ix = (int)(j % g.nx), iy = (int)((j / g.nx) % g.ny), iz = (int)(j / ((long long)g.nx * g.ny));
+        const double fj = f[j];
+        const int zr = (DIM == 3) ? 1 : 0;
+        for (int dz = -zr; dz <= zr; ++dz) {
+            const int z = iz + dz;
+            if (z < 0 || z >= (DIM == 3 ? g.nz : 1)) continue;
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int y = iy + dy;
+                if (y < 0 || y >= g.ny) continue;
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int x = ix + dx;
+                    if ((dx | dy | dz) == 0 || x < 0 || x >= g.nx) continue;
+                    const double fk = f[((long long)z * g.ny + y) * g.nx + x];
+                    const double d = fj - fk;
+                    v += d * d / (fj + fk + (double)gR * fabs(d) + (double)eps);
+                }
+            }
+        }
+    }
+    reduce_finish(v, R, s_red);
+}
+
+// ------------------------------------------------------------------ launchers
+
+static int fp_seg(long long nrays) {
+    if (nrays < (1 << 16)) return 16;
+    if (nrays < (1 << 20)) return 4;
+    return 1;
+}
+
+int fp_grid(const pet_os_geom* G, int n_al) {
+    long long nrays = (long long)n_al * G->n_planes * G->d.n_radial;
+    int rpb = NT / fp_seg(nrays);
+    return (int)((nrays + rpb - 1) / rpb);
+}
+
+int bp_grid(const pet_os_geom* G) {
+    if (G->d.dim == 2) {
+        return ((G->d.nx + 15) / 16) * ((G->d.ny + 15) / 16);
+    }
+    return ((G->d.nx + 7) / 8) * ((G->d.ny + 7) / 8) * ((G->d.nz + 3) / 4);
+}
+
+int elem_grid(int64_t n) { return (int)((n + NT - 1) / NT); }
+
+template <int DIM, int SEG>
+static void fp_launch_t(const GeoK& k, const FPArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_fp<DIM, SEG>), dim3(grid), dim3(NT), 0, s, k, a);
+}
+
+int launch_fp(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
+    FPArgs a;
+    a.f = L.f;
+    a.y = L.y;
+    a.r = L.r;
+    a.out = L.out;
+    a.angles = L.angles;
+    a.n_al = L.n_al;
+    a.mode = L.mode;
+    a.red = L.red;
+    long long nrays = (long long)L.n_al * G->n_planes * G->d.n_radial;
+    if (nrays == 0) return PET_OS_OK;
+    int seg = fp_seg(nrays);
+    int grid = fp_grid(G, L.n_al);
+    if (L.mode == FP_OBJECTIVE && grid > L.red.cap) return fail(PET_OS_ERR_DEVICE, "objective partials too small");
+    const bool d3 = G->d.dim == 3;
+    if (seg == 16) { if (d3) fp_launch_t<3, 16>(G->k, a, grid, s); else fp_launch_t<2, 16>(G->k, a, grid, s); }
+    else if (seg == 4) { if (d3) fp_launch_t<3, 4>(G->k, a, grid, s); else fp_launch_t<2, 4>(G->k, a, grid, s); }
+    else { if (d3) fp_launch_t<3, 1>(G->k, a, grid, s); else fp_launch_t<2, 1>(G->k, a, grid, s); }
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
+}
+
+// LDS footprint bounds of a back-projection tile (host side, conservative)
+static void bp_stage_shape(const pet_os_geom* G, int& nb_max, int& rows_max, int& chunk, size_t& lds) {
+    const auto& d = G->d;
+    const int TX = d.dim == 2 ? 16 : 8, TY = d.dim == 2 ? 16 : 8, TZ = d.dim == 2 ? 1 : 4;
+    nb_max = (int)std::ceil((TX * d.vx + TY * d.vy) / d.ds) + 4;
+    if (nb_max > d.n_radial) nb_max = d.n_radial;
+    if (d.dim == 2) {
+        rows_max = 1;
+    } else {
+        double rmin = 0.5 * std::sqrt(d.nx * d.nx * d.vx * d.vx + d.ny * d.ny * d.vy * d.vy);
+        double smax = 0.5 * (d.n_radial - 1) * d.ds;
+        double hmin = std::sqrt(std::max(1.0, d.det_radius * d.det_radius - smax * smax));
+        double dtau = std::sqrt(TX * TX * d.vx * d.vx + TY * TY * d.vy * d.vy) / (2.0 * hmin) + 1e-6;
+        (void)rmin;
+        int rows = 0;
+        for (int dd = -d.max_ring_diff; dd <= d.max_ring_diff; ++dd)
+            rows += std::min(d.n_rings, TZ + 3 + (int)std::ceil(std::abs(dd) * dtau));
+        rows_max = rows;
+    }
+    const size_t budget_floats = d.dim == 2 ? 4096 : 12288;
+    if ((size_t)nb_max * rows_max > budget_floats) rows_max = (int)(budget_floats / nb_max);
+    size_t slot = (size_t)nb_max * rows_max;
+    chunk = (int)std::max<size_t>(1, budget_floats / slot);
+    if (chunk > MAXCH) chunk = MAXCH;
+    if ((size_t)chunk * rows_max > MAXROWS) chunk = std::max(1, MAXROWS / rows_max);
+    if ((size_t)rows_max > MAXROWS) rows_max = MAXROWS;
+    lds = (size_t)chunk * slot * sizeof(float);
+}
+
+int launch_bp(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
+    if (G->d.dim == 3 && 2 * G->d.max_ring_diff + 1 > MAXD2)
+        return fail(PET_OS_ERR_INVALID_ARG, "max_ring_diff too large for the back-projector");
+    BPArgs a{};
+    a.w = L.w;
+    a.w_natural = L.w_natural;
+    if (L.w_natural) {
+        a.w_sa = G->d.n_radial;
+        a.w_sp = (long long)G->d.n_angles * G->d.n_radial;
+    } else {
+        a.w_sp = G->d.n_radial;
+        a.w_sa = (long long)G->n_planes * G->d.n_radial;
+    }
+    a.angles = L.angles;
+    a.n_al = L.n_al;
+    a.out = L.out;
+    a.f = L.f;
+    a.mu = L.mu;
+    a.want_mu = L.want_mu;
+    a.beta_over_M = L.beta_over_M;
+    a.gamma_R = L.gamma_R;
+    a.eps = L.eps;
+    a.total_f = L.total_f;
+    a.red_mu = L.red_mu;
+    size_t lds;
+    bp_stage_shape(G, a.nb_max, a.rows_max, a.chunk, lds);
+    if (L.w == nullptr) lds = 0;
+    int grid = bp_grid(G);
+    if (L.want_mu && grid > L.red_mu.cap) return fail(PET_OS_ERR_DEVICE, "mu partials too small");
+    if (G->d.dim == 3)
+        hipLaunchKernelGGL((k_bp<3>), dim3(grid), dim3(NT), lds, s, G->k, a);
+    else
+        hipLaunchKernelGGL((k_bp<2>), dim3(grid), dim3(NT), lds, s, G->k, a);
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
+}
+
+int launch_update(const pet_os_geom* G, const UpdLaunch& L, hipStream_t s) {
+    UpdArgs a;
+    a.f = L.f;
+    a.G = L.G;
+    a.mu = L.mu;
+    a.pnorm = L.pnorm;
+    a.nu_frozen = L.nu_frozen;
+    a.nu_mode = L.nu_mode;
+    a.step = L.step;
+    a.nu1 = L.nu1;
+    a.nu2 = L.nu2;
+    a.U = L.U;
+    a.t_clip = L.t_clip;
+    a.total_mu = L.total_mu;
+    a.red_f = L.red_f;
+    a.n = G->n_vox;
+    int grid = elem_grid(G->n_vox);
+    if (grid > L.red_f.cap) return fail(PET_OS_ERR_DEVICE, "sum partials too small");
+    hipLaunchKernelGGL(k_update, dim3(grid), dim3(NT), 0, s, a);
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
+}
+
+int launch_sum(const float* x, int64_t n, Reduction red, hipStream_t s) {
+    int grid = elem_grid(n);
+    if (grid > red.cap) return fail(PET_OS_ERR_DEVICE, "sum partials too small");
+    hipLaunchKernelGGL(k_sum, dim3(grid), dim3(NT), 0, s, x, (long long)n, red);
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
+}
+
+int launch_fill(float* x, int64_t n, float v, hipStream_t s) {
+    if (n == 0) return PET_OS_OK;
+    hipLaunchKernelGGL(k_fill, dim3(elem_grid(n)), dim3(NT), 0, s, x, (long long)n, v);
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
+}
+
+int launch_rdp_value(const pet_os_geom* G, const float* f, float gamma_R, float eps, Reduction red,
+                     hipStream_t s) {
+    int grid = elem_grid(G->n_vox);
+    if (grid > red.cap) return fail(PET_OS_ERR_DEVICE, "rdp partials too small");
+    if (G->d.dim == 3)
+        hipLaunchKernelGGL((k_rdp<3>), dim3(grid), dim3(NT), 0, s, G->k, f, gamma_R, eps, red);
+    else
+        hipLaunchKernelGGL((k_rdp<2>), dim3(grid), dim3(NT), 0, s, G->k, f, gamma_R, eps, red);
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
+}
+
+}  // namespace petos

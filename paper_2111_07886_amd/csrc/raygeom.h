@@ -1,0 +1,154 @@
+// raygeom.h -- per-ray geometry shared by the forward (ray-driven) and
+// back (voxel-driven) projectors, so that both evaluate the same chord
+// length a_ij with the same floating-point operations.
+//
+// System model (Sec. IV-A): a_ij = length of LOR i inside voxel j.  A ray is
+// walked along its "major" transaxial axis (rows when |cos| vx >= |sin| vy,
+// else columns).  Over one major cell m the ray's coordinate on the other
+// transaxial axis moves linearly, in grid units, from g(m) = P + Q m to
+// g(m) + Q (|Q| <= 1), and its axial grid coordinate from z(m) = Pz + Qz m to
+// z(m) + Qz.  With psi in [0,1] the position along that piece, the voxel
+// (minor cell c, slice k) receives L * |psi-interval(c) /\ psi-interval(k)|,
+// where L is the 3D length of the piece.  Axis-parallel rays (Q == 0) lie in
+// cell floor(P): a ray on a cell's lower edge belongs to that cell.
+//
+// All positions are FP64 so that the cell decisions of the two projectors
+// agree with each other exactly and with an FP64 reference to rounding.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace petos {
+
+// Per-angle constants, computed on the host in FP64.
+struct AngleK {
+    double c, s;        // cos, sin of theta_a (snapped at 0 and pi/2)
+    double Q, invQ;     // minor-coordinate step per major cell (invQ = 0 if Q == 0)
+    double icv, K;      // P(b) = s_b * icv + K   (unused when Q == 0)
+    double L;           // transaxial length of one major step
+    double Au, Bu;      // u at major boundary 0: u0(b) = s_b * Au + Bu
+    double du;          // du per major step
+    double wslope, wC;  // P(b) ~= wslope * b + wC (candidate windows only)
+    int row_major;      // 1: major axis = y (rows), minor = x
+    int pad;
+};
+
+// Per-bin constants.
+struct BinK {
+    double sb;          // radial position of the bin
+    double inv2h;       // 1 / (2 h), h = sqrt(Rd^2 - s_b^2)   (3D)
+    double h;
+    double axis_pos_x;  // exact grid position of an axis-parallel ray (x axis)
+    double axis_pos_y;  // same on the y axis
+};
+
+// Geometry handed to kernels by value.
+struct GeoK {
+    int dim, nx, ny, nz;
+    int n_angles, n_radial, n_subsets, n_planes;
+    int n_rings, max_rd;
+    int nvox;
+    int pad;
+    double vx, vy, vz, ds, det_radius;
+    const AngleK* ang;      // [n_angles]
+    const BinK* bin;        // [n_radial]
+    const int2* planes;     // [n_planes] (r1, d)
+    const double* kappa;    // [n_radial][2D+1] 3D length per transaxial length
+    const int* plane_base;  // [2D+1] first plane of ring difference d (index d + D)
+    const double* inv_d;    // [2D+1] 1/d (0 for d = 0)
+};
+
+struct TxRay {
+    double P, Q, invQ, L;
+    int row_major;
+};
+
+struct ZRay {
+    double Pz, Qz, invQz, kap;   // kap = 3D length factor
+};
+
+__device__ __forceinline__ TxRay tx_ray(const GeoK& g, const AngleK& A, int b) {
+    TxRay t;
+    t.row_major = A.row_major;
+    t.Q = A.Q;
+    t.invQ = A.invQ;
+    t.L = A.L;
+    if (A.Q == 0.0) {
+        t.P = A.row_major ? g.bin[b].axis_pos_x : g.bin[b].axis_pos_y;
+    } else {
+        t.P = __fma_rn(g.bin[b].sb, A.icv, A.K);
+    }
+    return t;
+}
+
+// axial part of the LOR in bin b: the axial grid position of plane (r1, d)
+// at major boundary m is r1 + 1/2 + d (tau0 + tauQ m), tau = (u + h)/(2h) the
+// fraction of the way from ring r1 to ring r1 + d (rings at slice centres).
+struct ZBin {
+    double tau0, tauQ, inv_tauQ;
+};
+
+__device__ __forceinline__ ZBin z_bin(const GeoK& g, const AngleK& A, int b) {
+    const BinK& B = g.bin[b];
+    ZBin zb;
+    double u0 = __fma_rn(B.sb, A.Au, A.Bu);
+    zb.tau0 = (u0 + B.h) * B.inv2h;
+    zb.tauQ = A.du * B.inv2h;
+    zb.inv_tauQ = 1.0 / zb.tauQ;
+    return zb;
+}
+
+__device__ __forceinline__ ZRay z_ray(const GeoK& g, const ZBin& zb, int b, int r1, int d) {
+    ZRay z;
+    if (d == 0) {
+        z.Pz = (double)r1 + 0.5;
+        z.Qz = 0.0;
+        z.invQz = 0.0;
+        z.kap = 1.0;
+        return z;
+    }
+    double dd = (double)d;
+    z.Pz = __fma_rn(dd, zb.tau0, (double)r1 + 0.5);
+    z.Qz = dd * zb.tauQ;
+    z.invQz = g.inv_d[d + g.max_rd] * zb.inv_tauQ;
+    z.kap = g.kappa[b * (2 * g.max_rd + 1) + d + g.max_rd];
+    return z;
+}
+
+// psi-interval [lo, hi] of cell `cell` for a coordinate starting at g0 and
+// moving by Q over psi in [0,1]; empty when hi <= lo.
+__device__ __forceinline__ void cell_interval(double g0, double Q, double invQ, int cell,
+                                              double& lo, double& hi) {
+    if (Q == 0.0) {
+        bool in = (floor(g0) == (double)cell);
+        lo = 0.0;
+        hi = in ? 1.0 : 0.0;
+        return;
+    }
+    double t0 = ((double)cell - g0) * invQ;
+    double t1 = ((double)cell + 1.0 - g0) * invQ;
+    lo = fmax(0.0, fmin(t0, t1));
+    hi = fmin(1.0, fmax(t0, t1));
+}
+
+// range of major cells [m0, m1] on which the minor coordinate can be inside
+// [0, n_minor); conservative by one cell on each side.
+__device__ __forceinline__ void major_range(const TxRay& t, int n_major, int n_minor, int& m0, int& m1) {
+    if (t.Q == 0.0) {
+        double c = floor(t.P);
+        if (c >= 0.0 && c < (double)n_minor) { m0 = 0; m1 = n_major - 1; }
+        else { m0 = 0; m1 = -1; }
+        return;
+    }
+    double B0 = (0.0 - t.P) * t.invQ;
+    double B1 = ((double)n_minor - t.P) * t.invQ;
+    double lo = fmin(B0, B1), hi = fmax(B0, B1);
+    double flo = floor(lo) - 1.0, fhi = ceil(hi) + 1.0;
+    if (flo < 0.0) flo = 0.0;
+    if (fhi > (double)(n_major - 1)) fhi = (double)(n_major - 1);
+    if (fhi < flo) { m0 = 0; m1 = -1; return; }
+    m0 = (int)flo;
+    m1 = (int)fhi;
+}
+
+}  // namespace petos

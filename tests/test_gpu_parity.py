@@ -1,0 +1,317 @@
+"""GPU parity: every kernel of the hot path, called through the C ABI, against
+the FP64 oracle on the same FP32 inputs.
+
+Tolerances: rel-L2 <= 1e-5 per projection (forward, back, sensitivity, one
+subiteration), <= 1e-4 on the image after the configured iterations, <= 1e-6
+relative on the objective."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def pet():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2111_07886_amd as pet
+    pet.lib()
+    return pet
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x, dtype=np.float32), device="cuda").contiguous()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().double().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+GEOMS = {
+    "c1": dict(dim=2, nx=64, ny=64, vx=2.0, vy=2.0, n_angles=60, n_radial=95, ds=2.0, n_subsets=4),
+    "ragged_aniso": dict(dim=2, nx=50, ny=37, vx=2.0, vy=2.5, n_angles=30, n_radial=71, ds=1.7, n_subsets=5),
+    "odd_angles": dict(dim=2, nx=41, ny=41, vx=1.5, vy=1.5, n_angles=45, n_radial=61, ds=1.5, n_subsets=9),
+    "even_bins": dict(dim=2, nx=32, ny=32, vx=2.0, vy=2.0, n_angles=16, n_radial=46, ds=2.0, n_subsets=16),
+    "c2": dict(dim=2, nx=256, ny=256, vx=300 / 256, vy=300 / 256, n_angles=288, n_radial=367,
+               ds=300 / 256, n_subsets=24),
+    "3d_small": dict(dim=3, nx=24, ny=20, nz=8, vx=2.5, vy=2.5, vz=3.0, n_angles=16, n_radial=33, ds=2.5,
+                     n_rings=8, max_ring_diff=3, ring_pitch=3.0, det_radius=120.0, n_subsets=4),
+    "3d_ragged": dict(dim=3, nx=35, ny=35, nz=13, vx=2.0, vy=2.0, vz=2.5, n_angles=24, n_radial=49, ds=2.0,
+                      n_rings=13, max_ring_diff=5, ring_pitch=2.5, det_radius=150.0, n_subsets=6),
+}
+
+
+def full_desc(d):
+    d = dict(d)
+    d.setdefault("nz", 1)
+    d.setdefault("vz", 1.0)
+    d.setdefault("n_rings", 1)
+    d.setdefault("max_ring_diff", 0)
+    d.setdefault("ring_pitch", 1.0)
+    d.setdefault("det_radius", 0.0)
+    return d
+
+
+@pytest.fixture(scope="module")
+def geoms(pet, orc):
+    out = {}
+    for k, d in GEOMS.items():
+        d = full_desc(d)
+        say(f"create geometry {k}")
+        out[k] = (pet.Geometry(d), orc.geom(d), d)
+    return out
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_sensitivity(geoms, orc, name):
+    G, g, _ = geoms[name]
+    say(f"sensitivity {name}")
+    s = host(G.sensitivity())
+    so = orc.sensitivity(g)
+    assert rel(s, so) <= 1e-5
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_forward_projection(geoms, orc, name):
+    G, g, _ = geoms[name]
+    rng = np.random.default_rng(1)
+    f = f32(rng.uniform(0.5, 2.0, G.img_shape))
+    subsets = [0, 1, g.n_subsets] if name != "c2" else [0, 7]
+    for subset in subsets:
+        say(f"forward {name} subset {subset}")
+        q = host(G.forward(dev(f), subset))
+        qo = orc.forward(g, f, subset)
+        mask = np.zeros(G.sino_shape, bool)
+        for a in range(g.n_angles):
+            if subset == 0 or a % g.n_subsets == subset - 1:
+                mask[:, a] = True
+        assert rel(q[mask], qo[mask]) <= 1e-5, (subset, rel(q[mask], qo[mask]))
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_back_projection(geoms, orc, name):
+    G, g, _ = geoms[name]
+    rng = np.random.default_rng(2)
+    w = f32(rng.uniform(-1.0, 1.0, G.sino_shape))
+    for subset in [0, 2]:
+        say(f"back {name} subset {subset}")
+        b = host(G.back(dev(w), subset))
+        bo = orc.back(g, w, subset)
+        assert rel(b, bo) <= 1e-5, (subset, rel(b, bo))
+
+
+@pytest.mark.parametrize("name", ["c1", "ragged_aniso", "3d_ragged"])
+def test_gpu_adjoint_identity(geoms, name):
+    G, g, _ = geoms[name]
+    rng = np.random.default_rng(3)
+    x = dev(rng.uniform(0, 1, G.img_shape))
+    yv = dev(rng.normal(0, 1, G.sino_shape))
+    say(f"adjoint {name}")
+    Ax = G.forward(x, 0)
+    ATy = G.back(yv, 0)
+    lhs = float((Ax.double() * yv.double()).sum())
+    rhs = float((x.double() * ATy.double()).sum())
+    scale = float((Ax.double().abs() * yv.double().abs()).sum())
+    assert abs(lhs - rhs) <= 1e-5 * scale
+
+
+def workload(name, orc):
+    from synth import configs, phantoms
+    if name == "c1":
+        return configs.c1()
+    if name == "c2":
+        return configs.c2()
+    if name == "3d_small":
+        d = full_desc(GEOMS["3d_small"])
+        w = phantoms.make_3d(d, seed=21, n_ell=4, counts=2e6, bg_uniform=0.15, bg_scatter=0.15,
+                             scatter_sigma_bins=4.0)
+        return w, configs.params_3d(U=w.U), 3
+    if name == "3d_ragged":
+        d = full_desc(GEOMS["3d_ragged"])
+        w = phantoms.make_3d(d, seed=22, n_ell=5, counts=5e6, bg_uniform=0.15, bg_scatter=0.15,
+                             scatter_sigma_bins=4.0)
+        return w, configs.params_3d(U=w.U), 2
+    d = full_desc(GEOMS[name])
+    w = phantoms.make_2d(d, seed=23, n_ell=5, counts=3e5, bg_frac=0.1)
+    return w, configs.params_2d(d["n_subsets"], 3e5, U=w.U), 4
+
+
+@pytest.mark.parametrize("mode", ["BSREM", "M1", "M2", "P1", "P2"])
+def test_subiterations_match_oracle(pet, orc, mode):
+    from synth import configs
+    w, _, _ = configs.c1()
+    p = configs.params_2d(4, 1e5, mode=mode, U=w.U)
+    p.update(J0=2, J1=6)                    # exercise nu = 1, adaptive, freeze, frozen
+    G = pet.Geometry(full_desc(w.desc))
+    st = pet.State(G, p)
+    f = dev(w.f0)
+    y, r = dev(w.y), dev(w.r)
+    rec = orc.Recon(orc.geom(w.desc), orc.params(p), w.f0, host(y), host(r))
+    for J in range(1, 10):
+        say(f"subiteration {mode} J={J}")
+        st.subiteration(f, y, r)
+        rec.subiteration()
+        e = rel(host(f), rec.image())
+        assert e <= 1e-5 * max(1, J / 2), (J, e)
+    assert st.position() == (2, 2)
+
+
+@pytest.mark.parametrize("mode", ["BSREM", "M1", "M2", "P1", "P2"])
+def test_c1_reconstruction_all_modes(pet, orc, mode):
+    from synth import configs
+    w, _, n_iter = configs.c1()
+    p = configs.params_2d(4, 1e5, mode=mode, U=w.U)
+    G = pet.Geometry(full_desc(w.desc))
+    f = dev(w.f0)
+    y, r = dev(w.y), dev(w.r)
+    say(f"C1 reconstruct {mode}")
+    obj = pet.reconstruct(G, p, f, y, r, n_iter, want_objective=True)
+    fo, objo = orc.reconstruct(orc.geom(w.desc), orc.params(p), w.f0, host(y), host(r), n_iter)
+    assert rel(host(f), fo) <= 1e-4
+    for k in range(n_iter + 1):
+        assert abs(obj[k] - objo[k]) <= 1e-6 * abs(objo[k]), (k, obj[k], objo[k])
+
+
+@pytest.mark.parametrize("name", ["ragged_aniso", "odd_angles", "even_bins", "3d_small", "3d_ragged"])
+def test_reconstruction_other_geometries(pet, orc, name):
+    w, p, n_iter = workload(name, orc)
+    G = pet.Geometry(full_desc(w.desc))
+    f = dev(w.f0)
+    y, r = dev(w.y), dev(w.r)
+    say(f"reconstruct {name}")
+    obj = pet.reconstruct(G, p, f, y, r, n_iter, want_objective=True)
+    fo, objo = orc.reconstruct(orc.geom(w.desc), orc.params(p), w.f0, host(y), host(r), n_iter)
+    assert rel(host(f), fo) <= 1e-4, rel(host(f), fo)
+    assert abs(obj[-1] - objo[-1]) <= 1e-6 * abs(objo[-1])
+
+
+def test_c2_full_reconstruction(pet, orc):
+    """The 256^2, 288 x 367, 24-subset workload, all 50 iterations (1,200
+    subiterations, nu frozen at J = 1000), in the launch configuration the
+    benchmark times."""
+    from synth import configs
+    w, p, n_iter = configs.c2()
+    G = pet.Geometry(full_desc(w.desc))
+    f = dev(w.f0)
+    y, r = dev(w.y), dev(w.r)
+    say("C2 reconstruct 50 iterations")
+    obj = pet.reconstruct(G, p, f, y, r, n_iter, want_objective=True)
+    say("C2 oracle")
+    fo, objo = orc.reconstruct(orc.geom(w.desc), orc.params(p), w.f0, host(y), host(r), n_iter)
+    e = rel(host(f), fo)
+    say(f"C2 image rel-L2 {e:.3e}, objective {obj[-1]:.9e} vs {objo[-1]:.9e}")
+    assert e <= 1e-4
+    assert abs(obj[-1] - objo[-1]) <= 1e-6 * abs(objo[-1])
+
+
+def test_determinism_and_reconstruct_equals_subiterations(pet):
+    from synth import configs
+    w, p, _ = configs.c1()
+    G = pet.Geometry(full_desc(w.desc))
+    y, r = dev(w.y), dev(w.r)
+    f1, f2, f3 = dev(w.f0), dev(w.f0), dev(w.f0)
+    say("determinism")
+    pet.reconstruct(G, p, f1, y, r, 3)
+    pet.reconstruct(G, p, f2, y, r, 3)
+    st = pet.State(G, p)
+    for _ in range(12):
+        st.subiteration(f3, y, r)
+    torch.cuda.synchronize()
+    assert torch.equal(f1, f2)
+    assert torch.equal(f1, f3)
+
+
+def test_checkpoint_resume_bitwise(pet):
+    from synth import configs
+    w, p, _ = configs.c1()
+    p = dict(p, J0=1, J1=5)
+    G = pet.Geometry(full_desc(w.desc))
+    y, r = dev(w.y), dev(w.r)
+    fa, fb = dev(w.f0), dev(w.f0)
+    say("checkpoint")
+    sa = pet.State(G, p)
+    for _ in range(16):
+        sa.subiteration(fa, y, r)
+    sb = pet.State(G, p)
+    for _ in range(7):
+        sb.subiteration(fb, y, r)
+    blob = sb.export()
+    sb.close()
+    sc = pet.State(G, p)
+    sc.import_(blob)
+    assert sc.position() == (1, 4)
+    for _ in range(9):
+        sc.subiteration(fb, y, r)
+    torch.cuda.synchronize()
+    assert torch.equal(fa, fb)
+    other = pet.State(pet.Geometry(full_desc(GEOMS["even_bins"])), configs.params_2d(16, 1e5, U=w.U))
+    with pytest.raises(pet.PetOSError) as e:
+        other.import_(blob)
+    assert e.value.code == -7
+
+
+def test_objective_and_default_U(pet, orc):
+    from synth import configs
+    w, p, _ = configs.c1()
+    G = pet.Geometry(full_desc(w.desc))
+    g = orc.geom(w.desc)
+    rng = np.random.default_rng(4)
+    f = f32(rng.uniform(0.2, 3.0, G.img_shape))
+    y, r = dev(w.y), dev(w.r)
+    say("objective/default U")
+    phi = G.objective(p, dev(f), y, r)
+    phio = orc.objective(g, f, host(y), host(r), p["beta"], p["gamma_R"], p["eps"])
+    assert abs(phi - phio) <= 1e-6 * abs(phio)
+    U = G.default_U(dev(f), y, r)
+    Uo = orc.default_U(g, f, host(y), host(r))
+    assert abs(U - Uo) <= 1e-5 * Uo
+
+
+def test_edge_subset_counts(pet, orc):
+    from synth import phantoms, configs
+    for M in (1, 16):
+        d = full_desc(dict(GEOMS["even_bins"], n_subsets=M))
+        w = phantoms.make_2d(d, seed=31, n_ell=3, counts=1e5, bg_frac=0.1)
+        p = configs.params_2d(M, 1e5, U=w.U)
+        G = pet.Geometry(d)
+        f = dev(w.f0)
+        y, r = dev(w.y), dev(w.r)
+        say(f"edge M={M}")
+        pet.reconstruct(G, p, f, y, r, 2)
+        fo, _ = orc.reconstruct(orc.geom(d), orc.params(p), w.f0, host(y), host(r), 2, want_obj=False)
+        assert rel(host(f), fo) <= 1e-4
+
+
+def test_invalid_params_rejected(pet):
+    from synth import configs
+    G = pet.Geometry(full_desc(GEOMS["even_bins"]))
+    base = configs.params_2d(16, 1e5)
+    for bad in (dict(eps=0.0), dict(t_clip=2e6), dict(nu1=3.0), dict(J0=5, J1=2), dict(a=-1.0),
+                dict(mode=7), dict(beta=-0.1)):
+        with pytest.raises(pet.PetOSError) as e:
+            pet.State(G, dict(base, **bad))
+        assert e.value.code == -1
+    f = torch.ones(G.img_shape, device="cuda")
+    with pytest.raises(ValueError):
+        G.forward(torch.ones(5, device="cuda"))
+    with pytest.raises(TypeError):
+        G.forward(f.double())
+    assert math.isfinite(G.objective(base, f, torch.ones(G.sino_shape, device="cuda"),
+                                     torch.ones(G.sino_shape, device="cuda")))
