@@ -188,6 +188,12 @@ int pet_os_state_profile_read(pet_os_state* state, double* total_ms, int64_t* la
  * projection in the system model.  Synchronous. */
 int pet_os_nnz(const pet_os_geom* geom, int32_t subset, int64_t* nnz);
 
+/* Position a state at subiteration (k, i) with Nesterov t = t_nest (>= 1) and,
+ * when nu_frozen (DEVICE, n_voxels floats) is not NULL, the frozen nu of
+ * eq:nuki (P1/P2 only; marks it present).  Used to resume from state held
+ * elsewhere.  Synchronous with respect to the device copy. */
+int pet_os_state_seek(pet_os_state* state, int64_t k, int32_t i, double t_nest, const float* nu_frozen);
+
 /* Checkpoint of a state: (k, i, t, params, geometry descriptor, frozen nu).
  * export: buf == NULL queries the size into *len; otherwise *len must be at
  * least that size.  Synchronous (copies the frozen nu to the host).

@@ -281,6 +281,18 @@ class Recon:
             raise RuntimeError("oracle subiteration failed")
         return nu
 
+    def clone_with(self, f):
+        """Same position, Nesterov t and frozen nu, with iterate f (for one-step
+        comparisons from a given input)."""
+        c = Recon.__new__(Recon)
+        c.g, c.p = self.g, self.p
+        c.f = _f64(f).reshape(-1).copy()
+        c.y, c.r, c.pnorm = self.y, self.r, self.pnorm
+        c.frozen = self.frozen.copy()
+        c.st = _State()
+        c.st.k, c.st.i, c.st.t_nest, c.st.have_frozen = self.st.k, self.st.i, self.st.t_nest, self.st.have_frozen
+        return c
+
     def image(self):
         return self.f.reshape(img_shape(self.g)).copy()
 

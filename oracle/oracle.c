@@ -291,7 +291,7 @@ void orc_back(const orc_geom* g, const double* w, int subset, double* out) {
         double* mine = priv + (size_t)tid * nv;
         int* vox = (int*)malloc(sizeof(int) * (size_t)cap);
         double* len = (double*)malloc(sizeof(double) * (size_t)cap);
-#pragma omp for schedule(dynamic, 64)
+#pragma omp for schedule(static)
         for (long ray = 0; ray < nrays; ++ray) {
             int b = (int)(ray % Nr);
             int al = (int)((ray / Nr) % na);

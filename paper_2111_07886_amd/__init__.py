@@ -28,7 +28,7 @@ EXPORTS = ["pet_os_last_error", "pet_os_version", "pet_os_create_geometry", "pet
            "pet_os_objective", "pet_os_default_U", "pet_os_state_create", "pet_os_state_destroy",
            "pet_os_state_position", "pet_os_subiteration", "pet_os_reconstruct",
            "pet_os_state_export", "pet_os_state_import", "pet_os_run", "pet_os_state_profile",
-           "pet_os_state_profile_read", "pet_os_nnz"]
+           "pet_os_state_profile_read", "pet_os_nnz", "pet_os_state_seek"]
 
 
 class PetOSError(RuntimeError):
@@ -89,6 +89,7 @@ def lib():
             "pet_os_state_profile": (C.c_int, [_P, i32]),
             "pet_os_state_profile_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(i64)]),
             "pet_os_nnz": (C.c_int, [_P, i32, C.POINTER(i64)]),
+            "pet_os_state_seek": (C.c_int, [_P, i64, i32, C.c_double, _P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -250,6 +251,12 @@ class State:
         _check(lib().pet_os_run(self.handle, _dev(f, g.n_voxels, "f"), _dev(y, g.n_bins, "y"),
                                 _dev(r, g.n_bins, "r"), int(n_iter), obj, _stream(stream)))
         return list(obj)[:n_iter] if want_objective else None
+
+    def seek(self, k: int, i: int, t_nest: float = 1.0, nu_frozen=None):
+        """pet_os_state_seek: continue from subiteration (k, i) with Nesterov t
+        and (optionally) the frozen nu."""
+        nu = None if nu_frozen is None else _dev(nu_frozen, self.geom.n_voxels, "nu_frozen")
+        _check(lib().pet_os_state_seek(self.handle, int(k), int(i), float(t_nest), nu))
 
     def profile(self, kernel: int):
         """Bracket every launch of kernel 0 (forward+ratio), 1 (back+stencil) or

@@ -382,7 +382,6 @@ int work_alloc(const pet_os_geom* g, bool need_nu, Work* w) {
     size_t o_red[RED_COUNT];
     for (int r = 0; r < RED_COUNT; ++r) o_red[r] = cv.take<double>((size_t)caps[r]);
     size_t o_tot = cv.take<double>(RED_COUNT);
-    size_t o_tk = cv.take<unsigned>(RED_COUNT);
     char* blk = nullptr;
     if (hipMalloc(&blk, cv.off) != hipSuccess) return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc of scratch failed");
     w->bytes = cv.off;
@@ -394,11 +393,9 @@ int work_alloc(const pet_os_geom* g, bool need_nu, Work* w) {
     for (int r = 0; r < RED_COUNT; ++r) {
         w->red[r].part = (double*)(blk + o_red[r]);
         w->red[r].total = (double*)(blk + o_tot) + r;
-        w->red[r].ticket = (unsigned*)(blk + o_tk) + r;
         w->red[r].cap = caps[r];
     }
-    if (hipMemset(blk + o_tot, 0, RED_COUNT * sizeof(double)) != hipSuccess ||
-        hipMemset(blk + o_tk, 0, RED_COUNT * sizeof(unsigned)) != hipSuccess) {
+    if (hipMemset(blk + o_tot, 0, RED_COUNT * sizeof(double)) != hipSuccess) {
         (void)hipFree(blk);
         return fail(PET_OS_ERR_DEVICE, "scratch init failed");
     }
@@ -534,7 +531,8 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
     B.beta_over_M = (float)(st->p.beta / (double)M);
     B.gamma_R = (float)st->p.gamma_R;
     B.eps = (float)st->p.eps;
-    B.total_f = st->w.red[RED_SUMF].total;
+    B.part_f = st->w.red[RED_SUMF].part;
+    B.n_part_f = elem_grid(g->n_vox);
     B.red_mu = st->w.red[RED_SUMMU];
     if ((rc = prof_begin(st, 1, s, &ev))) return rc;
     rc = launch_bp(g, B, s);
@@ -545,7 +543,8 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
     U.step = (float)(sc.lam * sc.alpha);
     U.nu1 = (float)st->p.nu1; U.nu2 = (float)st->p.nu2;
     U.U = (float)st->p.U; U.t_clip = (float)st->p.t_clip;
-    U.total_mu = st->w.red[RED_SUMMU].total;
+    U.part_mu = st->w.red[RED_SUMMU].part;
+    U.n_part_mu = bp_grid(g);
     U.red_f = st->w.red[RED_SUMF];
     if ((rc = prof_begin(st, 2, s, &ev))) return rc;
     rc = launch_update(g, U, s);
@@ -564,8 +563,9 @@ static int queue_objective(const pet_os_geom* g, const pet_os_params* p, Work* w
     F.f = f; F.y = y; F.r = r; F.out = nullptr; F.angles = ex->all_angles; F.n_al = g->d.n_angles;
     F.mode = FP_OBJECTIVE; F.red = w->red[RED_FID];
     int rc = launch_fp(g, F, s);
-    if (rc) return rc;
-    rc = launch_rdp_value(g, f, (float)p->gamma_R, (float)p->eps, w->red[RED_RDP], s);
+    if (!rc) rc = launch_finalize(w->red[RED_FID], fp_grid(g, g->d.n_angles), s);
+    if (!rc) rc = launch_rdp_value(g, f, (float)p->gamma_R, (float)p->eps, w->red[RED_RDP], s);
+    if (!rc) rc = launch_finalize(w->red[RED_RDP], elem_grid(g->n_vox), s);
     if (rc) return rc;
     PETOS_HIP(hipMemcpyAsync(dst, w->red[RED_FID].total, sizeof(double), hipMemcpyDeviceToDevice, s));
     PETOS_HIP(hipMemcpyAsync(dst + 1, w->red[RED_RDP].total, sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -680,7 +680,9 @@ int pet_os_default_U(const pet_os_geom* g, const float* f0, const float* y, cons
     int rc = work_alloc(g, false, &w);
     if (rc) return rc;
     rc = launch_sum(y, g->n_bins, w.red[RED_SUMY], s);
+    if (!rc) rc = launch_finalize(w.red[RED_SUMY], elem_grid(g->n_bins), s);
     if (!rc) rc = launch_sum(r, g->n_bins, w.red[RED_SUMR], s);
+    if (!rc) rc = launch_finalize(w.red[RED_SUMR], elem_grid(g->n_bins), s);
     double sy = 0, sr = 0;
     std::vector<float> fh((size_t)g->n_vox);
     if (!rc) {
@@ -789,6 +791,23 @@ int pet_os_reconstruct(const pet_os_geom* g, const pet_os_params* p, float* f, c
     return rc;
 }
 
+int pet_os_state_seek(pet_os_state* st, int64_t k, int32_t i, double t_nest, const float* nu_frozen) {
+    if (!st) return fail(PET_OS_ERR_INVALID_ARG, "state is NULL");
+    if (k < 0 || i < 1 || i > st->g->d.n_subsets) return fail(PET_OS_ERR_INVALID_ARG, "bad position");
+    if (!(std::isfinite(t_nest) && t_nest >= 1.0)) return fail(PET_OS_ERR_INVALID_ARG, "t_nest must be >= 1");
+    if (nu_frozen && !st->w.nu_frozen) return fail(PET_OS_ERR_INVALID_ARG, "state has no nu (mode is not P1/P2)");
+    if (nu_frozen) {
+        PETOS_HIP(hipDeviceSynchronize());
+        PETOS_HIP(hipMemcpy(st->w.nu_frozen, nu_frozen, (size_t)st->g->n_vox * sizeof(float),
+                            hipMemcpyDeviceToDevice));
+        st->have_frozen = 1;
+    }
+    st->k = k;
+    st->i = i;
+    st->t_nest = t_nest;
+    return PET_OS_OK;
+}
+
 int pet_os_state_profile(pet_os_state* st, int32_t kernel) {
     if (!st) return fail(PET_OS_ERR_INVALID_ARG, "state is NULL");
     if (kernel < -1 || kernel > 2) return fail(PET_OS_ERR_INVALID_ARG, "kernel must be -1..2");
@@ -832,6 +851,7 @@ int pet_os_nnz(const pet_os_geom* g, int32_t subset, int64_t* nnz) {
     F.angles = subset == 0 ? ex->all_angles : ex->subset_lists + (size_t)(subset - 1) * g->max_sub_angles;
     rc = launch_fp(g, F, nullptr);
     if (!rc) rc = launch_sum(cnt, n, red, nullptr);
+    if (!rc) rc = launch_finalize(red, elem_grid(n), nullptr);
     double tot = 0.0;
     if (!rc && (hipMemcpy(&tot, red.total, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess))
         rc = fail(PET_OS_ERR_DEVICE, "read-back failed");

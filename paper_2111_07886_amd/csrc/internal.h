@@ -24,13 +24,13 @@ int fail(int code, const std::string& msg);
     } while (0)
 
 // ---------------------------------------------------------------- reductions
-// Deterministic FP64 sums: each block writes one partial; the last block to
-// finish (integer ticket) adds the partials in index order into total[0] and
-// re-arms the ticket.  One Reduction slot per quantity.
+// Deterministic FP64 sums without device-wide fences: each block of the
+// producing kernel writes one partial; whoever needs the total (the next
+// kernel in the stream, or a one-block finalize kernel) adds the partials in
+// index order.  One Reduction slot per quantity.
 struct Reduction {
     double* part;       // [cap] partials
-    double* total;      // [1]
-    unsigned* ticket;   // [1]
+    double* total;      // [1] filled by launch_finalize
     int cap;
 };
 
@@ -100,7 +100,8 @@ struct BPLaunch {
     float* mu;               // written when want_mu
     int want_mu;
     float beta_over_M, gamma_R, eps;
-    const double* total_f;   // sum f of the current iterate (for mean f)
+    const double* part_f;    // partials of sum f of the current iterate (for mean f)
+    int n_part_f;
     Reduction red_mu;
 };
 int launch_bp(const pet_os_geom* g, const BPLaunch& L, hipStream_t s);
@@ -114,7 +115,8 @@ struct UpdLaunch {
     int nu_mode;
     float step;              // lambda_k * alpha_{k,i}
     float nu1, nu2, U, t_clip;
-    const double* total_mu;
+    const double* part_mu;   // partials of sum mu (from the back-projection)
+    int n_part_mu;
     Reduction red_f;         // sum of the new iterate
 };
 int launch_update(const pet_os_geom* g, const UpdLaunch& L, hipStream_t s);
@@ -123,6 +125,8 @@ int launch_sum(const float* x, int64_t n, Reduction red, hipStream_t s);
 int launch_rdp_value(const pet_os_geom* g, const float* f, float gamma_R, float eps, Reduction red,
                      hipStream_t s);
 int launch_fill(float* x, int64_t n, float v, hipStream_t s);
+// total = sum of the first n partials of red (one block, fixed order)
+int launch_finalize(Reduction red, int n, hipStream_t s);
 
 // grid sizes (for sizing partial arrays)
 int fp_grid(const pet_os_geom* g, int n_al);

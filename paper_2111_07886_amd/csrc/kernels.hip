@@ -44,30 +44,29 @@ __device__ double block_sum(double v, double* sh /* >= NT/64 */) {
     return t;
 }
 
-// Writes this block's partial; the last block to arrive sums all partials in
-// index order into *R.total and re-arms the ticket.  Every thread must call.
-__device__ void reduce_finish(double v, Reduction R, double* sh) {
-    __shared__ unsigned s_last;
+// Every thread must call: the block's sum of v goes to R.part[blockIdx.x].
+__device__ __forceinline__ void write_partial(double v, Reduction R, double* sh) {
     double bs = block_sum(v, sh);
-    int nblk = gridDim.x;
-    if (threadIdx.x == 0) {
-        R.part[blockIdx.x] = bs;
-        __threadfence();
-        unsigned t = atomicAdd(R.ticket, 1u);
-        s_last = (t == (unsigned)(nblk - 1)) ? 1u : 0u;
-    }
+    if (threadIdx.x == 0) R.part[blockIdx.x] = bs;
+}
+
+// Sum of part[0..n) in index-strided order, the same in every block; the
+// result is returned to every thread.  The partials were written by an
+// earlier kernel in the same stream.
+__device__ double sum_partials(const double* part, int n, double* sh) {
+    __shared__ double s_tot;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+    double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) s_tot = t;
     __syncthreads();
-    if (s_last) {
-        __threadfence();
-        double acc = 0.0;
-        const volatile double* part = R.part;
-        for (int i = threadIdx.x; i < nblk; i += blockDim.x) acc += part[i];
-        double tot = block_sum(acc, sh);
-        if (threadIdx.x == 0) {
-            *R.total = tot;
-            *R.ticket = 0u;
-        }
-    }
+    return s_tot;
+}
+
+__global__ __launch_bounds__(256) void k_finalize(Reduction R, int n) {
+    __shared__ double s_red[4];
+    double t = sum_partials(R.part, n, s_red);
+    if (threadIdx.x == 0) *R.total = t;
 }
 
 // ------------------------------------------------------------------ forward projection
@@ -198,7 +197,7 @@ __global__ __launch_bounds__(NT) void k_fp(GeoK g, FPArgs A) {
             term = q - (double)A.y[nat] * log(q + (double)A.r[nat]);
         }
     }
-    if (A.mode == FP_OBJECTIVE) reduce_finish(term, A.red, s_red);
+    if (A.mode == FP_OBJECTIVE) write_partial(term, A.red, s_red);
 }
 
 // ------------------------------------------------------------------ back projection
@@ -214,19 +213,24 @@ struct BPArgs {
     float* mu;
     int want_mu;
     float beta_over_M, gamma_R, eps;
-    const double* total_f;
+    const double* part_f;
+    int n_part_f;
     Reduction red_mu;
     int nb_max;              // staged bins per row
     int rows_max;            // staged rows (planes) per angle
     int chunk;               // angles staged together
 };
 
-template <int DIM>
-struct Tile;
-template <>
-struct Tile<2> { static constexpr int X = 16, Y = 16, Z = 1; };
-template <>
-struct Tile<3> { static constexpr int X = 8, Y = 8, Z = 4; };
+// Tile of the back-projector: X x Y x Z voxels, AG threads per voxel (each
+// takes every AG-th angle of the subset; partial sums added in group order).
+template <int DIM, int X_, int Y_, int Z_, int AG_>
+struct Tile {
+    static constexpr int D = DIM, X = X_, Y = Y_, Z = Z_, AG = AG_;
+    static_assert(X_ * Y_ * Z_ * AG_ == 256, "256 threads per block");
+};
+using Tile2L = Tile<2, 16, 16, 1, 1>;   // large 2D images
+using Tile2S = Tile<2, 8, 8, 1, 4>;     // small 2D images: 4 angle groups
+using Tile3 = Tile<3, 8, 8, 4, 1>;
 
 constexpr int MAXD2 = 63;    // ring differences -31..31
 constexpr int MAXCH = 16;    // angles per staging chunk
@@ -275,9 +279,10 @@ __device__ __forceinline__ void stencil_at(const float* sf, int HX, int HY, int 
     gmag = sqrtf(gx * gx + gy * gy + gz * gz);
 }
 
-template <int DIM>
+template <class T>
 __global__ __launch_bounds__(NT) void k_bp(GeoK g, BPArgs A) {
-    using T = Tile<DIM>;
+    constexpr int DIM = T::D;
+    constexpr int NV = T::X * T::Y * T::Z;          // voxels per tile
     constexpr int HX = T::X + 2, HY = T::Y + 2, HZ = (DIM == 3) ? T::Z + 2 : 1;
     constexpr int ND = (DIM == 3) ? MAXD2 : 1;
     extern __shared__ float s_w[];
@@ -290,6 +295,7 @@ __global__ __launch_bounds__(NT) void k_bp(GeoK g, BPArgs A) {
     __shared__ int s_ncol[NROWS];
     __shared__ int s_rows_total;
     __shared__ double s_red[NT / 64];
+    __shared__ float s_acc[T::AG > 1 ? T::AG * NV : 1];
 
     const int tiles_x = (g.nx + T::X - 1) / T::X;
     const int tiles_y = (g.ny + T::Y - 1) / T::Y;
@@ -298,9 +304,11 @@ __global__ __launch_bounds__(NT) void k_bp(GeoK g, BPArgs A) {
     t /= tiles_x;
     const int ty0 = (t % tiles_y) * T::Y;
     const int tz0 = (t / tiles_y) * T::Z;
-    const int lx = threadIdx.x % T::X;
-    const int ly = (threadIdx.x / T::X) % T::Y;
-    const int lz = threadIdx.x / (T::X * T::Y);
+    const int vox = threadIdx.x % NV;               // voxel of the tile
+    const int grp = threadIdx.x / NV;               // angle group
+    const int lx = vox % T::X;
+    const int ly = (vox / T::X) % T::Y;
+    const int lz = vox / (T::X * T::Y);
     const int ix = tx0 + lx, iy = ty0 + ly, iz = tz0 + lz;
     const int nzv = (DIM == 3) ? g.nz : 1;
     const bool inside = ix < g.nx && iy < g.ny && iz < nzv;
@@ -415,7 +423,7 @@ __global__ __launch_bounds__(NT) void k_bp(GeoK g, BPArgs A) {
 
         // (4) gather: every bin (and plane) whose LOR crosses this voxel
         if (inside) {
-            for (int j = 0; j < nch; ++j) {
+            for (int j = grp; j < nch; j += T::AG) {
                 const int al = c0 + j;
                 const int a = A.angles[al];
                 const AngleK& AK = g.ang[a];
@@ -483,9 +491,16 @@ __global__ __launch_bounds__(NT) void k_bp(GeoK g, BPArgs A) {
         __syncthreads();
     }
     (void)P;
+    if (T::AG > 1) {
+        s_acc[grp * NV + vox] = acc;
+        __syncthreads();
+        acc = 0.0f;
+        for (int k = 0; k < T::AG; ++k) acc += s_acc[k * NV + vox];
+    }
+    const bool owner = grp == 0;
 
     if (A.f == nullptr) {
-        if (inside) A.out[((long long)iz * g.ny + iy) * g.nx + ix] = acc;
+        if (inside && owner) A.out[((long long)iz * g.ny + iy) * g.nx + ix] = acc;
         return;
     }
 
@@ -500,20 +515,21 @@ __global__ __launch_bounds__(NT) void k_bp(GeoK g, BPArgs A) {
     }
     __syncthreads();
     double mu_part = 0.0;
-    if (inside) {
+    float meanf = 1.0f;
+    if (A.want_mu) meanf = (float)(sum_partials(A.part_f, A.n_part_f, s_red) / (double)g.nvox);
+    if (inside && owner) {
         float gradR, gmag;
         stencil_at<DIM>(s_f, HX, HY, lx + 1, ly + 1, (DIM == 3) ? lz + 1 : 0, ix, iy, iz, g, A.gamma_R, A.eps,
                         gradR, gmag);
         const long long j = ((long long)iz * g.ny + iy) * g.nx + ix;
         A.out[j] = fmaf(A.beta_over_M, gradR, acc);
         if (A.want_mu) {
-            const float meanf = (float)(*A.total_f / (double)g.nvox);
             const float mu = fmaxf(0.01f, gmag / meanf);
             A.mu[j] = mu;
             mu_part = (double)mu;
         }
     }
-    if (A.want_mu) reduce_finish(mu_part, A.red_mu, s_red);
+    if (A.want_mu) write_partial(mu_part, A.red_mu, s_red);
 }
 
 // ------------------------------------------------------------------ update
@@ -526,7 +542,8 @@ struct UpdArgs {
     float* nu_frozen;
     int nu_mode;
     float step, nu1, nu2, U, t_clip;
-    const double* total_mu;
+    const double* part_mu;
+    int n_part_mu;
     Reduction red_f;
     long long n;
 };
@@ -535,10 +552,12 @@ __global__ __launch_bounds__(NT) void k_update(UpdArgs A) {
     __shared__ double s_red[NT / 64];
     const long long j = (long long)blockIdx.x * NT + threadIdx.x;
     double part = 0.0;
+    const bool want_mu = A.nu_mode == NU_COMPUTE || A.nu_mode == NU_COMPUTE_FREEZE;
+    float meanmu = 1.0f;
+    if (want_mu) meanmu = (float)(sum_partials(A.part_mu, A.n_part_mu, s_red) / (double)A.n);
     if (j < A.n) {
         float nu = 1.0f;
-        if (A.nu_mode == NU_COMPUTE || A.nu_mode == NU_COMPUTE_FREEZE) {
-            const float meanmu = (float)(*A.total_mu / (double)A.n);
+        if (want_mu) {
             nu = fminf(A.nu2, fmaxf(A.nu1, meanmu / A.mu[j]));
             if (A.nu_mode == NU_COMPUTE_FREEZE) A.nu_frozen[j] = nu;
         } else if (A.nu_mode == NU_FROZEN) {
@@ -551,13 +570,13 @@ __global__ __launch_bounds__(NT) void k_update(UpdArgs A) {
         A.f[j] = fn;
         part = (double)fn;
     }
-    reduce_finish(part, A.red_f, s_red);
+    write_partial(part, A.red_f, s_red);
 }
 
 __global__ __launch_bounds__(NT) void k_sum(const float* x, long long n, Reduction R) {
     __shared__ double s_red[NT / 64];
     const long long j = (long long)blockIdx.x * NT + threadIdx.x;
-    reduce_finish(j < n ? (double)x[j] : 0.0, R, s_red);
+    write_partial(j < n ? (double)x[j] : 0.0, R, s_red);
 }
 
 __global__ __launch_bounds__(NT) void k_fill(float* x, long long n, float v) {
@@ -591,15 +610,17 @@ __global__ __launch_bounds__(NT) void k_rdp(GeoK g, const float* f, float gR, fl
             }
         }
     }
-    reduce_finish(v, R, s_red);
+    write_partial(v, R, s_red);
 }
 
 // ------------------------------------------------------------------ launchers
 
+// threads per ray: enough rays x segments to fill the chip (~2^18 threads)
 static int fp_seg(long long nrays) {
-    if (nrays < (1 << 16)) return 16;
-    if (nrays < (1 << 20)) return 4;
-    return 1;
+    const long long target = 1LL << 18;
+    if (nrays * 4 > target) return nrays >= target ? 1 : 4;
+    if (nrays * 16 > target) return 16;
+    return 64;
 }
 
 int fp_grid(const pet_os_geom* G, int n_al) {
@@ -608,11 +629,23 @@ int fp_grid(const pet_os_geom* G, int n_al) {
     return (int)((nrays + rpb - 1) / rpb);
 }
 
+// 0: Tile2L, 1: Tile2S, 2: Tile3
+static int bp_kind(const pet_os_geom* G) {
+    if (G->d.dim == 3) return 2;
+    long long tiles16 = (long long)((G->d.nx + 15) / 16) * ((G->d.ny + 15) / 16);
+    return tiles16 < 1024 ? 1 : 0;
+}
+
+static void bp_tile(int kind, int& TX, int& TY, int& TZ) {
+    TX = kind == 0 ? 16 : 8;
+    TY = kind == 0 ? 16 : 8;
+    TZ = kind == 2 ? 4 : 1;
+}
+
 int bp_grid(const pet_os_geom* G) {
-    if (G->d.dim == 2) {
-        return ((G->d.nx + 15) / 16) * ((G->d.ny + 15) / 16);
-    }
-    return ((G->d.nx + 7) / 8) * ((G->d.ny + 7) / 8) * ((G->d.nz + 3) / 4);
+    int TX, TY, TZ;
+    bp_tile(bp_kind(G), TX, TY, TZ);
+    return ((G->d.nx + TX - 1) / TX) * ((G->d.ny + TY - 1) / TY) * ((G->d.nz + TZ - 1) / TZ);
 }
 
 int elem_grid(int64_t n) { return (int)((n + NT - 1) / NT); }
@@ -638,7 +671,8 @@ int launch_fp(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
     int grid = fp_grid(G, L.n_al);
     if (L.mode == FP_OBJECTIVE && grid > L.red.cap) return fail(PET_OS_ERR_DEVICE, "objective partials too small");
     const bool d3 = G->d.dim == 3;
-    if (seg == 16) { if (d3) fp_launch_t<3, 16>(G->k, a, grid, s); else fp_launch_t<2, 16>(G->k, a, grid, s); }
+    if (seg == 64) { if (d3) fp_launch_t<3, 64>(G->k, a, grid, s); else fp_launch_t<2, 64>(G->k, a, grid, s); }
+    else if (seg == 16) { if (d3) fp_launch_t<3, 16>(G->k, a, grid, s); else fp_launch_t<2, 16>(G->k, a, grid, s); }
     else if (seg == 4) { if (d3) fp_launch_t<3, 4>(G->k, a, grid, s); else fp_launch_t<2, 4>(G->k, a, grid, s); }
     else { if (d3) fp_launch_t<3, 1>(G->k, a, grid, s); else fp_launch_t<2, 1>(G->k, a, grid, s); }
     PETOS_HIP(hipGetLastError());
@@ -648,7 +682,8 @@ int launch_fp(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
 // LDS footprint bounds of a back-projection tile (host side, conservative)
 static void bp_stage_shape(const pet_os_geom* G, int& nb_max, int& rows_max, int& chunk, size_t& lds) {
     const auto& d = G->d;
-    const int TX = d.dim == 2 ? 16 : 8, TY = d.dim == 2 ? 16 : 8, TZ = d.dim == 2 ? 1 : 4;
+    int TX, TY, TZ;
+    bp_tile(bp_kind(G), TX, TY, TZ);
     nb_max = (int)std::ceil((TX * d.vx + TY * d.vy) / d.ds) + 4;
     if (nb_max > d.n_radial) nb_max = d.n_radial;
     if (d.dim == 2) {
@@ -696,17 +731,19 @@ int launch_bp(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
     a.beta_over_M = L.beta_over_M;
     a.gamma_R = L.gamma_R;
     a.eps = L.eps;
-    a.total_f = L.total_f;
+    a.part_f = L.part_f;
+    a.n_part_f = L.n_part_f;
     a.red_mu = L.red_mu;
     size_t lds;
     bp_stage_shape(G, a.nb_max, a.rows_max, a.chunk, lds);
     if (L.w == nullptr) lds = 0;
     int grid = bp_grid(G);
     if (L.want_mu && grid > L.red_mu.cap) return fail(PET_OS_ERR_DEVICE, "mu partials too small");
-    if (G->d.dim == 3)
-        hipLaunchKernelGGL((k_bp<3>), dim3(grid), dim3(NT), lds, s, G->k, a);
-    else
-        hipLaunchKernelGGL((k_bp<2>), dim3(grid), dim3(NT), lds, s, G->k, a);
+    switch (bp_kind(G)) {
+        case 0: hipLaunchKernelGGL((k_bp<Tile2L>), dim3(grid), dim3(NT), lds, s, G->k, a); break;
+        case 1: hipLaunchKernelGGL((k_bp<Tile2S>), dim3(grid), dim3(NT), lds, s, G->k, a); break;
+        default: hipLaunchKernelGGL((k_bp<Tile3>), dim3(grid), dim3(NT), lds, s, G->k, a); break;
+    }
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;
 }
@@ -724,7 +761,8 @@ int launch_update(const pet_os_geom* G, const UpdLaunch& L, hipStream_t s) {
     a.nu2 = L.nu2;
     a.U = L.U;
     a.t_clip = L.t_clip;
-    a.total_mu = L.total_mu;
+    a.part_mu = L.part_mu;
+    a.n_part_mu = L.n_part_mu;
     a.red_f = L.red_f;
     a.n = G->n_vox;
     int grid = elem_grid(G->n_vox);
@@ -738,6 +776,13 @@ int launch_sum(const float* x, int64_t n, Reduction red, hipStream_t s) {
     int grid = elem_grid(n);
     if (grid > red.cap) return fail(PET_OS_ERR_DEVICE, "sum partials too small");
     hipLaunchKernelGGL(k_sum, dim3(grid), dim3(NT), 0, s, x, (long long)n, red);
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
+}
+
+int launch_finalize(Reduction red, int n, hipStream_t s) {
+    if (n > red.cap) return fail(PET_OS_ERR_DEVICE, "finalize beyond partial capacity");
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(NT), 0, s, red, n);
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;
 }
