@@ -24,6 +24,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "c2": "2D SDP-P2, 256x256 image (1.171875 mm), 288 angles x 367 bins, 24 subsets, 5e6 counts, "
+          "20% background; step = 1 iteration (24 subiterations) + FP64 objective",
+    "c1": "2D SDP-P2, 64x64 image (2 mm), 60 angles x 95 bins, 4 subsets, 1e5 counts, 10% background; "
+          "step = 1 iteration (4 subiterations) + FP64 objective",
+    "c3": "3D SDP-P2, 200x200x64 volume (1.5x1.5x3 mm), 224 angles x 281 bins x 1744 span-1 planes "
+          "(64 rings, |d| <= 15), 28 subsets, 5e8 counts, 30% background; step = 1 iteration "
+          "(28 subiterations) + FP64 objective",
+}
 KERNELS = {0: "k_fp (forward projection + Poisson ratio)",
            1: "k_bp (back-projection + RDP gradient + mu)",
            2: "k_update (nu, S, relaxed step, P_t)"}
@@ -60,7 +69,7 @@ def cpu_baseline(w, p, budget_s=12.0):
     M = w.desc["n_subsets"]
     n = 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and n < 50 * M:
+    while time.perf_counter() - t0 < budget_s and n < 50 * M and (n == 0 or budget_s > 0):
         rec.subiteration()
         n += 1
         if n % M == 0:
@@ -69,8 +78,7 @@ def cpu_baseline(w, p, budget_s=12.0):
     return {"value": round(n / dt, 3), "unit": "subiterations/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"first {n} subiterations (objective after each of the {n // M} full iterations) "
-                      f"of the same 256x256 / 288x367 / 24-subset P2 workload from f0, FP64 C oracle, "
-                      f"{dt:.1f} s wall"}
+                      f"of the same workload from f0, FP64 C oracle, {dt:.1f} s wall"}
 
 
 def main():
@@ -80,6 +88,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3"],
+                    help="c2 (default, the benchmark line); c1 / c3 for additional measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (for PMC byte-counter scaling)")
     args = ap.parse_args()
@@ -95,7 +105,7 @@ def main():
     import paper_2111_07886_amd as pet
     from synth import configs
 
-    w, p, _ = configs.c2()
+    w, p, _ = {"c1": configs.c1, "c2": configs.c2, "c3": configs.c3}[args.workload]()
     p = dict(p, objective_every=1)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -146,7 +156,7 @@ def main():
         K = per_kernel[dom]
         achieved = K["bytes"] / (K["avg_us"] * 1e-6) / 1e9
         traffic = None
-        tpath = os.path.join(ROOT, "profiles", "traffic_c2.json")
+        tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
         if os.path.exists(tpath):
             t = json.load(open(tpath))
             if t.get("kernel_source") == kernel_source_hash() and str(dom) in t.get("bytes_per_launch", {}):
@@ -157,6 +167,7 @@ def main():
                     "algorithmic_bytes_per_launch": int(K["bytes"]),
                     "per_kernel_us": {KERNELS[k].split()[0]: round(v["avg_us"], 3) for k, v in per_kernel.items()}}
 
+    del state
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, p)
 
     out = {
@@ -172,9 +183,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "2D SDP-P2, 256x256 image (1.171875 mm), 288 angles x 367 bins, "
-                               "24 subsets, 5e6 counts, 20% background; step = 1 iteration "
-                               "(24 subiterations) + FP64 objective",
+        "config": {"workload": WORKLOADS[args.workload],
                    "subsets": M, "nnz_per_subset": int(nnz_sub), "rays_per_subset": int(rays_sub),
                    "voxels": q, "objective_last": obj[-1] if obj else None},
         "roofline": roofline,

@@ -83,13 +83,15 @@ struct FPArgs {
 };
 
 // One ray per (thread-row of the block); SEG threads split its major cells.
+// With SEG > 1 the SEG threads of a ray are adjacent lanes of one wave and
+// their partial sums are added by a fixed shuffle tree.
 template <int DIM, int SEG>
 __global__ __launch_bounds__(NT) void k_fp(GeoK g, FPArgs A) {
+    static_assert(SEG == 1 || (64 % SEG == 0), "segments of a ray stay in one wave");
     constexpr int RPB = NT / SEG;
-    __shared__ float s_part[SEG][RPB];
     __shared__ double s_red[NT / 64];
-    const int lr = threadIdx.x % RPB;
-    const int seg = threadIdx.x / RPB;
+    const int lr = (SEG == 1) ? threadIdx.x : threadIdx.x / SEG;
+    const int seg = (SEG == 1) ? 0 : threadIdx.x % SEG;
     const int P = g.n_planes, Nr = g.n_radial;
     const long long nrays = (long long)A.n_al * P * Nr;
     const long long ray = (long long)blockIdx.x * RPB + lr;
@@ -173,14 +175,8 @@ __global__ __launch_bounds__(NT) void k_fp(GeoK g, FPArgs A) {
         }
     }
     if (SEG > 1) {
-        s_part[seg][lr] = acc;
-        __syncthreads();
-        if (seg == 0) {
-            float t = 0.0f;
-            #pragma unroll
-            for (int k = 0; k < SEG; ++k) t += s_part[k][lr];
-            acc = t;
-        }
+        #pragma unroll
+        for (int off = SEG / 2; off > 0; off >>= 1) acc += __shfl_down(acc, off, SEG);
     }
     double term = 0.0;
     if (seg == 0 && valid) {
@@ -319,6 +315,21 @@ __global__ __launch_bounds__(NT) void k_bp(GeoK g, BPArgs A) {
     // tile box in mm
     const double X0 = ((double)tx0 - 0.5 * g.nx) * g.vx, X1 = X0 + T::X * g.vx;
     const double Y0 = ((double)ty0 - 0.5 * g.ny) * g.vy, Y1 = Y0 + T::Y * g.vy;
+
+    // halo tile of f (fused stencil) and mean f: independent of the gather,
+    // so issued first
+    if (A.f != nullptr) {
+        for (int e = threadIdx.x; e < HX * HY * HZ; e += NT) {
+            const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
+            const int gx = tx0 - 1 + hx, gy = ty0 - 1 + hy, gz = (DIM == 3) ? tz0 - 1 + hz : 0;
+            float v = 0.0f;
+            if (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < nzv)
+                v = A.f[((long long)gz * g.ny + gy) * g.nx + gx];
+            s_f[e] = v;
+        }
+    }
+    float meanf = 1.0f;
+    if (A.f != nullptr && A.want_mu) meanf = (float)(sum_partials(A.part_f, A.n_part_f, s_red) / (double)g.nvox);
 
     float acc = 0.0f;
     for (int c0 = 0; c0 < A.n_al; c0 += A.chunk) {
@@ -505,18 +516,9 @@ __global__ __launch_bounds__(NT) void k_bp(GeoK g, BPArgs A) {
     }
 
     // (5) fused image-space part: grad R, mu, G = A_i^T w + (beta/M) grad R
-    for (int e = threadIdx.x; e < HX * HY * HZ; e += NT) {
-        const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
-        const int gx = tx0 - 1 + hx, gy = ty0 - 1 + hy, gz = (DIM == 3) ? tz0 - 1 + hz : 0;
-        float v = 0.0f;
-        if (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < nzv)
-            v = A.f[((long long)gz * g.ny + gy) * g.nx + gx];
-        s_f[e] = v;
-    }
+    // (the halo tile was loaded before the gather)
     __syncthreads();
     double mu_part = 0.0;
-    float meanf = 1.0f;
-    if (A.want_mu) meanf = (float)(sum_partials(A.part_f, A.n_part_f, s_red) / (double)g.nvox);
     if (inside && owner) {
         float gradR, gmag;
         stencil_at<DIM>(s_f, HX, HY, lx + 1, ly + 1, (DIM == 3) ? lz + 1 : 0, ix, iy, iz, g, A.gamma_R, A.eps,
@@ -553,19 +555,25 @@ __global__ __launch_bounds__(NT) void k_update(UpdArgs A) {
     const long long j = (long long)blockIdx.x * NT + threadIdx.x;
     double part = 0.0;
     const bool want_mu = A.nu_mode == NU_COMPUTE || A.nu_mode == NU_COMPUTE_FREEZE;
+    const bool in = j < A.n;
+    // operands first, so that their loads overlap the partial sum below
+    const float fj = in ? A.f[j] : 0.0f;
+    const float Gj = in ? A.G[j] : 0.0f;
+    const float pj = in ? A.pnorm[j] : 1.0f;
+    const float muj = (in && want_mu) ? A.mu[j] : 1.0f;
+    const float nuf = (in && A.nu_mode == NU_FROZEN) ? A.nu_frozen[j] : 1.0f;
     float meanmu = 1.0f;
     if (want_mu) meanmu = (float)(sum_partials(A.part_mu, A.n_part_mu, s_red) / (double)A.n);
-    if (j < A.n) {
+    if (in) {
         float nu = 1.0f;
         if (want_mu) {
-            nu = fminf(A.nu2, fmaxf(A.nu1, meanmu / A.mu[j]));
+            nu = fminf(A.nu2, fmaxf(A.nu1, meanmu / muj));
             if (A.nu_mode == NU_COMPUTE_FREEZE) A.nu_frozen[j] = nu;
         } else if (A.nu_mode == NU_FROZEN) {
-            nu = A.nu_frozen[j];
+            nu = nuf;
         }
-        const float fj = A.f[j];
-        const float S = (fj < 0.5f * A.U) ? fj / A.pnorm[j] : (A.U - fj) / A.pnorm[j];
-        const float ft = fj - A.step * nu * S * A.G[j];
+        const float S = (fj < 0.5f * A.U) ? fj / pj : (A.U - fj) / pj;
+        const float ft = fj - A.step * nu * S * Gj;
         const float fn = (ft <= 0.0f) ? A.t_clip : ((ft >= A.U) ? A.U - A.t_clip : ft);
         A.f[j] = fn;
         part = (double)fn;

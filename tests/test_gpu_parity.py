@@ -371,3 +371,29 @@ def test_invalid_params_rejected(pet):
         G.forward(f.double())
     assert math.isfinite(G.objective(base, f, torch.ones(G.sino_shape, device="cuda"),
                                      torch.ones(G.sino_shape, device="cuda")))
+
+
+def test_c3_full_size(pet, orc):
+    """The fully 3D 200x200x64 / 224 x 281 x 1744-plane / 28-subset workload at
+    full size: one subset's forward and back-projection, then one subiteration
+    from the oracle's state at J = 1 and J = 2 (rel-L2 <= 1e-5 each)."""
+    from synth import configs
+    w, p, _ = configs.c3()
+    d = full_desc(w.desc)
+    G, g = pet.Geometry(d), orc.geom(d)
+    rng = np.random.default_rng(7)
+    f = f32(rng.uniform(0.5, 2.0, G.img_shape))
+    say("C3 forward subset 5")
+    q = host(G.forward(dev(f), 5))
+    qo = orc.forward(g, f, 5)
+    sub = [a for a in range(g.n_angles) if a % g.n_subsets == 4]
+    assert rel(q[:, sub], qo[:, sub]) <= 1e-5
+    del q, qo
+    say("C3 back subset 11")
+    wv = f32(rng.uniform(-1.0, 1.0, G.sino_shape))
+    b = host(G.back(dev(wv), 11))
+    bo = orc.back(g, wv, 11)
+    assert rel(b, bo) <= 1e-5
+    del wv, b, bo
+    say("C3 stepwise J = 1, 2")
+    stepwise(pet, orc, w, p, {1, 2})
