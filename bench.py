@@ -81,6 +81,64 @@ def cpu_baseline(w, p, budget_s=12.0):
                       f"of the same workload from f0, FP64 C oracle, {dt:.1f} s wall"}
 
 
+def bench_batched(args):
+    """96 uneven 2D reconstructions (10 iterations each): one batch, one
+    captured step per subiteration, vs the same requests one at a time."""
+    import torch
+
+    import paper_2111_07886_amd as pet
+    from synth import configs
+
+    specs = configs.c4_specs()
+    reqs = [configs.c4_workload(sp) for sp in specs]
+    dev = torch.device("cuda:0")
+    geoms, ys, rs = [], [], []
+    for w, p, n in reqs:
+        G = pet.Geometry(w.desc)
+        pet.autotune(G)
+        geoms.append(G)
+        ys.append(torch.tensor(w.y, dtype=torch.float32, device=dev))
+        rs.append(torch.tensor(w.r, dtype=torch.float32, device=dev))
+    n_sub = sum(n * w.desc["n_subsets"] for w, _, n in reqs)
+    bytes_total = 0.0
+    for (w, p, n), G in zip(reqs, geoms):
+        M = w.desc["n_subsets"]
+        bytes_total += n * (8.0 * G.nnz(0) + 16.0 * G.n_bins + 32.0 * M * G.n_voxels)
+    params = [p for _, p, _ in reqs]
+    iters = [n for _, _, n in reqs]
+    # warm-up (graph capture, caches)
+    fs = [torch.tensor(w.f0, dtype=torch.float32, device=dev) for w, _, _ in reqs]
+    pet.reconstruct_batch(geoms, params, fs, ys, rs, [1] * len(reqs))
+    fs = [torch.tensor(w.f0, dtype=torch.float32, device=dev) for w, _, _ in reqs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pet.reconstruct_batch(geoms, params, fs, ys, rs, iters)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    fs2 = [torch.tensor(w.f0, dtype=torch.float32, device=dev) for w, _, _ in reqs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for G, p, f, y, r, n in zip(geoms, params, fs2, ys, rs, iters):
+        pet.reconstruct(G, p, f, y, r, n)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    same = all(torch.equal(a, b) for a, b in zip(fs, fs2))
+    out = {"metric": "recons/s", "value": round(len(reqs) / tb, 3), "unit": "recons/s", "n_gpus": 1,
+           "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * tb, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batched: 96 uneven 2D SDP-P2 reconstructions (64..320 px, 60..360 angles, "
+                                  "4..32 subsets, 1e5..1e7 counts), 10 iterations each; step = all 96 to the end",
+                      "subiterations": n_sub, "subiterations_per_s": round(n_sub / tb, 1),
+                      "plain_one_at_a_time_s": round(tp, 4), "plain_recons_per_s": round(len(reqs) / tp, 3),
+                      "speedup_vs_plain": round(tp / tb, 3), "batched_equals_plain_bitwise": same},
+           "roofline": {"bound": "hbm", "achieved": round(bytes_total / tb / 1e9, 2), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(bytes_total / tb / 1e9 / HBM_PEAK_GBS, 5), "traffic": None,
+                        "kernel": "whole batched step (all kernels), algorithmic bytes 8 nnz + 16 rays + 32 q "
+                                  "per subiteration"},
+           "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,7 +146,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4"],
                     help="c2 (default, the benchmark line); c1 / c3 for additional measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (for PMC byte-counter scaling)")
@@ -98,6 +156,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU sharding is "
                                    "described in DESIGN.md and is not measured", "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.workload == "c4":
+        return bench_batched(args)
 
     import numpy as np
     import torch

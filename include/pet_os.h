@@ -202,6 +202,56 @@ int pet_os_state_seek(pet_os_state* state, int64_t k, int32_t i, double t_nest, 
 int pet_os_state_export(const pet_os_state* state, void* buf, size_t* len);
 int pet_os_state_import(pet_os_state* state, const void* buf, size_t len);
 
+/* ------------------------------------------------------------------------
+ * Batched execution: many independent reconstructions of different sizes
+ * advanced together.  Every step advances each active request by one
+ * subiteration (Table I) with one persistent launch per kernel, over a
+ * device-resident work list of (request, block) items; the launch sequence
+ * is captured once in a hipGraph and replayed.  A request computes exactly
+ * what pet_os_reconstruct computes for it alone (same kernels, same
+ * reductions); the FP64 scalar schedule of every subiteration is evaluated on
+ * the host when the request is added.
+ * ------------------------------------------------------------------------ */
+typedef struct pet_os_batch pet_os_batch;
+
+/* A batch with room for max_slots concurrent requests (1..65536). */
+int pet_os_batch_create(int32_t max_slots, pet_os_batch** out);
+/* Waits for the device, frees every slot and the batch. */
+int pet_os_batch_destroy(pet_os_batch* batch);
+
+/* Admit a request: n_iter iterations of SDP-BSREM from f (in/out, device)
+ * with data y, r (device, natural layout) on `geom` (must outlive the slot).
+ * Allocates the request's scratch and schedule, queues sum(f) on `stream`;
+ * synchronises `stream` first (the slot table is read by queued steps).
+ * Errors: INVALID_ARG, BUDGET (no free slot), OUT_OF_MEMORY. */
+int pet_os_batch_add(pet_os_batch* batch, const pet_os_geom* geom, const pet_os_params* params, float* f,
+                     const float* y, const float* r, int32_t n_iter, pet_os_stream stream, int32_t* slot);
+/* Release a slot (synchronises `stream`); its f holds the last iterate. */
+int pet_os_batch_remove(pet_os_batch* batch, int32_t slot, pet_os_stream stream);
+/* Queue n_steps batched subiterations on `stream` (asynchronous). */
+int pet_os_batch_step(pet_os_batch* batch, int32_t n_steps, pet_os_stream stream);
+/* Queue as many steps as the longest active request still needs. */
+int pet_os_batch_run(pet_os_batch* batch, pet_os_stream stream);
+/* Host view of a slot: active (1 while subiterations remain) and the number
+ * of subiterations still to run once the queued steps complete. */
+int pet_os_batch_slot_status(const pet_os_batch* batch, int32_t slot, int32_t* active, int64_t* remaining);
+/* Device bytes held by the batch's slots (scratch and schedules). */
+int pet_os_batch_bytes(const pet_os_batch* batch, size_t* bytes);
+
+/* n requests (arrays of n geometries, parameter sets, f, y, r pointers and
+ * iteration counts) reconstructed in one batch; blocks until done. */
+int pet_os_reconstruct_batch(int32_t n, const pet_os_geom* const* geoms, const pet_os_params* params,
+                             float* const* f, const float* const* y, const float* const* r,
+                             const int32_t* n_iter, pet_os_stream stream);
+
+/* Autotuner: times the forward projector's threads per ray (1, 4, 16, 64) and,
+ * in 2D, the back-projector's tile (16x16, or 8x8 with four angle groups) on
+ * this geometry's first subset and keeps the fastest for all later launches
+ * with this geometry (plain and batched).  flags bit 0: ignore the cache.
+ * When the environment variable PET_OS_TUNE_CACHE names a file, results are
+ * read from / appended to it keyed by the geometry descriptor.  Synchronous. */
+int pet_os_autotune(pet_os_geom* geom, int32_t flags, pet_os_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,7 +28,10 @@ EXPORTS = ["pet_os_last_error", "pet_os_version", "pet_os_create_geometry", "pet
            "pet_os_objective", "pet_os_default_U", "pet_os_state_create", "pet_os_state_destroy",
            "pet_os_state_position", "pet_os_subiteration", "pet_os_reconstruct",
            "pet_os_state_export", "pet_os_state_import", "pet_os_run", "pet_os_state_profile",
-           "pet_os_state_profile_read", "pet_os_nnz", "pet_os_state_seek"]
+           "pet_os_state_profile_read", "pet_os_nnz", "pet_os_state_seek", "pet_os_batch_create",
+           "pet_os_batch_destroy", "pet_os_batch_add", "pet_os_batch_remove", "pet_os_batch_step",
+           "pet_os_batch_run", "pet_os_batch_slot_status", "pet_os_batch_bytes", "pet_os_reconstruct_batch",
+           "pet_os_autotune"]
 
 
 class PetOSError(RuntimeError):
@@ -90,6 +93,17 @@ def lib():
             "pet_os_state_profile_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(i64)]),
             "pet_os_nnz": (C.c_int, [_P, i32, C.POINTER(i64)]),
             "pet_os_state_seek": (C.c_int, [_P, i64, i32, C.c_double, _P]),
+            "pet_os_batch_create": (C.c_int, [i32, C.POINTER(_P)]),
+            "pet_os_batch_destroy": (C.c_int, [_P]),
+            "pet_os_batch_add": (C.c_int, [_P, _P, C.POINTER(Params), _P, _P, _P, i32, _P, C.POINTER(i32)]),
+            "pet_os_batch_remove": (C.c_int, [_P, i32, _P]),
+            "pet_os_batch_step": (C.c_int, [_P, i32, _P]),
+            "pet_os_batch_run": (C.c_int, [_P, _P]),
+            "pet_os_batch_slot_status": (C.c_int, [_P, i32, C.POINTER(i32), C.POINTER(i64)]),
+            "pet_os_batch_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+            "pet_os_reconstruct_batch": (C.c_int, [i32, C.POINTER(_P), C.POINTER(Params), C.POINTER(_P),
+                                                   C.POINTER(_P), C.POINTER(_P), C.POINTER(i32), _P]),
+            "pet_os_autotune": (C.c_int, [_P, i32, _P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -294,3 +308,72 @@ def reconstruct(geom: Geometry, params: dict, f, y, r, n_iter: int, want_objecti
                                     _dev(y, geom.n_bins, "y"), _dev(r, geom.n_bins, "r"), int(n_iter),
                                     obj, _stream(stream)))
     return list(obj) if want_objective else None
+
+
+class Batch:
+    """pet_os_batch: independent reconstructions advanced together, one
+    captured batched subiteration per step."""
+
+    def __init__(self, max_slots: int):
+        h = _P()
+        _check(lib().pet_os_batch_create(int(max_slots), C.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pet_os_batch_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, geom: Geometry, params: dict, f, y, r, n_iter: int, stream=None) -> int:
+        p = params_struct(params)
+        slot = C.c_int32()
+        _check(lib().pet_os_batch_add(self.handle, geom.handle, C.byref(p), _dev(f, geom.n_voxels, "f"),
+                                      _dev(y, geom.n_bins, "y"), _dev(r, geom.n_bins, "r"), int(n_iter),
+                                      _stream(stream), C.byref(slot)))
+        self._keep[slot.value] = (geom, f, y, r)
+        return slot.value
+
+    def remove(self, slot: int, stream=None):
+        _check(lib().pet_os_batch_remove(self.handle, int(slot), _stream(stream)))
+        self._keep.pop(slot, None)
+
+    def step(self, n_steps: int = 1, stream=None):
+        _check(lib().pet_os_batch_step(self.handle, int(n_steps), _stream(stream)))
+
+    def run(self, stream=None):
+        _check(lib().pet_os_batch_run(self.handle, _stream(stream)))
+
+    def status(self, slot: int):
+        a, rem = C.c_int32(), C.c_int64()
+        _check(lib().pet_os_batch_slot_status(self.handle, int(slot), C.byref(a), C.byref(rem)))
+        return bool(a.value), rem.value
+
+    def bytes(self) -> int:
+        n = C.c_size_t()
+        _check(lib().pet_os_batch_bytes(self.handle, C.byref(n)))
+        return n.value
+
+
+def reconstruct_batch(geoms, params, fs, ys, rs, n_iters, stream=None):
+    """pet_os_reconstruct_batch: every request in one batch; blocks until done."""
+    n = len(geoms)
+    G = (_P * n)(*[g.handle for g in geoms])
+    P = (Params * n)(*[params_struct(p) for p in params])
+    F = (_P * n)(*[_dev(f, g.n_voxels, "f") for f, g in zip(fs, geoms)])
+    Y = (_P * n)(*[_dev(y, g.n_bins, "y") for y, g in zip(ys, geoms)])
+    R = (_P * n)(*[_dev(r, g.n_bins, "r") for r, g in zip(rs, geoms)])
+    N = (C.c_int32 * n)(*[int(k) for k in n_iters])
+    _check(lib().pet_os_reconstruct_batch(n, G, P, F, Y, R, N, _stream(stream)))
+
+
+def autotune(geom: Geometry, force=False, stream=None):
+    """pet_os_autotune: pick the projector shapes for this geometry by timing."""
+    _check(lib().pet_os_autotune(geom.handle, 1 if force else 0, _stream(stream)))

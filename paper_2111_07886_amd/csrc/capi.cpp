@@ -156,11 +156,6 @@ struct Carver {
 };
 }  // namespace
 
-struct GeomExtra {
-    int* all_angles;     // [n_angles] 0..Na-1
-    int* subset_lists;   // [M][max_sub]
-    std::vector<int> subset_count;
-};
 
 // The subset lists live inside dev_block right after the tables; keep their
 // offsets in a side table keyed by the geometry.
@@ -169,7 +164,7 @@ struct GeomExtra {
 static std::mutex g_geo_mu;
 static std::map<const pet_os_geom*, GeomExtra> g_geo_extra;
 
-static GeomExtra* extra_of(const pet_os_geom* g) {
+GeomExtra* petos::extra_of(const pet_os_geom* g) {
     std::lock_guard<std::mutex> lk(g_geo_mu);
     auto it = g_geo_extra.find(g);
     return it == g_geo_extra.end() ? nullptr : &it->second;
@@ -258,6 +253,7 @@ int pet_os_create_geometry(const pet_os_geom_desc* desc, pet_os_geom** out) {
     size_t o_id = cv.take<double>(inv_d.size());
     size_t o_all = cv.take<int>(all.size());
     size_t o_lst = cv.take<int>(lists.size());
+    size_t o_cnt = cv.take<int>(counts.size());
     size_t o_pn = cv.take<float>((size_t)G->n_vox);
     size_t o_sn = cv.take<float>((size_t)G->n_vox);
     size_t total = cv.off;
@@ -277,7 +273,8 @@ int pet_os_create_geometry(const pet_os_geom_desc* desc, pet_os_geom** out) {
         up(o_pb, plane_base.data(), plane_base.size() * sizeof(int)) != hipSuccess ||
         up(o_id, inv_d.data(), inv_d.size() * sizeof(double)) != hipSuccess ||
         up(o_all, all.data(), all.size() * sizeof(int)) != hipSuccess ||
-        up(o_lst, lists.data(), lists.size() * sizeof(int)) != hipSuccess) {
+        up(o_lst, lists.data(), lists.size() * sizeof(int)) != hipSuccess ||
+        up(o_cnt, counts.data(), counts.size() * sizeof(int)) != hipSuccess) {
         (void)hipFree(blk);
         delete G;
         return fail(PET_OS_ERR_DEVICE, "upload of geometry tables failed");
@@ -300,6 +297,7 @@ int pet_os_create_geometry(const pet_os_geom_desc* desc, pet_os_geom** out) {
         GeomExtra& e = g_geo_extra[G];
         e.all_angles = (int*)(blk + o_all);
         e.subset_lists = (int*)(blk + o_lst);
+        e.d_subset_count = (int*)(blk + o_cnt);
         e.subset_count = counts;
     }
 
@@ -373,7 +371,7 @@ int work_alloc(const pet_os_geom* g, bool need_nu, Work* w) {
     size_t o_nu = need_nu ? cv.take<float>(nv) : 0;
     int caps[RED_COUNT];
     caps[RED_SUMF] = elem_grid(g->n_vox);
-    caps[RED_SUMMU] = bp_grid(g);
+    caps[RED_SUMMU] = bp_grid_max(g);
     caps[RED_FID] = fp_grid(g, g->d.n_angles);
     caps[RED_RDP] = elem_grid(g->n_vox);
     caps[RED_SUMY] = elem_grid(g->n_bins);
@@ -411,24 +409,10 @@ void work_free(Work* w) {
 
 // ---------------------------------------------------------------- state
 
-struct pet_os_state {
-    const pet_os_geom* g;
-    pet_os_params p;
-    int64_t k;
-    int32_t i;
-    double t_nest;
-    int have_frozen;
-    Work w;
-    double* obj_dev = nullptr;          // (fid, R) pairs of queued objective evaluations
-    int obj_cap = 0;
-    int prof_kernel = -1;               // kernel bracketed by events, -1 = none
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
-    size_t prof_used = 0;
-};
 
 namespace petos {
 
-static int validate_params(const pet_os_params* p, const pet_os_geom* g) {
+int validate_params(const pet_os_params* p, const pet_os_geom* g) {
     if (!p) return fail(PET_OS_ERR_INVALID_ARG, "params is NULL");
     if (p->mode < PET_OS_BSREM || p->mode > PET_OS_P2) return fail(PET_OS_ERR_INVALID_ARG, "unknown mode");
     if (!(std::isfinite(p->beta) && p->beta >= 0.0)) return fail(PET_OS_ERR_INVALID_ARG, "beta must be >= 0");
@@ -451,24 +435,19 @@ static int validate_params(const pet_os_params* p, const pet_os_geom* g) {
     return PET_OS_OK;
 }
 
-// FP64 scalar schedule of subiteration (k, i); advances the Nesterov t.
-struct Sched {
-    double lam, alpha;
-    int nu_mode;
-};
-
-static Sched schedule_step(pet_os_state* st) {
-    const pet_os_params& p = st->p;
-    const int M = st->g->d.n_subsets;
-    const int64_t J = st->k * (int64_t)M + st->i;
+// FP64 scalar schedule of subiteration (k, i): lambda_k (thm:SpecificSDPs),
+// alpha_{k,i} (preconditioner:Nesterov / preconditioner:KM) and the nu mode
+// of eq:nuki; advances the Nesterov t.
+Sched sched_next(const pet_os_params& p, int M, int64_t k, int i, double* t_nest, int have_frozen) {
+    const int64_t J = k * (int64_t)M + i;
     Sched s;
-    s.lam = p.lambda0 / (p.a * (double)st->k + 1.0);
+    s.lam = p.lambda0 / (p.a * (double)k + 1.0);
     s.alpha = 1.0;
     if (p.mode == PET_OS_M1 || p.mode == PET_OS_P1) {
-        double t = st->t_nest;
+        double t = *t_nest;
         double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
         s.alpha = 1.0 + (t - 1.0) / tn;
-        st->t_nest = tn;
+        *t_nest = tn;
     } else if (p.mode == PET_OS_M2 || p.mode == PET_OS_P2) {
         double n = (double)(J - 1);
         s.alpha = (p.rho * n + p.delta2) / (n + p.delta1);
@@ -478,9 +457,28 @@ static Sched schedule_step(pet_os_state* st) {
         if (J <= p.J0) s.nu_mode = NU_ONE;
         else if (J < p.J1) s.nu_mode = NU_COMPUTE;
         else if (J == p.J1) s.nu_mode = NU_COMPUTE_FREEZE;
-        else s.nu_mode = st->have_frozen ? NU_FROZEN : NU_ONE;
+        else s.nu_mode = have_frozen ? NU_FROZEN : NU_ONE;
     }
     return s;
+}
+
+void schedule_table(const pet_os_params& p, int M, int64_t n_sub, std::vector<float>& step, std::vector<int>& nu) {
+    step.resize((size_t)n_sub);
+    nu.resize((size_t)n_sub);
+    double t = 1.0;
+    int have = 0;
+    for (int64_t J = 1; J <= n_sub; ++J) {
+        const int64_t k = (J - 1) / M;
+        const int i = (int)((J - 1) % M) + 1;
+        Sched sc = sched_next(p, M, k, i, &t, have);
+        step[(size_t)(J - 1)] = (float)(sc.lam * sc.alpha);
+        nu[(size_t)(J - 1)] = sc.nu_mode;
+        if (sc.nu_mode == NU_COMPUTE_FREEZE) have = 1;
+    }
+}
+
+static Sched schedule_step(pet_os_state* st) {
+    return sched_next(st->p, st->g->d.n_subsets, st->k, st->i, &st->t_nest, st->have_frozen);
 }
 
 // events around launches of the profiled kernel
@@ -521,6 +519,8 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
     const int n_al = ex->subset_count[st->i - 1];
     FPLaunch F{};
     F.f = f; F.y = y; F.r = r; F.out = st->w.w; F.angles = angles; F.n_al = n_al; F.mode = FP_RATIO;
+    // threads per ray chosen for the largest subset, as the batched path does
+    F.seg = fp_seg_for(g, (long long)g->max_sub_angles * g->n_planes * g->d.n_radial, g->tuned_seg);
     hipEvent_t ev;
     if ((rc = prof_begin(st, 0, s, &ev))) return rc;
     rc = launch_fp(g, F, s);

@@ -51,6 +51,8 @@ struct pet_os_geom {
     float* sens;                        // A^T 1 (device, n_vox)
     double sens_sum;                    // sum_j (A^T 1)_j
     int device;
+    int tuned_seg = 0;                  // forward-projector segments per ray (0: heuristic)
+    int tuned_bp_kind = -1;             // back-projector tile kind (-1: heuristic)
     std::vector<int> subset_angles(int subset) const;   // subset in 1..M, 0 = all
 };
 
@@ -72,18 +74,38 @@ struct Work {
 int work_alloc(const pet_os_geom* g, bool need_nu, Work* w);
 void work_free(Work* w);
 
+// device angle lists of a geometry
+struct GeomExtra {
+    int* all_angles;     // [n_angles] 0..Na-1
+    int* subset_lists;   // [M][max_sub]
+    int* d_subset_count; // [M]
+    std::vector<int> subset_count;
+};
+GeomExtra* extra_of(const pet_os_geom* g);
+
+// FP64 scalar schedule
+struct Sched {
+    double lam, alpha;
+    int nu_mode;
+};
+Sched sched_next(const pet_os_params& p, int M, int64_t k, int i, double* t_nest, int have_frozen);
+// (float)(lambda alpha) and nu mode of subiterations J = 1..n_sub from the start
+void schedule_table(const pet_os_params& p, int M, int64_t n_sub, std::vector<float>& step, std::vector<int>& nu);
+int validate_params(const pet_os_params* p, const pet_os_geom* g);
+
 // ---------------------------------------------------------------- launchers (kernels.hip)
-enum FPMode { FP_RATIO = 0, FP_PLAIN = 1, FP_OBJECTIVE = 2, FP_COUNT = 3 };
+enum FPMode { FP_RATIO = 0, FP_PLAIN = 1, FP_OBJECTIVE = 2, FP_COUNT = 3, FP_COMPACT = 4 };
 
 struct FPLaunch {
     const float* f;
     const float* y;
     const float* r;
-    float* out;              // FP_RATIO, FP_COUNT: compact [al][plane][b]; FP_PLAIN: natural q
+    float* out;              // FP_RATIO, FP_COUNT, FP_COMPACT: compact [al][plane][b]; FP_PLAIN: natural q
     const int* angles;       // device list of natural angle indices for this pass
     int n_al;                // number of angles
     int mode;
     Reduction red;           // FP_OBJECTIVE
+    int seg = 0;             // threads per ray (0: tuned or heuristic)
 };
 int launch_fp(const pet_os_geom* g, const FPLaunch& L, hipStream_t s);
 
@@ -129,8 +151,71 @@ int launch_fill(float* x, int64_t n, float v, hipStream_t s);
 int launch_finalize(Reduction red, int n, hipStream_t s);
 
 // grid sizes (for sizing partial arrays)
+int fp_seg_for(const pet_os_geom* g, long long nrays, int requested);
+int fp_grid_seg(const pet_os_geom* g, int n_al, int seg);
 int fp_grid(const pet_os_geom* g, int n_al);
+int bp_kind_of(const pet_os_geom* g);
+int bp_grid_kind(const pet_os_geom* g, int kind);
 int bp_grid(const pet_os_geom* g);
+int bp_grid_max(const pet_os_geom* g);
 int elem_grid(int64_t n);
+void bp_stage_shape_kind(const pet_os_geom* G, int kind, int& nb_max, int& rows_max, int& chunk, size_t& lds);
+size_t bp_lds_budget(int kind);
+
+// ---------------------------------------------------------------- batched execution
+// One reconstruction request inside a batch, as the batched kernels see it.
+struct SlotDev {
+    GeoK g;
+    const float* pnorm;
+    float* f;
+    const float* y;
+    const float* r;
+    float* w;
+    float* G;
+    float* mu;
+    float* nu_frozen;
+    double* part_f;
+    double* part_mu;
+    int n_part_f, n_part_mu;
+    const int* subset_lists;
+    const int* subset_count;
+    int max_sub;
+    const float* sched_step;   // [J_end] lambda_k alpha_{k,i} of subiteration J (index J-1)
+    const int* sched_nu;       // [J_end] nu mode of subiteration J
+    int J, J_end;              // next subiteration (device-advanced), last one
+    float beta_over_M, gamma_R, eps, nu1, nu2, U, t_clip;
+    int fp_seg, bp_kind;
+    int nb_max, rows_max, chunk;
+    int active;
+};
+
+struct Item {
+    int slot;
+    int block;
+};
+
+enum { WL_FP = 0, WL_BP0 = 1, WL_BP1 = 2, WL_BP2 = 3, WL_UPD = 4, WL_COUNT = 5 };
+
+// Queue one batched subiteration (every active slot advances by one):
+// forward, back-projection (one launch per tile kind), update, advance.
+int launch_batch_step(SlotDev* d_slots, int n_slots, Item* const lists[WL_COUNT], const int* d_counts,
+                      const int grids[WL_COUNT], hipStream_t s);
 
 }  // namespace petos
+
+// per-request state of the plain path
+struct pet_os_state {
+    const pet_os_geom* g;
+    pet_os_params p;
+    int64_t k;
+    int32_t i;
+    double t_nest;
+    int have_frozen;
+    petos::Work w;
+    double* obj_dev = nullptr;          // (fid, R) pairs of queued objective evaluations
+    int obj_cap = 0;
+    int prof_kernel = -1;               // kernel bracketed by events, -1 = none
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+    size_t prof_used = 0;
+};
+

@@ -44,10 +44,10 @@ __device__ double block_sum(double v, double* sh /* >= NT/64 */) {
     return t;
 }
 
-// Every thread must call: the block's sum of v goes to R.part[blockIdx.x].
-__device__ __forceinline__ void write_partial(double v, Reduction R, double* sh) {
+// Every thread must call: the block's sum of v goes to R.part[vblock].
+__device__ __forceinline__ void write_partial(double v, Reduction R, double* sh, long long vblock) {
     double bs = block_sum(v, sh);
-    if (threadIdx.x == 0) R.part[blockIdx.x] = bs;
+    if (threadIdx.x == 0) R.part[vblock] = bs;
 }
 
 // Sum of part[0..n) in index-strided order, the same in every block; the
@@ -86,7 +86,7 @@ struct FPArgs {
 // With SEG > 1 the SEG threads of a ray are adjacent lanes of one wave and
 // their partial sums are added by a fixed shuffle tree.
 template <int DIM, int SEG>
-__global__ __launch_bounds__(NT) void k_fp(GeoK g, FPArgs A) {
+__device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
     static_assert(SEG == 1 || (64 % SEG == 0), "segments of a ray stay in one wave");
     constexpr int RPB = NT / SEG;
     __shared__ double s_red[NT / 64];
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(NT) void k_fp(GeoK g, FPArgs A) {
     const int seg = (SEG == 1) ? 0 : threadIdx.x % SEG;
     const int P = g.n_planes, Nr = g.n_radial;
     const long long nrays = (long long)A.n_al * P * Nr;
-    const long long ray = (long long)blockIdx.x * RPB + lr;
+    const long long ray = vblock * RPB + lr;
     const bool valid = ray < nrays;
 
     float acc = 0.0f;
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(NT) void k_fp(GeoK g, FPArgs A) {
         if (A.mode == FP_RATIO) {
             float q = acc;
             A.out[ray] = 1.0f - A.y[nat] / (q + A.r[nat]);
-        } else if (A.mode == FP_COUNT) {
+        } else if (A.mode == FP_COUNT || A.mode == FP_COMPACT) {
             A.out[ray] = acc;
         } else if (A.mode == FP_PLAIN) {
             A.out[nat] = acc;
@@ -193,7 +193,12 @@ __global__ __launch_bounds__(NT) void k_fp(GeoK g, FPArgs A) {
             term = q - (double)A.y[nat] * log(q + (double)A.r[nat]);
         }
     }
-    if (A.mode == FP_OBJECTIVE) write_partial(term, A.red, s_red);
+    if (A.mode == FP_OBJECTIVE) write_partial(term, A.red, s_red, vblock);
+}
+
+template <int DIM, int SEG>
+__global__ __launch_bounds__(NT) void k_fp(GeoK g, FPArgs A) {
+    fp_body<DIM, SEG>(g, A, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ back projection
@@ -276,7 +281,7 @@ __device__ __forceinline__ void stencil_at(const float* sf, int HX, int HY, int 
 }
 
 template <class T>
-__global__ __launch_bounds__(NT) void k_bp(GeoK g, BPArgs A) {
+__device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
     constexpr int DIM = T::D;
     constexpr int NV = T::X * T::Y * T::Z;          // voxels per tile
     constexpr int HX = T::X + 2, HY = T::Y + 2, HZ = (DIM == 3) ? T::Z + 2 : 1;
@@ -295,7 +300,7 @@ __global__ __launch_bounds__(NT) void k_bp(GeoK g, BPArgs A) {
 
     const int tiles_x = (g.nx + T::X - 1) / T::X;
     const int tiles_y = (g.ny + T::Y - 1) / T::Y;
-    int t = blockIdx.x;
+    int t = vblock;
     const int tx0 = (t % tiles_x) * T::X;
     t /= tiles_x;
     const int ty0 = (t % tiles_y) * T::Y;
@@ -531,7 +536,12 @@ __global__ __launch_bounds__(NT) void k_bp(GeoK g, BPArgs A) {
             mu_part = (double)mu;
         }
     }
-    if (A.want_mu) write_partial(mu_part, A.red_mu, s_red);
+    if (A.want_mu) write_partial(mu_part, A.red_mu, s_red, vblock);
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_bp(GeoK g, BPArgs A) {
+    bp_body<T>(g, A, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ update
@@ -550,9 +560,9 @@ struct UpdArgs {
     long long n;
 };
 
-__global__ __launch_bounds__(NT) void k_update(UpdArgs A) {
+__device__ void upd_body(const UpdArgs& A, long long vblock) {
     __shared__ double s_red[NT / 64];
-    const long long j = (long long)blockIdx.x * NT + threadIdx.x;
+    const long long j = vblock * NT + threadIdx.x;
     double part = 0.0;
     const bool want_mu = A.nu_mode == NU_COMPUTE || A.nu_mode == NU_COMPUTE_FREEZE;
     const bool in = j < A.n;
@@ -578,13 +588,19 @@ __global__ __launch_bounds__(NT) void k_update(UpdArgs A) {
         A.f[j] = fn;
         part = (double)fn;
     }
-    write_partial(part, A.red_f, s_red);
+    write_partial(part, A.red_f, s_red, vblock);
+}
+
+__global__ __launch_bounds__(NT) void k_update(UpdArgs A) { upd_body(A, blockIdx.x); }
+
+__device__ void sum_body(const float* x, long long n, Reduction R, long long vblock) {
+    __shared__ double s_red[NT / 64];
+    const long long j = vblock * NT + threadIdx.x;
+    write_partial(j < n ? (double)x[j] : 0.0, R, s_red, vblock);
 }
 
 __global__ __launch_bounds__(NT) void k_sum(const float* x, long long n, Reduction R) {
-    __shared__ double s_red[NT / 64];
-    const long long j = (long long)blockIdx.x * NT + threadIdx.x;
-    write_partial(j < n ? (double)x[j] : 0.0, R, s_red);
+    sum_body(x, n, R, blockIdx.x);
 }
 
 __global__ __launch_bounds__(NT) void k_fill(float* x, long long n, float v) {
@@ -618,28 +634,40 @@ __global__ __launch_bounds__(NT) void k_rdp(GeoK g, const float* f, float gR, fl
             }
         }
     }
-    write_partial(v, R, s_red);
+    write_partial(v, R, s_red, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ launchers
 
 // threads per ray: enough rays x segments to fill the chip (~2^18 threads)
-static int fp_seg(long long nrays) {
+static int fp_seg_heuristic(long long nrays) {
     const long long target = 1LL << 18;
     if (nrays * 4 > target) return nrays >= target ? 1 : 4;
     if (nrays * 16 > target) return 16;
     return 64;
 }
 
-int fp_grid(const pet_os_geom* G, int n_al) {
+int fp_seg_for(const pet_os_geom* G, long long nrays, int requested) {
+    if (requested > 0) return requested;
+    (void)G;
+    return fp_seg_heuristic(nrays);
+}
+
+int fp_grid_seg(const pet_os_geom* G, int n_al, int seg) {
     long long nrays = (long long)n_al * G->n_planes * G->d.n_radial;
-    int rpb = NT / fp_seg(nrays);
+    int rpb = NT / seg;
     return (int)((nrays + rpb - 1) / rpb);
 }
 
+int fp_grid(const pet_os_geom* G, int n_al) {
+    long long nrays = (long long)n_al * G->n_planes * G->d.n_radial;
+    return fp_grid_seg(G, n_al, fp_seg_heuristic(nrays));
+}
+
 // 0: Tile2L, 1: Tile2S, 2: Tile3
-static int bp_kind(const pet_os_geom* G) {
+int bp_kind_of(const pet_os_geom* G) {
     if (G->d.dim == 3) return 2;
+    if (G->tuned_bp_kind >= 0) return G->tuned_bp_kind;
     long long tiles16 = (long long)((G->d.nx + 15) / 16) * ((G->d.ny + 15) / 16);
     return tiles16 < 1024 ? 1 : 0;
 }
@@ -650,10 +678,17 @@ static void bp_tile(int kind, int& TX, int& TY, int& TZ) {
     TZ = kind == 2 ? 4 : 1;
 }
 
-int bp_grid(const pet_os_geom* G) {
+int bp_grid_kind(const pet_os_geom* G, int kind) {
     int TX, TY, TZ;
-    bp_tile(bp_kind(G), TX, TY, TZ);
+    bp_tile(kind, TX, TY, TZ);
     return ((G->d.nx + TX - 1) / TX) * ((G->d.ny + TY - 1) / TY) * ((G->d.nz + TZ - 1) / TZ);
+}
+
+int bp_grid(const pet_os_geom* G) { return bp_grid_kind(G, bp_kind_of(G)); }
+
+int bp_grid_max(const pet_os_geom* G) {
+    if (G->d.dim == 3) return bp_grid_kind(G, 2);
+    return std::max(bp_grid_kind(G, 0), bp_grid_kind(G, 1));
 }
 
 int elem_grid(int64_t n) { return (int)((n + NT - 1) / NT); }
@@ -675,8 +710,8 @@ int launch_fp(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
     a.red = L.red;
     long long nrays = (long long)L.n_al * G->n_planes * G->d.n_radial;
     if (nrays == 0) return PET_OS_OK;
-    int seg = fp_seg(nrays);
-    int grid = fp_grid(G, L.n_al);
+    int seg = fp_seg_for(G, nrays, L.seg);
+    int grid = fp_grid_seg(G, L.n_al, seg);
     if (L.mode == FP_OBJECTIVE && grid > L.red.cap) return fail(PET_OS_ERR_DEVICE, "objective partials too small");
     const bool d3 = G->d.dim == 3;
     if (seg == 64) { if (d3) fp_launch_t<3, 64>(G->k, a, grid, s); else fp_launch_t<2, 64>(G->k, a, grid, s); }
@@ -687,11 +722,13 @@ int launch_fp(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
     return PET_OS_OK;
 }
 
+size_t bp_lds_budget(int kind) { return (kind == 2 ? 12288 : 4096) * sizeof(float); }
+
 // LDS footprint bounds of a back-projection tile (host side, conservative)
-static void bp_stage_shape(const pet_os_geom* G, int& nb_max, int& rows_max, int& chunk, size_t& lds) {
+void bp_stage_shape_kind(const pet_os_geom* G, int kind, int& nb_max, int& rows_max, int& chunk, size_t& lds) {
     const auto& d = G->d;
     int TX, TY, TZ;
-    bp_tile(bp_kind(G), TX, TY, TZ);
+    bp_tile(kind, TX, TY, TZ);
     nb_max = (int)std::ceil((TX * d.vx + TY * d.vy) / d.ds) + 4;
     if (nb_max > d.n_radial) nb_max = d.n_radial;
     if (d.dim == 2) {
@@ -707,7 +744,7 @@ static void bp_stage_shape(const pet_os_geom* G, int& nb_max, int& rows_max, int
             rows += std::min(d.n_rings, TZ + 3 + (int)std::ceil(std::abs(dd) * dtau));
         rows_max = rows;
     }
-    const size_t budget_floats = d.dim == 2 ? 4096 : 12288;
+    const size_t budget_floats = bp_lds_budget(kind) / sizeof(float);
     if ((size_t)nb_max * rows_max > budget_floats) rows_max = (int)(budget_floats / nb_max);
     size_t slot = (size_t)nb_max * rows_max;
     chunk = (int)std::max<size_t>(1, budget_floats / slot);
@@ -743,11 +780,12 @@ int launch_bp(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
     a.n_part_f = L.n_part_f;
     a.red_mu = L.red_mu;
     size_t lds;
-    bp_stage_shape(G, a.nb_max, a.rows_max, a.chunk, lds);
+    const int kind = bp_kind_of(G);
+    bp_stage_shape_kind(G, kind, a.nb_max, a.rows_max, a.chunk, lds);
     if (L.w == nullptr) lds = 0;
     int grid = bp_grid(G);
     if (L.want_mu && grid > L.red_mu.cap) return fail(PET_OS_ERR_DEVICE, "mu partials too small");
-    switch (bp_kind(G)) {
+    switch (kind) {
         case 0: hipLaunchKernelGGL((k_bp<Tile2L>), dim3(grid), dim3(NT), lds, s, G->k, a); break;
         case 1: hipLaunchKernelGGL((k_bp<Tile2S>), dim3(grid), dim3(NT), lds, s, G->k, a); break;
         default: hipLaunchKernelGGL((k_bp<Tile3>), dim3(grid), dim3(NT), lds, s, G->k, a); break;
@@ -810,6 +848,130 @@ int launch_rdp_value(const pet_os_geom* G, const float* f, float gamma_R, float 
         hipLaunchKernelGGL((k_rdp<3>), dim3(grid), dim3(NT), 0, s, G->k, f, gamma_R, eps, red);
     else
         hipLaunchKernelGGL((k_rdp<2>), dim3(grid), dim3(NT), 0, s, G->k, f, gamma_R, eps, red);
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
+}
+
+// ------------------------------------------------------------------ batched (persistent) kernels
+// Every block walks a device-resident work list of (slot, block) items with a
+// grid stride; the lists, their lengths and the slot table live in device
+// memory, so one captured graph stays valid while requests come and go.
+
+__device__ __forceinline__ bool slot_live(const SlotDev& d) { return d.active && d.J <= d.J_end; }
+
+template <int DIM>
+__device__ void fp_dispatch(const GeoK& g, const FPArgs& A, int seg, long long vblock) {
+    switch (seg) {
+        case 64: fp_body<DIM, 64>(g, A, vblock); break;
+        case 16: fp_body<DIM, 16>(g, A, vblock); break;
+        case 4: fp_body<DIM, 4>(g, A, vblock); break;
+        default: fp_body<DIM, 1>(g, A, vblock); break;
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_fp_batch(const SlotDev* S, const Item* items, const int* count) {
+    const int n = *count;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const Item I = items[it];
+        const SlotDev& d = S[I.slot];
+        if (!slot_live(d)) continue;
+        const int i = (d.J - 1) % d.g.n_subsets;
+        FPArgs A{};
+        A.f = d.f;
+        A.y = d.y;
+        A.r = d.r;
+        A.out = d.w;
+        A.angles = d.subset_lists + (long long)i * d.max_sub;
+        A.n_al = d.subset_count[i];
+        A.mode = FP_RATIO;
+        if (d.g.dim == 3) fp_dispatch<3>(d.g, A, d.fp_seg, I.block);
+        else fp_dispatch<2>(d.g, A, d.fp_seg, I.block);
+        __syncthreads();
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_bp_batch(const SlotDev* S, const Item* items, const int* count) {
+    const int n = *count;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const Item I = items[it];
+        const SlotDev& d = S[I.slot];
+        if (!slot_live(d)) continue;
+        const int i = (d.J - 1) % d.g.n_subsets;
+        const int nu_mode = d.sched_nu[d.J - 1];
+        BPArgs A{};
+        A.w = d.w;
+        A.w_natural = 0;
+        A.w_sp = d.g.n_radial;
+        A.w_sa = (long long)d.g.n_planes * d.g.n_radial;
+        A.angles = d.subset_lists + (long long)i * d.max_sub;
+        A.n_al = d.subset_count[i];
+        A.out = d.G;
+        A.f = d.f;
+        A.mu = d.mu;
+        A.want_mu = (nu_mode == NU_COMPUTE || nu_mode == NU_COMPUTE_FREEZE) ? 1 : 0;
+        A.beta_over_M = d.beta_over_M;
+        A.gamma_R = d.gamma_R;
+        A.eps = d.eps;
+        A.part_f = d.part_f;
+        A.n_part_f = d.n_part_f;
+        A.red_mu.part = d.part_mu;
+        A.red_mu.total = nullptr;
+        A.red_mu.cap = d.n_part_mu;
+        A.nb_max = d.nb_max;
+        A.rows_max = d.rows_max;
+        A.chunk = d.chunk;
+        bp_body<T>(d.g, A, I.block);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_upd_batch(const SlotDev* S, const Item* items, const int* count) {
+    const int n = *count;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const Item I = items[it];
+        const SlotDev& d = S[I.slot];
+        if (!slot_live(d)) continue;
+        UpdArgs A{};
+        A.f = d.f;
+        A.G = d.G;
+        A.mu = d.mu;
+        A.pnorm = d.pnorm;
+        A.nu_frozen = d.nu_frozen;
+        A.nu_mode = d.sched_nu[d.J - 1];
+        A.step = d.sched_step[d.J - 1];
+        A.nu1 = d.nu1;
+        A.nu2 = d.nu2;
+        A.U = d.U;
+        A.t_clip = d.t_clip;
+        A.part_mu = d.part_mu;
+        A.n_part_mu = d.n_part_mu;
+        A.red_f.part = d.part_f;
+        A.red_f.total = nullptr;
+        A.red_f.cap = d.n_part_f;
+        A.n = d.g.nvox;
+        upd_body(A, I.block);
+        __syncthreads();
+    }
+}
+
+// J += 1 for every live slot (one thread per slot, after the update)
+__global__ __launch_bounds__(NT) void k_advance(SlotDev* S, int n_slots) {
+    const int sidx = blockIdx.x * NT + threadIdx.x;
+    if (sidx < n_slots && S[sidx].active && S[sidx].J <= S[sidx].J_end) S[sidx].J += 1;
+}
+
+int launch_batch_step(SlotDev* d_slots, int n_slots, Item* const lists[WL_COUNT], const int* d_counts,
+                      const int grids[WL_COUNT], hipStream_t s) {
+    hipLaunchKernelGGL(k_fp_batch, dim3(grids[WL_FP]), dim3(NT), 0, s, d_slots, lists[WL_FP], d_counts + WL_FP);
+    hipLaunchKernelGGL((k_bp_batch<Tile2L>), dim3(grids[WL_BP0]), dim3(NT), bp_lds_budget(0), s, d_slots,
+                       lists[WL_BP0], d_counts + WL_BP0);
+    hipLaunchKernelGGL((k_bp_batch<Tile2S>), dim3(grids[WL_BP1]), dim3(NT), bp_lds_budget(1), s, d_slots,
+                       lists[WL_BP1], d_counts + WL_BP1);
+    hipLaunchKernelGGL((k_bp_batch<Tile3>), dim3(grids[WL_BP2]), dim3(NT), bp_lds_budget(2), s, d_slots,
+                       lists[WL_BP2], d_counts + WL_BP2);
+    hipLaunchKernelGGL(k_upd_batch, dim3(grids[WL_UPD]), dim3(NT), 0, s, d_slots, lists[WL_UPD], d_counts + WL_UPD);
+    hipLaunchKernelGGL(k_advance, dim3((n_slots + NT - 1) / NT), dim3(NT), 0, s, d_slots, n_slots);
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;
 }
