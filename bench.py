@@ -139,6 +139,96 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_served(args):
+    """Poisson arrivals (200 req/s) of 2D (128..320 px) and 3D (128x128x32)
+    requests, 30 iterations each: the continuous-batching server vs the same
+    trace served one request at a time (FIFO) by pet_os_reconstruct."""
+    import numpy as np
+    import torch
+
+    import paper_2111_07886_amd as pet
+    from synth import configs, phantoms
+
+    trace = configs.c5_trace(n_requests=args.requests)
+    dev = torch.device("cuda:0")
+    reqs = []
+    for q in trace:
+        d = q["desc"]
+        if d["dim"] == 3:
+            w = phantoms.make_3d(d, seed=q["seed"], n_ell=11, counts=q["counts"], bg_uniform=0.1, bg_scatter=0.1)
+            p = configs.params_3d(U=w.U)
+        else:
+            w = phantoms.make_2d(d, seed=q["seed"], n_ell=8, counts=q["counts"], bg_frac=0.2)
+            p = configs.params_2d(d["n_subsets"], q["counts"], U=w.U)
+        y = torch.tensor(w.y, dtype=torch.float32, device=dev)
+        r = torch.tensor(w.r, dtype=torch.float32, device=dev)
+        f0 = torch.tensor(w.f0, dtype=torch.float32, device=dev)
+        reqs.append((w.desc, p, q["n_iter"], q["arrival_s"], f0, y, r))
+    # geometry caches warm in both paths: every distinct geometry once
+    keys = {}
+    for desc, p, n, at, f0, y, r in reqs:
+        keys.setdefault(json.dumps(desc, sort_keys=True), (desc, p, f0, y, r))
+    S = pet.Server(64 << 30, 128)
+    for desc, p, f0, y, r in keys.values():
+        S.wait(S.submit(desc, p, f0.clone(), y, r, 1))
+    plain_geoms = {}
+    for k, (desc, p, f0, y, r) in keys.items():
+        G = pet.Geometry(desc)
+        pet.autotune(G)
+        plain_geoms[k] = G
+    torch.cuda.synchronize()
+
+    def pct(v, q):
+        return float(np.percentile(np.asarray(v), q))
+
+    # served
+    fs = [f0.clone() for *_, f0, y, r in reqs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = []
+    for (desc, p, n, at, f0, y, r), f in zip(reqs, fs):
+        dt = at - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(S.submit(desc, p, f, y, r, n))
+    res = [S.wait(t) for t in tickets]
+    st = S.stats()
+    S.close()
+    lat_s = [r_["t_finish"] - r_["t_submit"] for r_ in res]
+    span_s = max(r_["t_finish"] for r_ in res) - min(r_["t_submit"] for r_ in res)
+    ok = sum(r_["status"] == 0 for r_ in res)
+    # plain: one at a time, arrival order, same arrival times
+    fs2 = [f0.clone() for *_, f0, y, r in reqs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat_p, fin = [], []
+    for (desc, p, n, at, f0, y, r), f in zip(reqs, fs2):
+        dt = at - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        pet.reconstruct(plain_geoms[json.dumps(desc, sort_keys=True)], p, f, y, r, n)
+        torch.cuda.synchronize()
+        now = time.perf_counter() - t0
+        lat_p.append(now - at)
+        fin.append(now)
+    span_p = fin[-1] - reqs[0][3]
+    same = sum(torch.equal(a, b) for a, b in zip(fs, fs2))
+    n = len(reqs)
+    out = {"metric": "served recons/s", "value": round(n / span_s, 3), "unit": "recons/s", "n_gpus": 1,
+           "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * span_s, 2), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"served: {n} requests, Poisson arrivals at 200/s, 98% 2D (128..320 px) / "
+                                  f"2% 3D (128x128x32, 180x185x424 planes), 30 iterations each",
+                      "completed": ok, "p50_latency_ms": round(1e3 * pct(lat_s, 50), 2),
+                      "p99_latency_ms": round(1e3 * pct(lat_s, 99), 2), "max_active": st["max_active"],
+                      "plain_recons_per_s": round(n / span_p, 3),
+                      "plain_p50_latency_ms": round(1e3 * pct(lat_p, 50), 2),
+                      "plain_p99_latency_ms": round(1e3 * pct(lat_p, 99), 2),
+                      "results_equal_to_plain": f"{same}/{n}"},
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,8 +236,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5"],
                     help="c2 (default, the benchmark line); c1 / c3 for additional measurements")
+    ap.add_argument("--requests", type=int, default=400, help="c5: requests taken from the arrival trace")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (for PMC byte-counter scaling)")
     args = ap.parse_args()
@@ -159,6 +250,8 @@ def main():
 
     if args.workload == "c4":
         return bench_batched(args)
+    if args.workload == "c5":
+        return bench_served(args)
 
     import numpy as np
     import torch

@@ -252,6 +252,67 @@ int pet_os_reconstruct_batch(int32_t n, const pet_os_geom* const* geoms, const p
  * read from / appended to it keyed by the geometry descriptor.  Synchronous. */
 int pet_os_autotune(pet_os_geom* geom, int32_t flags, pet_os_stream stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of reconstruction requests.  A worker thread
+ * admits queued requests in arrival order whenever a batch slot is free and
+ * the device memory they need (scratch, schedule, and their geometry if not
+ * cached) fits the budget; admitted requests join the running batch between
+ * two batched subiterations and leave it as soon as they finish.  Geometries
+ * (tables, sensitivity, autotuned shapes) are cached by descriptor and
+ * counted against the budget; unused ones are evicted first.  The caller's
+ * f, y, r buffers are not counted.
+ * ------------------------------------------------------------------------ */
+typedef struct pet_os_server pet_os_server;
+
+typedef struct {
+    pet_os_geom_desc desc;     /* geometry of the request */
+    pet_os_params params;      /* algorithm parameters (validated at submit) */
+    float* f;                  /* DEVICE: f0 in, result out; valid until the ticket completes */
+    const float* y;            /* DEVICE counts, natural layout */
+    const float* r;            /* DEVICE background, natural layout */
+    int32_t n_iter;            /* iterations (>= 1) */
+    int32_t want_objective;    /* nonzero: Phi(f) after the last iteration in the result */
+} pet_os_request;
+
+typedef struct {
+    int32_t status;            /* PET_OS_OK or an error code (BUDGET, NUMERIC, DEVICE, TIMEOUT = cancelled) */
+    int32_t pad;
+    double objective;          /* Phi of the result, NaN if not requested */
+    double t_submit, t_admit, t_start, t_finish;   /* seconds since the server was created */
+    int64_t subiterations;     /* subiterations run */
+    char message[128];         /* reason when status != PET_OS_OK */
+} pet_os_result;
+
+typedef struct {
+    int64_t queued, active, ticks, max_active;
+    size_t bytes_in_use;
+    int64_t geometries_cached;
+} pet_os_server_stats_t;
+
+/* A server on the current device with its own stream; hbm_budget_bytes caps
+ * the device memory it allocates, max_slots the concurrent requests. */
+int pet_os_server_create(size_t hbm_budget_bytes, int32_t max_slots, pet_os_server** out);
+/* Finishes every queued and running request, then stops. */
+int pet_os_server_destroy(pet_os_server* server);
+/* Queue a request; returns at once with a ticket.  Invalid descriptors,
+ * parameters or pointers are rejected synchronously (INVALID_ARG). */
+int pet_os_submit(pet_os_server* server, const pet_os_request* req, uint64_t* ticket);
+/* Wait up to timeout_us (< 0: forever) for a ticket; fills *out and releases
+ * the ticket.  PET_OS_ERR_TIMEOUT if it is still running. */
+int pet_os_wait(pet_os_server* server, uint64_t ticket, int64_t timeout_us, pet_os_result* out);
+/* Ask for a request to be dropped (before admission, or at the next step). */
+int pet_os_cancel(pet_os_server* server, uint64_t ticket);
+int pet_os_server_stats(pet_os_server* server, pet_os_server_stats_t* out);
+
+/* Host-only server for tests of scheduling and failure handling: no device
+ * calls are made (data pointers may be NULL); a batched step takes step_us of
+ * wall time.  pet_os_server_inject arms faults on it. */
+int pet_os_server_create_simulated(size_t budget_bytes, int32_t max_slots, int64_t step_us, pet_os_server** out);
+#define PET_OS_INJECT_ADMIT_OOM 1      /* the next admissions fail with OUT_OF_MEMORY */
+#define PET_OS_INJECT_STEP_FAILURE 2   /* the next batched steps fail (DEVICE) */
+#define PET_OS_INJECT_NAN_OBJECTIVE 3  /* the next objectives come back NaN */
+int pet_os_server_inject(pet_os_server* server, int32_t kind, int32_t count);
+
 #ifdef __cplusplus
 }
 #endif

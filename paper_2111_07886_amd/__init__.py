@@ -31,7 +31,8 @@ EXPORTS = ["pet_os_last_error", "pet_os_version", "pet_os_create_geometry", "pet
            "pet_os_state_profile_read", "pet_os_nnz", "pet_os_state_seek", "pet_os_batch_create",
            "pet_os_batch_destroy", "pet_os_batch_add", "pet_os_batch_remove", "pet_os_batch_step",
            "pet_os_batch_run", "pet_os_batch_slot_status", "pet_os_batch_bytes", "pet_os_reconstruct_batch",
-           "pet_os_autotune"]
+           "pet_os_autotune", "pet_os_server_create", "pet_os_server_destroy", "pet_os_submit", "pet_os_wait",
+           "pet_os_cancel", "pet_os_server_stats", "pet_os_server_create_simulated", "pet_os_server_inject"]
 
 
 class PetOSError(RuntimeError):
@@ -56,6 +57,24 @@ class Params(C.Structure):
                 ("nu2", C.c_double), ("J0", C.c_int64), ("J1", C.c_int64),
                 ("objective_every", C.c_int32)]
 
+
+class Request(C.Structure):
+    _fields_ = [("desc", GeomDesc), ("params", Params), ("f", C.c_void_p), ("y", C.c_void_p), ("r", C.c_void_p),
+                ("n_iter", C.c_int32), ("want_objective", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("pad", C.c_int32), ("objective", C.c_double), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_start", C.c_double), ("t_finish", C.c_double),
+                ("subiterations", C.c_int64), ("message", C.c_char * 128)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("queued", C.c_int64), ("active", C.c_int64), ("ticks", C.c_int64), ("max_active", C.c_int64),
+                ("bytes_in_use", C.c_size_t), ("geometries_cached", C.c_int64)]
+
+
+INJECT = {"admit_oom": 1, "step_failure": 2, "nan_objective": 3}
 
 _lib = None
 _P = C.c_void_p
@@ -104,6 +123,14 @@ def lib():
             "pet_os_reconstruct_batch": (C.c_int, [i32, C.POINTER(_P), C.POINTER(Params), C.POINTER(_P),
                                                    C.POINTER(_P), C.POINTER(_P), C.POINTER(i32), _P]),
             "pet_os_autotune": (C.c_int, [_P, i32, _P]),
+            "pet_os_server_create": (C.c_int, [C.c_size_t, i32, C.POINTER(_P)]),
+            "pet_os_server_destroy": (C.c_int, [_P]),
+            "pet_os_submit": (C.c_int, [_P, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+            "pet_os_wait": (C.c_int, [_P, C.c_uint64, i64, C.POINTER(Result)]),
+            "pet_os_cancel": (C.c_int, [_P, C.c_uint64]),
+            "pet_os_server_stats": (C.c_int, [_P, C.POINTER(ServerStats)]),
+            "pet_os_server_create_simulated": (C.c_int, [C.c_size_t, i32, i64, C.POINTER(_P)]),
+            "pet_os_server_inject": (C.c_int, [_P, i32, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -377,3 +404,65 @@ def reconstruct_batch(geoms, params, fs, ys, rs, n_iters, stream=None):
 def autotune(geom: Geometry, force=False, stream=None):
     """pet_os_autotune: pick the projector shapes for this geometry by timing."""
     _check(lib().pet_os_autotune(geom.handle, 1 if force else 0, _stream(stream)))
+
+
+class Server:
+    """pet_os_server: continuous-batching reconstruction server.  With
+    simulate=True no device call is made (host scheduling tests)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int, simulate=False, step_us=50):
+        h = _P()
+        if simulate:
+            _check(lib().pet_os_server_create_simulated(int(hbm_budget_bytes), int(max_slots), int(step_us),
+                                                        C.byref(h)))
+        else:
+            _check(lib().pet_os_server_create(int(hbm_budget_bytes), int(max_slots), C.byref(h)))
+        self.handle = h
+        self.simulate = simulate
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pet_os_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, desc: dict, params: dict, f=None, y=None, r=None, n_iter=1, want_objective=False) -> int:
+        rq = Request()
+        rq.desc = desc_struct(desc)
+        rq.params = params_struct(params)
+        if not self.simulate:
+            rq.f = _dev(f, name="f").value
+            rq.y = _dev(y, name="y").value
+            rq.r = _dev(r, name="r").value
+        rq.n_iter = int(n_iter)
+        rq.want_objective = 1 if want_objective else 0
+        t = C.c_uint64()
+        _check(lib().pet_os_submit(self.handle, C.byref(rq), C.byref(t)))
+        self._keep[t.value] = (f, y, r)
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> dict:
+        res = Result()
+        _check(lib().pet_os_wait(self.handle, int(ticket), int(timeout_us), C.byref(res)))
+        self._keep.pop(ticket, None)
+        return dict(status=res.status, objective=res.objective, t_submit=res.t_submit, t_admit=res.t_admit,
+                    t_start=res.t_start, t_finish=res.t_finish, subiterations=res.subiterations,
+                    message=res.message.decode(errors="replace"))
+
+    def cancel(self, ticket: int):
+        _check(lib().pet_os_cancel(self.handle, int(ticket)))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().pet_os_server_stats(self.handle, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def inject(self, kind: str, count: int = 1):
+        _check(lib().pet_os_server_inject(self.handle, INJECT[kind], int(count)))

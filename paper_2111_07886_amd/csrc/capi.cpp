@@ -31,7 +31,7 @@ static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 // ---------------------------------------------------------------- geometry validation
 
-static int validate_desc(const pet_os_geom_desc* d) {
+int validate_desc(const pet_os_geom_desc* d) {
     if (!d) return fail(PET_OS_ERR_INVALID_ARG, "desc is NULL");
     if (d->dim != 2 && d->dim != 3) return fail(PET_OS_ERR_INVALID_ARG, "dim must be 2 or 3");
     if (d->nx < 1 || d->ny < 1) return fail(PET_OS_ERR_INVALID_ARG, "nx, ny must be >= 1");

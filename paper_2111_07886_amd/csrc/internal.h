@@ -92,6 +92,7 @@ Sched sched_next(const pet_os_params& p, int M, int64_t k, int i, double* t_nest
 // (float)(lambda alpha) and nu mode of subiterations J = 1..n_sub from the start
 void schedule_table(const pet_os_params& p, int M, int64_t n_sub, std::vector<float>& step, std::vector<int>& nu);
 int validate_params(const pet_os_params* p, const pet_os_geom* g);
+int validate_desc(const pet_os_geom_desc* d);
 
 // ---------------------------------------------------------------- launchers (kernels.hip)
 enum FPMode { FP_RATIO = 0, FP_PLAIN = 1, FP_OBJECTIVE = 2, FP_COUNT = 3, FP_COMPACT = 4 };
