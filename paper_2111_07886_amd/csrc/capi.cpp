@@ -127,6 +127,8 @@ static void build_angles(const pet_os_geom_desc* d, std::vector<AngleK>& out) {
             K.Bu = 0.5 * d->nx * d->vx / s;
             K.du = -d->vx / s;
         }
+        K.inv_du = 1.0 / K.du;
+        K.inv_wslope = 1.0 / K.wslope;
         out[a] = K;
     }
 }
@@ -284,6 +286,7 @@ int pet_os_create_geometry(const pet_os_geom_desc* desc, pet_os_geom** out) {
     k.n_angles = d.n_angles; k.n_radial = d.n_radial; k.n_subsets = M; k.n_planes = G->n_planes;
     k.n_rings = d.n_rings; k.max_rd = D; k.nvox = (int)G->n_vox;
     k.vx = d.vx; k.vy = d.vy; k.vz = d.vz; k.ds = d.ds; k.det_radius = d.det_radius;
+    k.h0 = 0.5 * (double)(d.n_radial - 1);
     k.ang = (const AngleK*)(blk + o_ang);
     k.bin = (const BinK*)(blk + o_bin);
     k.planes = (const int2*)(blk + o_pl);

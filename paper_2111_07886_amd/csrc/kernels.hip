@@ -449,7 +449,7 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
                 const double base = __fma_rn(AK.Q, (double)m, AK.wC);
                 const double glo = (double)mc - fmax(AK.Q, 0.0) - 1e-7;
                 const double ghi = (double)mc + 1.0 - fmin(AK.Q, 0.0) + 1e-7;
-                const double bA = (glo - base) / AK.wslope, bB = (ghi - base) / AK.wslope;
+                const double bA = (glo - base) * AK.inv_wslope, bB = (ghi - base) * AK.inv_wslope;
                 const int b0 = (int)fmax(floor(fmin(bA, bB)), 0.0);
                 const int b1 = (int)fmin(ceil(fmax(bA, bB)), (double)(Nr - 1));
                 const int aidx = A.w_natural ? a : al;

@@ -28,7 +28,9 @@ struct AngleK {
     double L;           // transaxial length of one major step
     double Au, Bu;      // u at major boundary 0: u0(b) = s_b * Au + Bu
     double du;          // du per major step
+    double inv_du;      // 1 / du
     double wslope, wC;  // P(b) ~= wslope * b + wC (candidate windows only)
+    double inv_wslope;  // 1 / wslope
     int row_major;      // 1: major axis = y (rows), minor = x
     int pad;
 };
@@ -50,6 +52,7 @@ struct GeoK {
     int nvox;
     int pad;
     double vx, vy, vz, ds, det_radius;
+    double h0;              // (n_radial - 1) / 2: s_b = (b - h0) ds
     const AngleK* ang;      // [n_angles]
     const BinK* bin;        // [n_radial]
     const int2* planes;     // [n_planes] (r1, d)
@@ -67,6 +70,8 @@ struct ZRay {
     double Pz, Qz, invQz, kap;   // kap = 3D length factor
 };
 
+__device__ __forceinline__ double bin_pos(const GeoK& g, int b) { return ((double)b - g.h0) * g.ds; }
+
 __device__ __forceinline__ TxRay tx_ray(const GeoK& g, const AngleK& A, int b) {
     TxRay t;
     t.row_major = A.row_major;
@@ -76,7 +81,7 @@ __device__ __forceinline__ TxRay tx_ray(const GeoK& g, const AngleK& A, int b) {
     if (A.Q == 0.0) {
         t.P = A.row_major ? g.bin[b].axis_pos_x : g.bin[b].axis_pos_y;
     } else {
-        t.P = __fma_rn(g.bin[b].sb, A.icv, A.K);
+        t.P = __fma_rn(bin_pos(g, b), A.icv, A.K);
     }
     return t;
 }
@@ -91,10 +96,10 @@ struct ZBin {
 __device__ __forceinline__ ZBin z_bin(const GeoK& g, const AngleK& A, int b) {
     const BinK& B = g.bin[b];
     ZBin zb;
-    double u0 = __fma_rn(B.sb, A.Au, A.Bu);
+    double u0 = __fma_rn(bin_pos(g, b), A.Au, A.Bu);
     zb.tau0 = (u0 + B.h) * B.inv2h;
     zb.tauQ = A.du * B.inv2h;
-    zb.inv_tauQ = 1.0 / zb.tauQ;
+    zb.inv_tauQ = A.inv_du * (2.0 * B.h);
     return zb;
 }
 
