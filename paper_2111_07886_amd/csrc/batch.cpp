@@ -57,6 +57,7 @@ struct pet_os_batch {
     int count[WL_COUNT] = {};
     int* d_counts = nullptr;
     int grids[WL_COUNT] = {};
+    int live_mask = 0;               // lists launched by the captured graph
     bool lists_dirty = true;
     bool graph_ok = false;
     hipStream_t cap_stream = nullptr;
@@ -86,13 +87,17 @@ int rebuild_lists(pet_os_batch* B) {
     for (int s = 0; s < B->max_slots; ++s) {
         const BatchSlot& S = B->slots[s];
         if (!S.used) continue;
-        const int nfp = fp_grid_seg(S.g, S.g->max_sub_angles, S.fp_seg);
-        for (int b = 0; b < nfp; ++b) L[WL_FP].push_back({s, b});
+        const bool d3 = S.g->d.dim == 3;
+        const int nfp = d3 ? fp3_grid(S.g, S.g->max_sub_angles) : fp_grid_seg(S.g, S.g->max_sub_angles, S.fp_seg);
+        for (int b = 0; b < nfp; ++b) L[d3 ? WL_FP3 : WL_FP].push_back({s, b});
         const int nbp = bp_grid_kind(S.g, S.bp_kind);
-        for (int b = 0; b < nbp; ++b) L[WL_BP0 + S.bp_kind].push_back({s, b});
-        const int nup = elem_grid(S.g->n_vox);
-        for (int b = 0; b < nup; ++b) L[WL_UPD].push_back({s, b});
+        const int wbp = d3 ? (bp3_zb(S.g) == 16 ? WL_BP3_16 : (bp3_zb(S.g) == 32 ? WL_BP3_32 : WL_BP3_64))
+                           : WL_BP0 + S.bp_kind;
+        for (int b = 0; b < nbp; ++b) L[wbp].push_back({s, b});
+        const int nup = sumf_grid(S.g);
+        for (int b = 0; b < nup; ++b) L[d3 ? WL_UPD3 : WL_UPD].push_back({s, b});
     }
+    int mask = 0;
     for (int k = 0; k < WL_COUNT; ++k) {
         const int n = (int)L[k].size();
         if (n > B->cap[k]) {
@@ -106,6 +111,12 @@ int rebuild_lists(pet_os_batch* B) {
         }
         if (n) PETOS_HIP(hipMemcpy(B->d_items[k], L[k].data(), (size_t)n * sizeof(Item), hipMemcpyHostToDevice));
         B->count[k] = n;
+        if (n) mask |= 1 << k;
+    }
+    // the graph launches only the non-empty lists: capture again when that set changes
+    if (mask != B->live_mask) {
+        B->live_mask = mask;
+        B->graph_ok = false;
     }
     PETOS_HIP(hipMemcpy(B->d_counts, B->count, sizeof(B->count), hipMemcpyHostToDevice));
     B->lists_dirty = false;
@@ -117,7 +128,8 @@ int capture(pet_os_batch* B) {
     if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
     for (int k = 0; k < WL_COUNT; ++k) B->grids[k] = std::max(1, std::min(B->cap[k], GRID_CAP));
     PETOS_HIP(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = launch_batch_step(B->d_slots, B->max_slots, B->d_items, B->d_counts, B->grids, B->cap_stream);
+    int rc = launch_batch_step(B->d_slots, B->max_slots, B->d_items, B->d_counts, B->grids, B->live_mask,
+                               B->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(B->cap_stream, &g);
     if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
@@ -219,8 +231,9 @@ int pet_os_batch_add(pet_os_batch* B, const pet_os_geom* g, const pet_os_params*
     const long long nrays_sub = (long long)g->max_sub_angles * g->n_planes * g->d.n_radial;
     S.fp_seg = fp_seg_for(g, nrays_sub, g->tuned_seg);
     S.bp_kind = bp_kind_of(g);
-    // sum of f0 for mean f of the first adaptive subiteration
-    rc = launch_sum(f, g->n_vox, S.w.red[RED_SUMF], st);
+    // sum of f0 for mean f of the first adaptive subiteration (3D: and the
+    // z-fastest copy of f0 read by the forward projector)
+    rc = launch_sum_f(g, f, S.w.fz, S.w.red[RED_SUMF], st);
     if (rc) { slot_release(S); return rc; }
 
     SlotDev D{};
@@ -233,9 +246,10 @@ int pet_os_batch_add(pet_os_batch* B, const pet_os_geom* g, const pet_os_params*
     D.G = S.w.G;
     D.mu = S.w.mu;
     D.nu_frozen = S.w.nu_frozen;
+    D.fz = S.w.fz;
     D.part_f = S.w.red[RED_SUMF].part;
     D.part_mu = S.w.red[RED_SUMMU].part;
-    D.n_part_f = elem_grid(g->n_vox);
+    D.n_part_f = sumf_grid(g);
     D.n_part_mu = bp_grid_kind(g, S.bp_kind);
     D.subset_lists = ex->subset_lists;
     D.subset_count = ex->d_subset_count;
@@ -253,8 +267,13 @@ int pet_os_batch_add(pet_os_batch* B, const pet_os_geom* g, const pet_os_params*
     D.t_clip = (float)p->t_clip;
     D.fp_seg = S.fp_seg;
     D.bp_kind = S.bp_kind;
-    size_t lds;
-    bp_stage_shape_kind(g, S.bp_kind, D.nb_max, D.rows_max, D.chunk, lds);
+    if (g->d.dim == 3) {
+        rc = bp3_shape(g, D.nb_max, D.zb, D.rows_max, D.chunk);
+        if (rc) { slot_release(S); return rc; }
+    } else {
+        size_t lds;
+        bp_stage_shape_kind(g, S.bp_kind, D.nb_max, D.rows_max, D.chunk, lds);
+    }
     D.active = 1;
     S.used = true;
     B->slots[idx] = S;
@@ -411,12 +430,13 @@ extern "C" int pet_os_autotune(pet_os_geom* g, int32_t flags, pet_os_stream stre
     if (!g) return fail(PET_OS_ERR_INVALID_ARG, "geom is NULL");
     GeomExtra* ex = extra_of(g);
     if (!ex) return fail(PET_OS_ERR_INVALID_ARG, "invalid geometry");
+    if (g->d.dim == 3) return PET_OS_OK;     // the 3D projectors have a single shape
     std::lock_guard<std::mutex> lk(g_tune_mu);
     const std::string key = tune_key(g->d);
     int seg = 0, kind = -1;
     if (!(flags & 1) && cache_lookup(key, seg, kind)) {
         g->tuned_seg = seg;
-        g->tuned_bp_kind = g->d.dim == 3 ? -1 : kind;
+        g->tuned_bp_kind = kind;
         return PET_OS_OK;
     }
     hipStream_t s = (hipStream_t)stream;

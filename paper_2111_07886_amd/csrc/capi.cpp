@@ -372,8 +372,10 @@ int work_alloc(const pet_os_geom* g, bool need_nu, Work* w) {
     size_t o_G = cv.take<float>(nv);
     size_t o_mu = cv.take<float>(nv);
     size_t o_nu = need_nu ? cv.take<float>(nv) : 0;
+    const bool d3 = g->d.dim == 3;
+    size_t o_fz = d3 ? cv.take<float>(nv) : 0;
     int caps[RED_COUNT];
-    caps[RED_SUMF] = elem_grid(g->n_vox);
+    caps[RED_SUMF] = std::max(sumf_grid(g), elem_grid(g->n_vox));
     caps[RED_SUMMU] = bp_grid_max(g);
     caps[RED_FID] = fp_grid(g, g->d.n_angles);
     caps[RED_RDP] = elem_grid(g->n_vox);
@@ -391,6 +393,7 @@ int work_alloc(const pet_os_geom* g, bool need_nu, Work* w) {
     w->G = (float*)(blk + o_G);
     w->mu = (float*)(blk + o_mu);
     w->nu_frozen = need_nu ? (float*)(blk + o_nu) : nullptr;
+    w->fz = d3 ? (float*)(blk + o_fz) : nullptr;
     for (int r = 0; r < RED_COUNT; ++r) {
         w->red[r].part = (double*)(blk + o_red[r]);
         w->red[r].total = (double*)(blk + o_tot) + r;
@@ -514,14 +517,17 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
     Sched sc = schedule_step(st);
     const bool want_mu = sc.nu_mode == NU_COMPUTE || sc.nu_mode == NU_COMPUTE_FREEZE;
     int rc;
-    if (want_mu && !sumf_current) {
-        rc = launch_sum(f, g->n_vox, st->w.red[RED_SUMF], s);
+    // sum f of the entering iterate (mean f of the smoothness measure) and,
+    // in 3D, its z-fastest copy, unless the previous update left them
+    if ((want_mu || g->d.dim == 3) && !sumf_current) {
+        rc = launch_sum_f(g, f, st->w.fz, st->w.red[RED_SUMF], s);
         if (rc) return rc;
     }
     const int* angles = ex->subset_lists + (size_t)(st->i - 1) * g->max_sub_angles;
     const int n_al = ex->subset_count[st->i - 1];
     FPLaunch F{};
-    F.f = f; F.y = y; F.r = r; F.out = st->w.w; F.angles = angles; F.n_al = n_al; F.mode = FP_RATIO;
+    F.f = f; F.fz = st->w.fz; F.y = y; F.r = r; F.out = st->w.w; F.angles = angles; F.n_al = n_al;
+    F.mode = FP_RATIO;
     // threads per ray chosen for the largest subset, as the batched path does
     F.seg = fp_seg_for(g, (long long)g->max_sub_angles * g->n_planes * g->d.n_radial, g->tuned_seg);
     hipEvent_t ev;
@@ -535,13 +541,13 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
     B.gamma_R = (float)st->p.gamma_R;
     B.eps = (float)st->p.eps;
     B.part_f = st->w.red[RED_SUMF].part;
-    B.n_part_f = elem_grid(g->n_vox);
+    B.n_part_f = sumf_grid(g);
     B.red_mu = st->w.red[RED_SUMMU];
     if ((rc = prof_begin(st, 1, s, &ev))) return rc;
     rc = launch_bp(g, B, s);
     if (rc || (rc = prof_end(ev, s))) return rc;
     UpdLaunch U{};
-    U.f = f; U.G = st->w.G; U.mu = st->w.mu; U.pnorm = g->pnorm; U.nu_frozen = st->w.nu_frozen;
+    U.f = f; U.fz = st->w.fz; U.G = st->w.G; U.mu = st->w.mu; U.pnorm = g->pnorm; U.nu_frozen = st->w.nu_frozen;
     U.nu_mode = sc.nu_mode;
     U.step = (float)(sc.lam * sc.alpha);
     U.nu1 = (float)st->p.nu1; U.nu2 = (float)st->p.nu2;
@@ -562,10 +568,12 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
 static int queue_objective(const pet_os_geom* g, const pet_os_params* p, Work* w, const float* f,
                            const float* y, const float* r, double* dst, hipStream_t s) {
     GeomExtra* ex = extra_of(g);
+    int rc = PET_OS_OK;
+    if (g->d.dim == 3 && (rc = launch_prep3(g, f, w->fz, w->red[RED_SUMF], s))) return rc;
     FPLaunch F{};
-    F.f = f; F.y = y; F.r = r; F.out = nullptr; F.angles = ex->all_angles; F.n_al = g->d.n_angles;
+    F.f = f; F.fz = w->fz; F.y = y; F.r = r; F.out = nullptr; F.angles = ex->all_angles; F.n_al = g->d.n_angles;
     F.mode = FP_OBJECTIVE; F.red = w->red[RED_FID];
-    int rc = launch_fp(g, F, s);
+    rc = launch_fp(g, F, s);
     if (!rc) rc = launch_finalize(w->red[RED_FID], fp_grid(g, g->d.n_angles), s);
     if (!rc) rc = launch_rdp_value(g, f, (float)p->gamma_R, (float)p->eps, w->red[RED_RDP], s);
     if (!rc) rc = launch_finalize(w->red[RED_RDP], elem_grid(g->n_vox), s);
@@ -632,7 +640,19 @@ int pet_os_forward(const pet_os_geom* g, const float* f, int32_t subset, float* 
     F.f = f; F.out = q; F.mode = FP_PLAIN;
     F.angles = subset == 0 ? ex->all_angles : ex->subset_lists + (size_t)(subset - 1) * g->max_sub_angles;
     F.n_al = subset == 0 ? g->d.n_angles : ex->subset_count[subset - 1];
-    return launch_fp(g, F, (hipStream_t)stream);
+    if (g->d.dim == 2) return launch_fp(g, F, (hipStream_t)stream);
+    // 3D: the projector reads a z-fastest copy of f, made in scratch that is
+    // released before returning (this call waits for the stream)
+    hipStream_t s = (hipStream_t)stream;
+    Work w;
+    int rc = work_alloc(g, false, &w);
+    if (rc) return rc;
+    rc = launch_prep3(g, f, w.fz, w.red[RED_SUMF], s);
+    F.fz = w.fz;
+    if (!rc) rc = launch_fp(g, F, s);
+    if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = fail(PET_OS_ERR_DEVICE, "stream synchronize failed");
+    work_free(&w);
+    return rc;
 }
 
 int pet_os_back(const pet_os_geom* g, const float* w, int32_t subset, float* out, pet_os_stream stream) {

@@ -1,0 +1,94 @@
+// devutil.h -- device helpers shared by the kernel files: fixed-order FP64
+// block sums and partials, and the image-space stencil of the penalty.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace petos {
+
+constexpr int NT = 256;   // threads per block everywhere
+
+// ------------------------------------------------------------------ reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum of v over the block in a fixed order; valid in thread 0.
+__device__ inline double block_sum(double v, double* sh /* >= NT/64 */) {
+    v = wave_sum(v);
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+// Every thread must call: the block's sum of v goes to R.part[vblock].
+__device__ __forceinline__ void write_partial(double v, Reduction R, double* sh, long long vblock) {
+    double bs = block_sum(v, sh);
+    if (threadIdx.x == 0) R.part[vblock] = bs;
+}
+
+// Sum of part[0..n) in index-strided order, the same in every block; the
+// result is returned to every thread.  The partials were written by an
+// earlier kernel in the same stream.
+__device__ inline double sum_partials(const double* part, int n, double* sh) {
+    __shared__ double s_tot;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+    double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) s_tot = t;
+    __syncthreads();
+    return s_tot;
+}
+
+// RDP gradient (eqn:gradRD; in-image 8/26 neighbours, unit weights) and the
+// Matlab-style gradient magnitude of Sec. III-B at one voxel of the halo tile.
+template <int DIM>
+__device__ __forceinline__ void stencil_at(const float* sf, int HX, int HY, int hx, int hy, int hz, int ix,
+                                           int iy, int iz, const GeoK& g, float gR, float eps, float& gradR,
+                                           float& gmag) {
+    auto at = [&](int dx, int dy, int dz) -> float {
+        return sf[((hz + dz) * HY + (hy + dy)) * HX + (hx + dx)];
+    };
+    const float fj = at(0, 0, 0);
+    float acc = 0.0f;
+    const int zr = (DIM == 3) ? 1 : 0;
+    for (int dz = -zr; dz <= zr; ++dz) {
+        const int z = iz + dz;
+        if (z < 0 || z >= g.nz) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int y = iy + dy;
+            if (y < 0 || y >= g.ny) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int x = ix + dx;
+                if ((dx | dy | dz) == 0 || x < 0 || x >= g.nx) continue;
+                const float fk = at(dx, dy, dz);
+                const float d = fj - fk;
+                const float ad = fabsf(d);
+                const float den = fj + fk + gR * ad + eps;
+                const float num = d * (gR * ad + fj + 3.0f * fk + 2.0f * eps);
+                acc += num / (den * den);
+            }
+        }
+    }
+    gradR = 2.0f * acc;
+    auto der = [&](int i, int n, int dx, int dy, int dz) -> float {
+        if (n < 2) return 0.0f;
+        if (i == 0) return at(dx, dy, dz) - fj;
+        if (i == n - 1) return fj - at(-dx, -dy, -dz);
+        return 0.5f * (at(dx, dy, dz) - at(-dx, -dy, -dz));
+    };
+    const float gx = der(ix, g.nx, 1, 0, 0);
+    const float gy = der(iy, g.ny, 0, 1, 0);
+    const float gz = (DIM == 3) ? der(iz, g.nz, 0, 0, 1) : 0.0f;
+    gmag = sqrtf(gx * gx + gy * gy + gz * gz);
+}
+
+}  // namespace petos

@@ -64,7 +64,7 @@ struct Work {
     float* G = nullptr;        // subset gradient image
     float* mu = nullptr;       // smoothness measure
     float* nu_frozen = nullptr;
-    float* q_all = nullptr;    // (unused placeholder for objective if needed)
+    float* fz = nullptr;       // 3D: copy of the iterate with z fastest [(iy*nx+ix)*nz+iz]
     double* red_block = nullptr;   // reductions' storage
     Reduction red[RED_COUNT];
     int* angle_list = nullptr;     // device copy of all subset angle lists [M][max_sub]
@@ -99,6 +99,7 @@ enum FPMode { FP_RATIO = 0, FP_PLAIN = 1, FP_OBJECTIVE = 2, FP_COUNT = 3, FP_COM
 
 struct FPLaunch {
     const float* f;
+    const float* fz = nullptr;   // 3D: the image with z fastest (the 3D projector reads this, not f)
     const float* y;
     const float* r;
     float* out;              // FP_RATIO, FP_COUNT, FP_COMPACT: compact [al][plane][b]; FP_PLAIN: natural q
@@ -131,6 +132,7 @@ int launch_bp(const pet_os_geom* g, const BPLaunch& L, hipStream_t s);
 
 struct UpdLaunch {
     float* f;
+    float* fz = nullptr;     // 3D: z-fastest copy, rewritten with the new iterate
     const float* G;
     const float* mu;
     const float* pnorm;
@@ -160,6 +162,21 @@ int bp_grid_kind(const pet_os_geom* g, int kind);
 int bp_grid(const pet_os_geom* g);
 int bp_grid_max(const pet_os_geom* g);
 int elem_grid(int64_t n);
+// number of partials of sum f left by the update (and by launch_sum / launch_prep3)
+int sumf_grid(const pet_os_geom* g);
+int launch_sum_f(const pet_os_geom* g, const float* f, float* fz, Reduction red, hipStream_t s);
+
+// 3D projectors and update (kernels3d.hip)
+int fp3_grid(const pet_os_geom* g, int n_al);
+int bp3_grid(const pet_os_geom* g);
+int bp3_zb(const pet_os_geom* g);
+int upd3_grid(const pet_os_geom* g);
+int bp3_shape(const pet_os_geom* g, int& nb, int& zb, int& rw, int& dpg);
+int launch_fp3(const pet_os_geom* g, const FPLaunch& L, hipStream_t s);
+int launch_bp3(const pet_os_geom* g, const BPLaunch& L, hipStream_t s);
+int launch_update3(const pet_os_geom* g, const UpdLaunch& L, hipStream_t s);
+// z-fastest copy of f and the partials of sum f (same tiles and order as the 3D update)
+int launch_prep3(const pet_os_geom* g, const float* f, float* fz, Reduction red, hipStream_t s);
 void bp_stage_shape_kind(const pet_os_geom* G, int kind, int& nb_max, int& rows_max, int& chunk, size_t& lds);
 size_t bp_lds_budget(int kind);
 
@@ -175,6 +192,7 @@ struct SlotDev {
     float* G;
     float* mu;
     float* nu_frozen;
+    float* fz;                 // 3D: z-fastest copy of f
     double* part_f;
     double* part_mu;
     int n_part_f, n_part_mu;
@@ -186,7 +204,8 @@ struct SlotDev {
     int J, J_end;              // next subiteration (device-advanced), last one
     float beta_over_M, gamma_R, eps, nu1, nu2, U, t_clip;
     int fp_seg, bp_kind;
-    int nb_max, rows_max, chunk;
+    int nb_max, rows_max, chunk;   // back-projector staging (3D: bins, rows, ring differences per group)
+    int zb;                        // 3D: slices per back-projection block
     int active;
 };
 
@@ -195,12 +214,19 @@ struct Item {
     int block;
 };
 
-enum { WL_FP = 0, WL_BP0 = 1, WL_BP1 = 2, WL_BP2 = 3, WL_UPD = 4, WL_COUNT = 5 };
+// work lists: 2D forward, 2D back-projection per tile kind, 2D update, and
+// the 3D forward, back-projection per z-block size (16/32/64) and update
+enum { WL_FP = 0, WL_BP0 = 1, WL_BP1 = 2, WL_UPD = 3, WL_FP3 = 4, WL_BP3_16 = 5, WL_BP3_32 = 6, WL_BP3_64 = 7,
+       WL_UPD3 = 8, WL_COUNT = 9 };
 
 // Queue one batched subiteration (every active slot advances by one):
 // forward, back-projection (one launch per tile kind), update, advance.
+// Lists whose bit is clear in `live_mask` are not launched.
 int launch_batch_step(SlotDev* d_slots, int n_slots, Item* const lists[WL_COUNT], const int* d_counts,
-                      const int grids[WL_COUNT], hipStream_t s);
+                      const int grids[WL_COUNT], int live_mask, hipStream_t s);
+void launch_batch3_fp(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, hipStream_t s);
+void launch_batch3_bp(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, int zb, hipStream_t s);
+void launch_batch3_upd(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, hipStream_t s);
 
 }  // namespace petos
 

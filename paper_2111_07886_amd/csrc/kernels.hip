@@ -18,50 +18,10 @@
 #include <algorithm>
 #include <cmath>
 
+#include "devutil.h"
 #include "internal.h"
 
 namespace petos {
-
-constexpr int NT = 256;   // threads per block everywhere
-
-// ------------------------------------------------------------------ reductions
-
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
-
-// Sum of v over the block in a fixed order; valid in thread 0.
-__device__ double block_sum(double v, double* sh /* >= NT/64 */) {
-    v = wave_sum(v);
-    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) sh[wid] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
-    __syncthreads();
-    return t;
-}
-
-// Every thread must call: the block's sum of v goes to R.part[vblock].
-__device__ __forceinline__ void write_partial(double v, Reduction R, double* sh, long long vblock) {
-    double bs = block_sum(v, sh);
-    if (threadIdx.x == 0) R.part[vblock] = bs;
-}
-
-// Sum of part[0..n) in index-strided order, the same in every block; the
-// result is returned to every thread.  The partials were written by an
-// earlier kernel in the same stream.
-__device__ double sum_partials(const double* part, int n, double* sh) {
-    __shared__ double s_tot;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
-    double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) s_tot = t;
-    __syncthreads();
-    return s_tot;
-}
 
 __global__ __launch_bounds__(256) void k_finalize(Reduction R, int n) {
     __shared__ double s_red[4];
@@ -87,6 +47,7 @@ struct FPArgs {
 // their partial sums are added by a fixed shuffle tree.
 template <int DIM, int SEG>
 __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
+    static_assert(DIM == 2, "the 3D forward projector is k_fp3");
     static_assert(SEG == 1 || (64 % SEG == 0), "segments of a ray stay in one wave");
     constexpr int RPB = NT / SEG;
     __shared__ double s_red[NT / 64];
@@ -118,58 +79,20 @@ __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
         const int sx = tx.row_major ? 1 : g.nx;       // stride along the minor cell index
         const int sm = tx.row_major ? g.nx : 1;       // stride along the major index
         int qstep = (tx.Q > 0.0) ? 1 : -1;
-        if (DIM == 2) {
-            for (int m = s0; m <= s1; ++m) {
-                double gm = __fma_rn(tx.Q, (double)m, tx.P);
-                int c0 = (int)floor(gm);
-                #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    if (k == 1 && tx.Q == 0.0) break;
-                    int c = c0 + k * qstep;
-                    if (c < 0 || c >= n_minor) continue;
-                    double lo, hi;
-                    cell_interval(gm, tx.Q, tx.invQ, c, lo, hi);
-                    if (hi > lo) {
-                        if (A.mode == FP_COUNT) { acc += 1.0f; continue; }
-                        float aij = (float)(tx.L * (hi - lo));
-                        acc = fmaf(aij, A.f[(long long)m * sm + (long long)c * sx], acc);
-                    }
-                }
-            }
-        } else {
-            int2 pl = g.planes[plane];
-            ZBin zb = z_bin(g, AK, b);
-            ZRay z = z_ray(g, zb, b, pl.x, pl.y);
-            double Lk = tx.L * z.kap;
-            int zstep = (z.Qz > 0.0) ? 1 : -1;
-            const long long slab = (long long)g.nx * g.ny;
-            for (int m = s0; m <= s1; ++m) {
-                double gm = __fma_rn(tx.Q, (double)m, tx.P);
-                double zm = __fma_rn(z.Qz, (double)m, z.Pz);
-                int c0 = (int)floor(gm);
-                int k0 = (int)floor(zm);
-                #pragma unroll
-                for (int kx = 0; kx < 2; ++kx) {
-                    if (kx == 1 && tx.Q == 0.0) break;
-                    int c = c0 + kx * qstep;
-                    if (c < 0 || c >= n_minor) continue;
-                    double lx, hx;
-                    cell_interval(gm, tx.Q, tx.invQ, c, lx, hx);
-                    if (!(hx > lx)) continue;
-                    #pragma unroll
-                    for (int kz = 0; kz < 2; ++kz) {
-                        if (kz == 1 && z.Qz == 0.0) break;
-                        int kk = k0 + kz * zstep;
-                        if (kk < 0 || kk >= g.nz) continue;
-                        double lz, hz;
-                        cell_interval(zm, z.Qz, z.invQz, kk, lz, hz);
-                        double len = fmin(hx, hz) - fmax(lx, lz);
-                        if (len > 0.0) {
-                            if (A.mode == FP_COUNT) { acc += 1.0f; continue; }
-                            float aij = (float)(Lk * len);
-                            acc = fmaf(aij, A.f[kk * slab + (long long)m * sm + (long long)c * sx], acc);
-                        }
-                    }
+        for (int m = s0; m <= s1; ++m) {
+            double gm = __fma_rn(tx.Q, (double)m, tx.P);
+            int c0 = (int)floor(gm);
+            #pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if (k == 1 && tx.Q == 0.0) break;
+                int c = c0 + k * qstep;
+                if (c < 0 || c >= n_minor) continue;
+                double lo, hi;
+                cell_interval(gm, tx.Q, tx.invQ, c, lo, hi);
+                if (hi > lo) {
+                    if (A.mode == FP_COUNT) { acc += 1.0f; continue; }
+                    float aij = (float)(tx.L * (hi - lo));
+                    acc = fmaf(aij, A.f[(long long)m * sm + (long long)c * sx], acc);
                 }
             }
         }
@@ -217,104 +140,41 @@ struct BPArgs {
     const double* part_f;
     int n_part_f;
     Reduction red_mu;
-    int nb_max;              // staged bins per row
-    int rows_max;            // staged rows (planes) per angle
+    int nb_max;              // staged bins per angle
     int chunk;               // angles staged together
 };
 
-// Tile of the back-projector: X x Y x Z voxels, AG threads per voxel (each
-// takes every AG-th angle of the subset; partial sums added in group order).
-template <int DIM, int X_, int Y_, int Z_, int AG_>
+// Tile of the back-projector: X x Y pixels, AG threads per pixel (each takes
+// every AG-th angle of the subset; partial sums added in group order).
+template <int X_, int Y_, int AG_>
 struct Tile {
-    static constexpr int D = DIM, X = X_, Y = Y_, Z = Z_, AG = AG_;
-    static_assert(X_ * Y_ * Z_ * AG_ == 256, "256 threads per block");
+    static constexpr int X = X_, Y = Y_, AG = AG_;
+    static_assert(X_ * Y_ * AG_ == 256, "256 threads per block");
 };
-using Tile2L = Tile<2, 16, 16, 1, 1>;   // large 2D images
-using Tile2S = Tile<2, 8, 8, 1, 4>;     // small 2D images: 4 angle groups
-using Tile3 = Tile<3, 8, 8, 4, 1>;
+using Tile2L = Tile<16, 16, 1>;   // large images
+using Tile2S = Tile<8, 8, 4>;     // small images: 4 angle groups
 
-constexpr int MAXD2 = 63;    // ring differences -31..31
 constexpr int MAXCH = 16;    // angles per staging chunk
-constexpr int MAXROWS = 2048;
-
-// RDP gradient (eqn:gradRD; in-image 8/26 neighbours, unit weights) and the
-// Matlab-style gradient magnitude of Sec. III-B at one voxel of the halo tile.
-template <int DIM>
-__device__ __forceinline__ void stencil_at(const float* sf, int HX, int HY, int hx, int hy, int hz, int ix,
-                                           int iy, int iz, const GeoK& g, float gR, float eps, float& gradR,
-                                           float& gmag) {
-    auto at = [&](int dx, int dy, int dz) -> float {
-        return sf[((hz + dz) * HY + (hy + dy)) * HX + (hx + dx)];
-    };
-    const float fj = at(0, 0, 0);
-    float acc = 0.0f;
-    const int zr = (DIM == 3) ? 1 : 0;
-    for (int dz = -zr; dz <= zr; ++dz) {
-        const int z = iz + dz;
-        if (z < 0 || z >= g.nz) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int y = iy + dy;
-            if (y < 0 || y >= g.ny) continue;
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int x = ix + dx;
-                if ((dx | dy | dz) == 0 || x < 0 || x >= g.nx) continue;
-                const float fk = at(dx, dy, dz);
-                const float d = fj - fk;
-                const float ad = fabsf(d);
-                const float den = fj + fk + gR * ad + eps;
-                const float num = d * (gR * ad + fj + 3.0f * fk + 2.0f * eps);
-                acc += num / (den * den);
-            }
-        }
-    }
-    gradR = 2.0f * acc;
-    auto der = [&](int i, int n, int dx, int dy, int dz) -> float {
-        if (n < 2) return 0.0f;
-        if (i == 0) return at(dx, dy, dz) - fj;
-        if (i == n - 1) return fj - at(-dx, -dy, -dz);
-        return 0.5f * (at(dx, dy, dz) - at(-dx, -dy, -dz));
-    };
-    const float gx = der(ix, g.nx, 1, 0, 0);
-    const float gy = der(iy, g.ny, 0, 1, 0);
-    const float gz = (DIM == 3) ? der(iz, g.nz, 0, 0, 1) : 0.0f;
-    gmag = sqrtf(gx * gx + gy * gy + gz * gz);
-}
 
 template <class T>
 __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
-    constexpr int DIM = T::D;
-    constexpr int NV = T::X * T::Y * T::Z;          // voxels per tile
-    constexpr int HX = T::X + 2, HY = T::Y + 2, HZ = (DIM == 3) ? T::Z + 2 : 1;
-    constexpr int ND = (DIM == 3) ? MAXD2 : 1;
+    constexpr int NV = T::X * T::Y;                 // pixels per tile
+    constexpr int HX = T::X + 2, HY = T::Y + 2;
     extern __shared__ float s_w[];
-    __shared__ float s_f[HX * HY * HZ];
-    __shared__ int s_blo[MAXCH], s_nb[MAXCH], s_row0[MAXCH];
-    __shared__ double s_tau[MAXCH][2];
-    __shared__ short s_r1lo[MAXCH][ND], s_nrow[MAXCH][ND], s_rowb[MAXCH][ND];
-    constexpr int NROWS = (DIM == 3) ? MAXROWS : MAXCH;
-    __shared__ long long s_src[NROWS];
-    __shared__ int s_ncol[NROWS];
-    __shared__ int s_rows_total;
+    __shared__ float s_f[HX * HY];
+    __shared__ int s_blo[MAXCH], s_nb[MAXCH];
     __shared__ double s_red[NT / 64];
     __shared__ float s_acc[T::AG > 1 ? T::AG * NV : 1];
 
     const int tiles_x = (g.nx + T::X - 1) / T::X;
-    const int tiles_y = (g.ny + T::Y - 1) / T::Y;
-    int t = vblock;
-    const int tx0 = (t % tiles_x) * T::X;
-    t /= tiles_x;
-    const int ty0 = (t % tiles_y) * T::Y;
-    const int tz0 = (t / tiles_y) * T::Z;
-    const int vox = threadIdx.x % NV;               // voxel of the tile
+    const int tx0 = (vblock % tiles_x) * T::X;
+    const int ty0 = (vblock / tiles_x) * T::Y;
+    const int vox = threadIdx.x % NV;               // pixel of the tile
     const int grp = threadIdx.x / NV;               // angle group
-    const int lx = vox % T::X;
-    const int ly = (vox / T::X) % T::Y;
-    const int lz = vox / (T::X * T::Y);
-    const int ix = tx0 + lx, iy = ty0 + ly, iz = tz0 + lz;
-    const int nzv = (DIM == 3) ? g.nz : 1;
-    const bool inside = ix < g.nx && iy < g.ny && iz < nzv;
-    const int P = g.n_planes, Nr = g.n_radial, D = g.max_rd, R = g.n_rings;
-    const double h0 = 0.5 * (double)(Nr - 1);
+    const int lx = vox % T::X, ly = vox / T::X;
+    const int ix = tx0 + lx, iy = ty0 + ly;
+    const bool inside = ix < g.nx && iy < g.ny;
+    const int Nr = g.n_radial;
     const int nb_max = A.nb_max;
 
     // tile box in mm
@@ -324,12 +184,11 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
     // halo tile of f (fused stencil) and mean f: independent of the gather,
     // so issued first
     if (A.f != nullptr) {
-        for (int e = threadIdx.x; e < HX * HY * HZ; e += NT) {
-            const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
-            const int gx = tx0 - 1 + hx, gy = ty0 - 1 + hy, gz = (DIM == 3) ? tz0 - 1 + hz : 0;
+        for (int e = threadIdx.x; e < HX * HY; e += NT) {
+            const int hx = e % HX, hy = e / HX;
+            const int gx = tx0 - 1 + hx, gy = ty0 - 1 + hy;
             float v = 0.0f;
-            if (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < nzv)
-                v = A.f[((long long)gz * g.ny + gy) * g.nx + gx];
+            if (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny) v = A.f[(long long)gy * g.nx + gx];
             s_f[e] = v;
         }
     }
@@ -340,104 +199,37 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
     for (int c0 = 0; c0 < A.n_al; c0 += A.chunk) {
         const int nch = min(A.chunk, A.n_al - c0);
         if (A.w != nullptr) {
-            // (1) per-angle bin footprint of the tile (+1 bin margin) and tau range
+            // (1) per-angle bin footprint of the tile (+1 bin margin)
             if (threadIdx.x < nch) {
                 const int j = threadIdx.x;
                 const AngleK& AK = g.ang[A.angles[c0 + j]];
-                double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+                double umin = 1e300, umax = -1e300;
                 for (int k = 0; k < 4; ++k) {
                     const double x = (k & 1) ? X1 : X0, y = (k & 2) ? Y1 : Y0;
                     const double u = x * AK.c + y * AK.s;     // radial position
-                    const double v = -x * AK.s + y * AK.c;    // position along the ray
-                    umin = fmin(umin, u); umax = fmax(umax, u);
-                    vmin = fmin(vmin, v); vmax = fmax(vmax, v);
+                    umin = fmin(umin, u);
+                    umax = fmax(umax, u);
                 }
-                int blo = (int)floor(umin / g.ds + h0) - 1;
-                int bhi = (int)ceil(umax / g.ds + h0) + 1;
-                blo = max(blo, 0);
-                bhi = min(bhi, Nr - 1);
-                int nb = bhi - blo + 1;
-                if (nb > nb_max) nb = nb_max;
-                if (nb < 0) nb = 0;
+                int blo = max((int)floor(umin / g.ds + g.h0) - 1, 0);
+                int bhi = min((int)ceil(umax / g.ds + g.h0) + 1, Nr - 1);
                 s_blo[j] = blo;
-                s_nb[j] = nb;
-                if (DIM == 3 && nb > 0) {
-                    double hmin = fmin(g.bin[blo].h, g.bin[blo + nb - 1].h);
-                    double hmax = (blo <= h0 && blo + nb - 1 >= h0) ? g.det_radius
-                                                                      : fmax(g.bin[blo].h, g.bin[blo + nb - 1].h);
-                    s_tau[j][0] = 0.5 + vmin / (2.0 * (vmin < 0.0 ? hmin : hmax)) - 1e-9;
-                    s_tau[j][1] = 0.5 + vmax / (2.0 * (vmax > 0.0 ? hmin : hmax)) + 1e-9;
-                }
+                s_nb[j] = max(0, min(bhi - blo + 1, nb_max));
             }
             __syncthreads();
-            // (2) rows (planes) per ring difference
-            if (DIM == 3) {
-                for (int e = threadIdx.x; e < nch * (2 * D + 1); e += NT) {
-                    const int j = e / (2 * D + 1), di = e % (2 * D + 1), d = di - D;
-                    const double tlo = s_tau[j][0], thi = s_tau[j][1];
-                    const double a0 = d * tlo, a1 = d * thi;
-                    int lo = (int)floor((double)tz0 - 0.5 - fmax(a0, a1)) - 1;
-                    int hi = (int)ceil((double)(tz0 + T::Z) - 0.5 - fmin(a0, a1)) + 1;
-                    lo = max(lo, max(0, -d));
-                    hi = min(hi, min(R - 1, R - 1 - d));
-                    s_r1lo[j][di] = (short)lo;
-                    s_nrow[j][di] = (short)max(0, hi - lo + 1);
-                }
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    int tot = 0;
-                    for (int j = 0; j < nch; ++j) {
-                        s_row0[j] = tot;
-                        int rb = 0;
-                        for (int di = 0; di <= 2 * D; ++di) {
-                            int n = s_nrow[j][di];
-                            if (rb + n > A.rows_max) n = max(0, A.rows_max - rb);
-                            if (s_nb[j] == 0) n = 0;
-                            s_nrow[j][di] = (short)n;
-                            s_rowb[j][di] = (short)rb;
-                            rb += n;
-                        }
-                        tot += rb;
-                    }
-                    s_rows_total = tot;
-                }
-                __syncthreads();
-                for (int e = threadIdx.x; e < nch * (2 * D + 1); e += NT) {
-                    const int j = e / (2 * D + 1), di = e % (2 * D + 1), d = di - D;
+            // (2) stage the footprint rows into LDS
+            const int nel = nch * nb_max;
+            for (int e = threadIdx.x; e < nel; e += NT) {
+                const int j = e / nb_max, col = e - j * nb_max;
+                if (col < s_nb[j]) {
                     const int al = c0 + j;
                     const int aidx = A.w_natural ? A.angles[al] : al;
-                    const int pb = g.plane_base[di] - max(0, -d);
-                    for (int k = 0; k < s_nrow[j][di]; ++k) {
-                        const int row = s_row0[j] + s_rowb[j][di] + k;
-                        const int plane = pb + s_r1lo[j][di] + k;
-                        s_src[row] = (long long)plane * A.w_sp + (long long)aidx * A.w_sa + s_blo[j];
-                        s_ncol[row] = s_nb[j];
-                    }
+                    s_w[e] = A.w[(long long)aidx * A.w_sa + s_blo[j] + col];
                 }
-            } else {
-                if (threadIdx.x < nch) {
-                    const int j = threadIdx.x, al = c0 + j;
-                    const int aidx = A.w_natural ? A.angles[al] : al;
-                    s_row0[j] = j;
-                    s_r1lo[j][0] = 0;
-                    s_nrow[j][0] = (short)(s_nb[j] > 0 ? 1 : 0);
-                    s_rowb[j][0] = 0;
-                    s_src[j] = (long long)aidx * A.w_sa + s_blo[j];
-                    s_ncol[j] = s_nb[j];
-                }
-                if (threadIdx.x == 0) s_rows_total = nch;
-            }
-            __syncthreads();
-            // (3) stage the footprint rows into LDS
-            const int nel = s_rows_total * nb_max;
-            for (int e = threadIdx.x; e < nel; e += NT) {
-                const int row = e / nb_max, col = e - row * nb_max;
-                if (col < s_ncol[row]) s_w[e] = A.w[s_src[row] + col];
             }
             __syncthreads();
         }
 
-        // (4) gather: every bin (and plane) whose LOR crosses this voxel
+        // (3) gather: every bin whose ray crosses this pixel
         if (inside) {
             for (int j = grp; j < nch; j += T::AG) {
                 const int al = c0 + j;
@@ -459,54 +251,18 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
                     double ax, bx;
                     cell_interval(gm, tx.Q, tx.invQ, mc, ax, bx);
                     if (!(bx > ax)) continue;
-                    const int bcol = b - s_blo[j];
-                    const bool bin_staged = A.w != nullptr && bcol >= 0 && bcol < s_nb[j];
-                    if (DIM == 2) {
-                        float wv = 1.0f;
-                        if (A.w != nullptr)
-                            wv = bin_staged ? s_w[s_row0[j] * nb_max + bcol] : A.w[(long long)aidx * A.w_sa + b];
-                        const float aij = (float)(tx.L * (bx - ax));
-                        acc = fmaf(aij, wv, acc);
-                    } else {
-                        const ZBin zb = z_bin(g, AK, b);
-                        for (int d = -D; d <= D; ++d) {
-                            const double dd = (double)d;
-                            const double bza = 0.5 + dd * (zb.tau0 + zb.tauQ * ((double)m + ax));
-                            const double bzb = 0.5 + dd * (zb.tau0 + zb.tauQ * ((double)m + bx));
-                            int r1a = (int)ceil((double)iz - fmax(bza, bzb) - 1e-9);
-                            int r1b = (int)floor((double)iz + 1.0 - fmin(bza, bzb) + 1e-9);
-                            r1a = max(r1a, max(0, -d));
-                            r1b = min(r1b, min(R - 1, R - 1 - d));
-                            for (int r1 = r1a; r1 <= r1b; ++r1) {
-                                const ZRay z = z_ray(g, zb, b, r1, d);
-                                const double zm = __fma_rn(z.Qz, (double)m, z.Pz);
-                                double az, bzz;
-                                cell_interval(zm, z.Qz, z.invQz, iz, az, bzz);
-                                const double len = fmin(bx, bzz) - fmax(ax, az);
-                                if (!(len > 0.0)) continue;
-                                float wv = 1.0f;
-                                if (A.w != nullptr) {
-                                    const int di = d + D;
-                                    const int rr = r1 - s_r1lo[j][di];
-                                    if (bin_staged && rr >= 0 && rr < s_nrow[j][di]) {
-                                        wv = s_w[(s_row0[j] + s_rowb[j][di] + rr) * nb_max + bcol];
-                                    } else {
-                                        const int plane = g.plane_base[di] - max(0, -d) + r1;
-                                        wv = A.w[(long long)plane * A.w_sp + (long long)aidx * A.w_sa + b];
-                                    }
-                                }
-                                const double Lk = tx.L * z.kap;
-                                const float aij = (float)(Lk * len);
-                                acc = fmaf(aij, wv, acc);
-                            }
-                        }
+                    float wv = 1.0f;
+                    if (A.w != nullptr) {
+                        const int bcol = b - s_blo[j];
+                        wv = (bcol >= 0 && bcol < s_nb[j]) ? s_w[j * nb_max + bcol] : A.w[(long long)aidx * A.w_sa + b];
                     }
+                    const float aij = (float)(tx.L * (bx - ax));
+                    acc = fmaf(aij, wv, acc);
                 }
             }
         }
         __syncthreads();
     }
-    (void)P;
     if (T::AG > 1) {
         s_acc[grp * NV + vox] = acc;
         __syncthreads();
@@ -516,19 +272,18 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
     const bool owner = grp == 0;
 
     if (A.f == nullptr) {
-        if (inside && owner) A.out[((long long)iz * g.ny + iy) * g.nx + ix] = acc;
+        if (inside && owner) A.out[(long long)iy * g.nx + ix] = acc;
         return;
     }
 
-    // (5) fused image-space part: grad R, mu, G = A_i^T w + (beta/M) grad R
+    // (4) fused image-space part: grad R, mu, G = A_i^T w + (beta/M) grad R
     // (the halo tile was loaded before the gather)
     __syncthreads();
     double mu_part = 0.0;
     if (inside && owner) {
         float gradR, gmag;
-        stencil_at<DIM>(s_f, HX, HY, lx + 1, ly + 1, (DIM == 3) ? lz + 1 : 0, ix, iy, iz, g, A.gamma_R, A.eps,
-                        gradR, gmag);
-        const long long j = ((long long)iz * g.ny + iy) * g.nx + ix;
+        stencil_at<2>(s_f, HX, HY, lx + 1, ly + 1, 0, ix, iy, 0, g, A.gamma_R, A.eps, gradR, gmag);
+        const long long j = (long long)iy * g.nx + ix;
         A.out[j] = fmaf(A.beta_over_M, gradR, acc);
         if (A.want_mu) {
             const float mu = fmaxf(0.01f, gmag / meanf);
@@ -660,11 +415,13 @@ int fp_grid_seg(const pet_os_geom* G, int n_al, int seg) {
 }
 
 int fp_grid(const pet_os_geom* G, int n_al) {
+    if (G->d.dim == 3) return fp3_grid(G, n_al);
     long long nrays = (long long)n_al * G->n_planes * G->d.n_radial;
     return fp_grid_seg(G, n_al, fp_seg_heuristic(nrays));
 }
 
-// 0: Tile2L, 1: Tile2S, 2: Tile3
+// 2D tile kinds 0: 16x16, 1: 8x8 with four angle groups; 3D geometries use
+// kind 2, the column tiles of k_bp3
 int bp_kind_of(const pet_os_geom* G) {
     if (G->d.dim == 3) return 2;
     if (G->tuned_bp_kind >= 0) return G->tuned_bp_kind;
@@ -672,33 +429,36 @@ int bp_kind_of(const pet_os_geom* G) {
     return tiles16 < 1024 ? 1 : 0;
 }
 
-static void bp_tile(int kind, int& TX, int& TY, int& TZ) {
-    TX = kind == 0 ? 16 : 8;
-    TY = kind == 0 ? 16 : 8;
-    TZ = kind == 2 ? 4 : 1;
-}
-
 int bp_grid_kind(const pet_os_geom* G, int kind) {
-    int TX, TY, TZ;
-    bp_tile(kind, TX, TY, TZ);
-    return ((G->d.nx + TX - 1) / TX) * ((G->d.ny + TY - 1) / TY) * ((G->d.nz + TZ - 1) / TZ);
+    if (kind == 2) return bp3_grid(G);
+    const int T = kind == 0 ? 16 : 8;
+    return ((G->d.nx + T - 1) / T) * ((G->d.ny + T - 1) / T);
 }
 
 int bp_grid(const pet_os_geom* G) { return bp_grid_kind(G, bp_kind_of(G)); }
 
 int bp_grid_max(const pet_os_geom* G) {
-    if (G->d.dim == 3) return bp_grid_kind(G, 2);
+    if (G->d.dim == 3) return bp3_grid(G);
     return std::max(bp_grid_kind(G, 0), bp_grid_kind(G, 1));
 }
 
 int elem_grid(int64_t n) { return (int)((n + NT - 1) / NT); }
 
-template <int DIM, int SEG>
+int sumf_grid(const pet_os_geom* G) { return G->d.dim == 3 ? upd3_grid(G) : elem_grid(G->n_vox); }
+
+// partials of sum f of an image given by the caller (3D: also its z-fastest copy)
+int launch_sum_f(const pet_os_geom* G, const float* f, float* fz, Reduction red, hipStream_t s) {
+    if (G->d.dim == 3) return launch_prep3(G, f, fz, red, s);
+    return launch_sum(f, G->n_vox, red, s);
+}
+
+template <int SEG>
 static void fp_launch_t(const GeoK& k, const FPArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_fp<DIM, SEG>), dim3(grid), dim3(NT), 0, s, k, a);
+    hipLaunchKernelGGL((k_fp<2, SEG>), dim3(grid), dim3(NT), 0, s, k, a);
 }
 
 int launch_fp(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
+    if (G->d.dim == 3) return launch_fp3(G, L, s);
     FPArgs a;
     a.f = L.f;
     a.y = L.y;
@@ -713,50 +473,34 @@ int launch_fp(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
     int seg = fp_seg_for(G, nrays, L.seg);
     int grid = fp_grid_seg(G, L.n_al, seg);
     if (L.mode == FP_OBJECTIVE && grid > L.red.cap) return fail(PET_OS_ERR_DEVICE, "objective partials too small");
-    const bool d3 = G->d.dim == 3;
-    if (seg == 64) { if (d3) fp_launch_t<3, 64>(G->k, a, grid, s); else fp_launch_t<2, 64>(G->k, a, grid, s); }
-    else if (seg == 16) { if (d3) fp_launch_t<3, 16>(G->k, a, grid, s); else fp_launch_t<2, 16>(G->k, a, grid, s); }
-    else if (seg == 4) { if (d3) fp_launch_t<3, 4>(G->k, a, grid, s); else fp_launch_t<2, 4>(G->k, a, grid, s); }
-    else { if (d3) fp_launch_t<3, 1>(G->k, a, grid, s); else fp_launch_t<2, 1>(G->k, a, grid, s); }
+    if (seg == 64) fp_launch_t<64>(G->k, a, grid, s);
+    else if (seg == 16) fp_launch_t<16>(G->k, a, grid, s);
+    else if (seg == 4) fp_launch_t<4>(G->k, a, grid, s);
+    else fp_launch_t<1>(G->k, a, grid, s);
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;
 }
 
-size_t bp_lds_budget(int kind) { return (kind == 2 ? 12288 : 4096) * sizeof(float); }
+size_t bp_lds_budget(int kind) {
+    (void)kind;
+    return 4096 * sizeof(float);
+}
 
-// LDS footprint bounds of a back-projection tile (host side, conservative)
+// LDS footprint bounds of a 2D back-projection tile (host side, conservative)
 void bp_stage_shape_kind(const pet_os_geom* G, int kind, int& nb_max, int& rows_max, int& chunk, size_t& lds) {
     const auto& d = G->d;
-    int TX, TY, TZ;
-    bp_tile(kind, TX, TY, TZ);
-    nb_max = (int)std::ceil((TX * d.vx + TY * d.vy) / d.ds) + 4;
+    const int T = kind == 0 ? 16 : 8;
+    nb_max = (int)std::ceil(T * (d.vx + d.vy) / d.ds) + 4;
     if (nb_max > d.n_radial) nb_max = d.n_radial;
-    if (d.dim == 2) {
-        rows_max = 1;
-    } else {
-        double rmin = 0.5 * std::sqrt(d.nx * d.nx * d.vx * d.vx + d.ny * d.ny * d.vy * d.vy);
-        double smax = 0.5 * (d.n_radial - 1) * d.ds;
-        double hmin = std::sqrt(std::max(1.0, d.det_radius * d.det_radius - smax * smax));
-        double dtau = std::sqrt(TX * TX * d.vx * d.vx + TY * TY * d.vy * d.vy) / (2.0 * hmin) + 1e-6;
-        (void)rmin;
-        int rows = 0;
-        for (int dd = -d.max_ring_diff; dd <= d.max_ring_diff; ++dd)
-            rows += std::min(d.n_rings, TZ + 3 + (int)std::ceil(std::abs(dd) * dtau));
-        rows_max = rows;
-    }
+    rows_max = 1;
     const size_t budget_floats = bp_lds_budget(kind) / sizeof(float);
-    if ((size_t)nb_max * rows_max > budget_floats) rows_max = (int)(budget_floats / nb_max);
-    size_t slot = (size_t)nb_max * rows_max;
-    chunk = (int)std::max<size_t>(1, budget_floats / slot);
+    chunk = (int)std::max<size_t>(1, budget_floats / (size_t)nb_max);
     if (chunk > MAXCH) chunk = MAXCH;
-    if ((size_t)chunk * rows_max > MAXROWS) chunk = std::max(1, MAXROWS / rows_max);
-    if ((size_t)rows_max > MAXROWS) rows_max = MAXROWS;
-    lds = (size_t)chunk * slot * sizeof(float);
+    lds = (size_t)chunk * nb_max * sizeof(float);
 }
 
 int launch_bp(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
-    if (G->d.dim == 3 && 2 * G->d.max_ring_diff + 1 > MAXD2)
-        return fail(PET_OS_ERR_INVALID_ARG, "max_ring_diff too large for the back-projector");
+    if (G->d.dim == 3) return launch_bp3(G, L, s);
     BPArgs a{};
     a.w = L.w;
     a.w_natural = L.w_natural;
@@ -780,21 +524,22 @@ int launch_bp(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
     a.n_part_f = L.n_part_f;
     a.red_mu = L.red_mu;
     size_t lds;
+    int rows_unused;
     const int kind = bp_kind_of(G);
-    bp_stage_shape_kind(G, kind, a.nb_max, a.rows_max, a.chunk, lds);
+    bp_stage_shape_kind(G, kind, a.nb_max, rows_unused, a.chunk, lds);
     if (L.w == nullptr) lds = 0;
     int grid = bp_grid(G);
     if (L.want_mu && grid > L.red_mu.cap) return fail(PET_OS_ERR_DEVICE, "mu partials too small");
-    switch (kind) {
-        case 0: hipLaunchKernelGGL((k_bp<Tile2L>), dim3(grid), dim3(NT), lds, s, G->k, a); break;
-        case 1: hipLaunchKernelGGL((k_bp<Tile2S>), dim3(grid), dim3(NT), lds, s, G->k, a); break;
-        default: hipLaunchKernelGGL((k_bp<Tile3>), dim3(grid), dim3(NT), lds, s, G->k, a); break;
-    }
+    if (kind == 0)
+        hipLaunchKernelGGL((k_bp<Tile2L>), dim3(grid), dim3(NT), lds, s, G->k, a);
+    else
+        hipLaunchKernelGGL((k_bp<Tile2S>), dim3(grid), dim3(NT), lds, s, G->k, a);
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;
 }
 
 int launch_update(const pet_os_geom* G, const UpdLaunch& L, hipStream_t s) {
+    if (G->d.dim == 3) return launch_update3(G, L, s);
     UpdArgs a;
     a.f = L.f;
     a.G = L.G;
@@ -859,13 +604,12 @@ int launch_rdp_value(const pet_os_geom* G, const float* f, float gamma_R, float 
 
 __device__ __forceinline__ bool slot_live(const SlotDev& d) { return d.active && d.J <= d.J_end; }
 
-template <int DIM>
 __device__ void fp_dispatch(const GeoK& g, const FPArgs& A, int seg, long long vblock) {
     switch (seg) {
-        case 64: fp_body<DIM, 64>(g, A, vblock); break;
-        case 16: fp_body<DIM, 16>(g, A, vblock); break;
-        case 4: fp_body<DIM, 4>(g, A, vblock); break;
-        default: fp_body<DIM, 1>(g, A, vblock); break;
+        case 64: fp_body<2, 64>(g, A, vblock); break;
+        case 16: fp_body<2, 16>(g, A, vblock); break;
+        case 4: fp_body<2, 4>(g, A, vblock); break;
+        default: fp_body<2, 1>(g, A, vblock); break;
     }
 }
 
@@ -884,8 +628,7 @@ __global__ __launch_bounds__(NT) void k_fp_batch(const SlotDev* S, const Item* i
         A.angles = d.subset_lists + (long long)i * d.max_sub;
         A.n_al = d.subset_count[i];
         A.mode = FP_RATIO;
-        if (d.g.dim == 3) fp_dispatch<3>(d.g, A, d.fp_seg, I.block);
-        else fp_dispatch<2>(d.g, A, d.fp_seg, I.block);
+        fp_dispatch(d.g, A, d.fp_seg, I.block);
         __syncthreads();
     }
 }
@@ -919,7 +662,6 @@ __global__ __launch_bounds__(NT) void k_bp_batch(const SlotDev* S, const Item* i
         A.red_mu.total = nullptr;
         A.red_mu.cap = d.n_part_mu;
         A.nb_max = d.nb_max;
-        A.rows_max = d.rows_max;
         A.chunk = d.chunk;
         bp_body<T>(d.g, A, I.block);
         __syncthreads();
@@ -962,15 +704,24 @@ __global__ __launch_bounds__(NT) void k_advance(SlotDev* S, int n_slots) {
 }
 
 int launch_batch_step(SlotDev* d_slots, int n_slots, Item* const lists[WL_COUNT], const int* d_counts,
-                      const int grids[WL_COUNT], hipStream_t s) {
-    hipLaunchKernelGGL(k_fp_batch, dim3(grids[WL_FP]), dim3(NT), 0, s, d_slots, lists[WL_FP], d_counts + WL_FP);
-    hipLaunchKernelGGL((k_bp_batch<Tile2L>), dim3(grids[WL_BP0]), dim3(NT), bp_lds_budget(0), s, d_slots,
-                       lists[WL_BP0], d_counts + WL_BP0);
-    hipLaunchKernelGGL((k_bp_batch<Tile2S>), dim3(grids[WL_BP1]), dim3(NT), bp_lds_budget(1), s, d_slots,
-                       lists[WL_BP1], d_counts + WL_BP1);
-    hipLaunchKernelGGL((k_bp_batch<Tile3>), dim3(grids[WL_BP2]), dim3(NT), bp_lds_budget(2), s, d_slots,
-                       lists[WL_BP2], d_counts + WL_BP2);
-    hipLaunchKernelGGL(k_upd_batch, dim3(grids[WL_UPD]), dim3(NT), 0, s, d_slots, lists[WL_UPD], d_counts + WL_UPD);
+                      const int grids[WL_COUNT], int live_mask, hipStream_t s) {
+    auto live = [&](int k) { return (live_mask >> k) & 1; };
+    if (live(WL_FP))
+        hipLaunchKernelGGL(k_fp_batch, dim3(grids[WL_FP]), dim3(NT), 0, s, d_slots, lists[WL_FP], d_counts + WL_FP);
+    if (live(WL_FP3)) launch_batch3_fp(d_slots, lists[WL_FP3], d_counts + WL_FP3, grids[WL_FP3], s);
+    if (live(WL_BP0))
+        hipLaunchKernelGGL((k_bp_batch<Tile2L>), dim3(grids[WL_BP0]), dim3(NT), bp_lds_budget(0), s, d_slots,
+                           lists[WL_BP0], d_counts + WL_BP0);
+    if (live(WL_BP1))
+        hipLaunchKernelGGL((k_bp_batch<Tile2S>), dim3(grids[WL_BP1]), dim3(NT), bp_lds_budget(1), s, d_slots,
+                           lists[WL_BP1], d_counts + WL_BP1);
+    const int zbs[3] = {16, 32, 64};
+    for (int k = 0; k < 3; ++k)
+        if (live(WL_BP3_16 + k))
+            launch_batch3_bp(d_slots, lists[WL_BP3_16 + k], d_counts + WL_BP3_16 + k, grids[WL_BP3_16 + k], zbs[k], s);
+    if (live(WL_UPD))
+        hipLaunchKernelGGL(k_upd_batch, dim3(grids[WL_UPD]), dim3(NT), 0, s, d_slots, lists[WL_UPD], d_counts + WL_UPD);
+    if (live(WL_UPD3)) launch_batch3_upd(d_slots, lists[WL_UPD3], d_counts + WL_UPD3, grids[WL_UPD3], s);
     hipLaunchKernelGGL(k_advance, dim3((n_slots + NT - 1) / NT), dim3(NT), 0, s, d_slots, n_slots);
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;

@@ -1,0 +1,842 @@
+// kernels3d.hip -- fully-3D (span-1) forward and back projection and update.
+//
+// Axial shift invariance.  Rings sit at slice centres, so the LOR of plane
+// (r1, d) and that of plane (r1 + 1, d) (same angle and bin) cross the same
+// transaxial cells with the same lengths, one slice apart: relative to its
+// first ring the axial grid coordinate of a LOR over major cell m is
+// zeta(m + psi) = 1/2 + d (tau0 + tauQ (m + psi)), independent of r1, and
+// slice r1 + o is crossed exactly where zeta lies in [o, o + 1).  Both
+// projectors are built on that:
+//
+//   k_fp3    one wave per (angle, bin, ring difference); the lanes are the
+//            first rings r1.  The 64 lanes first walk 64 major cells in
+//            parallel and list the (transaxial cell, slice offset o, length)
+//            pieces of that stretch in LDS; then every lane adds
+//            length * f[cell, slice r1 + o] for every piece, from a copy of
+//            the image with z fastest, so that one wave load reads 64
+//            consecutive slices.  The Poisson ratio (or the FP64
+//            log-likelihood term) is the epilogue, as in 2D.
+//   k_bp3    one block per 8x8 column tile and z-range.  A lane owns one
+//            column; wave v takes ring differences v, v+4, ... of each
+//            staged group.  Per angle a lane finds the bins whose ray crosses
+//            its column's transaxial cell and, per ring difference, the one
+//            or two slice offsets o1, o1+1 with their lengths a1, a2; these
+//            apply to every slice of the column:
+//                acc[iz] += a1 w[r1 = iz - o1] + a2 w[r1 = iz - o1 - 1],
+//            with w staged in LDS as [d][bin][r1] (r1 fastest, zero outside
+//            the valid rings).  The four waves' partial sums are added in a
+//            fixed order, then the RDP gradient, mu and G of the column tile
+//            are computed from an LDS halo of f.  No atomics.
+//   k_upd3   the update of k_update on 64 x 32 (x, z) tiles, also writing
+//            the z-fastest copy through LDS; FP64 partials of sum f.
+//   k_prep3  the z-fastest copy and the sum-f partials of a caller's image
+//            (the same tiles and summation order as k_upd3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "devutil.h"
+#include "internal.h"
+
+namespace petos {
+
+// ------------------------------------------------------------------ forward projection
+
+struct FP3Args {
+    const float* fz;        // image with z fastest: fz[(iy * nx + ix) * nz + iz]
+    const float* y;
+    const float* r;
+    float* out;
+    const int* angles;
+    int n_al;
+    int mode;
+    Reduction red;
+};
+
+constexpr int FP3_W = NT / 64;      // waves per block: one (angle, bin, ring difference) each
+constexpr int FP3_CAP = 4 * 64;     // pieces of a stretch of 64 major cells (<= 4 per cell)
+
+struct Piece {
+    int off;      // (iy * nx + ix) * nz + o
+    float len;    // 3D length (1 when counting)
+};
+
+__host__ __device__ inline long long fp3_items(int n_al, int n_radial, int max_rd, int n_rings) {
+    return (long long)n_al * n_radial * (2 * max_rd + 1) * ((n_rings + 63) / 64);
+}
+
+// memory ordering of LDS traffic between the lanes of one wave
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ void fp3_body(const GeoK& g, const FP3Args& A, long long vblock) {
+    __shared__ Piece s_pc[FP3_W][FP3_CAP];
+    __shared__ double s_red[NT / 64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int D = g.max_rd, ND = 2 * D + 1, Nr = g.n_radial, R = g.n_rings;
+    const int nch = (R + 63) / 64;
+    const long long item = vblock * FP3_W + wave;
+    bool live = item < fp3_items(A.n_al, Nr, D, R);
+    int ch = 0, di = 0, b = 0, al = 0;
+    if (live) {
+        long long t = item;
+        ch = (int)(t % nch);
+        t /= nch;
+        di = (int)(t % ND);
+        t /= ND;
+        b = (int)(t % Nr);
+        al = (int)(t / Nr);
+    }
+    const int d = di - D;
+    const int r1lo = max(0, -d), r1hi = min(R - 1, R - 1 - d);
+    const int r1 = r1lo + ch * 64 + lane;
+    live = live && (r1lo + ch * 64 <= r1hi);
+    const bool lane_ok = live && r1 <= r1hi;
+    const bool counting = A.mode == FP_COUNT;
+
+    float acc = 0.0f;
+    int a = 0;
+    if (live) {
+        a = A.angles[al];
+        const AngleK& AK = g.ang[a];
+        const TxRay tx = tx_ray(g, AK, b);
+        const int n_major = tx.row_major ? g.ny : g.nx;
+        const int n_minor = tx.row_major ? g.nx : g.ny;
+        int m0, m1;
+        major_range(tx, n_major, n_minor, m0, m1);
+        const ZBin zb = z_bin(g, AK, b);
+        const double zeta0 = __fma_rn((double)d, zb.tau0, 0.5);
+        const double Qz = (double)d * zb.tauQ;
+        const double invQz = (d == 0) ? 0.0 : g.inv_d[di] * zb.inv_tauQ;
+        const double Lk = tx.L * g.kappa[(long long)b * ND + di];
+        const int qstep = (tx.Q > 0.0) ? 1 : -1;
+        const int zstep = (Qz > 0.0) ? 1 : -1;
+        // a LOR between rings r1 and r1 + d stays in slices r1 + [min(0,d), max(0,d)]
+        const int olo = min(0, d), ohi = max(0, d);
+        for (int mb = m0; mb <= m1; mb += 64) {
+            // (1) the lane's major cell: up to four pieces (minor cell c0 or
+            // its neighbour) x (slice offset o0 or its neighbour)
+            const int m = mb + lane;
+            int off[4] = {0, 0, 0, 0};
+            float len[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            int present = 0;
+            if (m <= m1) {
+                const double gm = __fma_rn(tx.Q, (double)m, tx.P);
+                const double zm = __fma_rn(Qz, (double)m, zeta0);
+                const int c0 = (int)floor(gm), o0 = (int)floor(zm);
+#pragma unroll
+                for (int kx = 0; kx < 2; ++kx) {
+                    const int c = c0 + kx * qstep;
+                    if ((kx == 1 && tx.Q == 0.0) || c < 0 || c >= n_minor) continue;
+                    double lx, hx;
+                    cell_interval(gm, tx.Q, tx.invQ, c, lx, hx);
+                    if (!(hx > lx)) continue;
+                    const int ix = tx.row_major ? c : m, iy = tx.row_major ? m : c;
+                    const int col = (iy * g.nx + ix) * g.nz;
+#pragma unroll
+                    for (int kz = 0; kz < 2; ++kz) {
+                        if (kz == 1 && Qz == 0.0) continue;
+                        const int o = o0 + kz * zstep;
+                        if (o < olo || o > ohi) continue;
+                        double lz, hz;
+                        cell_interval(zm, Qz, invQz, o, lz, hz);
+                        const double l = fmin(hx, hz) - fmax(lx, lz);
+                        if (l > 0.0) {
+                            off[2 * kx + kz] = col + o;
+                            len[2 * kx + kz] = counting ? 1.0f : (float)(Lk * l);
+                            present |= 1 << (2 * kx + kz);
+                        }
+                    }
+                }
+            }
+            // (2) compact the pieces of the 64 cells, in cell order, into LDS
+            const int cnt = __popc(present);
+            int incl = cnt;
+#pragma unroll
+            for (int s = 1; s < 64; s <<= 1) {
+                const int t = __shfl_up(incl, s, 64);
+                if (lane >= s) incl += t;
+            }
+            const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
+            int pos = incl - cnt;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (present & (1 << k)) {
+                    s_pc[wave][pos] = Piece{off[k], len[k]};
+                    ++pos;
+                }
+            }
+            wave_lds_sync();
+            // (3) every lane (first ring r1) applies every piece
+            if (lane_ok) {
+                if (counting) {
+                    for (int j = 0; j < total; ++j) acc += s_pc[wave][j].len;
+                } else {
+                    const float* fr = A.fz + r1;
+#pragma unroll 4
+                    for (int j = 0; j < total; ++j) {
+                        const Piece p = s_pc[wave][j];
+                        acc = fmaf(p.len, fr[p.off], acc);
+                    }
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+
+    double term = 0.0;
+    if (lane_ok) {
+        const int plane = g.plane_base[di] + (r1 - r1lo);
+        const long long nat = ((long long)plane * g.n_angles + a) * Nr + b;
+        const long long ray = ((long long)al * g.n_planes + plane) * Nr + b;
+        if (A.mode == FP_RATIO) {
+            A.out[ray] = 1.0f - A.y[nat] / (acc + A.r[nat]);
+        } else if (A.mode == FP_COUNT || A.mode == FP_COMPACT) {
+            A.out[ray] = acc;
+        } else if (A.mode == FP_PLAIN) {
+            A.out[nat] = acc;
+        } else {
+            const double q = (double)acc;
+            term = q - (double)A.y[nat] * log(q + (double)A.r[nat]);
+        }
+    }
+    if (A.mode == FP_OBJECTIVE) write_partial(term, A.red, s_red, vblock);
+}
+
+__global__ __launch_bounds__(NT) void k_fp3(GeoK g, FP3Args A) { fp3_body(g, A, blockIdx.x); }
+
+// ------------------------------------------------------------------ back projection
+
+struct BP3Args {
+    const float* w;          // null => unit weights (sensitivity)
+    long long w_sp, w_sa;    // w index = plane * w_sp + angle_index * w_sa + b
+    int w_natural;           // angle_index = natural angle (1) or position in the list (0)
+    const int* angles;
+    int n_al;
+    float* out;
+    const float* f;          // non-null => fused stencil, out = G
+    float* mu;
+    int want_mu;
+    float beta_over_M, gamma_R, eps;
+    const double* part_f;
+    int n_part_f;
+    Reduction red_mu;
+    int nb;                  // staged bins per angle
+    int zb;                  // slices per block: 16, 32 or 64
+    int rw;                  // staged rows per (ring difference, bin)
+    int dpg;                 // ring differences staged together: 4 or 8
+};
+
+constexpr int BP3_T = 8;         // columns per tile side
+constexpr int BP3_ZMAX = 64;
+constexpr int BP3_HMAX = 2;      // candidate bins of a column handled per pass
+constexpr int BP3_LDS = 12288;   // floats of the staging area (48 KB)
+constexpr int BP3_MAXND = 63;    // ring differences -31..31
+
+// acc[i] += a1 w(r1 = iz - o1) + a2 w(r1 = iz - o1 - 1) for the ZB slices of
+// the block; sp[i + 1] holds w(r1 = z0 + i - o1), sp[i] the row before it.
+template <int ZB>
+__device__ __forceinline__ void bp3_apply(float (&acc)[BP3_ZMAX], const float* sp, float a1, float a2) {
+    float prev = sp[0];
+#pragma unroll
+    for (int i = 0; i < ZB; ++i) {
+        const float cur = sp[i + 1];
+        acc[i] = fmaf(a1, cur, fmaf(a2, prev, acc[i]));
+        prev = cur;
+    }
+}
+
+// After all angles: add the four waves' partial sums in wave order into
+// s_fin[lz][column] (top of the LDS area), then either store the
+// back-projection or compute the RDP gradient, mu and G of the tile's voxels.
+template <int ZB>
+__device__ void bp3_finish(const GeoK& g, const BP3Args& A, float (&acc)[BP3_ZMAX], float* s_w, double* s_red,
+                           float meanf, int vblock, int tx0, int ty0, int z0) {
+    constexpr int QS = ZB / 4;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float* s_fin = s_w + (BP3_LDS - ZB * 64);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < QS; ++i) s_w[(wave * QS + i) * 64 + lane] = acc[q * QS + i];
+        __syncthreads();
+        if (wave == q) {
+#pragma unroll 4
+            for (int i = 0; i < QS; ++i) {
+                float s = s_w[i * 64 + lane];
+                s += s_w[(QS + i) * 64 + lane];
+                s += s_w[(2 * QS + i) * 64 + lane];
+                s += s_w[(3 * QS + i) * 64 + lane];
+                s_fin[(q * QS + i) * 64 + lane] = s;
+            }
+        }
+    }
+    __syncthreads();
+    if (A.f == nullptr) {
+        for (int e = threadIdx.x; e < ZB * 64; e += NT) {
+            const int c = e & 63, lz = e >> 6;
+            const int ix = tx0 + (c & 7), iy = ty0 + (c >> 3), iz = z0 + lz;
+            if (ix < g.nx && iy < g.ny && iz < g.nz) A.out[((long long)iz * g.ny + iy) * g.nx + ix] = s_fin[e];
+        }
+        return;
+    }
+    // halo tile of f: (8+2) x (8+2) x (ZB+2), below s_fin
+    constexpr int HX = BP3_T + 2, HY = BP3_T + 2, HZ = ZB + 2;
+    static_assert(HX * HY * HZ <= BP3_LDS - ZB * 64, "halo and sums share the staging area");
+    for (int e = threadIdx.x; e < HX * HY * HZ; e += NT) {
+        const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
+        const int gx = tx0 - 1 + hx, gy = ty0 - 1 + hy, gz = z0 - 1 + hz;
+        float v = 0.0f;
+        if (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz)
+            v = A.f[((long long)gz * g.ny + gy) * g.nx + gx];
+        s_w[e] = v;
+    }
+    __syncthreads();
+    double mu_part = 0.0;
+    for (int e = threadIdx.x; e < ZB * 64; e += NT) {
+        const int c = e & 63, lz = e >> 6;
+        const int lx = c & 7, ly = c >> 3;
+        const int ix = tx0 + lx, iy = ty0 + ly, iz = z0 + lz;
+        if (ix < g.nx && iy < g.ny && iz < g.nz) {
+            float gradR, gmag;
+            stencil_at<3>(s_w, HX, HY, lx + 1, ly + 1, lz + 1, ix, iy, iz, g, A.gamma_R, A.eps, gradR, gmag);
+            const long long j = ((long long)iz * g.ny + iy) * g.nx + ix;
+            A.out[j] = fmaf(A.beta_over_M, gradR, s_fin[e]);
+            if (A.want_mu) {
+                const float mu = fmaxf(0.01f, gmag / meanf);
+                A.mu[j] = mu;
+                mu_part += (double)mu;
+            }
+        }
+    }
+    if (A.want_mu) write_partial(mu_part, A.red_mu, s_red, vblock);
+}
+
+template <int ZB>
+__device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock) {
+    __shared__ float s_w[BP3_LDS];
+    __shared__ int s_blo, s_nb;
+    __shared__ double s_tau[2];
+    __shared__ int s_omin[BP3_MAXND], s_omax[BP3_MAXND];
+    __shared__ int s_npass;
+    __shared__ double s_red[NT / 64];
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tiles_x = (g.nx + BP3_T - 1) / BP3_T, tiles_y = (g.ny + BP3_T - 1) / BP3_T;
+    int t = vblock;
+    const int tx0 = (t % tiles_x) * BP3_T;
+    t /= tiles_x;
+    const int ty0 = (t % tiles_y) * BP3_T;
+    const int z0 = (t / tiles_y) * ZB;
+    const int ix = tx0 + (lane & 7), iy = ty0 + (lane >> 3);
+    const bool col_in = ix < g.nx && iy < g.ny;
+    const int D = g.max_rd, ND = 2 * D + 1, Nr = g.n_radial, R = g.n_rings;
+    const int rw = A.rw, dpg = A.dpg;
+
+    // tile box in mm
+    const double X0 = ((double)tx0 - 0.5 * g.nx) * g.vx, X1 = X0 + BP3_T * g.vx;
+    const double Y0 = ((double)ty0 - 0.5 * g.ny) * g.vy, Y1 = Y0 + BP3_T * g.vy;
+
+    float meanf = 1.0f;
+    if (A.f != nullptr && A.want_mu) meanf = (float)(sum_partials(A.part_f, A.n_part_f, s_red) / (double)g.nvox);
+
+    float acc[BP3_ZMAX];
+#pragma unroll
+    for (int i = 0; i < BP3_ZMAX; ++i) acc[i] = 0.0f;
+
+    for (int al = 0; al < A.n_al; ++al) {
+        const int a = A.angles[al];
+        const AngleK& AK = g.ang[a];
+        const int aidx = A.w_natural ? a : al;
+        // (1) the tile's bins [blo, blo + nb) (+1 bin margin) and tau range
+        if (threadIdx.x == 0) {
+            s_npass = 0;
+            double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+            for (int k = 0; k < 4; ++k) {
+                const double x = (k & 1) ? X1 : X0, y = (k & 2) ? Y1 : Y0;
+                const double u = x * AK.c + y * AK.s;      // radial position
+                const double v = -x * AK.s + y * AK.c;     // position along the ray
+                umin = fmin(umin, u);
+                umax = fmax(umax, u);
+                vmin = fmin(vmin, v);
+                vmax = fmax(vmax, v);
+            }
+            int blo = max((int)floor(umin / g.ds + g.h0) - 1, 0);
+            int bhi = min((int)ceil(umax / g.ds + g.h0) + 1, Nr - 1);
+            const int nb = max(0, min(bhi - blo + 1, A.nb));
+            s_blo = blo;
+            s_nb = nb;
+            double hmin = g.det_radius, hmax = g.det_radius;
+            if (nb > 0) {
+                const int bl = blo + nb - 1;
+                hmin = fmin(g.bin[blo].h, g.bin[bl].h);
+                hmax = ((double)blo <= g.h0 && (double)bl >= g.h0) ? g.det_radius : fmax(g.bin[blo].h, g.bin[bl].h);
+            }
+            s_tau[0] = 0.5 + vmin / (2.0 * (vmin < 0.0 ? hmin : hmax)) - 1e-9;
+            s_tau[1] = 0.5 + vmax / (2.0 * (vmax > 0.0 ? hmin : hmax)) + 1e-9;
+        }
+        __syncthreads();
+        // (2) slice-offset range of every ring difference over the tile (+1 margin)
+        if (threadIdx.x < ND) {
+            const double dd = (double)((int)threadIdx.x - D);
+            const double za = 0.5 + dd * s_tau[0], zc = 0.5 + dd * s_tau[1];
+            s_omin[threadIdx.x] = (int)floor(fmin(za, zc)) - 1;
+            s_omax[threadIdx.x] = (int)floor(fmax(za, zc)) + 1;
+        }
+        // (3) candidate bins of the column: g(m) in [mc - max(Q,0), mc + 1 - min(Q,0)]
+        const int m = AK.row_major ? iy : ix;
+        const int mc = AK.row_major ? ix : iy;
+        int b0 = 0, b1 = -1;
+        if (col_in) {
+            const double base = __fma_rn(AK.Q, (double)m, AK.wC);
+            const double glo = (double)mc - fmax(AK.Q, 0.0) - 1e-7;
+            const double ghi = (double)mc + 1.0 - fmin(AK.Q, 0.0) + 1e-7;
+            const double bA = (glo - base) * AK.inv_wslope, bB = (ghi - base) * AK.inv_wslope;
+            b0 = (int)fmax(floor(fmin(bA, bB)), 0.0);
+            b1 = (int)fmin(ceil(fmax(bA, bB)), (double)(Nr - 1));
+        }
+        // passes over the candidates, HMAX at a time: the most any column needs
+        if (b1 >= b0) atomicMax(&s_npass, (b1 - b0) / BP3_HMAX + 1);
+        __syncthreads();
+        const int npass = s_npass;
+        for (int pass = 0; pass < npass; ++pass) {
+            const int bp0 = b0 + pass * BP3_HMAX;
+            // (4) hits of this pass: transaxial psi-interval [ax, bx] of the
+            // column's cell in major cell m, kept as its tau end points
+            int hb[BP3_HMAX];
+            double htA[BP3_HMAX], htB[BP3_HMAX], hL[BP3_HMAX];
+            bool hv[BP3_HMAX];
+#pragma unroll
+            for (int k = 0; k < BP3_HMAX; ++k) {
+                const int b = bp0 + k;
+                hb[k] = b;
+                hv[k] = false;
+                htA[k] = htB[k] = hL[k] = 0.0;
+                if (b <= b1) {
+                    const TxRay tx = tx_ray(g, AK, b);
+                    const double gm = __fma_rn(tx.Q, (double)m, tx.P);
+                    double ax, bx;
+                    cell_interval(gm, tx.Q, tx.invQ, mc, ax, bx);
+                    if (bx > ax) {
+                        const ZBin zbk = z_bin(g, AK, b);
+                        htA[k] = __fma_rn(zbk.tauQ, (double)m + ax, zbk.tau0);
+                        htB[k] = __fma_rn(zbk.tauQ, (double)m + bx, zbk.tau0);
+                        hL[k] = tx.L * (bx - ax);
+                        hv[k] = true;
+                    }
+                }
+            }
+            const int blo = s_blo, nbv = s_nb;
+            for (int dg = 0; dg < ND; dg += dpg) {
+                // (5) stage w of ring differences dg .. dg+dpg-1 as [d][bin][r1]
+                __syncthreads();
+                const int nel = dpg * rw * nbv;
+                for (int e = threadIdx.x; e < nel; e += NT) {
+                    const int bcol = e % nbv;
+                    const int rem = e / nbv;
+                    const int row = rem % rw, ds = rem / rw;
+                    const int di = dg + ds;
+                    float v = 0.0f;
+                    if (di < ND && row >= 1) {
+                        const int d = di - D;
+                        const int r1 = z0 - s_omax[di] + row - 1;
+                        const int lo = max(0, -d), hi = min(R - 1, R - 1 - d);
+                        if (r1 >= lo && r1 <= hi) {
+                            if (A.w == nullptr) {
+                                v = 1.0f;
+                            } else {
+                                const int plane = g.plane_base[di] + r1 - lo;
+                                v = A.w[(long long)plane * A.w_sp + (long long)aidx * A.w_sa + blo + bcol];
+                            }
+                        }
+                    }
+                    s_w[(ds * nbv + bcol) * rw + row] = v;
+                }
+                __syncthreads();
+                // (6) gather: wave v takes the group's ring differences v, v+4
+                for (int ds = wave; ds < dpg; ds += 4) {
+                    const int di = dg + ds;
+                    if (di >= ND) break;
+                    const double dd = (double)(di - D);
+                    const int omin = s_omin[di], omax = s_omax[di];
+#pragma unroll
+                    for (int k = 0; k < BP3_HMAX; ++k) {
+                        if (!hv[k]) continue;
+                        const double zA = __fma_rn(dd, htA[k], 0.5), zB = __fma_rn(dd, htB[k], 0.5);
+                        const double zlo = fmin(zA, zB), zhi = fmax(zA, zB);
+                        const int o1 = (int)floor(zlo), o2 = (int)floor(zhi);
+                        const double LK = hL[k] * g.kappa[(long long)hb[k] * ND + di];
+                        float a1, a2;
+                        if (o2 == o1) {
+                            a1 = (float)LK;
+                            a2 = 0.0f;
+                        } else {
+                            const double inv = 1.0 / (zhi - zlo);
+                            a1 = (float)(LK * (((double)o2 - zlo) * inv));
+                            a2 = (float)(LK * ((zhi - (double)o2) * inv));
+                        }
+                        // inside the staged footprint by construction: the tile's bin
+                        // window and tau range contain every hit of its columns, and
+                        // the host-side bounds on bins and slice-offset span hold; the
+                        // test only keeps LDS reads in range
+                        const int bcol = hb[k] - blo;
+                        if (bcol >= 0 && bcol < nbv && o1 >= omin && o2 <= omax && omax - omin + ZB + 1 <= rw)
+                            bp3_apply<ZB>(acc, s_w + (ds * nbv + bcol) * rw + (omax - o1), a1, a2);
+                    }
+                }
+            }
+        }
+        __syncthreads();    // the angle's shared values are read no more
+    }
+    bp3_finish<ZB>(g, A, acc, s_w, s_red, meanf, vblock, tx0, ty0, z0);
+}
+
+template <int ZB>
+__global__ __launch_bounds__(NT) void k_bp3(GeoK g, BP3Args A) {
+    bp3_body<ZB>(g, A, blockIdx.x);
+}
+
+// ------------------------------------------------------------------ update and z-fastest copy
+
+struct Upd3Args {
+    float* f;
+    float* fz;
+    const float* G;
+    const float* mu;
+    const float* pnorm;
+    float* nu_frozen;
+    int nu_mode;
+    float step, nu1, nu2, U, t_clip;
+    const double* part_mu;
+    int n_part_mu;
+    Reduction red_f;
+    int nx, ny, nz;
+};
+
+constexpr int U3X = 64, U3Z = 32;
+
+// update == false: only copy f into fz and write the partials of sum f
+__device__ void upd3_body(const Upd3Args& A, long long vblock, bool update) {
+    __shared__ float s_t[U3X * (U3Z + 1)];
+    __shared__ double s_red[NT / 64];
+    const int nxt = (A.nx + U3X - 1) / U3X;
+    long long t = vblock;
+    const int xt = (int)(t % nxt);
+    t /= nxt;
+    const int y = (int)(t % A.ny);
+    const int z0 = (int)(t / A.ny) * U3Z, x0 = xt * U3X;
+    const int lx = threadIdx.x & 63, zq = threadIdx.x >> 6;
+    const int x = x0 + lx;
+    const long long nvox = (long long)A.nx * A.ny * A.nz;
+    const bool want_mu = update && (A.nu_mode == NU_COMPUTE || A.nu_mode == NU_COMPUTE_FREEZE);
+    float meanmu = 1.0f;
+    if (want_mu) meanmu = (float)(sum_partials(A.part_mu, A.n_part_mu, s_red) / (double)nvox);
+    double part = 0.0;
+#pragma unroll
+    for (int k = 0; k < U3Z / 4; ++k) {
+        const int zz = zq + 4 * k, z = z0 + zz;
+        float v = 0.0f;
+        if (x < A.nx && z < A.nz) {
+            const long long j = ((long long)z * A.ny + y) * A.nx + x;
+            const float fj = A.f[j];
+            if (update) {
+                const float Gj = A.G[j];
+                const float pj = A.pnorm[j];
+                float nu = 1.0f;
+                if (want_mu) {
+                    nu = fminf(A.nu2, fmaxf(A.nu1, meanmu / A.mu[j]));
+                    if (A.nu_mode == NU_COMPUTE_FREEZE) A.nu_frozen[j] = nu;
+                } else if (A.nu_mode == NU_FROZEN) {
+                    nu = A.nu_frozen[j];
+                }
+                const float S = (fj < 0.5f * A.U) ? fj / pj : (A.U - fj) / pj;
+                const float ft = fj - A.step * nu * S * Gj;
+                const float fn = (ft <= 0.0f) ? A.t_clip : ((ft >= A.U) ? A.U - A.t_clip : ft);
+                A.f[j] = fn;
+                v = fn;
+            } else {
+                v = fj;
+            }
+            part += (double)v;
+        }
+        s_t[lx * (U3Z + 1) + zz] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < U3Z * U3X / NT; ++k) {
+        const int e = threadIdx.x + NT * k;
+        const int xx = e / U3Z, zz = e % U3Z;
+        const int xg = x0 + xx, z = z0 + zz;
+        if (xg < A.nx && z < A.nz) A.fz[((long long)y * A.nx + xg) * A.nz + z] = s_t[xx * (U3Z + 1) + zz];
+    }
+    write_partial(part, A.red_f, s_red, vblock);
+}
+
+__global__ __launch_bounds__(NT) void k_upd3(Upd3Args A) { upd3_body(A, blockIdx.x, true); }
+__global__ __launch_bounds__(NT) void k_prep3(Upd3Args A) { upd3_body(A, blockIdx.x, false); }
+
+// ------------------------------------------------------------------ host side
+
+int fp3_grid(const pet_os_geom* G, int n_al) {
+    const long long n = fp3_items(n_al, G->d.n_radial, G->d.max_ring_diff, G->d.n_rings);
+    return (int)((n + FP3_W - 1) / FP3_W);
+}
+
+int bp3_zb(const pet_os_geom* G) { return G->d.nz <= 16 ? 16 : (G->d.nz <= 32 ? 32 : 64); }
+
+int bp3_grid(const pet_os_geom* G) {
+    const int zb = bp3_zb(G);
+    return ((G->d.nx + BP3_T - 1) / BP3_T) * ((G->d.ny + BP3_T - 1) / BP3_T) * ((G->d.nz + zb - 1) / zb);
+}
+
+int upd3_grid(const pet_os_geom* G) {
+    return ((G->d.nx + U3X - 1) / U3X) * G->d.ny * ((G->d.nz + U3Z - 1) / U3Z);
+}
+
+// Staging shape of the 3D back-projector: bins per angle (bound on the
+// tile's radial extent), rows per (ring difference, bin) = slices + slice
+// offset span + 1 pad row (odd, for conflict-free LDS writes), and the ring
+// differences staged together.  Fails if the footprint cannot fit in LDS.
+int bp3_shape(const pet_os_geom* G, int& nb, int& zb, int& rw, int& dpg) {
+    const auto& d = G->d;
+    nb = (int)std::ceil(BP3_T * (d.vx + d.vy) / d.ds) + 4;
+    if (nb > d.n_radial) nb = d.n_radial;
+    zb = bp3_zb(G);
+    const double smax = 0.5 * (d.n_radial - 1) * d.ds;
+    const double hmin = std::sqrt(d.det_radius * d.det_radius - smax * smax);
+    const double hmax = d.det_radius;
+    const double vhalf = 0.5 * std::sqrt((double)d.nx * d.nx * d.vx * d.vx + (double)d.ny * d.ny * d.vy * d.vy);
+    const double dtau_tile = BP3_T * std::sqrt(d.vx * d.vx + d.vy * d.vy) / (2.0 * hmin);
+    const double dtau_h = vhalf * (hmax - hmin) / (2.0 * hmin * hmin);
+    const int span = (int)std::ceil(d.max_ring_diff * (dtau_tile + dtau_h) + 1e-9) + 3;
+    rw = zb + span + 1;
+    if ((rw & 1) == 0) rw += 1;
+    dpg = 8;
+    if ((long long)dpg * nb * rw > BP3_LDS) dpg = 4;
+    if ((long long)dpg * nb * rw > BP3_LDS)
+        return fail(PET_OS_ERR_INVALID_ARG, "3D geometry: back-projection footprint does not fit in LDS "
+                                            "(bins per voxel tile too many for ds)");
+    return PET_OS_OK;
+}
+
+int launch_fp3(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
+    FP3Args a;
+    a.fz = L.fz;
+    a.y = L.y;
+    a.r = L.r;
+    a.out = L.out;
+    a.angles = L.angles;
+    a.n_al = L.n_al;
+    a.mode = L.mode;
+    a.red = L.red;
+    if (L.n_al == 0) return PET_OS_OK;
+    if (L.mode != FP_COUNT && L.fz == nullptr) return fail(PET_OS_ERR_DEVICE, "3D forward projection without z copy");
+    const int grid = fp3_grid(G, L.n_al);
+    if (L.mode == FP_OBJECTIVE && grid > L.red.cap) return fail(PET_OS_ERR_DEVICE, "objective partials too small");
+    hipLaunchKernelGGL(k_fp3, dim3(grid), dim3(NT), 0, s, G->k, a);
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
+}
+
+static void fill_bp3(const pet_os_geom* G, const BPLaunch& L, BP3Args& a) {
+    a = BP3Args{};
+    a.w = L.w;
+    a.w_natural = L.w_natural;
+    if (L.w_natural) {
+        a.w_sa = G->d.n_radial;
+        a.w_sp = (long long)G->d.n_angles * G->d.n_radial;
+    } else {
+        a.w_sp = G->d.n_radial;
+        a.w_sa = (long long)G->n_planes * G->d.n_radial;
+    }
+    a.angles = L.angles;
+    a.n_al = L.n_al;
+    a.out = L.out;
+    a.f = L.f;
+    a.mu = L.mu;
+    a.want_mu = L.want_mu;
+    a.beta_over_M = L.beta_over_M;
+    a.gamma_R = L.gamma_R;
+    a.eps = L.eps;
+    a.part_f = L.part_f;
+    a.n_part_f = L.n_part_f;
+    a.red_mu = L.red_mu;
+}
+
+int launch_bp3(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
+    if (2 * G->d.max_ring_diff + 1 > BP3_MAXND) return fail(PET_OS_ERR_INVALID_ARG, "max_ring_diff too large");
+    BP3Args a;
+    fill_bp3(G, L, a);
+    int rc = bp3_shape(G, a.nb, a.zb, a.rw, a.dpg);
+    if (rc) return rc;
+    const int grid = bp3_grid(G);
+    if (L.want_mu && grid > L.red_mu.cap) return fail(PET_OS_ERR_DEVICE, "mu partials too small");
+    switch (a.zb) {
+        case 16: hipLaunchKernelGGL((k_bp3<16>), dim3(grid), dim3(NT), 0, s, G->k, a); break;
+        case 32: hipLaunchKernelGGL((k_bp3<32>), dim3(grid), dim3(NT), 0, s, G->k, a); break;
+        default: hipLaunchKernelGGL((k_bp3<64>), dim3(grid), dim3(NT), 0, s, G->k, a); break;
+    }
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
+}
+
+static void fill_upd3(const pet_os_geom* G, const UpdLaunch& L, Upd3Args& a) {
+    a.f = L.f;
+    a.fz = L.fz;
+    a.G = L.G;
+    a.mu = L.mu;
+    a.pnorm = L.pnorm;
+    a.nu_frozen = L.nu_frozen;
+    a.nu_mode = L.nu_mode;
+    a.step = L.step;
+    a.nu1 = L.nu1;
+    a.nu2 = L.nu2;
+    a.U = L.U;
+    a.t_clip = L.t_clip;
+    a.part_mu = L.part_mu;
+    a.n_part_mu = L.n_part_mu;
+    a.red_f = L.red_f;
+    a.nx = G->d.nx;
+    a.ny = G->d.ny;
+    a.nz = G->d.nz;
+}
+
+int launch_update3(const pet_os_geom* G, const UpdLaunch& L, hipStream_t s) {
+    Upd3Args a;
+    fill_upd3(G, L, a);
+    const int grid = upd3_grid(G);
+    if (grid > L.red_f.cap) return fail(PET_OS_ERR_DEVICE, "sum partials too small");
+    if (L.fz == nullptr) return fail(PET_OS_ERR_DEVICE, "3D update without z copy");
+    hipLaunchKernelGGL(k_upd3, dim3(grid), dim3(NT), 0, s, a);
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
+}
+
+int launch_prep3(const pet_os_geom* G, const float* f, float* fz, Reduction red, hipStream_t s) {
+    UpdLaunch L{};
+    L.f = const_cast<float*>(f);    // read only when update == false
+    L.fz = fz;
+    L.red_f = red;
+    Upd3Args a;
+    fill_upd3(G, L, a);
+    const int grid = upd3_grid(G);
+    if (grid > red.cap) return fail(PET_OS_ERR_DEVICE, "sum partials too small");
+    hipLaunchKernelGGL(k_prep3, dim3(grid), dim3(NT), 0, s, a);
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
+}
+
+// ------------------------------------------------------------------ batched (persistent) kernels
+
+__device__ __forceinline__ bool slot_live3(const SlotDev& d) { return d.active && d.J <= d.J_end; }
+
+__global__ __launch_bounds__(NT) void k_fp3_batch(const SlotDev* S, const Item* items, const int* count) {
+    const int n = *count;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const Item I = items[it];
+        const SlotDev& d = S[I.slot];
+        if (!slot_live3(d)) continue;
+        const int i = (d.J - 1) % d.g.n_subsets;
+        FP3Args A{};
+        A.fz = d.fz;
+        A.y = d.y;
+        A.r = d.r;
+        A.out = d.w;
+        A.angles = d.subset_lists + (long long)i * d.max_sub;
+        A.n_al = d.subset_count[i];
+        A.mode = FP_RATIO;
+        fp3_body(d.g, A, I.block);
+        __syncthreads();
+    }
+}
+
+template <int ZB>
+__global__ __launch_bounds__(NT) void k_bp3_batch(const SlotDev* S, const Item* items, const int* count) {
+    const int n = *count;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const Item I = items[it];
+        const SlotDev& d = S[I.slot];
+        if (!slot_live3(d) || d.zb != ZB) continue;
+        const int i = (d.J - 1) % d.g.n_subsets;
+        const int nu_mode = d.sched_nu[d.J - 1];
+        BP3Args A{};
+        A.w = d.w;
+        A.w_natural = 0;
+        A.w_sp = d.g.n_radial;
+        A.w_sa = (long long)d.g.n_planes * d.g.n_radial;
+        A.angles = d.subset_lists + (long long)i * d.max_sub;
+        A.n_al = d.subset_count[i];
+        A.out = d.G;
+        A.f = d.f;
+        A.mu = d.mu;
+        A.want_mu = (nu_mode == NU_COMPUTE || nu_mode == NU_COMPUTE_FREEZE) ? 1 : 0;
+        A.beta_over_M = d.beta_over_M;
+        A.gamma_R = d.gamma_R;
+        A.eps = d.eps;
+        A.part_f = d.part_f;
+        A.n_part_f = d.n_part_f;
+        A.red_mu.part = d.part_mu;
+        A.red_mu.total = nullptr;
+        A.red_mu.cap = d.n_part_mu;
+        A.nb = d.nb_max;
+        A.zb = d.zb;
+        A.rw = d.rows_max;
+        A.dpg = d.chunk;
+        bp3_body<ZB>(d.g, A, I.block);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_upd3_batch(const SlotDev* S, const Item* items, const int* count) {
+    const int n = *count;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const Item I = items[it];
+        const SlotDev& d = S[I.slot];
+        if (!slot_live3(d)) continue;
+        Upd3Args A{};
+        A.f = d.f;
+        A.fz = d.fz;
+        A.G = d.G;
+        A.mu = d.mu;
+        A.pnorm = d.pnorm;
+        A.nu_frozen = d.nu_frozen;
+        A.nu_mode = d.sched_nu[d.J - 1];
+        A.step = d.sched_step[d.J - 1];
+        A.nu1 = d.nu1;
+        A.nu2 = d.nu2;
+        A.U = d.U;
+        A.t_clip = d.t_clip;
+        A.part_mu = d.part_mu;
+        A.n_part_mu = d.n_part_mu;
+        A.red_f.part = d.part_f;
+        A.red_f.total = nullptr;
+        A.red_f.cap = d.n_part_f;
+        A.nx = d.g.nx;
+        A.ny = d.g.ny;
+        A.nz = d.g.nz;
+        upd3_body(A, I.block, true);
+        __syncthreads();
+    }
+}
+
+// the 3D part of one batched subiteration (lists WL_FP3, WL_BP3_*, WL_UPD3)
+void launch_batch3_fp(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_fp3_batch, dim3(grid), dim3(NT), 0, s, d_slots, list, cnt);
+}
+
+void launch_batch3_bp(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, int zb, hipStream_t s) {
+    if (zb == 16) hipLaunchKernelGGL((k_bp3_batch<16>), dim3(grid), dim3(NT), 0, s, d_slots, list, cnt);
+    else if (zb == 32) hipLaunchKernelGGL((k_bp3_batch<32>), dim3(grid), dim3(NT), 0, s, d_slots, list, cnt);
+    else hipLaunchKernelGGL((k_bp3_batch<64>), dim3(grid), dim3(NT), 0, s, d_slots, list, cnt);
+}
+
+void launch_batch3_upd(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_upd3_batch, dim3(grid), dim3(NT), 0, s, d_slots, list, cnt);
+}
+
+}  // namespace petos
