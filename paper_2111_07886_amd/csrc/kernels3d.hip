@@ -207,7 +207,20 @@ __device__ void fp3_body(const GeoK& g, const FP3Args& A, long long vblock) {
     if (A.mode == FP_OBJECTIVE) write_partial(term, A.red, s_red, vblock);
 }
 
-__global__ __launch_bounds__(NT) void k_fp3(GeoK g, FP3Args A) { fp3_body(g, A, blockIdx.x); }
+// Workgroups are dealt to the 8 XCDs round-robin by block index; renumber
+// them so that each XCD (and its L2) takes a contiguous run of work: the ring
+// differences of one bin read the same image columns, neighbouring tiles the
+// same sinogram rows.  The grid is 8 * ceil(n / 8) blocks.
+__device__ __forceinline__ long long xcd_block(long long block, long long n) {
+    const long long per = (n + 7) / 8;
+    return (block % 8) * per + block / 8;
+}
+
+__global__ __launch_bounds__(NT) void k_fp3(GeoK g, FP3Args A, long long n_blocks) {
+    const long long vb = xcd_block(blockIdx.x, n_blocks);
+    if (vb >= n_blocks) return;
+    fp3_body(g, A, vb);
+}
 
 // ------------------------------------------------------------------ back projection
 
@@ -237,16 +250,35 @@ constexpr int BP3_HMAX = 2;      // candidate bins of a column handled per pass
 constexpr int BP3_LDS = 12288;   // floats of the staging area (48 KB)
 constexpr int BP3_MAXND = 63;    // ring differences -31..31
 
+// LDS row stride of the staged footprint: 20 bins (3 rows per wave load) or 40
+__host__ __device__ inline int bp3_nbs(int nb) { return nb <= 20 ? 20 : 40; }
+
+// LDS shared by the back-projector's phases (declared once per kernel)
+struct BP3Shared {
+    float w[BP3_LDS];
+    double tau[2];
+    int blo, nb, npass;
+    int omin[BP3_MAXND], omax[BP3_MAXND];
+    double red[NT / 64];
+};
+
 // acc[i] += a1 w(r1 = iz - o1) + a2 w(r1 = iz - o1 - 1) for the ZB slices of
-// the block; sp[i + 1] holds w(r1 = z0 + i - o1), sp[i] the row before it.
-template <int ZB>
+// the block; sp[(i + 1) * NBS] holds w(r1 = z0 + i - o1), sp[i * NBS] the
+// row before it.  Loads go in batches of 16 to bound the live registers.
+template <int ZB, int NBS>
 __device__ __forceinline__ void bp3_apply(float (&acc)[BP3_ZMAX], const float* sp, float a1, float a2) {
     float prev = sp[0];
 #pragma unroll
-    for (int i = 0; i < ZB; ++i) {
-        const float cur = sp[i + 1];
-        acc[i] = fmaf(a1, cur, fmaf(a2, prev, acc[i]));
-        prev = cur;
+    for (int c = 0; c < ZB; c += 16) {
+        float v[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = sp[(c + i + 1) * NBS];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            acc[c + i] = fmaf(a1, v[i], fmaf(a2, prev, acc[c + i]));
+            prev = v[i];
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -254,10 +286,11 @@ __device__ __forceinline__ void bp3_apply(float (&acc)[BP3_ZMAX], const float* s
 // s_fin[lz][column] (top of the LDS area), then either store the
 // back-projection or compute the RDP gradient, mu and G of the tile's voxels.
 template <int ZB>
-__device__ void bp3_finish(const GeoK& g, const BP3Args& A, float (&acc)[BP3_ZMAX], float* s_w, double* s_red,
-                           float meanf, int vblock, int tx0, int ty0, int z0) {
+__device__ void bp3_finish(const GeoK& g, const BP3Args& A, float (&acc)[BP3_ZMAX], BP3Shared& sh, float meanf,
+                           int vblock, int tx0, int ty0, int z0) {
     constexpr int QS = ZB / 4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float* s_w = sh.w;
     float* s_fin = s_w + (BP3_LDS - ZB * 64);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -314,18 +347,96 @@ __device__ void bp3_finish(const GeoK& g, const BP3Args& A, float (&acc)[BP3_ZMA
             }
         }
     }
-    if (A.want_mu) write_partial(mu_part, A.red_mu, s_red, vblock);
+    if (A.want_mu) write_partial(mu_part, A.red_mu, sh.red, vblock);
 }
 
-template <int ZB>
-__device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock) {
-    __shared__ float s_w[BP3_LDS];
-    __shared__ int s_blo, s_nb;
-    __shared__ double s_tau[2];
-    __shared__ int s_omin[BP3_MAXND], s_omax[BP3_MAXND];
-    __shared__ int s_npass;
-    __shared__ double s_red[NT / 64];
+// Stage w of ring differences dg .. dg+dpg-1 into buf as [d][row][bin], row r
+// of d holding r1 = z0 - omax(d) + r - 1 (row 0 and invalid rings: zeros;
+// unit weights: ones).  NBS is the row stride; one wave instruction copies
+// 64/NBS consecutive rows straight from device memory into LDS.  Returns
+// without waiting: the caller waits for the loads before the barrier that
+// publishes the buffer.
+template <int NBS>
+__device__ __forceinline__ void bp3_stage(const GeoK& g, const BP3Args& A, const BP3Shared& sh, float* buf, int dg,
+                                          int z0, int aidx, int blo, int nbv) {
+    constexpr int LPI = 64 / NBS;                   // rows per wave instruction
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int sub = lane / NBS, col = lane - sub * NBS;
+    const int D = g.max_rd, ND = 2 * D + 1, R = g.n_rings, rw = A.rw, dpg = A.dpg;
+    const int nchunk = (rw + LPI - 1) / LPI;
+    for (int ds = 0; ds < dpg; ++ds) {
+        const int di = dg + ds;
+        if (di >= ND) break;
+        const int d = di - D;
+        const int lo = max(0, -d), hi = min(R - 1, R - 1 - d);
+        const int om = __builtin_amdgcn_readfirstlane(sh.omax[di]);
+        const long long plane0 = (long long)g.plane_base[di] - lo;
+        for (int ch = wave; ch < nchunk; ch += 4) {
+            const int row0 = ch * LPI;
+            float* dst = buf + (ds * rw + row0) * NBS;
+            const int row = row0 + sub;
+            const int r1 = z0 - om + row - 1;
+            const bool in_rows = sub < LPI && row < rw && col < nbv;
+            const bool ring_ok = row >= 1 && r1 >= lo && r1 <= hi;
+            if (A.w != nullptr && in_rows && ring_ok) {
+                const float* src = A.w + (plane0 + r1) * A.w_sp + (long long)aidx * A.w_sa + blo + col;
+                __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 4, 0, 0);
+            } else if (in_rows) {
+                dst[sub * NBS + col] = (A.w == nullptr && ring_ok) ? 1.0f : 0.0f;
+            }
+        }
+    }
+}
 
+// Hits of one column for one angle: the transaxial psi-interval [ax, bx] of
+// the column's cell in major cell m, for every bin b0..b1 whose ray crosses it,
+// kept as the tau values at its ends, the transaxial length and the axial
+// slope ck = ring_pitch / (2 h_b) per unit ring difference.  Slots take hits
+// first .. first + BP3_HMAX - 1 (in bin order); returns the number of hits.
+struct Hits {
+    int b[BP3_HMAX];
+    double tA[BP3_HMAX], tB[BP3_HMAX];
+    float L[BP3_HMAX], ck[BP3_HMAX];
+    bool v[BP3_HMAX];
+};
+
+__device__ __forceinline__ int col_hits(const GeoK& g, const AngleK& AK, int m, int mc, int b0, int b1, int first,
+                                        float ck0, Hits& H) {
+#pragma unroll
+    for (int k = 0; k < BP3_HMAX; ++k) {
+        H.b[k] = 0;
+        H.tA[k] = H.tB[k] = 0.0;
+        H.L[k] = H.ck[k] = 0.0f;
+        H.v[k] = false;
+    }
+    int n = 0;
+    for (int b = b0; b <= b1; ++b) {
+        const TxRay tx = tx_ray(g, AK, b);
+        const double gm = __fma_rn(tx.Q, (double)m, tx.P);
+        double ax, bx;
+        cell_interval(gm, tx.Q, tx.invQ, mc, ax, bx);
+        if (!(bx > ax)) continue;
+        const int slot = n - first;
+#pragma unroll
+        for (int k = 0; k < BP3_HMAX; ++k) {
+            if (slot == k) {
+                const ZBin zbk = z_bin(g, AK, b);
+                H.b[k] = b;
+                H.tA[k] = __fma_rn(zbk.tauQ, (double)m + ax, zbk.tau0);
+                H.tB[k] = __fma_rn(zbk.tauQ, (double)m + bx, zbk.tau0);
+                H.L[k] = (float)(tx.L * (bx - ax));
+                H.ck[k] = ck0 * (float)g.bin[b].inv2h;
+                H.v[k] = true;
+            }
+        }
+        ++n;
+    }
+    return n;
+}
+
+template <int ZB, int NBS>
+__device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared& sh) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tiles_x = (g.nx + BP3_T - 1) / BP3_T, tiles_y = (g.ny + BP3_T - 1) / BP3_T;
     int t = vblock;
@@ -335,15 +446,16 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock) {
     const int z0 = (t / tiles_y) * ZB;
     const int ix = tx0 + (lane & 7), iy = ty0 + (lane >> 3);
     const bool col_in = ix < g.nx && iy < g.ny;
-    const int D = g.max_rd, ND = 2 * D + 1, Nr = g.n_radial, R = g.n_rings;
+    const int D = g.max_rd, ND = 2 * D + 1, Nr = g.n_radial;
     const int rw = A.rw, dpg = A.dpg;
+    const float ck0 = (float)g.vz;      // ring pitch (== vz)
 
     // tile box in mm
     const double X0 = ((double)tx0 - 0.5 * g.nx) * g.vx, X1 = X0 + BP3_T * g.vx;
     const double Y0 = ((double)ty0 - 0.5 * g.ny) * g.vy, Y1 = Y0 + BP3_T * g.vy;
 
     float meanf = 1.0f;
-    if (A.f != nullptr && A.want_mu) meanf = (float)(sum_partials(A.part_f, A.n_part_f, s_red) / (double)g.nvox);
+    if (A.f != nullptr && A.want_mu) meanf = (float)(sum_partials(A.part_f, A.n_part_f, sh.red) / (double)g.nvox);
 
     float acc[BP3_ZMAX];
 #pragma unroll
@@ -355,7 +467,7 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock) {
         const int aidx = A.w_natural ? a : al;
         // (1) the tile's bins [blo, blo + nb) (+1 bin margin) and tau range
         if (threadIdx.x == 0) {
-            s_npass = 0;
+            sh.npass = 0;
             double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
             for (int k = 0; k < 4; ++k) {
                 const double x = (k & 1) ? X1 : X0, y = (k & 2) ? Y1 : Y0;
@@ -366,27 +478,27 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock) {
                 vmin = fmin(vmin, v);
                 vmax = fmax(vmax, v);
             }
-            int blo = max((int)floor(umin / g.ds + g.h0) - 1, 0);
-            int bhi = min((int)ceil(umax / g.ds + g.h0) + 1, Nr - 1);
-            const int nb = max(0, min(bhi - blo + 1, A.nb));
-            s_blo = blo;
-            s_nb = nb;
+            const int blo = max((int)floor(umin / g.ds + g.h0) - 1, 0);
+            const int bhi = min((int)ceil(umax / g.ds + g.h0) + 1, Nr - 1);
+            const int nb = max(0, min(bhi - blo + 1, min(A.nb, NBS)));
+            sh.blo = blo;
+            sh.nb = nb;
             double hmin = g.det_radius, hmax = g.det_radius;
             if (nb > 0) {
                 const int bl = blo + nb - 1;
                 hmin = fmin(g.bin[blo].h, g.bin[bl].h);
                 hmax = ((double)blo <= g.h0 && (double)bl >= g.h0) ? g.det_radius : fmax(g.bin[blo].h, g.bin[bl].h);
             }
-            s_tau[0] = 0.5 + vmin / (2.0 * (vmin < 0.0 ? hmin : hmax)) - 1e-9;
-            s_tau[1] = 0.5 + vmax / (2.0 * (vmax > 0.0 ? hmin : hmax)) + 1e-9;
+            sh.tau[0] = 0.5 + vmin / (2.0 * (vmin < 0.0 ? hmin : hmax)) - 1e-9;
+            sh.tau[1] = 0.5 + vmax / (2.0 * (vmax > 0.0 ? hmin : hmax)) + 1e-9;
         }
         __syncthreads();
         // (2) slice-offset range of every ring difference over the tile (+1 margin)
-        if (threadIdx.x < ND) {
+        if ((int)threadIdx.x < ND) {
             const double dd = (double)((int)threadIdx.x - D);
-            const double za = 0.5 + dd * s_tau[0], zc = 0.5 + dd * s_tau[1];
-            s_omin[threadIdx.x] = (int)floor(fmin(za, zc)) - 1;
-            s_omax[threadIdx.x] = (int)floor(fmax(za, zc)) + 1;
+            const double za = 0.5 + dd * sh.tau[0], zc = 0.5 + dd * sh.tau[1];
+            sh.omin[threadIdx.x] = (int)floor(fmin(za, zc)) - 1;
+            sh.omax[threadIdx.x] = (int)floor(fmax(za, zc)) + 1;
         }
         // (3) candidate bins of the column: g(m) in [mc - max(Q,0), mc + 1 - min(Q,0)]
         const int m = AK.row_major ? iy : ix;
@@ -400,105 +512,73 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock) {
             b0 = (int)fmax(floor(fmin(bA, bB)), 0.0);
             b1 = (int)fmin(ceil(fmax(bA, bB)), (double)(Nr - 1));
         }
-        // passes over the candidates, HMAX at a time: the most any column needs
-        if (b1 >= b0) atomicMax(&s_npass, (b1 - b0) / BP3_HMAX + 1);
+        // (4) the column's hits: bins whose ray crosses its cell, in bin order.
+        // A pass takes BP3_HMAX of them; one pass covers any column when ds is
+        // at least half the pixel's radial extent (e.g. ds == vx == vy).
+        Hits H;
+        const int nh = col_hits(g, AK, m, mc, b0, b1, 0, ck0, H);
+        if (nh > 0) atomicMax(&sh.npass, (nh + BP3_HMAX - 1) / BP3_HMAX);
         __syncthreads();
-        const int npass = s_npass;
+        const int npass = sh.npass;
+        const int blo = sh.blo, nbv = sh.nb;
         for (int pass = 0; pass < npass; ++pass) {
-            const int bp0 = b0 + pass * BP3_HMAX;
-            // (4) hits of this pass: transaxial psi-interval [ax, bx] of the
-            // column's cell in major cell m, kept as its tau end points
-            int hb[BP3_HMAX];
-            double htA[BP3_HMAX], htB[BP3_HMAX], hL[BP3_HMAX];
-            bool hv[BP3_HMAX];
-#pragma unroll
-            for (int k = 0; k < BP3_HMAX; ++k) {
-                const int b = bp0 + k;
-                hb[k] = b;
-                hv[k] = false;
-                htA[k] = htB[k] = hL[k] = 0.0;
-                if (b <= b1) {
-                    const TxRay tx = tx_ray(g, AK, b);
-                    const double gm = __fma_rn(tx.Q, (double)m, tx.P);
-                    double ax, bx;
-                    cell_interval(gm, tx.Q, tx.invQ, mc, ax, bx);
-                    if (bx > ax) {
-                        const ZBin zbk = z_bin(g, AK, b);
-                        htA[k] = __fma_rn(zbk.tauQ, (double)m + ax, zbk.tau0);
-                        htB[k] = __fma_rn(zbk.tauQ, (double)m + bx, zbk.tau0);
-                        hL[k] = tx.L * (bx - ax);
-                        hv[k] = true;
-                    }
-                }
-            }
-            const int blo = s_blo, nbv = s_nb;
-            for (int dg = 0; dg < ND; dg += dpg) {
-                // (5) stage w of ring differences dg .. dg+dpg-1 as [d][bin][r1]
-                __syncthreads();
-                const int nel = dpg * rw * nbv;
-                for (int e = threadIdx.x; e < nel; e += NT) {
-                    const int bcol = e % nbv;
-                    const int rem = e / nbv;
-                    const int row = rem % rw, ds = rem / rw;
-                    const int di = dg + ds;
-                    float v = 0.0f;
-                    if (di < ND && row >= 1) {
-                        const int d = di - D;
-                        const int r1 = z0 - s_omax[di] + row - 1;
-                        const int lo = max(0, -d), hi = min(R - 1, R - 1 - d);
-                        if (r1 >= lo && r1 <= hi) {
-                            if (A.w == nullptr) {
-                                v = 1.0f;
-                            } else {
-                                const int plane = g.plane_base[di] + r1 - lo;
-                                v = A.w[(long long)plane * A.w_sp + (long long)aidx * A.w_sa + blo + bcol];
-                            }
-                        }
-                    }
-                    s_w[(ds * nbv + bcol) * rw + row] = v;
-                }
-                __syncthreads();
-                // (6) gather: wave v takes the group's ring differences v, v+4
+            if (pass > 0) (void)col_hits(g, AK, m, mc, b0, b1, pass * BP3_HMAX, ck0, H);
+            // (5) stage w of ring differences in groups of dpg, double buffered:
+            // the loads of group k+1 run while group k is gathered
+            const int ngr = (ND + dpg - 1) / dpg;
+            __syncthreads();
+            bp3_stage<NBS>(g, A, sh, sh.w, 0, z0, aidx, blo, nbv);
+            for (int gi = 0; gi < ngr; ++gi) {
+                const int dg = gi * dpg;
+                float* buf = sh.w + (gi & 1) * (BP3_LDS / 2);
+                __builtin_amdgcn_s_waitcnt(0);      // this thread's loads into buf have landed
+                __syncthreads();                    // ... everyone's; the other buffer is free
+                if (gi + 1 < ngr)
+                    bp3_stage<NBS>(g, A, sh, sh.w + ((gi + 1) & 1) * (BP3_LDS / 2), dg + dpg, z0, aidx, blo, nbv);
+                // (6) gather: wave v takes the group's ring differences v, v+4, ...
                 for (int ds = wave; ds < dpg; ds += 4) {
                     const int di = dg + ds;
                     if (di >= ND) break;
-                    const double dd = (double)(di - D);
-                    const int omin = s_omin[di], omax = s_omax[di];
+                    const int d = di - D;
+                    const double dd = (double)d;
+                    const int omin = sh.omin[di], omax = sh.omax[di];
 #pragma unroll
                     for (int k = 0; k < BP3_HMAX; ++k) {
-                        if (!hv[k]) continue;
-                        const double zA = __fma_rn(dd, htA[k], 0.5), zB = __fma_rn(dd, htB[k], 0.5);
+                        if (!H.v[k]) continue;
+                        const double zA = __fma_rn(dd, H.tA[k], 0.5), zB = __fma_rn(dd, H.tB[k], 0.5);
                         const double zlo = fmin(zA, zB), zhi = fmax(zA, zB);
                         const int o1 = (int)floor(zlo), o2 = (int)floor(zhi);
-                        const double LK = hL[k] * g.kappa[(long long)hb[k] * ND + di];
-                        float a1, a2;
-                        if (o2 == o1) {
-                            a1 = (float)LK;
-                            a2 = 0.0f;
-                        } else {
-                            const double inv = 1.0 / (zhi - zlo);
-                            a1 = (float)(LK * (((double)o2 - zlo) * inv));
-                            a2 = (float)(LK * ((zhi - (double)o2) * inv));
+                        // 3D length per transaxial length of this (bin, d)
+                        const float x = (float)d * H.ck[k];
+                        const float LK = H.L[k] * sqrtf(fmaf(x, x, 1.0f));
+                        float a1 = LK, a2 = 0.0f;
+                        if (o2 != o1) {
+                            // the piece crosses slice boundary o2: split in proportion
+                            a1 = LK * ((float)((double)o2 - zlo) / (float)(zhi - zlo));
+                            a2 = LK - a1;
                         }
                         // inside the staged footprint by construction: the tile's bin
                         // window and tau range contain every hit of its columns, and
                         // the host-side bounds on bins and slice-offset span hold; the
                         // test only keeps LDS reads in range
-                        const int bcol = hb[k] - blo;
+                        const int bcol = H.b[k] - blo;
                         if (bcol >= 0 && bcol < nbv && o1 >= omin && o2 <= omax && omax - omin + ZB + 1 <= rw)
-                            bp3_apply<ZB>(acc, s_w + (ds * nbv + bcol) * rw + (omax - o1), a1, a2);
+                            bp3_apply<ZB, NBS>(acc, buf + (ds * rw + (omax - o1)) * NBS + bcol, a1, a2);
                     }
                 }
             }
         }
         __syncthreads();    // the angle's shared values are read no more
     }
-    bp3_finish<ZB>(g, A, acc, s_w, s_red, meanf, vblock, tx0, ty0, z0);
+    bp3_finish<ZB>(g, A, acc, sh, meanf, vblock, tx0, ty0, z0);
 }
 
-template <int ZB>
-__global__ __launch_bounds__(NT) void k_bp3(GeoK g, BP3Args A) {
-    bp3_body<ZB>(g, A, blockIdx.x);
+template <int ZB, int NBS>
+__global__ __launch_bounds__(NT) void k_bp3(GeoK g, BP3Args A, int n_tiles) {
+    __shared__ BP3Shared sh;
+    const int tile = (int)xcd_block(blockIdx.x, n_tiles);
+    if (tile >= n_tiles) return;
+    bp3_body<ZB, NBS>(g, A, tile, sh);
 }
 
 // ------------------------------------------------------------------ update and z-fastest copy
@@ -589,6 +669,7 @@ int fp3_grid(const pet_os_geom* G, int n_al) {
 
 int bp3_zb(const pet_os_geom* G) { return G->d.nz <= 16 ? 16 : (G->d.nz <= 32 ? 32 : 64); }
 
+
 int bp3_grid(const pet_os_geom* G) {
     const int zb = bp3_zb(G);
     return ((G->d.nx + BP3_T - 1) / BP3_T) * ((G->d.ny + BP3_T - 1) / BP3_T) * ((G->d.nz + zb - 1) / zb);
@@ -606,6 +687,7 @@ int bp3_shape(const pet_os_geom* G, int& nb, int& zb, int& rw, int& dpg) {
     const auto& d = G->d;
     nb = (int)std::ceil(BP3_T * (d.vx + d.vy) / d.ds) + 4;
     if (nb > d.n_radial) nb = d.n_radial;
+    if (nb > 40) return fail(PET_OS_ERR_INVALID_ARG, "3D geometry: more than 40 bins per 8x8 voxel tile (ds too small)");
     zb = bp3_zb(G);
     const double smax = 0.5 * (d.n_radial - 1) * d.ds;
     const double hmin = std::sqrt(d.det_radius * d.det_radius - smax * smax);
@@ -615,12 +697,12 @@ int bp3_shape(const pet_os_geom* G, int& nb, int& zb, int& rw, int& dpg) {
     const double dtau_h = vhalf * (hmax - hmin) / (2.0 * hmin * hmin);
     const int span = (int)std::ceil(d.max_ring_diff * (dtau_tile + dtau_h) + 1e-9) + 3;
     rw = zb + span + 1;
-    if ((rw & 1) == 0) rw += 1;
+    const int nbs = bp3_nbs(nb);
+    // two staging buffers of BP3_LDS/2 floats
     dpg = 8;
-    if ((long long)dpg * nb * rw > BP3_LDS) dpg = 4;
-    if ((long long)dpg * nb * rw > BP3_LDS)
-        return fail(PET_OS_ERR_INVALID_ARG, "3D geometry: back-projection footprint does not fit in LDS "
-                                            "(bins per voxel tile too many for ds)");
+    if ((long long)dpg * nbs * rw > BP3_LDS / 2) dpg = 4;
+    if ((long long)dpg * nbs * rw > BP3_LDS / 2)
+        return fail(PET_OS_ERR_INVALID_ARG, "3D geometry: back-projection footprint does not fit in LDS");
     return PET_OS_OK;
 }
 
@@ -638,7 +720,7 @@ int launch_fp3(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
     if (L.mode != FP_COUNT && L.fz == nullptr) return fail(PET_OS_ERR_DEVICE, "3D forward projection without z copy");
     const int grid = fp3_grid(G, L.n_al);
     if (L.mode == FP_OBJECTIVE && grid > L.red.cap) return fail(PET_OS_ERR_DEVICE, "objective partials too small");
-    hipLaunchKernelGGL(k_fp3, dim3(grid), dim3(NT), 0, s, G->k, a);
+    hipLaunchKernelGGL(k_fp3, dim3(8 * ((grid + 7) / 8)), dim3(NT), 0, s, G->k, a, (long long)grid);
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;
 }
@@ -676,10 +758,21 @@ int launch_bp3(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
     if (rc) return rc;
     const int grid = bp3_grid(G);
     if (L.want_mu && grid > L.red_mu.cap) return fail(PET_OS_ERR_DEVICE, "mu partials too small");
+    const bool wide = bp3_nbs(a.nb) == 40;
+    const dim3 blocks(8 * ((grid + 7) / 8));
     switch (a.zb) {
-        case 16: hipLaunchKernelGGL((k_bp3<16>), dim3(grid), dim3(NT), 0, s, G->k, a); break;
-        case 32: hipLaunchKernelGGL((k_bp3<32>), dim3(grid), dim3(NT), 0, s, G->k, a); break;
-        default: hipLaunchKernelGGL((k_bp3<64>), dim3(grid), dim3(NT), 0, s, G->k, a); break;
+        case 16:
+            if (wide) hipLaunchKernelGGL((k_bp3<16, 40>), blocks, dim3(NT), 0, s, G->k, a, grid);
+            else hipLaunchKernelGGL((k_bp3<16, 20>), blocks, dim3(NT), 0, s, G->k, a, grid);
+            break;
+        case 32:
+            if (wide) hipLaunchKernelGGL((k_bp3<32, 40>), blocks, dim3(NT), 0, s, G->k, a, grid);
+            else hipLaunchKernelGGL((k_bp3<32, 20>), blocks, dim3(NT), 0, s, G->k, a, grid);
+            break;
+        default:
+            if (wide) hipLaunchKernelGGL((k_bp3<64, 40>), blocks, dim3(NT), 0, s, G->k, a, grid);
+            else hipLaunchKernelGGL((k_bp3<64, 20>), blocks, dim3(NT), 0, s, G->k, a, grid);
+            break;
     }
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;
@@ -757,6 +850,7 @@ __global__ __launch_bounds__(NT) void k_fp3_batch(const SlotDev* S, const Item* 
 
 template <int ZB>
 __global__ __launch_bounds__(NT) void k_bp3_batch(const SlotDev* S, const Item* items, const int* count) {
+    __shared__ BP3Shared sh;
     const int n = *count;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const Item I = items[it];
@@ -787,7 +881,8 @@ __global__ __launch_bounds__(NT) void k_bp3_batch(const SlotDev* S, const Item* 
         A.zb = d.zb;
         A.rw = d.rows_max;
         A.dpg = d.chunk;
-        bp3_body<ZB>(d.g, A, I.block);
+        if (bp3_nbs(A.nb) == 40) bp3_body<ZB, 40>(d.g, A, I.block, sh);
+        else bp3_body<ZB, 20>(d.g, A, I.block, sh);
         __syncthreads();
     }
 }
