@@ -129,6 +129,12 @@ static void build_angles(const pet_os_geom_desc* d, std::vector<AngleK>& out) {
         }
         K.inv_du = 1.0 / K.du;
         K.inv_wslope = 1.0 / K.wslope;
+        if (c != 0.0 && s != 0.0) {
+            const double ex = 0.5 * d->vx * std::fabs(c), ey = 0.5 * d->vy * std::fabs(s);
+            K.e_out = ex + ey;
+            K.inv_de = 1.0 / (K.e_out - std::fabs(ex - ey));
+            K.Lmax = std::min(d->vx / std::fabs(s), d->vy / std::fabs(c));
+        }
         out[a] = K;
     }
 }

@@ -176,6 +176,10 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
     const bool inside = ix < g.nx && iy < g.ny;
     const int Nr = g.n_radial;
     const int nb_max = A.nb_max;
+    const double inv_ds = 1.0 / g.ds;
+    // pixel centre in mm
+    const double xc = ((double)ix - 0.5 * (double)(g.nx - 1)) * g.vx;
+    const double yc = ((double)iy - 0.5 * (double)(g.ny - 1)) * g.vy;
 
     // tile box in mm
     const double X0 = ((double)tx0 - 0.5 * g.nx) * g.vx, X1 = X0 + T::X * g.vx;
@@ -229,35 +233,47 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
             __syncthreads();
         }
 
-        // (3) gather: every bin whose ray crosses this pixel
+        // (3) gather: every bin whose ray crosses this pixel.  Oblique angles
+        // use the closed form of the chord length through the pixel (a
+        // trapezoid in the radial offset t of the ray from the pixel centre),
+        // so the window holds just the bins with |t| < e_out; axis-parallel
+        // angles keep the half-open cell rule of the forward projector.
         if (inside) {
             for (int j = grp; j < nch; j += T::AG) {
                 const int al = c0 + j;
                 const int a = A.angles[al];
                 const AngleK& AK = g.ang[a];
-                const int m = AK.row_major ? iy : ix;
-                const int mc = AK.row_major ? ix : iy;
-                // g(m) in [mc - max(Q,0), mc + 1 - min(Q,0)] selects the bins
-                const double base = __fma_rn(AK.Q, (double)m, AK.wC);
-                const double glo = (double)mc - fmax(AK.Q, 0.0) - 1e-7;
-                const double ghi = (double)mc + 1.0 - fmin(AK.Q, 0.0) + 1e-7;
-                const double bA = (glo - base) * AK.inv_wslope, bB = (ghi - base) * AK.inv_wslope;
-                const int b0 = (int)fmax(floor(fmin(bA, bB)), 0.0);
-                const int b1 = (int)fmin(ceil(fmax(bA, bB)), (double)(Nr - 1));
                 const int aidx = A.w_natural ? a : al;
-                for (int b = b0; b <= b1; ++b) {
-                    const TxRay tx = tx_ray(g, AK, b);
-                    const double gm = __fma_rn(tx.Q, (double)m, tx.P);
-                    double ax, bx;
-                    cell_interval(gm, tx.Q, tx.invQ, mc, ax, bx);
-                    if (!(bx > ax)) continue;
-                    float wv = 1.0f;
-                    if (A.w != nullptr) {
-                        const int bcol = b - s_blo[j];
-                        wv = (bcol >= 0 && bcol < s_nb[j]) ? s_w[j * nb_max + bcol] : A.w[(long long)aidx * A.w_sa + b];
+                const int bst = s_blo[j], nbs = s_nb[j];
+                auto wval = [&](int b) -> float {
+                    if (A.w == nullptr) return 1.0f;
+                    const int bcol = b - bst;
+                    return (bcol >= 0 && bcol < nbs) ? s_w[j * nb_max + bcol] : A.w[(long long)aidx * A.w_sa + b];
+                };
+                if (AK.Q != 0.0) {
+                    const double uc = __fma_rn(xc, AK.c, yc * AK.s);
+                    const int b0 = max((int)ceil((uc - AK.e_out) * inv_ds + g.h0), 0);
+                    const int b1 = min((int)floor((uc + AK.e_out) * inv_ds + g.h0), Nr - 1);
+                    for (int b = b0; b <= b1; ++b) {
+                        const double tt = fabs(__fma_rn((double)b - g.h0, g.ds, -uc));
+                        const double len = AK.Lmax * fmin(1.0, (AK.e_out - tt) * AK.inv_de);
+                        if (len > 0.0) acc = fmaf((float)len, wval(b), acc);
                     }
-                    const float aij = (float)(tx.L * (bx - ax));
-                    acc = fmaf(aij, wv, acc);
+                } else {
+                    const int m = AK.row_major ? iy : ix;
+                    const int mc = AK.row_major ? ix : iy;
+                    // axis-parallel: bins whose exact position falls in cell mc
+                    const double base = AK.wC;
+                    const double bA = ((double)mc - 1e-7 - base) * AK.inv_wslope;
+                    const double bB = ((double)mc + 1.0 + 1e-7 - base) * AK.inv_wslope;
+                    const int b0 = (int)fmax(floor(fmin(bA, bB)), 0.0);
+                    const int b1 = (int)fmin(ceil(fmax(bA, bB)), (double)(Nr - 1));
+                    for (int b = b0; b <= b1; ++b) {
+                        const TxRay tx = tx_ray(g, AK, b);
+                        double ax, bx;
+                        cell_interval(__fma_rn(tx.Q, (double)m, tx.P), tx.Q, tx.invQ, mc, ax, bx);
+                        if (bx > ax) acc = fmaf((float)(tx.L * (bx - ax)), wval(b), acc);
+                    }
                 }
             }
         }

@@ -1,6 +1,5 @@
-// raygeom.h -- per-ray geometry shared by the forward (ray-driven) and
-// back (voxel-driven) projectors, so that both evaluate the same chord
-// length a_ij with the same floating-point operations.
+// raygeom.h -- per-ray geometry of the forward (ray-driven) and back
+// (voxel-driven) projectors.
 //
 // System model (Sec. IV-A): a_ij = length of LOR i inside voxel j.  A ray is
 // walked along its "major" transaxial axis (rows when |cos| vx >= |sin| vy,
@@ -12,8 +11,10 @@
 // where L is the 3D length of the piece.  Axis-parallel rays (Q == 0) lie in
 // cell floor(P): a ray on a cell's lower edge belongs to that cell.
 //
-// All positions are FP64 so that the cell decisions of the two projectors
-// agree with each other exactly and with an FP64 reference to rounding.
+// All positions are FP64, so that cell decisions agree with an FP64 reference
+// up to rounding.  The 2D back-projector evaluates the same chord length in
+// closed form for oblique rays (AngleK::e_out, inv_de, Lmax); the 3D one
+// splits the transaxial piece among slices by the same axial coordinate.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -31,6 +32,12 @@ struct AngleK {
     double inv_du;      // 1 / du
     double wslope, wC;  // P(b) ~= wslope * b + wC (candidate windows only)
     double inv_wslope;  // 1 / wslope
+    // chord length through one vx x vy cell as a function of the offset t of
+    // the line from the cell centre (radially): Lmax for |t| <= e_in, falling
+    // linearly to 0 at |t| = e_out (oblique angles only)
+    double e_out;       // (vx |c| + vy |s|) / 2
+    double inv_de;      // 1 / (e_out - e_in), e_in = |vx |c| - vy |s|| / 2
+    double Lmax;        // min(vx / |s|, vy / |c|)
     int row_major;      // 1: major axis = y (rows), minor = x
     int pad;
 };
@@ -66,10 +73,6 @@ struct TxRay {
     int row_major;
 };
 
-struct ZRay {
-    double Pz, Qz, invQz, kap;   // kap = 3D length factor
-};
-
 __device__ __forceinline__ double bin_pos(const GeoK& g, int b) { return ((double)b - g.h0) * g.ds; }
 
 __device__ __forceinline__ TxRay tx_ray(const GeoK& g, const AngleK& A, int b) {
@@ -101,23 +104,6 @@ __device__ __forceinline__ ZBin z_bin(const GeoK& g, const AngleK& A, int b) {
     zb.tauQ = A.du * B.inv2h;
     zb.inv_tauQ = A.inv_du * (2.0 * B.h);
     return zb;
-}
-
-__device__ __forceinline__ ZRay z_ray(const GeoK& g, const ZBin& zb, int b, int r1, int d) {
-    ZRay z;
-    if (d == 0) {
-        z.Pz = (double)r1 + 0.5;
-        z.Qz = 0.0;
-        z.invQz = 0.0;
-        z.kap = 1.0;
-        return z;
-    }
-    double dd = (double)d;
-    z.Pz = __fma_rn(dd, zb.tau0, (double)r1 + 0.5);
-    z.Qz = dd * zb.tauQ;
-    z.invQz = g.inv_d[d + g.max_rd] * zb.inv_tauQ;
-    z.kap = g.kappa[b * (2 * g.max_rd + 1) + d + g.max_rd];
-    return z;
 }
 
 // psi-interval [lo, hi] of cell `cell` for a coordinate starting at g0 and
