@@ -36,6 +36,9 @@ WORKLOADS = {
 KERNELS = {0: "k_fp (forward projection + Poisson ratio)",
            1: "k_bp (back-projection + RDP gradient + mu)",
            2: "k_update (nu, S, relaxed step, P_t)"}
+# 2D: two launches per subiteration (the update is fused into the back-projection)
+KERNELS_2D = {0: "k_fp_px (forward projection + Poisson ratio; snapshot of f and mu)",
+              1: "k_bp (back-projection + RDP gradient + nu, S, relaxed step, P_t)"}
 
 
 def kernel_source_hash():
@@ -46,11 +49,18 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(kernel, nnz_sub, rays_sub, q):
-    """Bytes one launch must move (A is computed on the fly, never stored):
-    forward: 4 B image gather per nonzero + read y, r and write w per ray;
-    back: 4 B w gather per nonzero + stage w once per ray + read f, write G, mu;
-    update: read f, G, mu, p and write f per voxel."""
+def algorithmic_bytes(kernel, nnz_sub, rays_sub, q, dim=3):
+    """Bytes one launch must move (A is computed on the fly, never stored).
+    3D: forward: 4 B image gather per nonzero + read y, r and write w per ray;
+    back: 4 B w gather per nonzero + stage w once per ray + read f, write G,
+    mu; update: read f, G, mu, p and write f per voxel.  2D, two launches:
+    forward + pixel pass (read f, write its snapshot and mu), and
+    back-projection + update (read the snapshot, mu, p, write f).  Either way
+    8 nnz + 16 rays + 32 q per subiteration."""
+    if dim == 2:
+        if kernel == 0:
+            return 4.0 * nnz_sub + 12.0 * rays_sub + 12.0 * q
+        return 4.0 * nnz_sub + 4.0 * rays_sub + 20.0 * q
     if kernel == 0:
         return 4.0 * nnz_sub + 12.0 * rays_sub
     if kernel == 1:
@@ -143,12 +153,17 @@ def bench_served(args):
     """Poisson arrivals (200 req/s) of 2D (128..320 px) and 3D (128x128x32)
     requests, 30 iterations each: the continuous-batching server vs the same
     trace served one request at a time (FIFO) by pet_os_reconstruct."""
+    import tempfile
+
     import numpy as np
     import torch
 
     import paper_2111_07886_amd as pet
     from synth import configs, phantoms
 
+    # the server and the plain path take the same autotuned shapes for a
+    # geometry (the tuning result is timed, so it may differ run to run)
+    os.environ["PET_OS_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="petos_tune_"), "tune.txt")
     trace = configs.c5_trace(n_requests=args.requests)
     dev = torch.device("cuda:0")
     reqs = []
@@ -296,14 +311,17 @@ def main():
     rays_sub = geom.n_bins / M
     q = geom.n_voxels
     per_kernel = {}
+    dim = w.desc["dim"]
+    names = KERNELS_2D if dim == 2 else KERNELS
     if not args.no_profile:
-        for k in (0, 1, 2):
+        for k in names:
             state.profile(k)
             state.run(f, y, r, min(args.steps, 10), want_objective=True)
             ms, n = state.profile_read()
             state.profile(-1)
-            per_kernel[k] = dict(avg_us=1e3 * ms / max(n, 1), launches=n,
-                                 bytes=algorithmic_bytes(k, nnz_sub, rays_sub, q))
+            if n:
+                per_kernel[k] = dict(avg_us=1e3 * ms / n, launches=n,
+                                     bytes=algorithmic_bytes(k, nnz_sub, rays_sub, q, dim))
     roofline = None
     if per_kernel:
         dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"])
@@ -317,9 +335,9 @@ def main():
                 traffic = t["bytes_per_launch"][str(dom)]
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                    "kernel": KERNELS[dom], "avg_launch_us": round(K["avg_us"], 3),
+                    "kernel": names[dom], "avg_launch_us": round(K["avg_us"], 3),
                     "algorithmic_bytes_per_launch": int(K["bytes"]),
-                    "per_kernel_us": {KERNELS[k].split()[0]: round(v["avg_us"], 3) for k, v in per_kernel.items()}}
+                    "per_kernel_us": {names[k].split()[0]: round(v["avg_us"], 3) for k, v in per_kernel.items()}}
 
     del state
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, p)

@@ -88,14 +88,18 @@ int rebuild_lists(pet_os_batch* B) {
         const BatchSlot& S = B->slots[s];
         if (!S.used) continue;
         const bool d3 = S.g->d.dim == 3;
-        const int nfp = d3 ? fp3_grid(S.g, S.g->max_sub_angles) : fp_grid_seg(S.g, S.g->max_sub_angles, S.fp_seg);
+        // 2D: forward blocks, then the pixel-pass blocks (snapshot, mu)
+        const int nfp = d3 ? fp3_grid(S.g, S.g->max_sub_angles)
+                           : fp_grid_seg(S.g, S.g->max_sub_angles, S.fp_seg) + px_grid(S.g);
         for (int b = 0; b < nfp; ++b) L[d3 ? WL_FP3 : WL_FP].push_back({s, b});
         const int nbp = bp_grid_kind(S.g, S.bp_kind);
         const int wbp = d3 ? (bp3_zb(S.g) == 16 ? WL_BP3_16 : (bp3_zb(S.g) == 32 ? WL_BP3_32 : WL_BP3_64))
                            : WL_BP0 + S.bp_kind;
         for (int b = 0; b < nbp; ++b) L[wbp].push_back({s, b});
-        const int nup = sumf_grid(S.g);
-        for (int b = 0; b < nup; ++b) L[d3 ? WL_UPD3 : WL_UPD].push_back({s, b});
+        if (d3) {
+            const int nup = upd3_grid(S.g);
+            for (int b = 0; b < nup; ++b) L[WL_UPD3].push_back({s, b});
+        }
     }
     int mask = 0;
     for (int k = 0; k < WL_COUNT; ++k) {
@@ -247,10 +251,12 @@ int pet_os_batch_add(pet_os_batch* B, const pet_os_geom* g, const pet_os_params*
     D.mu = S.w.mu;
     D.nu_frozen = S.w.nu_frozen;
     D.fz = S.w.fz;
+    D.fsnap = S.w.fsnap;
+    D.n_fp = g->d.dim == 3 ? 0 : fp_grid_seg(g, g->max_sub_angles, S.fp_seg);
     D.part_f = S.w.red[RED_SUMF].part;
     D.part_mu = S.w.red[RED_SUMMU].part;
     D.n_part_f = sumf_grid(g);
-    D.n_part_mu = bp_grid_kind(g, S.bp_kind);
+    D.n_part_mu = g->d.dim == 3 ? bp_grid_kind(g, S.bp_kind) : px_grid(g);
     D.subset_lists = ex->subset_lists;
     D.subset_count = ex->d_subset_count;
     D.max_sub = g->max_sub_angles;

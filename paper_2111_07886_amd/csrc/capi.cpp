@@ -380,9 +380,10 @@ int work_alloc(const pet_os_geom* g, bool need_nu, Work* w) {
     size_t o_nu = need_nu ? cv.take<float>(nv) : 0;
     const bool d3 = g->d.dim == 3;
     size_t o_fz = d3 ? cv.take<float>(nv) : 0;
+    size_t o_snap = d3 ? 0 : cv.take<float>(nv);
     int caps[RED_COUNT];
-    caps[RED_SUMF] = std::max(sumf_grid(g), elem_grid(g->n_vox));
-    caps[RED_SUMMU] = bp_grid_max(g);
+    caps[RED_SUMF] = std::max(std::max(sumf_grid(g), bp_grid_max(g)), elem_grid(g->n_vox));
+    caps[RED_SUMMU] = std::max(bp_grid_max(g), elem_grid(g->n_vox));
     caps[RED_FID] = fp_grid(g, g->d.n_angles);
     caps[RED_RDP] = elem_grid(g->n_vox);
     caps[RED_SUMY] = elem_grid(g->n_bins);
@@ -400,6 +401,7 @@ int work_alloc(const pet_os_geom* g, bool need_nu, Work* w) {
     w->mu = (float*)(blk + o_mu);
     w->nu_frozen = need_nu ? (float*)(blk + o_nu) : nullptr;
     w->fz = d3 ? (float*)(blk + o_fz) : nullptr;
+    w->fsnap = d3 ? nullptr : (float*)(blk + o_snap);
     for (int r = 0; r < RED_COUNT; ++r) {
         w->red[r].part = (double*)(blk + o_red[r]);
         w->red[r].total = (double*)(blk + o_tot) + r;
@@ -531,39 +533,63 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
     }
     const int* angles = ex->subset_lists + (size_t)(st->i - 1) * g->max_sub_angles;
     const int n_al = ex->subset_count[st->i - 1];
+    const bool d3 = g->d.dim == 3;
     FPLaunch F{};
     F.f = f; F.fz = st->w.fz; F.y = y; F.r = r; F.out = st->w.w; F.angles = angles; F.n_al = n_al;
     F.mode = FP_RATIO;
     // threads per ray chosen for the largest subset, as the batched path does
     F.seg = fp_seg_for(g, (long long)g->max_sub_angles * g->n_planes * g->d.n_radial, g->tuned_seg);
+    if (!d3) {
+        // 2D: the pixel pass (snapshot of f, mu) rides in the forward launch
+        F.px_fsnap = st->w.fsnap;
+        F.px_mu = st->w.mu;
+        F.px_want_mu = want_mu ? 1 : 0;
+        F.px_part_f = st->w.red[RED_SUMF].part;
+        F.px_n_part_f = sumf_grid(g);
+        F.px_red_mu = st->w.red[RED_SUMMU];
+    }
     hipEvent_t ev;
     if ((rc = prof_begin(st, 0, s, &ev))) return rc;
     rc = launch_fp(g, F, s);
     if (rc || (rc = prof_end(ev, s))) return rc;
     BPLaunch B{};
-    B.w = st->w.w; B.w_natural = 0; B.angles = angles; B.n_al = n_al; B.out = st->w.G;
-    B.f = f; B.mu = st->w.mu; B.want_mu = want_mu ? 1 : 0;
+    B.w = st->w.w; B.w_natural = 0; B.angles = angles; B.n_al = n_al;
     B.beta_over_M = (float)(st->p.beta / (double)M);
     B.gamma_R = (float)st->p.gamma_R;
     B.eps = (float)st->p.eps;
-    B.part_f = st->w.red[RED_SUMF].part;
-    B.n_part_f = sumf_grid(g);
-    B.red_mu = st->w.red[RED_SUMMU];
-    if ((rc = prof_begin(st, 1, s, &ev))) return rc;
-    rc = launch_bp(g, B, s);
-    if (rc || (rc = prof_end(ev, s))) return rc;
-    UpdLaunch U{};
-    U.f = f; U.fz = st->w.fz; U.G = st->w.G; U.mu = st->w.mu; U.pnorm = g->pnorm; U.nu_frozen = st->w.nu_frozen;
-    U.nu_mode = sc.nu_mode;
-    U.step = (float)(sc.lam * sc.alpha);
-    U.nu1 = (float)st->p.nu1; U.nu2 = (float)st->p.nu2;
-    U.U = (float)st->p.U; U.t_clip = (float)st->p.t_clip;
-    U.part_mu = st->w.red[RED_SUMMU].part;
-    U.n_part_mu = bp_grid(g);
-    U.red_f = st->w.red[RED_SUMF];
-    if ((rc = prof_begin(st, 2, s, &ev))) return rc;
-    rc = launch_update(g, U, s);
-    if (rc || (rc = prof_end(ev, s))) return rc;
+    const float step = (float)(sc.lam * sc.alpha);
+    if (!d3) {
+        // 2D: back-projection, penalty gradient and update of each tile in one launch
+        B.f = st->w.fsnap; B.out = nullptr; B.mu = st->w.mu; B.want_mu = 0;
+        B.fnew = f; B.pnorm = g->pnorm; B.nu_frozen = st->w.nu_frozen; B.nu_mode = sc.nu_mode;
+        B.step = step; B.nu1 = (float)st->p.nu1; B.nu2 = (float)st->p.nu2;
+        B.U = (float)st->p.U; B.t_clip = (float)st->p.t_clip;
+        B.part_mu = st->w.red[RED_SUMMU].part; B.n_part_mu = px_grid(g);
+        B.red_f = st->w.red[RED_SUMF];
+        if ((rc = prof_begin(st, 1, s, &ev))) return rc;
+        rc = launch_bp(g, B, s);
+        if (rc || (rc = prof_end(ev, s))) return rc;
+    } else {
+        B.f = f; B.out = st->w.G; B.mu = st->w.mu; B.want_mu = want_mu ? 1 : 0;
+        B.part_f = st->w.red[RED_SUMF].part;
+        B.n_part_f = sumf_grid(g);
+        B.red_mu = st->w.red[RED_SUMMU];
+        if ((rc = prof_begin(st, 1, s, &ev))) return rc;
+        rc = launch_bp(g, B, s);
+        if (rc || (rc = prof_end(ev, s))) return rc;
+        UpdLaunch U{};
+        U.f = f; U.fz = st->w.fz; U.G = st->w.G; U.mu = st->w.mu; U.pnorm = g->pnorm; U.nu_frozen = st->w.nu_frozen;
+        U.nu_mode = sc.nu_mode;
+        U.step = step;
+        U.nu1 = (float)st->p.nu1; U.nu2 = (float)st->p.nu2;
+        U.U = (float)st->p.U; U.t_clip = (float)st->p.t_clip;
+        U.part_mu = st->w.red[RED_SUMMU].part;
+        U.n_part_mu = bp_grid(g);
+        U.red_f = st->w.red[RED_SUMF];
+        if ((rc = prof_begin(st, 2, s, &ev))) return rc;
+        rc = launch_update(g, U, s);
+        if (rc || (rc = prof_end(ev, s))) return rc;
+    }
     if (sc.nu_mode == NU_COMPUTE_FREEZE) st->have_frozen = 1;
     st->i += 1;
     if (st->i > M) { st->i = 1; st->k += 1; }

@@ -65,6 +65,7 @@ struct Work {
     float* mu = nullptr;       // smoothness measure
     float* nu_frozen = nullptr;
     float* fz = nullptr;       // 3D: copy of the iterate with z fastest [(iy*nx+ix)*nz+iz]
+    float* fsnap = nullptr;    // 2D: snapshot of the iterate entering the subiteration
     double* red_block = nullptr;   // reductions' storage
     Reduction red[RED_COUNT];
     int* angle_list = nullptr;     // device copy of all subset angle lists [M][max_sub]
@@ -108,6 +109,13 @@ struct FPLaunch {
     int mode;
     Reduction red;           // FP_OBJECTIVE
     int seg = 0;             // threads per ray (0: tuned or heuristic)
+    // 2D subiteration: pixel pass in the same launch (snapshot of f and mu)
+    float* px_fsnap = nullptr;
+    float* px_mu = nullptr;
+    int px_want_mu = 0;
+    const double* px_part_f = nullptr;
+    int px_n_part_f = 0;
+    Reduction px_red_mu{};
 };
 int launch_fp(const pet_os_geom* g, const FPLaunch& L, hipStream_t s);
 
@@ -127,6 +135,15 @@ struct BPLaunch {
     const double* part_f;    // partials of sum f of the current iterate (for mean f)
     int n_part_f;
     Reduction red_mu;
+    // 2D fused update (fnew non-null; f is the snapshot of the iterate)
+    float* fnew = nullptr;
+    const float* pnorm = nullptr;
+    float* nu_frozen = nullptr;
+    int nu_mode = 0;
+    float step = 0, nu1 = 0, nu2 = 0, U = 0, t_clip = 0;
+    const double* part_mu = nullptr;   // partials of sum mu from the pixel pass
+    int n_part_mu = 0;
+    Reduction red_f{};                 // partials of sum of the new iterate
 };
 int launch_bp(const pet_os_geom* g, const BPLaunch& L, hipStream_t s);
 
@@ -162,6 +179,7 @@ int bp_grid_kind(const pet_os_geom* g, int kind);
 int bp_grid(const pet_os_geom* g);
 int bp_grid_max(const pet_os_geom* g);
 int elem_grid(int64_t n);
+int px_grid(const pet_os_geom* g);   // blocks of the 2D pixel pass (partials of sum mu)
 // number of partials of sum f left by the update (and by launch_sum / launch_prep3)
 int sumf_grid(const pet_os_geom* g);
 int launch_sum_f(const pet_os_geom* g, const float* f, float* fz, Reduction red, hipStream_t s);
@@ -193,6 +211,8 @@ struct SlotDev {
     float* mu;
     float* nu_frozen;
     float* fz;                 // 3D: z-fastest copy of f
+    float* fsnap;              // 2D: snapshot of f
+    int n_fp;                  // 2D: forward-projection blocks before the pixel blocks
     double* part_f;
     double* part_mu;
     int n_part_f, n_part_mu;
@@ -214,10 +234,11 @@ struct Item {
     int block;
 };
 
-// work lists: 2D forward, 2D back-projection per tile kind, 2D update, and
-// the 3D forward, back-projection per z-block size (16/32/64) and update
-enum { WL_FP = 0, WL_BP0 = 1, WL_BP1 = 2, WL_UPD = 3, WL_FP3 = 4, WL_BP3_16 = 5, WL_BP3_32 = 6, WL_BP3_64 = 7,
-       WL_UPD3 = 8, WL_COUNT = 9 };
+// work lists: 2D forward + pixel pass, 2D back-projection + update per tile
+// kind, and the 3D forward, back-projection per z-block size (16/32/64) and
+// update
+enum { WL_FP = 0, WL_BP0 = 1, WL_BP1 = 2, WL_FP3 = 3, WL_BP3_16 = 4, WL_BP3_32 = 5, WL_BP3_64 = 6,
+       WL_UPD3 = 7, WL_COUNT = 8 };
 
 // Queue one batched subiteration (every active slot advances by one):
 // forward, back-projection (one launch per tile kind), update, advance.

@@ -142,7 +142,35 @@ struct BPArgs {
     Reduction red_mu;
     int nb_max;              // staged bins per angle
     int chunk;               // angles staged together
+    // fused update of a 2D subiteration (fnew non-null): f is then the
+    // snapshot of the entering iterate, G is not stored, and the new iterate
+    // of the tile goes to fnew with the FP64 partials of its sum
+    float* fnew;
+    const float* pnorm;
+    float* nu_frozen;
+    int nu_mode;
+    float step, nu1, nu2, U, t_clip;
+    const double* part_mu;
+    int n_part_mu;
+    Reduction red_f;
 };
+
+// nu of eq:nuki, S of eq:preconditioner, the relaxed step of Table I and P_t
+// of eq:OperatorPt at one voxel; meanmu is mean(mu) when nu is recomputed
+__device__ __forceinline__ float sdp_update(float fj, float Gj, float pj, float muj, float meanmu, float* nu_frozen,
+                                            long long j, int nu_mode, float step, float nu1, float nu2, float U,
+                                            float t_clip) {
+    float nu = 1.0f;
+    if (nu_mode == NU_COMPUTE || nu_mode == NU_COMPUTE_FREEZE) {
+        nu = fminf(nu2, fmaxf(nu1, meanmu / muj));
+        if (nu_mode == NU_COMPUTE_FREEZE) nu_frozen[j] = nu;
+    } else if (nu_mode == NU_FROZEN) {
+        nu = nu_frozen[j];
+    }
+    const float S = (fj < 0.5f * U) ? fj / pj : (U - fj) / pj;
+    const float ft = fj - step * nu * S * Gj;
+    return (ft <= 0.0f) ? t_clip : ((ft >= U) ? U - t_clip : ft);
+}
 
 // Tile of the back-projector: X x Y pixels, AG threads per pixel (each takes
 // every AG-th angle of the subset; partial sums added in group order).
@@ -198,6 +226,9 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
     }
     float meanf = 1.0f;
     if (A.f != nullptr && A.want_mu) meanf = (float)(sum_partials(A.part_f, A.n_part_f, s_red) / (double)g.nvox);
+    float meanmu = 1.0f;
+    if (A.fnew != nullptr && (A.nu_mode == NU_COMPUTE || A.nu_mode == NU_COMPUTE_FREEZE))
+        meanmu = (float)(sum_partials(A.part_mu, A.n_part_mu, s_red) / (double)g.nvox);
 
     float acc = 0.0f;
     for (int c0 = 0; c0 < A.n_al; c0 += A.chunk) {
@@ -292,22 +323,49 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
         return;
     }
 
-    // (4) fused image-space part: grad R, mu, G = A_i^T w + (beta/M) grad R
-    // (the halo tile was loaded before the gather)
+    // (4) fused image-space part: grad R, G = A_i^T w + (beta/M) grad R and
+    // either mu (Sec. III-B) or the update of the tile (the halo tile was
+    // loaded before the gather)
     __syncthreads();
-    double mu_part = 0.0;
+    double part = 0.0;
     if (inside && owner) {
         float gradR, gmag;
         stencil_at<2>(s_f, HX, HY, lx + 1, ly + 1, 0, ix, iy, 0, g, A.gamma_R, A.eps, gradR, gmag);
         const long long j = (long long)iy * g.nx + ix;
-        A.out[j] = fmaf(A.beta_over_M, gradR, acc);
-        if (A.want_mu) {
-            const float mu = fmaxf(0.01f, gmag / meanf);
-            A.mu[j] = mu;
-            mu_part = (double)mu;
+        const float Gj = fmaf(A.beta_over_M, gradR, acc);
+        if (A.fnew != nullptr) {
+            const float fj = s_f[(ly + 1) * HX + lx + 1];
+            const bool need_mu = A.nu_mode == NU_COMPUTE || A.nu_mode == NU_COMPUTE_FREEZE;
+            const float fn = sdp_update(fj, Gj, A.pnorm[j], need_mu ? A.mu[j] : 1.0f, meanmu, A.nu_frozen, j,
+                                        A.nu_mode, A.step, A.nu1, A.nu2, A.U, A.t_clip);
+            A.fnew[j] = fn;
+            part = (double)fn;
+        } else {
+            A.out[j] = Gj;
+            if (A.want_mu) {
+                const float mu = fmaxf(0.01f, gmag / meanf);
+                A.mu[j] = mu;
+                part = (double)mu;
+            }
         }
     }
-    if (A.want_mu) write_partial(mu_part, A.red_mu, s_red, vblock);
+    if (A.fnew != nullptr) write_partial(part, A.red_f, s_red, vblock);
+    else if (A.want_mu) write_partial(part, A.red_mu, s_red, vblock);
+}
+
+// Partials of sum f over the same tiles, threads and order as the fused
+// update writes them (for an iterate handed in by the caller).
+template <class T>
+__global__ __launch_bounds__(NT) void k_sum_tiles(GeoK g, const float* f, Reduction R) {
+    __shared__ double s_red[NT / 64];
+    constexpr int NV = T::X * T::Y;
+    const int tiles_x = (g.nx + T::X - 1) / T::X;
+    const int vox = threadIdx.x % NV;
+    const int ix = (blockIdx.x % tiles_x) * T::X + vox % T::X;
+    const int iy = (blockIdx.x / tiles_x) * T::Y + vox / T::X;
+    double v = 0.0;
+    if ((int)threadIdx.x < NV && ix < g.nx && iy < g.ny) v = (double)f[(long long)iy * g.nx + ix];
+    write_partial(v, R, s_red, blockIdx.x);
 }
 
 template <class T>
@@ -317,52 +375,73 @@ __global__ __launch_bounds__(NT) void k_bp(GeoK g, BPArgs A) {
 
 // ------------------------------------------------------------------ update
 
-struct UpdArgs {
-    float* f;
-    const float* G;
-    const float* mu;
-    const float* pnorm;
-    float* nu_frozen;
-    int nu_mode;
-    float step, nu1, nu2, U, t_clip;
-    const double* part_mu;
-    int n_part_mu;
-    Reduction red_f;
-    long long n;
-};
-
-__device__ void upd_body(const UpdArgs& A, long long vblock) {
-    __shared__ double s_red[NT / 64];
-    const long long j = vblock * NT + threadIdx.x;
-    double part = 0.0;
-    const bool want_mu = A.nu_mode == NU_COMPUTE || A.nu_mode == NU_COMPUTE_FREEZE;
-    const bool in = j < A.n;
-    // operands first, so that their loads overlap the partial sum below
-    const float fj = in ? A.f[j] : 0.0f;
-    const float Gj = in ? A.G[j] : 0.0f;
-    const float pj = in ? A.pnorm[j] : 1.0f;
-    const float muj = (in && want_mu) ? A.mu[j] : 1.0f;
-    const float nuf = (in && A.nu_mode == NU_FROZEN) ? A.nu_frozen[j] : 1.0f;
-    float meanmu = 1.0f;
-    if (want_mu) meanmu = (float)(sum_partials(A.part_mu, A.n_part_mu, s_red) / (double)A.n);
-    if (in) {
-        float nu = 1.0f;
-        if (want_mu) {
-            nu = fminf(A.nu2, fmaxf(A.nu1, meanmu / muj));
-            if (A.nu_mode == NU_COMPUTE_FREEZE) A.nu_frozen[j] = nu;
-        } else if (A.nu_mode == NU_FROZEN) {
-            nu = nuf;
-        }
-        const float S = (fj < 0.5f * A.U) ? fj / pj : (A.U - fj) / pj;
-        const float ft = fj - A.step * nu * S * Gj;
-        const float fn = (ft <= 0.0f) ? A.t_clip : ((ft >= A.U) ? A.U - A.t_clip : ft);
-        A.f[j] = fn;
-        part = (double)fn;
+// Matlab-style gradient magnitude (unit spacing, central differences
+// inside, one-sided at the edges) of a 2D image at pixel (ix, iy)
+__device__ __forceinline__ float gmag2(const float* f, const GeoK& g, int ix, int iy, float fj) {
+    const long long j = (long long)iy * g.nx + ix;
+    float gx = 0.0f, gy = 0.0f;
+    if (g.nx > 1) {
+        if (ix == 0) gx = f[j + 1] - fj;
+        else if (ix == g.nx - 1) gx = fj - f[j - 1];
+        else gx = 0.5f * (f[j + 1] - f[j - 1]);
     }
-    write_partial(part, A.red_f, s_red, vblock);
+    if (g.ny > 1) {
+        if (iy == 0) gy = f[j + g.nx] - fj;
+        else if (iy == g.ny - 1) gy = fj - f[j - g.nx];
+        else gy = 0.5f * (f[j + g.nx] - f[j - g.nx]);
+    }
+    return sqrtf(gx * gx + gy * gy);
 }
 
-__global__ __launch_bounds__(NT) void k_update(UpdArgs A) { upd_body(A, blockIdx.x); }
+constexpr int PX_PER_BLOCK = 1024;   // pixels per block of the 2D pixel pass
+
+int px_grid(const pet_os_geom* G) { return (int)((G->n_vox + PX_PER_BLOCK - 1) / PX_PER_BLOCK); }
+
+struct PxArgs {
+    const float* f;          // iterate entering the subiteration
+    float* fsnap;            // its copy, read by the fused back-projection/update
+    float* mu;
+    int want_mu;
+    const double* part_f;    // partials of sum f
+    int n_part_f;
+    Reduction red_mu;        // partials of sum mu, one per pixel block
+};
+
+// Pixel part of the first kernel of a 2D subiteration, PX_PER_BLOCK pixels
+// per block: the snapshot of f and, when nu of eq:nuki is recomputed,
+// mu = max(0.01, |grad f| / mean f) of Sec. III-B with its FP64 partial sums.
+__device__ void px_body(const GeoK& g, const PxArgs& P, long long pblock) {
+    __shared__ double s_red[NT / 64];
+    constexpr int K = PX_PER_BLOCK / NT;
+    float fv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const long long j = pblock * PX_PER_BLOCK + k * NT + threadIdx.x;
+        fv[k] = j < g.nvox ? P.f[j] : 0.0f;
+        if (j < g.nvox) P.fsnap[j] = fv[k];
+    }
+    if (!P.want_mu) return;
+    const float meanf = (float)(sum_partials(P.part_f, P.n_part_f, s_red) / (double)g.nvox);
+    double part = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const long long j = pblock * PX_PER_BLOCK + k * NT + threadIdx.x;
+        if (j < g.nvox) {
+            const float mu = fmaxf(0.01f, gmag2(P.f, g, (int)(j % g.nx), (int)(j / g.nx), fv[k]) / meanf);
+            P.mu[j] = mu;
+            part += (double)mu;
+        }
+    }
+    write_partial(part, P.red_mu, s_red, pblock);
+}
+
+// First kernel of a 2D subiteration: blocks [0, n_fp) project the subset and
+// form the Poisson ratio, the rest run the pixel pass.
+template <int SEG>
+__global__ __launch_bounds__(NT) void k_fp_px(GeoK g, FPArgs A, PxArgs P, int n_fp) {
+    if ((int)blockIdx.x < n_fp) fp_body<2, SEG>(g, A, blockIdx.x);
+    else px_body(g, P, (long long)blockIdx.x - n_fp);
+}
 
 __device__ void sum_body(const float* x, long long n, Reduction R, long long vblock) {
     __shared__ double s_red[NT / 64];
@@ -460,12 +539,20 @@ int bp_grid_max(const pet_os_geom* G) {
 
 int elem_grid(int64_t n) { return (int)((n + NT - 1) / NT); }
 
-int sumf_grid(const pet_os_geom* G) { return G->d.dim == 3 ? upd3_grid(G) : elem_grid(G->n_vox); }
+// the update leaves one partial of sum f per 3D update tile, or per 2D
+// back-projection tile (the 2D update is fused into the back-projection)
+int sumf_grid(const pet_os_geom* G) { return G->d.dim == 3 ? upd3_grid(G) : bp_grid(G); }
 
-// partials of sum f of an image given by the caller (3D: also its z-fastest copy)
+// partials of sum f of an image given by the caller, over the same blocks and
+// in the same order as the update leaves them (3D: also its z-fastest copy)
 int launch_sum_f(const pet_os_geom* G, const float* f, float* fz, Reduction red, hipStream_t s) {
     if (G->d.dim == 3) return launch_prep3(G, f, fz, red, s);
-    return launch_sum(f, G->n_vox, red, s);
+    const int grid = bp_grid(G);
+    if (grid > red.cap) return fail(PET_OS_ERR_DEVICE, "sum partials too small");
+    if (bp_kind_of(G) == 0) hipLaunchKernelGGL((k_sum_tiles<Tile2L>), dim3(grid), dim3(NT), 0, s, G->k, f, red);
+    else hipLaunchKernelGGL((k_sum_tiles<Tile2S>), dim3(grid), dim3(NT), 0, s, G->k, f, red);
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
 }
 
 template <int SEG>
@@ -489,6 +576,26 @@ int launch_fp(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
     int seg = fp_seg_for(G, nrays, L.seg);
     int grid = fp_grid_seg(G, L.n_al, seg);
     if (L.mode == FP_OBJECTIVE && grid > L.red.cap) return fail(PET_OS_ERR_DEVICE, "objective partials too small");
+    if (L.px_fsnap != nullptr) {
+        // 2D subiteration: the pixel pass rides in the same launch
+        PxArgs P;
+        P.f = L.f;
+        P.fsnap = L.px_fsnap;
+        P.mu = L.px_mu;
+        P.want_mu = L.px_want_mu;
+        P.part_f = L.px_part_f;
+        P.n_part_f = L.px_n_part_f;
+        P.red_mu = L.px_red_mu;
+        const int npx = px_grid(G);
+        if (P.want_mu && npx > P.red_mu.cap) return fail(PET_OS_ERR_DEVICE, "mu partials too small");
+        const dim3 blocks(grid + npx);
+        if (seg == 64) hipLaunchKernelGGL((k_fp_px<64>), blocks, dim3(NT), 0, s, G->k, a, P, grid);
+        else if (seg == 16) hipLaunchKernelGGL((k_fp_px<16>), blocks, dim3(NT), 0, s, G->k, a, P, grid);
+        else if (seg == 4) hipLaunchKernelGGL((k_fp_px<4>), blocks, dim3(NT), 0, s, G->k, a, P, grid);
+        else hipLaunchKernelGGL((k_fp_px<1>), blocks, dim3(NT), 0, s, G->k, a, P, grid);
+        PETOS_HIP(hipGetLastError());
+        return PET_OS_OK;
+    }
     if (seg == 64) fp_launch_t<64>(G->k, a, grid, s);
     else if (seg == 16) fp_launch_t<16>(G->k, a, grid, s);
     else if (seg == 4) fp_launch_t<4>(G->k, a, grid, s);
@@ -539,27 +646,7 @@ int launch_bp(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
     a.part_f = L.part_f;
     a.n_part_f = L.n_part_f;
     a.red_mu = L.red_mu;
-    size_t lds;
-    int rows_unused;
-    const int kind = bp_kind_of(G);
-    bp_stage_shape_kind(G, kind, a.nb_max, rows_unused, a.chunk, lds);
-    if (L.w == nullptr) lds = 0;
-    int grid = bp_grid(G);
-    if (L.want_mu && grid > L.red_mu.cap) return fail(PET_OS_ERR_DEVICE, "mu partials too small");
-    if (kind == 0)
-        hipLaunchKernelGGL((k_bp<Tile2L>), dim3(grid), dim3(NT), lds, s, G->k, a);
-    else
-        hipLaunchKernelGGL((k_bp<Tile2S>), dim3(grid), dim3(NT), lds, s, G->k, a);
-    PETOS_HIP(hipGetLastError());
-    return PET_OS_OK;
-}
-
-int launch_update(const pet_os_geom* G, const UpdLaunch& L, hipStream_t s) {
-    if (G->d.dim == 3) return launch_update3(G, L, s);
-    UpdArgs a;
-    a.f = L.f;
-    a.G = L.G;
-    a.mu = L.mu;
+    a.fnew = L.fnew;
     a.pnorm = L.pnorm;
     a.nu_frozen = L.nu_frozen;
     a.nu_mode = L.nu_mode;
@@ -571,12 +658,27 @@ int launch_update(const pet_os_geom* G, const UpdLaunch& L, hipStream_t s) {
     a.part_mu = L.part_mu;
     a.n_part_mu = L.n_part_mu;
     a.red_f = L.red_f;
-    a.n = G->n_vox;
-    int grid = elem_grid(G->n_vox);
-    if (grid > L.red_f.cap) return fail(PET_OS_ERR_DEVICE, "sum partials too small");
-    hipLaunchKernelGGL(k_update, dim3(grid), dim3(NT), 0, s, a);
+    size_t lds;
+    int rows_unused;
+    const int kind = bp_kind_of(G);
+    bp_stage_shape_kind(G, kind, a.nb_max, rows_unused, a.chunk, lds);
+    if (L.w == nullptr) lds = 0;
+    int grid = bp_grid(G);
+    if (L.want_mu && grid > L.red_mu.cap) return fail(PET_OS_ERR_DEVICE, "mu partials too small");
+    if (L.fnew != nullptr && grid > L.red_f.cap) return fail(PET_OS_ERR_DEVICE, "sum partials too small");
+    if (kind == 0)
+        hipLaunchKernelGGL((k_bp<Tile2L>), dim3(grid), dim3(NT), lds, s, G->k, a);
+    else
+        hipLaunchKernelGGL((k_bp<Tile2S>), dim3(grid), dim3(NT), lds, s, G->k, a);
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;
+}
+
+// the separate update kernel serves 3D geometries; in 2D it is fused into
+// the back-projection (BPLaunch::fnew)
+int launch_update(const pet_os_geom* G, const UpdLaunch& L, hipStream_t s) {
+    if (G->d.dim == 3) return launch_update3(G, L, s);
+    return fail(PET_OS_ERR_DEVICE, "2D update is fused into the back-projection");
 }
 
 int launch_sum(const float* x, int64_t n, Reduction red, hipStream_t s) {
@@ -636,15 +738,31 @@ __global__ __launch_bounds__(NT) void k_fp_batch(const SlotDev* S, const Item* i
         const SlotDev& d = S[I.slot];
         if (!slot_live(d)) continue;
         const int i = (d.J - 1) % d.g.n_subsets;
-        FPArgs A{};
-        A.f = d.f;
-        A.y = d.y;
-        A.r = d.r;
-        A.out = d.w;
-        A.angles = d.subset_lists + (long long)i * d.max_sub;
-        A.n_al = d.subset_count[i];
-        A.mode = FP_RATIO;
-        fp_dispatch(d.g, A, d.fp_seg, I.block);
+        if (I.block >= d.n_fp) {
+            // pixel pass: snapshot of f and mu
+            const int nu_mode = d.sched_nu[d.J - 1];
+            PxArgs P;
+            P.f = d.f;
+            P.fsnap = d.fsnap;
+            P.mu = d.mu;
+            P.want_mu = (nu_mode == NU_COMPUTE || nu_mode == NU_COMPUTE_FREEZE) ? 1 : 0;
+            P.part_f = d.part_f;
+            P.n_part_f = d.n_part_f;
+            P.red_mu.part = d.part_mu;
+            P.red_mu.total = nullptr;
+            P.red_mu.cap = d.n_part_mu;
+            px_body(d.g, P, I.block - d.n_fp);
+        } else {
+            FPArgs A{};
+            A.f = d.f;
+            A.y = d.y;
+            A.r = d.r;
+            A.out = d.w;
+            A.angles = d.subset_lists + (long long)i * d.max_sub;
+            A.n_al = d.subset_count[i];
+            A.mode = FP_RATIO;
+            fp_dispatch(d.g, A, d.fp_seg, I.block);
+        }
         __syncthreads();
     }
 }
@@ -665,38 +783,19 @@ __global__ __launch_bounds__(NT) void k_bp_batch(const SlotDev* S, const Item* i
         A.w_sa = (long long)d.g.n_planes * d.g.n_radial;
         A.angles = d.subset_lists + (long long)i * d.max_sub;
         A.n_al = d.subset_count[i];
-        A.out = d.G;
-        A.f = d.f;
+        A.out = nullptr;
+        A.f = d.fsnap;
         A.mu = d.mu;
-        A.want_mu = (nu_mode == NU_COMPUTE || nu_mode == NU_COMPUTE_FREEZE) ? 1 : 0;
+        A.want_mu = 0;
         A.beta_over_M = d.beta_over_M;
         A.gamma_R = d.gamma_R;
         A.eps = d.eps;
-        A.part_f = d.part_f;
-        A.n_part_f = d.n_part_f;
-        A.red_mu.part = d.part_mu;
-        A.red_mu.total = nullptr;
-        A.red_mu.cap = d.n_part_mu;
         A.nb_max = d.nb_max;
         A.chunk = d.chunk;
-        bp_body<T>(d.g, A, I.block);
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(NT) void k_upd_batch(const SlotDev* S, const Item* items, const int* count) {
-    const int n = *count;
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
-        const Item I = items[it];
-        const SlotDev& d = S[I.slot];
-        if (!slot_live(d)) continue;
-        UpdArgs A{};
-        A.f = d.f;
-        A.G = d.G;
-        A.mu = d.mu;
+        A.fnew = d.f;
         A.pnorm = d.pnorm;
         A.nu_frozen = d.nu_frozen;
-        A.nu_mode = d.sched_nu[d.J - 1];
+        A.nu_mode = nu_mode;
         A.step = d.sched_step[d.J - 1];
         A.nu1 = d.nu1;
         A.nu2 = d.nu2;
@@ -707,8 +806,7 @@ __global__ __launch_bounds__(NT) void k_upd_batch(const SlotDev* S, const Item* 
         A.red_f.part = d.part_f;
         A.red_f.total = nullptr;
         A.red_f.cap = d.n_part_f;
-        A.n = d.g.nvox;
-        upd_body(A, I.block);
+        bp_body<T>(d.g, A, I.block);
         __syncthreads();
     }
 }
@@ -735,8 +833,6 @@ int launch_batch_step(SlotDev* d_slots, int n_slots, Item* const lists[WL_COUNT]
     for (int k = 0; k < 3; ++k)
         if (live(WL_BP3_16 + k))
             launch_batch3_bp(d_slots, lists[WL_BP3_16 + k], d_counts + WL_BP3_16 + k, grids[WL_BP3_16 + k], zbs[k], s);
-    if (live(WL_UPD))
-        hipLaunchKernelGGL(k_upd_batch, dim3(grids[WL_UPD]), dim3(NT), 0, s, d_slots, lists[WL_UPD], d_counts + WL_UPD);
     if (live(WL_UPD3)) launch_batch3_upd(d_slots, lists[WL_UPD3], d_counts + WL_UPD3, grids[WL_UPD3], s);
     hipLaunchKernelGGL(k_advance, dim3((n_slots + NT - 1) / NT), dim3(NT), 0, s, d_slots, n_slots);
     PETOS_HIP(hipGetLastError());
