@@ -90,7 +90,7 @@ int rebuild_lists(pet_os_batch* B) {
         const bool d3 = S.g->d.dim == 3;
         // 2D: forward blocks, then the pixel-pass blocks (snapshot, mu)
         const int nfp = d3 ? fp3_grid(S.g, S.g->max_sub_angles)
-                           : fp_grid_seg(S.g, S.g->max_sub_angles, S.fp_seg) + px_grid(S.g);
+                           : fp_grid_seg(S.g, S.g->max_sub_angles, S.fp_seg) + px_items(S.g);
         for (int b = 0; b < nfp; ++b) L[d3 ? WL_FP3 : WL_FP].push_back({s, b});
         const int nbp = bp_grid_kind(S.g, S.bp_kind);
         const int wbp = d3 ? (bp3_zb(S.g) == 16 ? WL_BP3_16 : (bp3_zb(S.g) == 32 ? WL_BP3_32 : WL_BP3_64))

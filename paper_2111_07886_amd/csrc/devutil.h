@@ -40,8 +40,16 @@ __device__ __forceinline__ void write_partial(double v, Reduction R, double* sh,
 // earlier kernel in the same stream.
 __device__ inline double sum_partials(const double* part, int n, double* sh) {
     __shared__ double s_tot;
+    // thread t adds part[t], part[t + NT], ... in that order; eight loads are
+    // issued before they are added, so they wait for memory together
     double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+    for (int base = threadIdx.x; base < n; base += 8 * NT) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = (base + k * NT < n) ? part[base + k * NT] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += v[k];
+    }
     double t = block_sum(acc, sh);
     if (threadIdx.x == 0) s_tot = t;
     __syncthreads();

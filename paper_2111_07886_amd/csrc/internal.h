@@ -180,6 +180,7 @@ int bp_grid(const pet_os_geom* g);
 int bp_grid_max(const pet_os_geom* g);
 int elem_grid(int64_t n);
 int px_grid(const pet_os_geom* g);   // blocks of the 2D pixel pass (partials of sum mu)
+int px_items(const pet_os_geom* g);  // batched work items of the 2D pixel pass
 // number of partials of sum f left by the update (and by launch_sum / launch_prep3)
 int sumf_grid(const pet_os_geom* g);
 int launch_sum_f(const pet_os_geom* g, const float* f, float* fz, Reduction red, hipStream_t s);

@@ -393,9 +393,11 @@ __device__ __forceinline__ float gmag2(const float* f, const GeoK& g, int ix, in
     return sqrtf(gx * gx + gy * gy);
 }
 
-constexpr int PX_PER_BLOCK = 1024;   // pixels per block of the 2D pixel pass
+constexpr int PX_PER_BLOCK = 256;    // pixels per block of the 2D pixel pass
+constexpr int PX_ITEM = 4;           // pixel blocks per batched work item
 
 int px_grid(const pet_os_geom* G) { return (int)((G->n_vox + PX_PER_BLOCK - 1) / PX_PER_BLOCK); }
+int px_items(const pet_os_geom* G) { return (px_grid(G) + PX_ITEM - 1) / PX_ITEM; }
 
 struct PxArgs {
     const float* f;          // iterate entering the subiteration
@@ -739,7 +741,7 @@ __global__ __launch_bounds__(NT) void k_fp_batch(const SlotDev* S, const Item* i
         if (!slot_live(d)) continue;
         const int i = (d.J - 1) % d.g.n_subsets;
         if (I.block >= d.n_fp) {
-            // pixel pass: snapshot of f and mu
+            // pixel pass: snapshot of f and mu, PX_ITEM pixel blocks per item
             const int nu_mode = d.sched_nu[d.J - 1];
             PxArgs P;
             P.f = d.f;
@@ -751,7 +753,11 @@ __global__ __launch_bounds__(NT) void k_fp_batch(const SlotDev* S, const Item* i
             P.red_mu.part = d.part_mu;
             P.red_mu.total = nullptr;
             P.red_mu.cap = d.n_part_mu;
-            px_body(d.g, P, I.block - d.n_fp);
+            const int pb0 = (I.block - d.n_fp) * PX_ITEM;
+            for (int pb = pb0; pb < min(pb0 + PX_ITEM, d.n_part_mu); ++pb) {
+                px_body(d.g, P, pb);
+                __syncthreads();
+            }
         } else {
             FPArgs A{};
             A.f = d.f;
