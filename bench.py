@@ -43,10 +43,40 @@ KERNELS_2D = {0: "k_fp_px (forward projection + Poisson ratio; snapshot of f and
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("kernels.hip", "raygeom.h"):
+    for name in ("kernels.hip", "kernels3d.hip", "devutil.h", "raygeom.h"):
         with open(os.path.join(ROOT, "paper_2111_07886_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+# kernel-name prefixes of the per-subiteration launches, by kernel index
+TRAFFIC_KERNELS = {2: {0: "void petos::k_fp_px<", 1: "void petos::k_bp<"},
+                   3: {0: "petos::k_fp3(", 1: "void petos::k_bp3<", 2: "petos::k_upd3("}}
+COPY_BYTES = 64 * 1024 * 1024 * 4      # the --calibrate-copy transfer
+
+
+def traffic_from_pmc(fetch_csv, write_csv, dim):
+    """Measured memory-side bytes per launch from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+    same counter reads for the plain copy of COPY_BYTES (--calibrate-copy);
+    the median over the launches of each kernel."""
+    import csv
+    import statistics
+
+    def per_kernel(path):
+        rows = list(csv.DictReader(open(path)))
+        copy = max(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"])
+        scale = COPY_BYTES / (copy * 1024.0)
+        out = {}
+        for k, prefix in TRAFFIC_KERNELS[dim].items():
+            vals = [float(r["Counter_Value"]) * 1024.0 * scale for r in rows if r["Kernel_Name"].startswith(prefix)]
+            if vals:
+                out[k] = statistics.median(vals)
+        return out, scale
+
+    fetch, sf = per_kernel(fetch_csv)
+    write, sw = per_kernel(write_csv)
+    return {str(k): int(fetch[k] + write.get(k, 0.0)) for k in fetch}, {"fetch": sf, "write": sw}
 
 
 def algorithmic_bytes(kernel, nnz_sub, rays_sub, q, dim=3):
@@ -256,6 +286,9 @@ def main():
     ap.add_argument("--requests", type=int, default=400, help="c5: requests taken from the arrival trace")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (for PMC byte-counter scaling)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic_<workload>.json from two rocprofv3 --pmc counter CSVs "
+                         "(FETCH_SIZE, WRITE_SIZE) of this workload run with --calibrate-copy, and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -263,6 +296,18 @@ def main():
                                    "described in DESIGN.md and is not measured", "n_gpus": args.gpus}))
         sys.exit(2)
 
+    if args.traffic_from:
+        dim = 3 if args.workload == "c3" else 2
+        per, scale = traffic_from_pmc(args.traffic_from[0], args.traffic_from[1], dim)
+        out = {"workload": args.workload, "kernel_source": kernel_source_hash(), "bytes_per_launch": per,
+               "counter_scale": scale,
+               "note": "memory-side bytes (FETCH_SIZE + WRITE_SIZE) per launch, median over launches, "
+                       "scaled by the counters of a plain 256 MiB copy"}
+        path = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
+        with open(path, "w") as fh:
+            json.dump(out, fh, indent=1)
+        print(json.dumps(out))
+        return
     if args.workload == "c4":
         return bench_batched(args)
     if args.workload == "c5":
