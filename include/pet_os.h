@@ -228,7 +228,12 @@ int pet_os_batch_add(pet_os_batch* batch, const pet_os_geom* geom, const pet_os_
                      const float* y, const float* r, int32_t n_iter, pet_os_stream stream, int32_t* slot);
 /* Release a slot (synchronises `stream`); its f holds the last iterate. */
 int pet_os_batch_remove(pet_os_batch* batch, int32_t slot, pet_os_stream stream);
-/* Queue n_steps batched subiterations on `stream` (asynchronous). */
+/* Queue n_steps batched subiterations on `stream` (asynchronous).  After
+ * slots joined or left, the first step rebuilds the work lists and captures
+ * a new graph (on a private stream, thread-local capture mode).  A capture
+ * fails if another thread issues default-stream (NULL-stream) work at the
+ * same time, so a program that drives batches and other pet_os calls from
+ * several threads serializes those calls (the server does). */
 int pet_os_batch_step(pet_os_batch* batch, int32_t n_steps, pet_os_stream stream);
 /* Queue as many steps as the longest active request still needs. */
 int pet_os_batch_run(pet_os_batch* batch, pet_os_stream stream);
@@ -253,14 +258,16 @@ int pet_os_reconstruct_batch(int32_t n, const pet_os_geom* const* geoms, const p
 int pet_os_autotune(pet_os_geom* geom, int32_t flags, pet_os_stream stream);
 
 /* ------------------------------------------------------------------------
- * Serving: continuous batching of reconstruction requests.  A worker thread
- * admits queued requests in arrival order whenever a batch slot is free and
+ * Serving: continuous batching of reconstruction requests.  2D and 3D
+ * requests have a lane each (batch, stream, worker thread), running
+ * concurrently on the device.  A lane admits the queued requests of its class
+ * in arrival order whenever a slot is free (max_slots counts both lanes) and
  * the device memory they need (scratch, schedule, and their geometry if not
- * cached) fits the budget; admitted requests join the running batch between
- * two batched subiterations and leave it as soon as they finish.  Geometries
- * (tables, sensitivity, autotuned shapes) are cached by descriptor and
- * counted against the budget; unused ones are evicted first.  The caller's
- * f, y, r buffers are not counted.
+ * cached) fits the shared budget; admitted requests join the lane's running
+ * batch between two batched subiterations and leave it as soon as they
+ * finish.  Geometries (tables, sensitivity, autotuned shapes) are cached by
+ * descriptor and counted against the budget; unused ones are evicted first.
+ * The caller's f, y, r buffers are not counted.
  * ------------------------------------------------------------------------ */
 typedef struct pet_os_server pet_os_server;
 
@@ -289,7 +296,7 @@ typedef struct {
     int64_t geometries_cached;
 } pet_os_server_stats_t;
 
-/* A server on the current device with its own stream; hbm_budget_bytes caps
+/* A server on the current device with its own streams; hbm_budget_bytes caps
  * the device memory it allocates, max_slots the concurrent requests. */
 int pet_os_server_create(size_t hbm_budget_bytes, int32_t max_slots, pet_os_server** out);
 /* Finishes every queued and running request, then stops. */
@@ -306,7 +313,7 @@ int pet_os_server_stats(pet_os_server* server, pet_os_server_stats_t* out);
 
 /* Host-only server for tests of scheduling and failure handling: no device
  * calls are made (data pointers may be NULL); a batched step takes step_us of
- * wall time.  pet_os_server_inject arms faults on it. */
+ * wall time.  pet_os_server_inject arms faults on the lane of 2D requests. */
 int pet_os_server_create_simulated(size_t budget_bytes, int32_t max_slots, int64_t step_us, pet_os_server** out);
 #define PET_OS_INJECT_ADMIT_OOM 1      /* the next admissions fail with OUT_OF_MEMORY */
 #define PET_OS_INJECT_STEP_FAILURE 2   /* the next batched steps fail (DEVICE) */

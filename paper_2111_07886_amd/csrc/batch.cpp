@@ -93,8 +93,8 @@ int rebuild_lists(pet_os_batch* B) {
                            : fp_grid_seg(S.g, S.g->max_sub_angles, S.fp_seg) + px_items(S.g);
         for (int b = 0; b < nfp; ++b) L[d3 ? WL_FP3 : WL_FP].push_back({s, b});
         const int nbp = bp_grid_kind(S.g, S.bp_kind);
-        const int wbp = d3 ? (bp3_zb(S.g) == 16 ? WL_BP3_16 : (bp3_zb(S.g) == 32 ? WL_BP3_32 : WL_BP3_64))
-                           : WL_BP0 + S.bp_kind;
+        const int zi = d3 ? (bp3_zb(S.g) == 16 ? 0 : (bp3_zb(S.g) == 32 ? 1 : 2)) : 0;
+        const int wbp = d3 ? WL_BP3 + 2 * zi + (bp3_nbs_of(S.g) == 40 ? 1 : 0) : WL_BP0 + S.bp_kind;
         for (int b = 0; b < nbp; ++b) L[wbp].push_back({s, b});
         if (d3) {
             const int nup = upd3_grid(S.g);
@@ -130,7 +130,8 @@ int rebuild_lists(pet_os_batch* B) {
 int capture(pet_os_batch* B) {
     if (B->exec) { (void)hipGraphExecDestroy(B->exec); B->exec = nullptr; }
     if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
-    for (int k = 0; k < WL_COUNT; ++k) B->grids[k] = std::max(1, std::min(B->cap[k], GRID_CAP));
+    // multiples of 8: the kernels deal contiguous item runs to each XCD
+    for (int k = 0; k < WL_COUNT; ++k) B->grids[k] = 8 * ((std::max(1, std::min(B->cap[k], GRID_CAP)) + 7) / 8);
     PETOS_HIP(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
     int rc = launch_batch_step(B->d_slots, B->max_slots, B->d_items, B->d_counts, B->grids, B->live_mask,
                                B->cap_stream);

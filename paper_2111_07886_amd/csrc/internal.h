@@ -238,8 +238,9 @@ struct Item {
 // work lists: 2D forward + pixel pass, 2D back-projection + update per tile
 // kind, and the 3D forward, back-projection per z-block size (16/32/64) and
 // update
-enum { WL_FP = 0, WL_BP0 = 1, WL_BP1 = 2, WL_FP3 = 3, WL_BP3_16 = 4, WL_BP3_32 = 5, WL_BP3_64 = 6,
-       WL_UPD3 = 7, WL_COUNT = 8 };
+// (lists WL_BP3 + 2 * zi + wi: z-block 16/32/64 for zi = 0/1/2, LDS row
+// stride 20/40 bins for wi = 0/1)
+enum { WL_FP = 0, WL_BP0 = 1, WL_BP1 = 2, WL_FP3 = 3, WL_BP3 = 4, WL_UPD3 = 10, WL_COUNT = 11 };
 
 // Queue one batched subiteration (every active slot advances by one):
 // forward, back-projection (one launch per tile kind), update, advance.
@@ -247,7 +248,9 @@ enum { WL_FP = 0, WL_BP0 = 1, WL_BP1 = 2, WL_FP3 = 3, WL_BP3_16 = 4, WL_BP3_32 =
 int launch_batch_step(SlotDev* d_slots, int n_slots, Item* const lists[WL_COUNT], const int* d_counts,
                       const int grids[WL_COUNT], int live_mask, hipStream_t s);
 void launch_batch3_fp(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, hipStream_t s);
-void launch_batch3_bp(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, int zb, hipStream_t s);
+void launch_batch3_bp(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, int zb, int nbs,
+                      hipStream_t s);
+int bp3_nbs_of(const pet_os_geom* g);   // LDS row stride of the 3D back-projector (20 or 40)
 void launch_batch3_upd(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, hipStream_t s);
 
 }  // namespace petos

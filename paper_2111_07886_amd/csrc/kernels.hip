@@ -836,9 +836,10 @@ int launch_batch_step(SlotDev* d_slots, int n_slots, Item* const lists[WL_COUNT]
         hipLaunchKernelGGL((k_bp_batch<Tile2S>), dim3(grids[WL_BP1]), dim3(NT), bp_lds_budget(1), s, d_slots,
                            lists[WL_BP1], d_counts + WL_BP1);
     const int zbs[3] = {16, 32, 64};
-    for (int k = 0; k < 3; ++k)
-        if (live(WL_BP3_16 + k))
-            launch_batch3_bp(d_slots, lists[WL_BP3_16 + k], d_counts + WL_BP3_16 + k, grids[WL_BP3_16 + k], zbs[k], s);
+    for (int k = 0; k < 6; ++k)
+        if (live(WL_BP3 + k))
+            launch_batch3_bp(d_slots, lists[WL_BP3 + k], d_counts + WL_BP3 + k, grids[WL_BP3 + k], zbs[k / 2],
+                             (k & 1) ? 40 : 20, s);
     if (live(WL_UPD3)) launch_batch3_upd(d_slots, lists[WL_UPD3], d_counts + WL_UPD3, grids[WL_UPD3], s);
     hipLaunchKernelGGL(k_advance, dim3((n_slots + NT - 1) / NT), dim3(NT), 0, s, d_slots, n_slots);
     PETOS_HIP(hipGetLastError());

@@ -828,9 +828,14 @@ int launch_prep3(const pet_os_geom* G, const float* f, float* fz, Reduction red,
 
 __device__ __forceinline__ bool slot_live3(const SlotDev& d) { return d.active && d.J <= d.J_end; }
 
+// Position of a persistent block in the item list: each XCD (blocks are
+// dealt to the 8 XCDs round-robin) takes contiguous runs of items.  The grid
+// is a multiple of 8.
+__device__ __forceinline__ int xcd_item(int block, int grid) { return (block % 8) * (grid / 8) + block / 8; }
+
 __global__ __launch_bounds__(NT) void k_fp3_batch(const SlotDev* S, const Item* items, const int* count) {
     const int n = *count;
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    for (int it = xcd_item(blockIdx.x, gridDim.x); it < n; it += gridDim.x) {
         const Item I = items[it];
         const SlotDev& d = S[I.slot];
         if (!slot_live3(d)) continue;
@@ -848,11 +853,11 @@ __global__ __launch_bounds__(NT) void k_fp3_batch(const SlotDev* S, const Item* 
     }
 }
 
-template <int ZB>
+template <int ZB, int NBS>
 __global__ __launch_bounds__(NT) void k_bp3_batch(const SlotDev* S, const Item* items, const int* count) {
     __shared__ BP3Shared sh;
     const int n = *count;
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    for (int it = xcd_item(blockIdx.x, gridDim.x); it < n; it += gridDim.x) {
         const Item I = items[it];
         const SlotDev& d = S[I.slot];
         if (!slot_live3(d) || d.zb != ZB) continue;
@@ -881,15 +886,14 @@ __global__ __launch_bounds__(NT) void k_bp3_batch(const SlotDev* S, const Item* 
         A.zb = d.zb;
         A.rw = d.rows_max;
         A.dpg = d.chunk;
-        if (bp3_nbs(A.nb) == 40) bp3_body<ZB, 40>(d.g, A, I.block, sh);
-        else bp3_body<ZB, 20>(d.g, A, I.block, sh);
+        bp3_body<ZB, NBS>(d.g, A, I.block, sh);
         __syncthreads();
     }
 }
 
 __global__ __launch_bounds__(NT) void k_upd3_batch(const SlotDev* S, const Item* items, const int* count) {
     const int n = *count;
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    for (int it = xcd_item(blockIdx.x, gridDim.x); it < n; it += gridDim.x) {
         const Item I = items[it];
         const SlotDev& d = S[I.slot];
         if (!slot_live3(d)) continue;
@@ -924,10 +928,20 @@ void launch_batch3_fp(const SlotDev* d_slots, const Item* list, const int* cnt, 
     hipLaunchKernelGGL(k_fp3_batch, dim3(grid), dim3(NT), 0, s, d_slots, list, cnt);
 }
 
-void launch_batch3_bp(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, int zb, hipStream_t s) {
-    if (zb == 16) hipLaunchKernelGGL((k_bp3_batch<16>), dim3(grid), dim3(NT), 0, s, d_slots, list, cnt);
-    else if (zb == 32) hipLaunchKernelGGL((k_bp3_batch<32>), dim3(grid), dim3(NT), 0, s, d_slots, list, cnt);
-    else hipLaunchKernelGGL((k_bp3_batch<64>), dim3(grid), dim3(NT), 0, s, d_slots, list, cnt);
+void launch_batch3_bp(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, int zb, int nbs,
+                      hipStream_t s) {
+    if (zb == 16 && nbs == 20) hipLaunchKernelGGL((k_bp3_batch<16, 20>), dim3(grid), dim3(NT), 0, s, d_slots, list, cnt);
+    else if (zb == 16) hipLaunchKernelGGL((k_bp3_batch<16, 40>), dim3(grid), dim3(NT), 0, s, d_slots, list, cnt);
+    else if (zb == 32 && nbs == 20) hipLaunchKernelGGL((k_bp3_batch<32, 20>), dim3(grid), dim3(NT), 0, s, d_slots, list, cnt);
+    else if (zb == 32) hipLaunchKernelGGL((k_bp3_batch<32, 40>), dim3(grid), dim3(NT), 0, s, d_slots, list, cnt);
+    else if (nbs == 20) hipLaunchKernelGGL((k_bp3_batch<64, 20>), dim3(grid), dim3(NT), 0, s, d_slots, list, cnt);
+    else hipLaunchKernelGGL((k_bp3_batch<64, 40>), dim3(grid), dim3(NT), 0, s, d_slots, list, cnt);
+}
+
+int bp3_nbs_of(const pet_os_geom* G) {
+    int nb, zb, rw, dpg;
+    if (bp3_shape(G, nb, zb, rw, dpg)) return 40;
+    return bp3_nbs(nb);
 }
 
 void launch_batch3_upd(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, hipStream_t s) {

@@ -1,14 +1,17 @@
 // server.cpp -- continuous-batching reconstruction server.
 //
 // Requests (geometry descriptor, parameters, device f/y/r, iterations) are
-// queued by pet_os_submit and admitted in arrival order by a worker thread
-// as soon as a batch slot and the device-memory budget allow; admitted
-// requests join the running batch between two steps, and every step advances
-// all of them by one subiteration (one replay of the captured batched
-// launch sequence).  A request that finishes leaves the batch at once and
-// frees its memory, so later arrivals are admitted while others still run.
-// Geometries (tables, sensitivity, autotuned shapes) are cached by
-// descriptor and count against the budget; unused ones are evicted first.
+// queued by pet_os_submit.  Each class of request (2D, 3D) has a lane: its
+// own batch, stream and worker thread.  A lane admits the queued requests of
+// its class in arrival order as soon as a slot and the device-memory budget
+// allow; admitted requests join the lane's running batch between two steps,
+// and every step advances all of them by one subiteration (one replay of the
+// captured batched launch sequence).  A request that finishes leaves at once
+// and frees its memory, so later arrivals are admitted while others still
+// run.  The lanes run concurrently on the device, so a slow 3D subiteration
+// does not pace the 2D requests.  Geometries (tables, sensitivity,
+// autotuned shapes) are cached by descriptor and count against the shared
+// budget; unused ones are evicted first.
 //
 // The device work sits behind a small executor interface.  Besides the HIP
 // executor there is a host-only simulation (no device calls) so that the
@@ -72,7 +75,7 @@ std::string desc_key(const pet_os_geom_desc& d) {
 size_t request_bytes(const pet_os_geom_desc& d, int n_planes, int max_sub, int n_iter, bool nu) {
     const size_t nv = (size_t)d.nx * d.ny * (d.dim == 3 ? d.nz : 1);
     const size_t nb = (size_t)n_planes * d.n_angles * d.n_radial;
-    size_t b = (size_t)max_sub * n_planes * d.n_radial * 4 + nv * 4 * (nu ? 3 : 2);
+    size_t b = (size_t)max_sub * n_planes * d.n_radial * 4 + nv * 4 * (nu ? 4 : 3);
     b += 8 * (2 * nv / 256 + nv / 64 + (size_t)d.n_angles * n_planes * d.n_radial / 16 + 2 * nb / 256 + 64);
     b += (size_t)n_iter * d.n_subsets * 8;
     return b + 4096;
@@ -198,32 +201,59 @@ struct GeoEntry {
 
 }  // namespace
 
+namespace {
+constexpr int N_LANES = 2;                    // lane 0: 2D requests, lane 1: 3D
+int lane_of(const pet_os_geom_desc& d) { return d.dim == 3 ? 1 : 0; }
+
+struct Lane {
+    std::unique_ptr<Executor> ex;
+    std::vector<std::shared_ptr<Req>> active;
+    std::thread worker;
+};
+}  // namespace
+
 struct pet_os_server {
     size_t budget = 0;
     int max_slots = 0;
     int device = 0;
     bool simulate = false;
-    std::unique_ptr<Executor> ex;
-    SimExecutor* sim = nullptr;
+    Lane lanes[N_LANES];
+    SimExecutor* sim = nullptr;                           // lane 0's, when simulated
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<std::shared_ptr<Req>> queue;               // submitted, not admitted
     std::map<uint64_t, std::shared_ptr<Req>> all;         // every unclaimed request
-    std::vector<std::shared_ptr<Req>> active;
     std::map<std::string, GeoEntry> geos;
     size_t used_bytes = 0;
     uint64_t next_ticket = 1;
     uint64_t use_clock = 0;
+    uint64_t gen = 0;              // bumped on every submit, cancel and departure
+    int admitting = 0;             // admissions in progress (slots reserved)
+    // Device API calls of the lanes (geometry creation, joining, the step that
+    // may capture a graph, objective, leaving) are serialized: a graph capture
+    // in one lane must not overlap default-stream work issued by the other
+    // (the runtime then invalidates the capture).  Waiting on a lane's own
+    // stream is not serialized.  Taken after mu when both are held.
+    std::mutex api_mu;
     bool stop = false;
-    std::thread worker;
     Clock::time_point t0 = Clock::now();
     // statistics
     int64_t ticks = 0, max_active = 0;
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
-    void run();
+    int64_t n_active() const {
+        int64_t n = 0;
+        for (const auto& L : lanes) n += (int64_t)L.active.size();
+        return n;
+    }
+    bool queued_for(int lane) const {
+        for (const auto& r : queue)
+            if (lane_of(r->rq.desc) == lane) return true;
+        return false;
+    }
+    void run(int lane);
     void finish(const std::shared_ptr<Req>& r, int status, const std::string& msg);
-    bool try_admit(std::unique_lock<std::mutex>& lk);
+    bool try_admit(int lane, std::unique_lock<std::mutex>& lk);
     void evict_unused(size_t need);
 };
 
@@ -241,7 +271,10 @@ void pet_os_server::evict_unused(size_t need) {
             if (it->second.refs == 0 && (victim == geos.end() || it->second.last_use < victim->second.last_use))
                 victim = it;
         if (victim == geos.end()) return;
-        ex->drop_geometry(victim->second.g);
+        {
+            std::lock_guard<std::mutex> api(api_mu);
+            lanes[0].ex->drop_geometry(victim->second.g);     // any lane's executor releases geometries
+        }
         used_bytes -= victim->second.bytes;
         geos.erase(victim);
     }
@@ -249,11 +282,18 @@ void pet_os_server::evict_unused(size_t need) {
 
 // Admit the request at the head of the queue if a slot and the budget allow.
 // Called with the lock held; drops it around device work.
-bool pet_os_server::try_admit(std::unique_lock<std::mutex>& lk) {
-    if (queue.empty() || (int)active.size() >= max_slots) return false;
-    std::shared_ptr<Req> r = queue.front();
+bool pet_os_server::try_admit(int lane, std::unique_lock<std::mutex>& lk) {
+    if (n_active() + admitting >= max_slots) return false;
+    // the oldest queued request of this lane's class
+    auto qit = std::find_if(queue.begin(), queue.end(), [&](const std::shared_ptr<Req>& q) {
+        return lane_of(q->rq.desc) == lane;
+    });
+    if (qit == queue.end()) return false;
+    std::shared_ptr<Req> r = *qit;
+    Executor* ex = lanes[lane].ex.get();
+    auto& active = lanes[lane].active;
     if (r->cancelled) {
-        queue.pop_front();
+        queue.erase(qit);
         finish(r, PET_OS_ERR_TIMEOUT, "cancelled before admission");
         cv_done.notify_all();
         return true;
@@ -266,37 +306,66 @@ bool pet_os_server::try_admit(std::unique_lock<std::mutex>& lk) {
     auto git = geos.find(r->geo_key);
     const size_t gbytes = git == geos.end() ? geometry_bytes(d, np) : 0;
     if (r->bytes + gbytes > budget) {
-        queue.pop_front();
+        queue.erase(qit);
         finish(r, PET_OS_ERR_BUDGET, "request needs more device memory than the whole budget");
         cv_done.notify_all();
         return true;
     }
     if (used_bytes + r->bytes + gbytes > budget) evict_unused(r->bytes + gbytes);
     if (used_bytes + r->bytes + gbytes > budget) return false;      // wait for running requests to leave
-    queue.pop_front();
+    queue.erase(qit);
     r->res.t_admit = now();
+    // reserve the slot, the memory and a cached geometry before the lock is
+    // dropped: the other lane admits and evicts meanwhile
+    ++admitting;
+    used_bytes += r->bytes + gbytes;
+    if (git != geos.end()) git->second.refs++;
+    const bool new_geo = git == geos.end();
     // device work without the lock
     lk.unlock();
     int rc = PET_OS_OK;
     void* g = nullptr;
     size_t gb = 0;
-    if (git == geos.end()) rc = ex->geometry(d, &g, &gb);
+    if (new_geo) {
+        std::lock_guard<std::mutex> api(api_mu);
+        rc = ex->geometry(d, &g, &gb);
+    }
     int slot = -1;
     lk.lock();
-    if (!rc && git == geos.end()) {
-        GeoEntry e;
-        e.g = g;
-        e.bytes = gb;
-        geos[r->geo_key] = e;
-        used_bytes += gb;
+    used_bytes -= gbytes;                  // the estimate; the real geometry bytes follow
+    GeoEntry* ge = nullptr;
+    if (!rc) {
+        if (new_geo) {
+            GeoEntry e;
+            e.g = g;
+            e.bytes = gb;
+            e.refs = 1;
+            auto ins = geos.emplace(r->geo_key, e);
+            if (ins.second) {
+                used_bytes += gb;
+            } else {                       // made meanwhile by another admission: keep that one
+                std::lock_guard<std::mutex> api(api_mu);
+                ex->drop_geometry(g);
+                ins.first->second.refs++;
+            }
+            ge = &ins.first->second;
+        } else {
+            ge = &geos[r->geo_key];
+        }
+        ge->last_use = ++use_clock;
+    } else if (!new_geo) {
+        geos[r->geo_key].refs--;
     }
-    GeoEntry* ge = rc ? nullptr : &geos[r->geo_key];
-    if (ge) { ge->refs++; ge->last_use = ++use_clock; }
     lk.unlock();
-    if (!rc) rc = ex->add(ge->g, r->rq, &slot);
+    if (!rc) {
+        std::lock_guard<std::mutex> api(api_mu);
+        rc = ex->add(ge->g, r->rq, &slot);
+    }
     lk.lock();
+    --admitting;
     if (rc) {
         if (ge) ge->refs--;
+        used_bytes -= r->bytes;
         finish(r, rc, pet_os_last_error());
         cv_done.notify_all();
         return true;
@@ -304,32 +373,43 @@ bool pet_os_server::try_admit(std::unique_lock<std::mutex>& lk) {
     r->slot = slot;
     r->remaining = (int64_t)r->rq.n_iter * d.n_subsets;
     r->res.t_start = now();
-    used_bytes += r->bytes;
     active.push_back(r);
-    max_active = std::max<int64_t>(max_active, (int64_t)active.size());
+    max_active = std::max<int64_t>(max_active, n_active());
     return true;
 }
 
-void pet_os_server::run() {
+void pet_os_server::run(int lane) {
     if (!simulate) (void)hipSetDevice(device);
+    Executor* ex = lanes[lane].ex.get();
+    auto& active = lanes[lane].active;
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
-        while (try_admit(lk)) {
+        while (try_admit(lane, lk)) {
         }
         if (active.empty()) {
-            if (stop && queue.empty()) break;
-            cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+            if (stop && !queued_for(lane)) break;
+            // idle until something changes: an arrival, a cancellation, or a
+            // departure in the other lane freeing a slot or memory
+            const uint64_t seen = gen;
+            cv_work.wait(lk, [&] { return stop || gen != seen; });
             continue;
         }
         lk.unlock();
-        int rc = ex->step();
+        int rc;
+        {
+            std::lock_guard<std::mutex> api(api_mu);
+            rc = ex->step();
+        }
         lk.lock();
         ++ticks;
         if (rc) {
             // device failure: every running request fails, the batch is rebuilt
             std::string msg = pet_os_last_error();
             lk.unlock();
-            (void)ex->reset();
+            {
+                std::lock_guard<std::mutex> api(api_mu);
+                (void)ex->reset();
+            }
             lk.lock();
             for (auto& r : active) {
                 used_bytes -= r->bytes;
@@ -337,7 +417,9 @@ void pet_os_server::run() {
                 finish(r, rc, msg);
             }
             active.clear();
+            ++gen;
             cv_done.notify_all();
+            cv_work.notify_all();
             continue;
         }
         std::vector<std::shared_ptr<Req>> leaving;
@@ -362,12 +444,19 @@ void pet_os_server::run() {
                     g = geos[r->geo_key].g;
                 }
                 double phi = 0;
-                int orc = ex->objective(g, r->rq, &phi);
+                int orc;
+                {
+                    std::lock_guard<std::mutex> api(api_mu);
+                    orc = ex->objective(g, r->rq, &phi);
+                }
                 if (orc) { status[k] = orc; msgs[k] = pet_os_last_error(); }
                 else if (!std::isfinite(phi)) { status[k] = PET_OS_ERR_NUMERIC; msgs[k] = "objective is not finite"; }
                 r->res.objective = phi;
             }
-            (void)ex->remove(r->slot);
+            {
+                std::lock_guard<std::mutex> api(api_mu);
+                (void)ex->remove(r->slot);
+            }
         }
         lk.lock();
         for (size_t k = 0; k < leaving.size(); ++k) {
@@ -377,13 +466,15 @@ void pet_os_server::run() {
             geos[r->geo_key].refs--;
             finish(r, status[k], msgs[k]);
         }
+        ++gen;
         cv_done.notify_all();
+        cv_work.notify_all();     // slots and memory are free for the other lane too
     }
 }
 
 namespace {
 
-int server_create(size_t budget, int32_t max_slots, bool simulate, pet_os_server** out) {
+int server_create(size_t budget, int32_t max_slots, bool simulate, int64_t step_us, pet_os_server** out) {
     if (!out) return fail(PET_OS_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (budget == 0) return fail(PET_OS_ERR_INVALID_ARG, "hbm_budget_bytes must be > 0");
@@ -392,18 +483,24 @@ int server_create(size_t budget, int32_t max_slots, bool simulate, pet_os_server
     S->budget = budget;
     S->max_slots = max_slots;
     S->simulate = simulate;
-    if (simulate) {
-        auto* sim = new SimExecutor(max_slots);
-        S->sim = sim;
-        S->ex.reset(sim);
-    } else {
-        if (hipGetDevice(&S->device) != hipSuccess) { delete S; return fail(PET_OS_ERR_DEVICE, "no HIP device"); }
-        auto* hx = new HipExecutor(max_slots);
-        S->ex.reset(hx);
-        int rc = hx->init();
-        if (rc) { delete S; return rc; }
+    if (!simulate && hipGetDevice(&S->device) != hipSuccess) {
+        delete S;
+        return fail(PET_OS_ERR_DEVICE, "no HIP device");
     }
-    S->worker = std::thread([S] { S->run(); });
+    for (int l = 0; l < N_LANES; ++l) {
+        if (simulate) {
+            auto* sim = new SimExecutor(max_slots);
+            sim->step_us = std::max<int64_t>(0, step_us);
+            if (l == 0) S->sim = sim;
+            S->lanes[l].ex.reset(sim);
+        } else {
+            auto* hx = new HipExecutor(max_slots);
+            S->lanes[l].ex.reset(hx);
+            int rc = hx->init();
+            if (rc) { delete S; return rc; }
+        }
+    }
+    for (int l = 0; l < N_LANES; ++l) S->lanes[l].worker = std::thread([S, l] { S->run(l); });
     *out = S;
     return PET_OS_OK;
 }
@@ -413,13 +510,11 @@ int server_create(size_t budget, int32_t max_slots, bool simulate, pet_os_server
 extern "C" {
 
 int pet_os_server_create(size_t hbm_budget_bytes, int32_t max_slots, pet_os_server** out) {
-    return server_create(hbm_budget_bytes, max_slots, false, out);
+    return server_create(hbm_budget_bytes, max_slots, false, 0, out);
 }
 
 int pet_os_server_create_simulated(size_t budget_bytes, int32_t max_slots, int64_t step_us, pet_os_server** out) {
-    int rc = server_create(budget_bytes, max_slots, true, out);
-    if (!rc) (*out)->sim->step_us = std::max<int64_t>(0, step_us);
-    return rc;
+    return server_create(budget_bytes, max_slots, true, step_us, out);
 }
 
 int pet_os_server_inject(pet_os_server* S, int32_t kind, int32_t count) {
@@ -441,8 +536,9 @@ int pet_os_server_destroy(pet_os_server* S) {
         S->stop = true;
     }
     S->cv_work.notify_all();
-    if (S->worker.joinable()) S->worker.join();
-    for (auto& kv : S->geos) S->ex->drop_geometry(kv.second.g);
+    for (auto& L : S->lanes)
+        if (L.worker.joinable()) L.worker.join();
+    for (auto& kv : S->geos) S->lanes[0].ex->drop_geometry(kv.second.g);
     S->geos.clear();
     delete S;
     return PET_OS_OK;
@@ -473,6 +569,7 @@ int pet_os_submit(pet_os_server* S, const pet_os_request* req, uint64_t* ticket)
         S->queue.push_back(r);
         S->all[r->ticket] = r;
         *ticket = r->ticket;
+        ++S->gen;
     }
     S->cv_work.notify_all();
     return PET_OS_OK;
@@ -484,6 +581,7 @@ int pet_os_cancel(pet_os_server* S, uint64_t ticket) {
     auto it = S->all.find(ticket);
     if (it == S->all.end()) return fail(PET_OS_ERR_INVALID_ARG, "unknown ticket");
     it->second->cancelled = true;
+    ++S->gen;
     S->cv_work.notify_all();
     return PET_OS_OK;
 }
@@ -507,7 +605,7 @@ int pet_os_server_stats(pet_os_server* S, pet_os_server_stats_t* out) {
     if (!S || !out) return fail(PET_OS_ERR_INVALID_ARG, "NULL argument");
     std::lock_guard<std::mutex> lk(S->mu);
     out->queued = (int64_t)S->queue.size();
-    out->active = (int64_t)S->active.size();
+    out->active = S->n_active();
     out->ticks = S->ticks;
     out->max_active = S->max_active;
     out->bytes_in_use = S->used_bytes;

@@ -66,7 +66,8 @@ def test_served_results_equal_solo(pet, tmp_path, monkeypatch):
     res = [S.wait(t) for t in tickets]
     st = S.stats()
     S.close()
-    assert all(r["status"] == 0 for r in res), [r["message"] for r in res]
+    assert all(r["status"] == 0 for r in res), [(k, r["status"], r["message"]) for k, r in enumerate(res)
+                                                if r["status"] != 0]
     assert st["max_active"] > 1
     for k, ((f, _, _), ref) in enumerate(zip(data, solo)):
         assert torch.equal(f, ref), k

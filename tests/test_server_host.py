@@ -159,3 +159,43 @@ def test_geometry_cache_reuse_and_eviction(pet):
     S.wait(S.submit(d2, p2, n_iter=1))
     assert S.stats()["geometries_cached"] == 2
     S.close()
+
+
+def req3d(n=32, nz=8, M=4):
+    import math
+    nr = 2 * int(math.ceil(n / math.sqrt(2))) + 3
+    return configs.desc_3d(n, nz, 4 * M, nr, 300.0 / n, 3.0, nz, 3, M), configs.params_3d()
+
+
+def test_lanes_by_class(pet):
+    """2D and 3D requests run in lanes of their own: a 3D request waiting for
+    memory does not hold back the 2D requests queued behind it, and each class
+    is admitted in its own arrival order."""
+    d2, p2 = req(64, M=4)
+    d3, p3 = req3d(48, 16)
+    S = pet.Server(1 << 40, 16, simulate=True, step_us=2000)
+    one2 = S.submit(d2, p2, n_iter=1)
+    while S.stats()["active"] == 0:
+        time.sleep(0.001)
+    per2 = S.stats()["bytes_in_use"]
+    S.wait(one2)
+    g2 = S.stats()["bytes_in_use"]          # the cached 2D geometry
+    r2 = per2 - g2
+    t3 = S.submit(d3, p3, n_iter=1)
+    while S.stats()["active"] == 0:
+        time.sleep(0.001)
+    per3 = S.stats()["bytes_in_use"]        # the 3D request, its geometry and the cached 2D one
+    S.wait(t3)
+    S.close()
+    assert per3 > 3 * per2
+    # room for the 3D request alone, or for 2D requests, not for the 3D one beside a 2D one
+    S = pet.Server(per3 + r2 // 2, 16, simulate=True, step_us=2000)
+    a = S.submit(d2, p2, n_iter=20)          # long, holds memory
+    b = S.submit(d3, p3, n_iter=1)           # cannot fit until a leaves
+    c = S.submit(d2, p2, n_iter=1)           # fits beside a
+    ra, rb, rc = S.wait(a), S.wait(b), S.wait(c)
+    S.close()
+    assert ra["status"] == rc["status"] == 0
+    assert rb["status"] == 0
+    assert rc["t_admit"] < rb["t_admit"] and rc["t_finish"] < ra["t_finish"]
+    assert rb["t_admit"] >= ra["t_finish"] - 1e-3        # b waited for a's memory
