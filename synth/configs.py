@@ -50,6 +50,24 @@ def params_2d(M: int, counts: float, mode: str = "P2", U: float = 1e6) -> dict:
     return p
 
 
+def params_2d_uniform(mode: str, U: float = 1e6) -> dict:
+    """Table II, uniform phantom column (24 subsets, high count): BSREM, P1
+    and P2; beta = 0.1 (high count).  Other modes take the brain-phantom
+    rows (params_2d)."""
+    p = params_2d(24, 1e7, mode=mode, U=U)
+    if mode == "BSREM":
+        p.update(a=1 / 35)
+    elif mode == "P1":
+        p.update(a=0.5, nu1=1.8, nu2=2.5)
+    elif mode == "P2":
+        p.update(a=0.7, rho=3.0, delta1=7.0, delta2=7.0, nu1=1.4, nu2=2.3)
+    return p
+
+
+# Sec. IV-A: total counts and the scatter / random fractions of the simulations
+TC_HIGH, TC_LOW, SF, RF = 6.8e6, 6.8e5, 0.25, 0.25
+
+
 def params_3d(U: float = 1e6, mode: str = "P2") -> dict:
     return dict(mode=mode, gamma_R=2.0, eps=1e-12, t_clip=1e-4, U=U, lambda0=1.6, a=1 / 4,
                 rho=2.2, delta1=0.1, delta2=1.6, nu1=0.6, nu2=1.25, J0=0, J1=1000, beta=0.1)

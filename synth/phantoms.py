@@ -266,3 +266,70 @@ def make_3d(desc, seed, n_ell, counts, bg_uniform, bg_scatter, scatter_sigma_bin
     return Workload(desc=desc, f_true=f_true, y=y, r=gamma, f0=f0, U=U,
                     meta=dict(seed=seed, counts=counts, bg_uniform=bg_uniform, bg_scatter=bg_scatter,
                               n_ellipsoids=len(ells)))
+
+
+# ----------------------------------------------------------------------------
+# the uniform phantom and data model of the paper's simulations (Sec. IV-A)
+# ----------------------------------------------------------------------------
+
+UNIFORM_DISCS = ((4, "hot"), (6, "hot"), (8, "cold"), (10, "cold"), (12, "hot"), (14, "hot"))
+
+
+def uniform_phantom_2d(n=256, body_radius_px=110.0, ring_radius_px=70.0, hot=10.0, sub=4):
+    """Uniform phantom of Fig. 1b / Sec. IV-A: a uniform background disc with
+    six discs of radii 4, 6, 8 (cold), 10 (cold), 12 and 14 pixels, contrast
+    0:1 (cold) and 10:1 (hot, our reading of the printed "1:10").  The paper
+    gives no positions: the discs sit on a ring of ring_radius_px around the
+    centre, 60 degrees apart, inside a body of radius body_radius_px.  The
+    image is rasterised with sub x sub supersampling (unit pixel pitch).
+
+    ROIs (Fig. 6): each disc, a background disc of radius 25 px at the centre,
+    and "all" = their union; an ROI takes the pixels whose centre lies at least
+    one pixel inside its disc edge."""
+    c = 0.5 * (n - 1)
+    s = (np.arange(sub) + 0.5) / sub - 0.5
+    yy, xx = np.mgrid[0:n, 0:n].astype(np.float64)
+    discs = []
+    for k, (rad, kind) in enumerate(UNIFORM_DISCS):
+        th = 2.0 * np.pi * k / 6.0
+        discs.append((c + ring_radius_px * np.cos(th), c + ring_radius_px * np.sin(th), float(rad), kind))
+    img = np.zeros((n, n))
+    for dy in s:
+        for dx in s:
+            px, py = xx + dx, yy + dy
+            v = ((px - c) ** 2 + (py - c) ** 2 <= body_radius_px ** 2).astype(np.float64)
+            for cx, cy, rad, kind in discs:
+                inside = (px - cx) ** 2 + (py - cy) ** 2 <= rad ** 2
+                v = np.where(inside, hot if kind == "hot" else 0.0, v)
+            img += v
+    img /= sub * sub
+    rois = {}
+    for (cx, cy, rad, kind), (r0, _) in zip(discs, UNIFORM_DISCS):
+        rois[f"{kind}{int(r0)}"] = (xx - cx) ** 2 + (yy - cy) ** 2 <= (rad - 1.0) ** 2
+    rois["background"] = (xx - c) ** 2 + (yy - c) ** 2 <= 25.0 ** 2
+    allm = np.zeros((n, n), bool)
+    for m in rois.values():
+        allm |= m
+    rois["all"] = allm
+    return img, rois
+
+
+def simulate_sdp_counts(Af, TC, rng, SF=0.25, RF=0.25, scatter_sigma_bins=20.0):
+    """Data model of Sec. IV-A without the PSF and the attenuation: trues are
+    the projection Af of the phantom through the reconstruction system matrix,
+    scatter a smoothed copy of it scaled to SF = S/(T+S), randoms uniform with
+    RF = R/(T+S+R), total mean count TC = T+S+R; y is Poisson.  Returns
+    (y, r, scale) with r = S + R the known background mean and scale the
+    factor that turns the phantom into the activity whose projection is T."""
+    Af = np.asarray(Af, dtype=np.float64)
+    T_tot = (1.0 - SF) * (1.0 - RF) * TC
+    S_tot = SF * (1.0 - RF) * TC
+    R_tot = RF * TC
+    scale = T_tot / Af.sum()
+    T = Af * scale
+    sm = _smooth_bins(Af, scatter_sigma_bins)
+    S = sm * (S_tot / sm.sum())
+    R = np.full_like(T, R_tot / T.size)
+    r = S + R
+    y = rng.poisson(T + r).astype(np.float64)
+    return y, r, scale

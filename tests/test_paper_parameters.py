@@ -41,3 +41,17 @@ def test_momentum_rows(M, key):
 
 def test_table3_row():
     _check(configs.params_3d(), GOLD["table3_P2_nonTOF"])
+
+
+@pytest.mark.parametrize("mode,row", [("BSREM", "BSREM24"), ("P1", "P1_24"), ("P2", "P2_24")])
+def test_uniform_phantom_rows(mode, row):
+    p = configs.params_2d_uniform(mode)
+    _check(p, GOLD["table2_uniform"][row]["high"])
+    assert p["beta"] == GOLD["common_2d"]["beta_high"]
+    if mode == "P2":
+        assert p["delta2"] == p["delta1"]
+
+
+def test_simulation_constants():
+    s = GOLD["simulation_2d"]
+    assert (configs.TC_HIGH, configs.TC_LOW, configs.SF, configs.RF) == (s["TC_high"], s["TC_low"], s["SF"], s["RF"])
