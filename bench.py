@@ -274,6 +274,66 @@ def bench_served(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_gradcons(args):
+    """Gradient-consistency diagnostic (Sec. IV-B, Fig. 2) riding along the
+    reconstruction: every subiteration is followed by grad Phi_i at the new
+    iterate and the two angles.  value = such subiterations per second; the
+    plain rate of the same workload is reported beside it.  The per-kernel
+    durations of the diagnostic come from rocprofv3 (the entry points are
+    synchronous calls that allocate their scratch, so HIP events around them
+    would include host time)."""
+    import torch
+
+    import paper_2111_07886_amd as pet
+    from paper_2111_07886_amd.diagnostics import gradient_consistency
+    from synth import configs
+
+    three = args.workload == "gradcons3"
+    w, p, _ = (configs.c3 if three else configs.c2)()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    y = torch.tensor(w.y, dtype=torch.float32, device=dev).contiguous()
+    r = torch.tensor(w.r, dtype=torch.float32, device=dev).contiguous()
+    geom = pet.Geometry(w.desc)
+    M = w.desc["n_subsets"]
+    steps = max(1, args.steps if not three else min(args.steps, 3))
+    f = torch.tensor(w.f0, dtype=torch.float32, device=dev).contiguous()
+    st = pet.State(geom, p)
+    gradient_consistency(geom, p, f, y, r, 1, state=st)          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = gradient_consistency(geom, p, f, y, r, steps, state=st)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st.close()
+    f = torch.tensor(w.f0, dtype=torch.float32, device=dev).contiguous()
+    st = pet.State(geom, p)
+    st.run(f, y, r, 1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st.run(f, y, r, steps)
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t1
+    st.close()
+    deg = 180.0 / 3.141592653589793
+    res = {
+        "metric": "subiterations/s (with the gradient-consistency diagnostic)",
+        "value": round(steps * M / elapsed, 2),
+        "unit": "subiterations/s",
+        "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": round(1e3 * elapsed / steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "gradient consistency along SDP-P2 on " + WORKLOADS["c3" if three else "c2"].split(";")[0]
+                               + "; step = 1 iteration, each subiteration followed by grad Phi_i and the two angles",
+                   "plain_subiterations_per_s": round(steps * M / plain, 2),
+                   "theta_mean_deg_last": round(out["theta_mean"][-1] * deg, 4),
+                   "theta_tilde_mean_deg_last": round(out["theta_tilde_mean"][-1] * deg, 4)},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,7 +341,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5", "gradcons", "gradcons3"],
                     help="c2 (default, the benchmark line); c1 / c3 for additional measurements")
     ap.add_argument("--requests", type=int, default=400, help="c5: requests taken from the arrival trace")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -312,6 +372,8 @@ def main():
         return bench_batched(args)
     if args.workload == "c5":
         return bench_served(args)
+    if args.workload in ("gradcons", "gradcons3"):
+        return bench_gradcons(args)
 
     import numpy as np
     import torch
