@@ -79,14 +79,24 @@ def traffic_from_pmc(fetch_csv, write_csv, dim):
     return {str(k): int(fetch[k] + write.get(k, 0.0)) for k in fetch}, {"fetch": sf, "write": sw}
 
 
-def algorithmic_bytes(kernel, nnz_sub, rays_sub, q, dim=3):
+def algorithmic_bytes(kernel, nnz_sub, rays_sub, q, dim=3, osem=False):
     """Bytes one launch must move (A is computed on the fly, never stored).
     3D: forward: 4 B image gather per nonzero + read y, r and write w per ray;
     back: 4 B w gather per nonzero + stage w once per ray + read f, write G,
     mu; update: read f, G, mu, p and write f per voxel.  2D, two launches:
     forward + pixel pass (read f, write its snapshot and mu), and
     back-projection + update (read the snapshot, mu, p, write f).  Either way
-    8 nnz + 16 rays + 32 q per subiteration."""
+    8 nnz + 16 rays + 32 q per subiteration.  OSEM has no mu or p but reads
+    the subset sensitivity: 2D forward + pixel pass 8 q, back + update 12 q;
+    3D back 8 q (f, G), update 20 q (f, G, s_i in; f and its z copy out)."""
+    if osem:
+        if dim == 2:
+            return 4.0 * nnz_sub + (12.0 * rays_sub + 8.0 * q if kernel == 0 else 4.0 * rays_sub + 12.0 * q)
+        if kernel == 0:
+            return 4.0 * nnz_sub + 12.0 * rays_sub
+        if kernel == 1:
+            return 4.0 * nnz_sub + 4.0 * rays_sub + 8.0 * q
+        return 20.0 * q
     if dim == 2:
         if kernel == 0:
             return 4.0 * nnz_sub + 12.0 * rays_sub + 12.0 * q
@@ -98,11 +108,36 @@ def algorithmic_bytes(kernel, nnz_sub, rays_sub, q, dim=3):
     return 20.0 * q
 
 
+def cpu_baseline_osem(w, budget_s=12.0):
+    """The FP64 OSEM oracle on the same workload: subiterations from f0 until
+    ~budget_s of CPU work is done."""
+    import oracle
+    from oracle import osem as O
+    oracle.build(force=False)
+    g = oracle.geom(w.desc)
+    M = w.desc["n_subsets"]
+    sens = [O.subset_sensitivity(g, i) for i in range(1, M + 1)]
+    f = w.f0
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and n < 50 * M:
+        i = n % M + 1
+        f = O.osem_subiteration(g, f, w.y_f32, w.r_f32, i, sens[i - 1])
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt, 3), "unit": "subiterations/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {n} OSEM subiterations of the same workload from f0 (subset sensitivities "
+                      f"precomputed), FP64 oracle, {dt:.1f} s wall"}
+
+
 def cpu_baseline(w, p, budget_s=12.0):
     """The FP64 oracle, as it stands, on the same workload: subiterations from
     f0 with the objective after every full iteration, until ~budget_s of CPU
     work is done."""
     import oracle
+    if p["mode"] == "OSEM":
+        return cpu_baseline_osem(w, budget_s)
     oracle.build(force=False)
     g = oracle.geom(w.desc)
     rec = oracle.Recon(g, oracle.params(p), w.f0, w.y_f32, w.r_f32)
@@ -344,6 +379,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5", "gradcons", "gradcons3"],
                     help="c2 (default, the benchmark line); c1 / c3 for additional measurements")
     ap.add_argument("--requests", type=int, default=400, help="c5: requests taken from the arrival trace")
+    ap.add_argument("--mode", default=None, choices=["BSREM", "M1", "M2", "P1", "P2", "OSEM"],
+                    help="c1/c2/c3: run this algorithm instead of the workload's SDP-P2 (OSEM: the "
+                         "initialisation of Sec. IV-C)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (for PMC byte-counter scaling)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -382,6 +420,10 @@ def main():
     from synth import configs
 
     w, p, _ = {"c1": configs.c1, "c2": configs.c2, "c3": configs.c3}[args.workload]()
+    if args.mode == "OSEM":
+        p = pet.osem_params(p["beta"], p["gamma_R"], p["eps"])
+    elif args.mode:
+        p = dict(p, mode=args.mode)
     p = dict(p, objective_every=1)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -428,7 +470,8 @@ def main():
             state.profile(-1)
             if n:
                 per_kernel[k] = dict(avg_us=1e3 * ms / n, launches=n,
-                                     bytes=algorithmic_bytes(k, nnz_sub, rays_sub, q, dim))
+                                     bytes=algorithmic_bytes(k, nnz_sub, rays_sub, q, dim,
+                                                             osem=p["mode"] == "OSEM"))
     roofline = None
     if per_kernel:
         dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"])
@@ -462,7 +505,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload],
+        "config": {"workload": WORKLOADS[args.workload] if not args.mode else
+                   WORKLOADS[args.workload].replace("SDP-P2", "OSEM" if args.mode == "OSEM" else "SDP-" + args.mode),
                    "subsets": M, "nnz_per_subset": int(nnz_sub), "rays_per_subset": int(rays_sub),
                    "voxels": q, "objective_last": obj[-1] if obj else None},
         "roofline": roofline,

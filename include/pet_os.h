@@ -57,12 +57,21 @@ extern "C" {
 #define PET_OS_ERR_STATE_MISMATCH (-7)
 
 /* preconditioner variants of Sec. III-B: BSREM (alpha = nu = 1), M1/P1
- * (Nesterov alpha), M2/P2 (KM alpha); P* also use the smoothness vector nu. */
+ * (Nesterov alpha), M2/P2 (KM alpha); P* also use the smoothness vector nu.
+ * PET_OS_OSEM: the ordered-subsets EM of Hudson and Larkin, used by the
+ * paper (Sec. IV-C) to initialise SDP-BSREM:
+ *   f_j <- f_j (A_i^T (y_i / (A_i f + r_i)))_j / (A_i^T 1)_j,
+ * f_j kept where the subset sensitivity (A_i^T 1)_j is 0.  It uses no
+ * penalty, relaxation or clamp; of the parameters only beta, gamma_R and
+ * eps (objective evaluations) and objective_every are read.  States and
+ * pet_os_reconstruct only (not the batched or served paths); the state
+ * holds the M subset sensitivities (M * n_voxels floats). */
 #define PET_OS_BSREM 0
 #define PET_OS_M1 1
 #define PET_OS_M2 2
 #define PET_OS_P1 3
 #define PET_OS_P2 4
+#define PET_OS_OSEM 5
 
 typedef struct pet_os_geom pet_os_geom;
 typedef struct pet_os_state pet_os_state;
@@ -85,7 +94,7 @@ typedef struct {
 
 /* Algorithm parameters (Sec. II, III-B, IV-A). */
 typedef struct {
-    int32_t mode;             /* PET_OS_BSREM .. PET_OS_P2 */
+    int32_t mode;             /* PET_OS_BSREM .. PET_OS_P2, or PET_OS_OSEM */
     double beta;              /* >= 0, eq:ObjectiveFunction */
     double gamma_R;           /* >= 0, eq:RDP */
     double eps;               /* > 0, eq:RDP */
@@ -139,6 +148,29 @@ int pet_os_objective(const pet_os_geom* geom, const pet_os_params* params, const
  * U = 1e3 * max(max_j f0_j, (sum y - sum r)_+ / sum_j s_j).  Synchronous. */
 int pet_os_default_U(const pet_os_geom* geom, const float* f0, const float* y, const float* r,
                      double* U, pet_os_stream stream);
+
+/* Subset gradient of Sec. II-B: grad Phi_i(f) = A_i^T (1 - y_i/(A_i f + r_i))
+ * + (beta/M) grad R(f) for subset i in 1..M, or grad Phi(f) (every ray, full
+ * weight beta) when subset == 0.  Only params->beta, gamma_R and eps are
+ * used.  f, grad: n_voxels floats (device, natural layout); y, r: n_bins
+ * floats.  Scratch is allocated and released inside; synchronous. */
+int pet_os_subset_gradient(const pet_os_geom* geom, const pet_os_params* params, const float* f,
+                           const float* y, const float* r, int32_t subset, float* grad,
+                           pet_os_stream stream);
+
+/* Gradient-consistency measure of Sec. IV-B (Fig. 2): with m = mean(f) and
+ * grad(f) the gradient magnitude of the smoothness measure (Sec. III-B), the
+ * smooth area I_s = {j : grad(f)_j < smooth_frac m} and the variable area
+ * I_v = {j : grad(f)_j > var_frac m} (the paper uses 0.01 and 0.2; both
+ * decisions in FP64), and the angle arccos(<u, v>/(|u| |v|)) between
+ * h_prev and h_cur restricted to each area, in radians (NaN when the area
+ * is empty or either restriction is zero).  theta: HOST double[2] (smooth,
+ * variable); count: HOST int64[2] (|I_s|, |I_v|) or NULL.  h_prev, h_cur,
+ * f: n_voxels floats (device).  Sums in FP64 in a fixed order (bitwise
+ * reproducible).  Scratch is allocated and released inside; synchronous. */
+int pet_os_gradient_angles(const pet_os_geom* geom, const float* h_prev, const float* h_cur,
+                           const float* f, double smooth_frac, double var_frac, double* theta,
+                           int64_t* count, pet_os_stream stream);
 
 /* Per-reconstruction state: position (k, i) of the next subiteration, the
  * Nesterov t (FP64), the frozen nu of eq:nuki, and device scratch.  `params`

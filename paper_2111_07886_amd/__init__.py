@@ -18,14 +18,15 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpet_os.so")
 
-MODES = {"BSREM": 0, "M1": 1, "M2": 2, "P1": 3, "P2": 4}
+MODES = {"BSREM": 0, "M1": 1, "M2": 2, "P1": 3, "P2": 4, "OSEM": 5}
 ERRORS = {-1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "DEVICE", -4: "BUDGET", -5: "NUMERIC",
           -6: "TIMEOUT", -7: "STATE_MISMATCH"}
 
 # every symbol declared in include/pet_os.h
 EXPORTS = ["pet_os_last_error", "pet_os_version", "pet_os_create_geometry", "pet_os_destroy_geometry",
            "pet_os_geometry_info", "pet_os_sensitivity", "pet_os_forward", "pet_os_back",
-           "pet_os_objective", "pet_os_default_U", "pet_os_state_create", "pet_os_state_destroy",
+           "pet_os_objective", "pet_os_default_U", "pet_os_subset_gradient", "pet_os_gradient_angles",
+           "pet_os_state_create", "pet_os_state_destroy",
            "pet_os_state_position", "pet_os_subiteration", "pet_os_reconstruct",
            "pet_os_state_export", "pet_os_state_import", "pet_os_run", "pet_os_state_profile",
            "pet_os_state_profile_read", "pet_os_nnz", "pet_os_state_seek", "pet_os_batch_create",
@@ -99,6 +100,9 @@ def lib():
             "pet_os_back": (C.c_int, [_P, _P, i32, _P, _P]),
             "pet_os_objective": (C.c_int, [_P, C.POINTER(Params), _P, _P, _P, C.POINTER(C.c_double), _P]),
             "pet_os_default_U": (C.c_int, [_P, _P, _P, _P, C.POINTER(C.c_double), _P]),
+            "pet_os_subset_gradient": (C.c_int, [_P, C.POINTER(Params), _P, _P, _P, i32, _P, _P]),
+            "pet_os_gradient_angles": (C.c_int, [_P, _P, _P, _P, C.c_double, C.c_double,
+                                                 C.POINTER(C.c_double), C.POINTER(i64), _P]),
             "pet_os_state_create": (C.c_int, [_P, C.POINTER(Params), C.POINTER(_P)]),
             "pet_os_state_destroy": (C.c_int, [_P]),
             "pet_os_state_position": (C.c_int, [_P, C.POINTER(i64), C.POINTER(i32)]),
@@ -178,10 +182,12 @@ def desc_struct(d: dict) -> GeomDesc:
 def params_struct(p: dict) -> Params:
     q = Params()
     q.mode = MODES[p["mode"]] if isinstance(p["mode"], str) else int(p["mode"])
+    osem = q.mode == MODES["OSEM"]
     for k in ("beta", "gamma_R", "eps", "t_clip", "U", "lambda0", "a", "rho", "delta1", "delta2",
               "nu1", "nu2"):
-        setattr(q, k, float(p[k]))
-    q.J0, q.J1 = int(p["J0"]), int(p["J1"])
+        # OSEM reads only beta, gamma_R and eps (objective); the rest may be absent
+        setattr(q, k, float(p.get(k, 0.0) if osem else p[k]))
+    q.J0, q.J1 = (int(p.get("J0", 0)), int(p.get("J1", 0))) if osem else (int(p["J0"]), int(p["J1"]))
     q.objective_every = int(p.get("objective_every", 1))
     return q
 
@@ -245,6 +251,26 @@ class Geometry:
                                       _dev(y, self.n_bins, "y"), _dev(r, self.n_bins, "r"),
                                       C.byref(phi), _stream(stream)))
         return phi.value
+
+    def subset_gradient(self, params: dict, f, y, r, subset, out=None, stream=None):
+        """pet_os_subset_gradient: grad Phi_i(f) (subset 1..M) or grad Phi(f) (0)."""
+        if out is None:
+            out = torch.empty(self.img_shape, device="cuda", dtype=torch.float32)
+        p = params_struct(params)
+        _check(lib().pet_os_subset_gradient(self.handle, C.byref(p), _dev(f, self.n_voxels, "f"),
+                                            _dev(y, self.n_bins, "y"), _dev(r, self.n_bins, "r"), int(subset),
+                                            _dev(out, self.n_voxels, "grad"), _stream(stream)))
+        return out
+
+    def gradient_angles(self, h_prev, h_cur, f, smooth_frac=0.01, var_frac=0.2, stream=None):
+        """pet_os_gradient_angles: (theta_smooth, theta_variable) in radians and
+        the sizes of the two areas."""
+        th = (C.c_double * 2)()
+        cnt = (C.c_int64 * 2)()
+        _check(lib().pet_os_gradient_angles(self.handle, _dev(h_prev, self.n_voxels, "h_prev"),
+                                            _dev(h_cur, self.n_voxels, "h_cur"), _dev(f, self.n_voxels, "f"),
+                                            float(smooth_frac), float(var_frac), th, cnt, _stream(stream)))
+        return th[0], th[1], cnt[0], cnt[1]
 
     def nnz(self, subset=0) -> int:
         n = C.c_int64()
@@ -324,6 +350,24 @@ class State:
     def import_(self, blob: bytes):
         buf = C.create_string_buffer(blob, len(blob))
         _check(lib().pet_os_state_import(self.handle, buf, len(blob)))
+
+
+def osem_params(beta=0.0, gamma_R=2.0, eps=1e-12):
+    """Parameters of the OSEM initialisation (Sec. IV-C): beta, gamma_R and
+    eps only enter the objective evaluations."""
+    return dict(mode="OSEM", beta=beta, gamma_R=gamma_R, eps=eps)
+
+
+def reconstruct_osem_init(geom: Geometry, params: dict, f, y, r, n_osem: int, n_iter: int, stream=None):
+    """The clinical procedure of Sec. IV-C: n_osem OSEM iterations on f (in
+    place) with the geometry's subsets, then n_iter SDP-BSREM iterations of
+    ``params`` from that image (k starts at 0)."""
+    st = State(geom, osem_params(params.get("beta", 0.0), params.get("gamma_R", 2.0), params.get("eps", 1e-12)))
+    try:
+        st.run(f, y, r, n_osem, stream=stream)
+    finally:
+        st.close()
+    return reconstruct(geom, params, f, y, r, n_iter, stream=stream)
 
 
 def reconstruct(geom: Geometry, params: dict, f, y, r, n_iter: int, want_objective=False, stream=None):

@@ -428,6 +428,14 @@ namespace petos {
 
 int validate_params(const pet_os_params* p, const pet_os_geom* g) {
     if (!p) return fail(PET_OS_ERR_INVALID_ARG, "params is NULL");
+    if (p->mode == PET_OS_OSEM) {
+        // OSEM reads only what the objective needs
+        if (!(std::isfinite(p->beta) && p->beta >= 0.0)) return fail(PET_OS_ERR_INVALID_ARG, "beta must be >= 0");
+        if (!(std::isfinite(p->gamma_R) && p->gamma_R >= 0.0))
+            return fail(PET_OS_ERR_INVALID_ARG, "gamma_R must be >= 0");
+        if (!finite_pos(p->eps)) return fail(PET_OS_ERR_INVALID_ARG, "eps must be > 0");
+        return PET_OS_OK;
+    }
     if (p->mode < PET_OS_BSREM || p->mode > PET_OS_P2) return fail(PET_OS_ERR_INVALID_ARG, "unknown mode");
     if (!(std::isfinite(p->beta) && p->beta >= 0.0)) return fail(PET_OS_ERR_INVALID_ARG, "beta must be >= 0");
     if (!(std::isfinite(p->gamma_R) && p->gamma_R >= 0.0)) return fail(PET_OS_ERR_INVALID_ARG, "gamma_R must be >= 0");
@@ -467,6 +475,10 @@ Sched sched_next(const pet_os_params& p, int M, int64_t k, int i, double* t_nest
         s.alpha = (p.rho * n + p.delta2) / (n + p.delta1);
     }
     s.nu_mode = NU_ONE;
+    if (p.mode == PET_OS_OSEM) {
+        s.lam = 1.0;
+        return s;
+    }
     if (p.mode == PET_OS_P1 || p.mode == PET_OS_P2) {
         if (J <= p.J0) s.nu_mode = NU_ONE;
         else if (J < p.J1) s.nu_mode = NU_COMPUTE;
@@ -536,7 +548,9 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
     const bool d3 = g->d.dim == 3;
     FPLaunch F{};
     F.f = f; F.fz = st->w.fz; F.y = y; F.r = r; F.out = st->w.w; F.angles = angles; F.n_al = n_al;
-    F.mode = FP_RATIO;
+    const bool osem = st->p.mode == PET_OS_OSEM;
+    const float* sens_i = osem ? st->osem_sens + (size_t)(st->i - 1) * g->n_vox : nullptr;
+    F.mode = osem ? FP_EM : FP_RATIO;
     // threads per ray chosen for the largest subset, as the batched path does
     F.seg = fp_seg_for(g, (long long)g->max_sub_angles * g->n_planes * g->d.n_radial, g->tuned_seg);
     if (!d3) {
@@ -566,6 +580,8 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
         B.U = (float)st->p.U; B.t_clip = (float)st->p.t_clip;
         B.part_mu = st->w.red[RED_SUMMU].part; B.n_part_mu = px_grid(g);
         B.red_f = st->w.red[RED_SUMF];
+        B.osem_sens = sens_i;
+        if (osem) B.beta_over_M = 0.0f;
         if ((rc = prof_begin(st, 1, s, &ev))) return rc;
         rc = launch_bp(g, B, s);
         if (rc || (rc = prof_end(ev, s))) return rc;
@@ -574,10 +590,12 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
         B.part_f = st->w.red[RED_SUMF].part;
         B.n_part_f = sumf_grid(g);
         B.red_mu = st->w.red[RED_SUMMU];
+        if (osem) B.beta_over_M = 0.0f;
         if ((rc = prof_begin(st, 1, s, &ev))) return rc;
         rc = launch_bp(g, B, s);
         if (rc || (rc = prof_end(ev, s))) return rc;
         UpdLaunch U{};
+        U.osem_sens = sens_i;
         U.f = f; U.fz = st->w.fz; U.G = st->w.G; U.mu = st->w.mu; U.pnorm = g->pnorm; U.nu_frozen = st->w.nu_frozen;
         U.nu_mode = sc.nu_mode;
         U.step = step;
@@ -635,6 +653,31 @@ int pet_os_state_create(const pet_os_geom* g, const pet_os_params* p, pet_os_sta
     const bool need_nu = p->mode == PET_OS_P1 || p->mode == PET_OS_P2;
     rc = work_alloc(g, need_nu, &st->w);
     if (rc) { delete st; return rc; }
+    if (p->mode == PET_OS_OSEM) {
+        // the M subset sensitivities A_i^T 1 of the EM update
+        GeomExtra* ex = extra_of(g);
+        const int M = g->d.n_subsets;
+        if (hipMalloc(&st->osem_sens, sizeof(float) * (size_t)M * g->n_vox) != hipSuccess) {
+            work_free(&st->w);
+            delete st;
+            return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc of the subset sensitivities failed");
+        }
+        for (int i = 0; i < M && !rc; ++i) {
+            BPLaunch L{};
+            L.w = nullptr;
+            L.angles = ex->subset_lists + (size_t)i * g->max_sub_angles;
+            L.n_al = ex->subset_count[i];
+            L.out = st->osem_sens + (size_t)i * g->n_vox;
+            rc = launch_bp(g, L, nullptr);
+        }
+        if (!rc && hipDeviceSynchronize() != hipSuccess) rc = fail(PET_OS_ERR_DEVICE, "subset sensitivities failed");
+        if (rc) {
+            (void)hipFree(st->osem_sens);
+            work_free(&st->w);
+            delete st;
+            return rc;
+        }
+    }
     *out = st;
     return PET_OS_OK;
 }
@@ -642,6 +685,7 @@ int pet_os_state_create(const pet_os_geom* g, const pet_os_params* p, pet_os_sta
 int pet_os_state_destroy(pet_os_state* st) {
     if (!st) return fail(PET_OS_ERR_INVALID_ARG, "state is NULL");
     work_free(&st->w);
+    if (st->osem_sens) (void)hipFree(st->osem_sens);
     if (st->obj_dev) (void)hipFree(st->obj_dev);
     for (auto& pr : st->prof_ev) {
         (void)hipEventDestroy(pr.first);
@@ -753,6 +797,94 @@ int pet_os_default_U(const pet_os_geom* g, const float* f0, const float* y, cons
     for (float v : fh) fmax = std::max(fmax, (double)v);
     double chat = (sy - sr > 0.0 && g->sens_sum > 0.0) ? (sy - sr) / g->sens_sum : 0.0;
     *U = 1e3 * std::max(fmax, chat);
+    return PET_OS_OK;
+}
+
+int pet_os_subset_gradient(const pet_os_geom* g, const pet_os_params* p, const float* f, const float* y,
+                           const float* r, int32_t subset, float* grad, pet_os_stream stream) {
+    if (!g || !p || !f || !y || !r || !grad) return fail(PET_OS_ERR_INVALID_ARG, "NULL argument");
+    GeomExtra* ex = extra_of(g);
+    if (!ex) return fail(PET_OS_ERR_INVALID_ARG, "invalid geometry");
+    if (subset < 0 || subset > g->d.n_subsets) return fail(PET_OS_ERR_INVALID_ARG, "subset out of range");
+    if (!(std::isfinite(p->beta) && p->beta >= 0.0 && std::isfinite(p->gamma_R) && p->gamma_R >= 0.0 &&
+          std::isfinite(p->eps) && p->eps >= 0.0))
+        return fail(PET_OS_ERR_INVALID_ARG, "beta, gamma_R and eps must be finite and >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    const int* angles = subset == 0 ? ex->all_angles : ex->subset_lists + (size_t)(subset - 1) * g->max_sub_angles;
+    const int n_al = subset == 0 ? g->d.n_angles : ex->subset_count[subset - 1];
+    Work w;
+    int rc = work_alloc(g, false, &w);
+    if (rc) return rc;
+    // the ratio sinogram of every ray does not fit the subset-sized scratch
+    float* wsino = w.w;
+    float* big = nullptr;
+    if (n_al > g->max_sub_angles) {
+        if (hipMalloc(&big, sizeof(float) * (size_t)n_al * g->n_planes * g->d.n_radial) != hipSuccess) {
+            work_free(&w);
+            return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc of the ratio sinogram failed");
+        }
+        wsino = big;
+    }
+    if (g->d.dim == 3) rc = launch_prep3(g, f, w.fz, w.red[RED_SUMF], s);
+    FPLaunch F{};
+    F.f = f; F.fz = w.fz; F.y = y; F.r = r; F.out = wsino; F.angles = angles; F.n_al = n_al;
+    F.mode = FP_RATIO;
+    F.seg = fp_seg_for(g, (long long)n_al * g->n_planes * g->d.n_radial, g->tuned_seg);
+    if (!rc) rc = launch_fp(g, F, s);
+    BPLaunch B{};
+    B.w = wsino; B.w_natural = 0; B.angles = angles; B.n_al = n_al;
+    B.f = f; B.out = grad; B.mu = w.mu; B.want_mu = 0;
+    B.beta_over_M = (float)(subset == 0 ? p->beta : p->beta / (double)g->d.n_subsets);
+    B.gamma_R = (float)p->gamma_R;
+    B.eps = (float)p->eps;
+    B.part_f = w.red[RED_SUMF].part;
+    B.n_part_f = sumf_grid(g);
+    B.red_mu = w.red[RED_SUMMU];
+    if (!rc) rc = launch_bp(g, B, s);
+    if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = fail(PET_OS_ERR_DEVICE, "stream synchronize failed");
+    if (big) (void)hipFree(big);
+    work_free(&w);
+    return rc;
+}
+
+static double angle_of(double ab, double aa, double bb) {
+    if (!(aa > 0.0) || !(bb > 0.0)) return std::nan("");
+    const double c = ab / std::sqrt(aa * bb);
+    return std::acos(std::max(-1.0, std::min(1.0, c)));
+}
+
+int pet_os_gradient_angles(const pet_os_geom* g, const float* h_prev, const float* h_cur, const float* f,
+                           double smooth_frac, double var_frac, double* theta, int64_t* count,
+                           pet_os_stream stream) {
+    if (!g || !h_prev || !h_cur || !f || !theta) return fail(PET_OS_ERR_INVALID_ARG, "NULL argument");
+    if (!extra_of(g)) return fail(PET_OS_ERR_INVALID_ARG, "invalid geometry");
+    if (!(std::isfinite(smooth_frac) && smooth_frac >= 0.0 && std::isfinite(var_frac) && var_frac >= 0.0))
+        return fail(PET_OS_ERR_INVALID_ARG, "smooth_frac and var_frac must be finite and >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    const int ng = elem_grid(g->n_vox);
+    const int na = angle_grid(g->n_vox);
+    // [sum f partials ng][sum f total 1][angle partials 8 na][sums 8]
+    double* blk = nullptr;
+    const size_t nd = (size_t)ng + 1 + 8 * (size_t)na + 8;
+    if (hipMalloc(&blk, nd * sizeof(double)) != hipSuccess) return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc failed");
+    Reduction R{blk, blk + ng, ng};
+    double* part = blk + ng + 1;
+    double* sums = part + 8 * (size_t)na;
+    int rc = launch_sum(f, g->n_vox, R, s);
+    if (!rc) rc = launch_finalize(R, ng, s);
+    if (!rc) rc = launch_angle_terms(g, h_prev, h_cur, f, R.total, smooth_frac, var_frac, part, na, sums, s);
+    double h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (!rc && (hipMemcpyAsync(h, sums, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess))
+        rc = fail(PET_OS_ERR_DEVICE, "angle read-back failed");
+    (void)hipFree(blk);
+    if (rc) return rc;
+    theta[0] = angle_of(h[0], h[1], h[2]);
+    theta[1] = angle_of(h[4], h[5], h[6]);
+    if (count) {
+        count[0] = (int64_t)h[3];
+        count[1] = (int64_t)h[7];
+    }
     return PET_OS_OK;
 }
 

@@ -96,14 +96,14 @@ int validate_params(const pet_os_params* p, const pet_os_geom* g);
 int validate_desc(const pet_os_geom_desc* d);
 
 // ---------------------------------------------------------------- launchers (kernels.hip)
-enum FPMode { FP_RATIO = 0, FP_PLAIN = 1, FP_OBJECTIVE = 2, FP_COUNT = 3, FP_COMPACT = 4 };
+enum FPMode { FP_RATIO = 0, FP_PLAIN = 1, FP_OBJECTIVE = 2, FP_COUNT = 3, FP_COMPACT = 4, FP_EM = 5 };
 
 struct FPLaunch {
     const float* f;
     const float* fz = nullptr;   // 3D: the image with z fastest (the 3D projector reads this, not f)
     const float* y;
     const float* r;
-    float* out;              // FP_RATIO, FP_COUNT, FP_COMPACT: compact [al][plane][b]; FP_PLAIN: natural q
+    float* out;              // FP_RATIO, FP_EM, FP_COUNT, FP_COMPACT: compact [al][plane][b]; FP_PLAIN: natural q
     const int* angles;       // device list of natural angle indices for this pass
     int n_al;                // number of angles
     int mode;
@@ -144,6 +144,7 @@ struct BPLaunch {
     const double* part_mu = nullptr;   // partials of sum mu from the pixel pass
     int n_part_mu = 0;
     Reduction red_f{};                 // partials of sum of the new iterate
+    const float* osem_sens = nullptr;  // 2D fused OSEM update: subset sensitivity of this subset
 };
 int launch_bp(const pet_os_geom* g, const BPLaunch& L, hipStream_t s);
 
@@ -160,6 +161,7 @@ struct UpdLaunch {
     const double* part_mu;   // partials of sum mu (from the back-projection)
     int n_part_mu;
     Reduction red_f;         // sum of the new iterate
+    const float* osem_sens = nullptr;   // OSEM: subset sensitivity; G = A_i^T (y/(q+r))
 };
 int launch_update(const pet_os_geom* g, const UpdLaunch& L, hipStream_t s);
 
@@ -169,6 +171,13 @@ int launch_rdp_value(const pet_os_geom* g, const float* f, float gamma_R, float 
 int launch_fill(float* x, int64_t n, float v, hipStream_t s);
 // total = sum of the first n partials of red (one block, fixed order)
 int launch_finalize(Reduction red, int n, hipStream_t s);
+
+// gradient-consistency measure (diag.hip): partials [8][grid] then the eight
+// FP64 sums <a,b>, |a|^2, |b|^2, count over the smooth and the variable area
+int angle_grid(int64_t n);
+int launch_angle_terms(const pet_os_geom* G, const float* hp, const float* hc, const float* f,
+                       const double* sumf, double smooth_frac, double var_frac, double* part, int grid,
+                       double* out, hipStream_t s);
 
 // grid sizes (for sizing partial arrays)
 int fp_seg_for(const pet_os_geom* g, long long nrays, int requested);
@@ -264,6 +273,7 @@ struct pet_os_state {
     double t_nest;
     int have_frozen;
     petos::Work w;
+    float* osem_sens = nullptr;         // OSEM: the M subset sensitivities [M][n_voxels]
     double* obj_dev = nullptr;          // (fid, R) pairs of queued objective evaluations
     int obj_cap = 0;
     int prof_kernel = -1;               // kernel bracketed by events, -1 = none

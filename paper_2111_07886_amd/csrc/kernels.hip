@@ -107,6 +107,8 @@ __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
         if (A.mode == FP_RATIO) {
             float q = acc;
             A.out[ray] = 1.0f - A.y[nat] / (q + A.r[nat]);
+        } else if (A.mode == FP_EM) {
+            A.out[ray] = A.y[nat] / (acc + A.r[nat]);
         } else if (A.mode == FP_COUNT || A.mode == FP_COMPACT) {
             A.out[ray] = acc;
         } else if (A.mode == FP_PLAIN) {
@@ -153,6 +155,7 @@ struct BPArgs {
     const double* part_mu;
     int n_part_mu;
     Reduction red_f;
+    const float* osem_sens;  // OSEM (fused): f <- f * (A_i^T w) / s_i with w = y/(q+r)
 };
 
 // nu of eq:nuki, S of eq:preconditioner, the relaxed step of Table I and P_t
@@ -333,7 +336,14 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
         stencil_at<2>(s_f, HX, HY, lx + 1, ly + 1, 0, ix, iy, 0, g, A.gamma_R, A.eps, gradR, gmag);
         const long long j = (long long)iy * g.nx + ix;
         const float Gj = fmaf(A.beta_over_M, gradR, acc);
-        if (A.fnew != nullptr) {
+        if (A.fnew != nullptr && A.osem_sens != nullptr) {
+            // ordered-subsets EM (Hudson-Larkin): multiplicative update
+            const float fj = s_f[(ly + 1) * HX + lx + 1];
+            const float sj = A.osem_sens[j];
+            const float fn = (sj > 0.0f) ? fj * acc / sj : fj;
+            A.fnew[j] = fn;
+            part = (double)fn;
+        } else if (A.fnew != nullptr) {
             const float fj = s_f[(ly + 1) * HX + lx + 1];
             const bool need_mu = A.nu_mode == NU_COMPUTE || A.nu_mode == NU_COMPUTE_FREEZE;
             const float fn = sdp_update(fj, Gj, A.pnorm[j], need_mu ? A.mu[j] : 1.0f, meanmu, A.nu_frozen, j,
@@ -660,6 +670,7 @@ int launch_bp(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
     a.part_mu = L.part_mu;
     a.n_part_mu = L.n_part_mu;
     a.red_f = L.red_f;
+    a.osem_sens = L.osem_sens;
     size_t lds;
     int rows_unused;
     const int kind = bp_kind_of(G);

@@ -195,6 +195,8 @@ __device__ void fp3_body(const GeoK& g, const FP3Args& A, long long vblock) {
         const long long ray = ((long long)al * g.n_planes + plane) * Nr + b;
         if (A.mode == FP_RATIO) {
             A.out[ray] = 1.0f - A.y[nat] / (acc + A.r[nat]);
+        } else if (A.mode == FP_EM) {
+            A.out[ray] = A.y[nat] / (acc + A.r[nat]);
         } else if (A.mode == FP_COUNT || A.mode == FP_COMPACT) {
             A.out[ray] = acc;
         } else if (A.mode == FP_PLAIN) {
@@ -596,6 +598,7 @@ struct Upd3Args {
     int n_part_mu;
     Reduction red_f;
     int nx, ny, nz;
+    const float* osem_sens;  // OSEM: f <- f * G / s_i (G = A_i^T (y/(q+r)))
 };
 
 constexpr int U3X = 64, U3Z = 32;
@@ -624,7 +627,13 @@ __device__ void upd3_body(const Upd3Args& A, long long vblock, bool update) {
         if (x < A.nx && z < A.nz) {
             const long long j = ((long long)z * A.ny + y) * A.nx + x;
             const float fj = A.f[j];
-            if (update) {
+            if (update && A.osem_sens != nullptr) {
+                // ordered-subsets EM (Hudson-Larkin): multiplicative update
+                const float sj = A.osem_sens[j];
+                const float fn = (sj > 0.0f) ? fj * A.G[j] / sj : fj;
+                A.f[j] = fn;
+                v = fn;
+            } else if (update) {
                 const float Gj = A.G[j];
                 const float pj = A.pnorm[j];
                 float nu = 1.0f;
@@ -797,6 +806,7 @@ static void fill_upd3(const pet_os_geom* G, const UpdLaunch& L, Upd3Args& a) {
     a.nx = G->d.nx;
     a.ny = G->d.ny;
     a.nz = G->d.nz;
+    a.osem_sens = L.osem_sens;
 }
 
 int launch_update3(const pet_os_geom* G, const UpdLaunch& L, hipStream_t s) {
