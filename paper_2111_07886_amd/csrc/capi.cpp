@@ -861,18 +861,11 @@ int pet_os_gradient_angles(const pet_os_geom* g, const float* h_prev, const floa
     if (!(std::isfinite(smooth_frac) && smooth_frac >= 0.0 && std::isfinite(var_frac) && var_frac >= 0.0))
         return fail(PET_OS_ERR_INVALID_ARG, "smooth_frac and var_frac must be finite and >= 0");
     hipStream_t s = (hipStream_t)stream;
-    const int ng = elem_grid(g->n_vox);
-    const int na = angle_grid(g->n_vox);
-    // [sum f partials ng][sum f total 1][angle partials 8 na][sums 8]
+    const size_t nd = angle_scratch_doubles(g->n_vox);
     double* blk = nullptr;
-    const size_t nd = (size_t)ng + 1 + 8 * (size_t)na + 8;
     if (hipMalloc(&blk, nd * sizeof(double)) != hipSuccess) return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc failed");
-    Reduction R{blk, blk + ng, ng};
-    double* part = blk + ng + 1;
-    double* sums = part + 8 * (size_t)na;
-    int rc = launch_sum(f, g->n_vox, R, s);
-    if (!rc) rc = launch_finalize(R, ng, s);
-    if (!rc) rc = launch_angle_terms(g, h_prev, h_cur, f, R.total, smooth_frac, var_frac, part, na, sums, s);
+    double* sums = blk + nd - 8;
+    int rc = launch_gradient_angles(g, h_prev, h_cur, f, smooth_frac, var_frac, blk, s);
     double h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (!rc && (hipMemcpyAsync(h, sums, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess))

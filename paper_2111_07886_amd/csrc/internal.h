@@ -172,12 +172,13 @@ int launch_fill(float* x, int64_t n, float v, hipStream_t s);
 // total = sum of the first n partials of red (one block, fixed order)
 int launch_finalize(Reduction red, int n, hipStream_t s);
 
-// gradient-consistency measure (diag.hip): partials [8][grid] then the eight
-// FP64 sums <a,b>, |a|^2, |b|^2, count over the smooth and the variable area
+// gradient-consistency measure (diag.hip): sum f, then the eight FP64 sums
+// <a,b>, |a|^2, |b|^2, count over the smooth and the variable area, which
+// end in the last 8 doubles of scratch (angle_scratch_doubles(n_vox) long)
 int angle_grid(int64_t n);
-int launch_angle_terms(const pet_os_geom* G, const float* hp, const float* hc, const float* f,
-                       const double* sumf, double smooth_frac, double var_frac, double* part, int grid,
-                       double* out, hipStream_t s);
+size_t angle_scratch_doubles(int64_t n_vox);
+int launch_gradient_angles(const pet_os_geom* G, const float* hp, const float* hc, const float* f,
+                           double smooth_frac, double var_frac, double* scratch, hipStream_t s);
 
 // grid sizes (for sizing partial arrays)
 int fp_seg_for(const pet_os_geom* g, long long nrays, int requested);
