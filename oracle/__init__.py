@@ -41,7 +41,8 @@ class _Geom(C.Structure):
                 ("n_angles", C.c_int), ("n_radial", C.c_int), ("ds", C.c_double),
                 ("n_rings", C.c_int), ("max_ring_diff", C.c_int),
                 ("ring_pitch", C.c_double), ("det_radius", C.c_double),
-                ("n_subsets", C.c_int)]
+                ("n_subsets", C.c_int), ("n_sub", C.c_int), ("psf_fwhm", C.c_double),
+                ("att", C.POINTER(C.c_double))]
 
 
 class _Params(C.Structure):
@@ -75,6 +76,13 @@ def _load():
             "orc_angle": (None, [G, C.c_int, _D, _D]),
             "orc_trace": (C.c_int, [G, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), _D, C.c_int]),
             "orc_chord_clip": (C.c_double, [G, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
+            "orc_chord_clip_off": (C.c_double, [G, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
+                                                C.c_int]),
+            "orc_trace_off": (C.c_int, [G, C.c_int, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_int), _D,
+                                        C.c_int]),
+            "orc_subray_offset": (C.c_double, [G, C.c_int]),
+            "orc_blur": (None, [G, _D, _D]),
+            "orc_psf_radius": (C.c_int, [G, C.c_double]),
             "orc_forward": (None, [G, _D, C.c_int, _D]),
             "orc_back": (None, [G, _D, C.c_int, _D]),
             "orc_sensitivity": (None, [G, _D]),
@@ -128,6 +136,12 @@ def geom(desc: dict) -> _Geom:
     g.ring_pitch = float(desc.get("ring_pitch", g.vz))
     g.det_radius = float(desc.get("det_radius", 0.0))
     g.n_subsets = int(desc["n_subsets"])
+    g.n_sub = int(desc.get("n_subrays", 1))
+    g.psf_fwhm = float(desc.get("psf_fwhm", 0.0))
+    if desc.get("att") is not None:
+        # the factors live as long as the geometry object
+        g._att = np.ascontiguousarray(np.asarray(desc["att"], dtype=np.float64).reshape(-1))
+        g.att = g._att.ctypes.data_as(C.POINTER(C.c_double))
     if g.dim == 3 and (g.n_rings != g.nz or g.ring_pitch != g.vz):
         raise ValueError("oracle: rings must sit at slice centres (n_rings == nz, ring_pitch == vz)")
     return g
@@ -179,6 +193,25 @@ def trace(g, plane, a, b):
 
 def chord_clip(g, plane, a, b, ix, iy, iz=0):
     return _load().orc_chord_clip(C.byref(g), plane, a, b, ix, iy, iz)
+
+
+def chord_clip_off(g, plane, a, b, off, ix, iy, iz=0):
+    return _load().orc_chord_clip_off(C.byref(g), plane, a, b, off, ix, iy, iz)
+
+
+def subray_offset(g, k):
+    return _load().orc_subray_offset(C.byref(g), k)
+
+
+def blur(g, f):
+    f = _f64(f).reshape(-1)
+    out = np.zeros_like(f)
+    _load().orc_blur(C.byref(g), _ptr(f), _ptr(out))
+    return out.reshape(img_shape(g))
+
+
+def psf_radius(g, v):
+    return _load().orc_psf_radius(C.byref(g), v)
 
 
 def forward(g, f, subset=0):

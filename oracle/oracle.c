@@ -89,16 +89,24 @@ typedef struct {
     int constcell[MAXAX];   /* cell index if D[k] == 0, else -2 */
 } lor_t;
 
-static void make_lor(const orc_geom* g, int plane, int a, int b, lor_t* L) {
+/* LOR of bin b moved by off [mm] along its normal (off = 0: the bin's line;
+ * otherwise a sub-ray, 2D).  An axis-parallel sub-ray's cell follows the same
+ * half-open rule, from its coordinate in FP64. */
+static void make_lor(const orc_geom* g, int plane, int a, int b, double off, lor_t* L) {
     double c, s;
     orc_angle(g, a, &c, &s);
-    double sb = bin_pos(g, b);
+    double sb = bin_pos(g, b) + off;
     L->P0[0] = sb * c;
     L->P0[1] = sb * s;
     L->D[0] = -s;
     L->D[1] = c;
-    L->constcell[0] = (s == 0.0) ? axis_cell(g, b, g->nx, g->vx) : -2;
-    L->constcell[1] = (c == 0.0) ? axis_cell(g, b, g->ny, g->vy) : -2;
+    if (off == 0.0) {
+        L->constcell[0] = (s == 0.0) ? axis_cell(g, b, g->nx, g->vx) : -2;
+        L->constcell[1] = (c == 0.0) ? axis_cell(g, b, g->ny, g->vy) : -2;
+    } else {
+        L->constcell[0] = (s == 0.0) ? (int)floor((sb + 0.5 * g->nx * g->vx) / g->vx) : -2;
+        L->constcell[1] = (c == 0.0) ? (int)floor((sb + 0.5 * g->ny * g->vy) / g->vy) : -2;
+    }
     if (g->dim == 2) {
         L->P0[2] = 0.0; L->D[2] = 0.0; L->constcell[2] = 0; L->kappa = 1.0;
         return;
@@ -126,8 +134,12 @@ static void axis_dims(const orc_geom* g, int n[MAXAX], double v[MAXAX], double l
  * each interval between successive crossings lies in one voxel, found from
  * its midpoint. */
 int orc_trace(const orc_geom* g, int plane, int a, int b, int* vox, double* len, int cap) {
+    return orc_trace_off(g, plane, a, b, 0.0, vox, len, cap);
+}
+
+int orc_trace_off(const orc_geom* g, int plane, int a, int b, double off, int* vox, double* len, int cap) {
     lor_t L;
-    make_lor(g, plane, a, b, &L);
+    make_lor(g, plane, a, b, off, &L);
     int n[MAXAX]; double v[MAXAX], lo[MAXAX];
     axis_dims(g, n, v, lo);
 
@@ -204,8 +216,12 @@ int orc_trace(const orc_geom* g, int plane, int a, int b, int* vox, double* len,
  * slabs one at a time; an axis-parallel LOR is inside a slab iff its constant
  * coordinate lies in the half-open interval [lower, upper). */
 double orc_chord_clip(const orc_geom* g, int plane, int a, int b, int ix, int iy, int iz) {
+    return orc_chord_clip_off(g, plane, a, b, 0.0, ix, iy, iz);
+}
+
+double orc_chord_clip_off(const orc_geom* g, int plane, int a, int b, double off, int ix, int iy, int iz) {
     lor_t L;
-    make_lor(g, plane, a, b, &L);
+    make_lor(g, plane, a, b, off, &L);
     int n[MAXAX]; double v[MAXAX], lo[MAXAX];
     axis_dims(g, n, v, lo);
     int id[MAXAX] = {ix, iy, iz};
@@ -247,10 +263,73 @@ static long nat_index(const orc_geom* g, int plane, int a, int b) {
     return ((long)plane * g->n_angles + a) * g->n_radial + b;
 }
 
-/* q = A_i f (sec. II-B): one Siddon sum per ray of the subset */
+double orc_subray_offset(const orc_geom* g, int k) {
+    int ns = g->n_sub > 1 ? g->n_sub : 1;
+    return (((double)k + 0.5) / (double)ns - 0.5) * g->ds;
+}
+
+/* ------------------------------------------------------------------ */
+/* PSF of Sec. IV-A: Gaussian, FWHM given, applied in image space      */
+/* ------------------------------------------------------------------ */
+
+int orc_psf_radius(const orc_geom* g, double v) {
+    double sigma = g->psf_fwhm / (2.0 * sqrt(2.0 * log(2.0)));
+    return (int)ceil(3.0 * sigma / v);
+}
+
+static void psf_taps(const orc_geom* g, double v, int K, double* w) {
+    double sigma = g->psf_fwhm / (2.0 * sqrt(2.0 * log(2.0)));
+    double sum = 0.0;
+    for (int k = -K; k <= K; ++k) {
+        double x = k * v;
+        w[k + K] = exp(-x * x / (2.0 * sigma * sigma));
+        sum += w[k + K];
+    }
+    for (int k = 0; k <= 2 * K; ++k) w[k] /= sum;
+}
+
+void orc_blur(const orc_geom* g, const double* in, double* out) {
+    int nx = g->nx, ny = g->ny;
+    int Kx = orc_psf_radius(g, g->vx), Ky = orc_psf_radius(g, g->vy);
+    double* wx = (double*)malloc(sizeof(double) * (size_t)(2 * Kx + 1));
+    double* wy = (double*)malloc(sizeof(double) * (size_t)(2 * Ky + 1));
+    psf_taps(g, g->vx, Kx, wx);
+    psf_taps(g, g->vy, Ky, wy);
+    double* tmp = (double*)malloc(sizeof(double) * (size_t)nx * ny);
+    for (int iy = 0; iy < ny; ++iy)          /* along x */
+        for (int ix = 0; ix < nx; ++ix) {
+            double acc = 0.0;
+            for (int k = -Kx; k <= Kx; ++k) {
+                int x = ix + k;
+                if (x >= 0 && x < nx) acc += wx[k + Kx] * in[iy * nx + x];
+            }
+            tmp[iy * nx + ix] = acc;
+        }
+    for (int iy = 0; iy < ny; ++iy)          /* along y */
+        for (int ix = 0; ix < nx; ++ix) {
+            double acc = 0.0;
+            for (int k = -Ky; k <= Ky; ++k) {
+                int y = iy + k;
+                if (y >= 0 && y < ny) acc += wy[k + Ky] * tmp[y * nx + ix];
+            }
+            out[iy * nx + ix] = acc;
+        }
+    free(tmp); free(wx); free(wy);
+}
+
+/* q = A_i f (sec. II-B), A = diag(att) P B: the image blurred by the PSF (if
+ * any), then per ray of the subset the mean over its sub-rays of the Siddon
+ * sums, times the ray's attenuation factor (if any) */
 void orc_forward(const orc_geom* g, const double* f, int subset, double* q) {
     int* angles = (int*)malloc(sizeof(int) * (size_t)g->n_angles);
     int na = subset_angles(g, subset, angles);
+    int ns = g->n_sub > 1 ? g->n_sub : 1;
+    double* fb = NULL;
+    if (g->psf_fwhm > 0.0) {
+        fb = (double*)malloc(sizeof(double) * (size_t)orc_n_voxels(g));
+        orc_blur(g, f, fb);
+        f = fb;
+    }
     int P = orc_n_planes(g), Nr = g->n_radial, cap = trace_cap(g);
     long nrays = (long)P * na * Nr;
 #pragma omp parallel
@@ -262,21 +341,32 @@ void orc_forward(const orc_geom* g, const double* f, int subset, double* q) {
             int b = (int)(ray % Nr);
             int al = (int)((ray / Nr) % na);
             int plane = (int)(ray / ((long)Nr * na));
-            int cnt = orc_trace(g, plane, angles[al], b, vox, len, cap);
             double acc = 0.0;
-            for (int m = 0; m < cnt; ++m) acc += len[m] * f[vox[m]];
-            q[nat_index(g, plane, angles[al], b)] = acc;
+            for (int k = 0; k < ns; ++k) {
+                double off = (ns > 1) ? orc_subray_offset(g, k) : 0.0;
+                int cnt = orc_trace_off(g, plane, angles[al], b, off, vox, len, cap);
+                double part = 0.0;
+                for (int m = 0; m < cnt; ++m) part += len[m] * f[vox[m]];
+                acc += part;
+            }
+            acc /= (double)ns;
+            long i = nat_index(g, plane, angles[al], b);
+            q[i] = g->att ? g->att[i] * acc : acc;
         }
         free(vox); free(len);
     }
     free(angles);
+    free(fb);
 }
 
-/* out = A_i^T w: each ray of the subset scatters w_i a_ij into its voxels
- * (thread-private images summed afterwards).  w == NULL means w = 1. */
+/* out = A_i^T w = B^T P^T (att w): each ray of the subset scatters
+ * att_i w_i a_ij into its voxels, every sub-ray with weight 1/n_sub
+ * (thread-private images summed afterwards), then the PSF (symmetric) is
+ * applied.  w == NULL means w = 1. */
 void orc_back(const orc_geom* g, const double* w, int subset, double* out) {
     int* angles = (int*)malloc(sizeof(int) * (size_t)g->n_angles);
     int na = subset_angles(g, subset, angles);
+    int ns = g->n_sub > 1 ? g->n_sub : 1;
     int P = orc_n_planes(g), Nr = g->n_radial, cap = trace_cap(g);
     int nv = orc_n_voxels(g);
     long nrays = (long)P * na * Nr;
@@ -296,17 +386,27 @@ void orc_back(const orc_geom* g, const double* w, int subset, double* out) {
             int b = (int)(ray % Nr);
             int al = (int)((ray / Nr) % na);
             int plane = (int)(ray / ((long)Nr * na));
-            double wi = w ? w[nat_index(g, plane, angles[al], b)] : 1.0;
+            long i = nat_index(g, plane, angles[al], b);
+            double wi = w ? w[i] : 1.0;
+            if (g->att) wi *= g->att[i];
             if (wi == 0.0) continue;
-            int cnt = orc_trace(g, plane, angles[al], b, vox, len, cap);
-            for (int m = 0; m < cnt; ++m) mine[vox[m]] += len[m] * wi;
+            for (int k = 0; k < ns; ++k) {
+                double off = (ns > 1) ? orc_subray_offset(g, k) : 0.0;
+                int cnt = orc_trace_off(g, plane, angles[al], b, off, vox, len, cap);
+                for (int m = 0; m < cnt; ++m) mine[vox[m]] += len[m] * wi / (double)ns;
+            }
         }
         free(vox); free(len);
     }
+    double* acc_img = (g->psf_fwhm > 0.0) ? (double*)malloc(sizeof(double) * (size_t)nv) : out;
     for (int j = 0; j < nv; ++j) {
         double acc = 0.0;
         for (int t = 0; t < nt; ++t) acc += priv[(size_t)t * nv + j];
-        out[j] = acc;
+        acc_img[j] = acc;
+    }
+    if (g->psf_fwhm > 0.0) {
+        orc_blur(g, acc_img, out);
+        free(acc_img);
     }
     free(priv);
     free(angles);

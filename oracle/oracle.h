@@ -8,7 +8,10 @@
  * Every routine is written for clarity, not speed: the system matrix A is the
  * classic Siddon ray tracer (sorted plane crossings, midpoint cell lookup),
  * back-projection is the same trace scattered ray by ray, and the iteration is
- * Table I (tab:SDPBSREM) step by step in double precision.
+ * Table I (tab:SDPBSREM) step by step in double precision.  The full 2D model
+ * of Sec. IV-A (sub-rays per bin, Gaussian PSF, attenuation factors) is the
+ * same tracer applied per sub-ray, a plain separable convolution and a
+ * per-bin product (orc_geom fields n_sub, psf_fwhm, att).
  *
  * Geometry conventions (the paper gives only the Matlab set-up of Sec. IV-A):
  *   pixel centres x = (ix - (nx-1)/2) vx, cells half-open [x0, x1);
@@ -38,6 +41,13 @@ typedef struct {
     int n_rings, max_ring_diff;
     double ring_pitch, det_radius;
     int n_subsets;
+    /* full 2D system model of Sec. IV-A (all optional; 0 / NULL = off):
+     * A = diag(att) P B with P the mean over n_sub parallel sub-rays per bin,
+     * spread evenly over the bin width ds (offsets ((k + 1/2)/n_sub - 1/2) ds),
+     * and B the image-space Gaussian PSF of FWHM psf_fwhm [mm]. */
+    int n_sub;               /* sub-rays per bin (0 or 1: the single line s_b) */
+    double psf_fwhm;         /* PSF FWHM [mm], 2D only */
+    const double* att;       /* per-bin attenuation factors [n_bins], natural layout */
 } orc_geom;
 
 enum { ORC_BSREM = 0, ORC_M1 = 1, ORC_M2 = 2, ORC_P1 = 3, ORC_P2 = 4 };
@@ -69,6 +79,17 @@ int    orc_trace(const orc_geom* g, int plane, int a, int b, int* vox, double* l
 
 /* chord length of the LOR inside one voxel by direct slab clipping (no trace) */
 double orc_chord_clip(const orc_geom* g, int plane, int a, int b, int ix, int iy, int iz);
+/* the same for the line x cos + y sin = s_b + off (a sub-ray; 2D) */
+double orc_chord_clip_off(const orc_geom* g, int plane, int a, int b, double off, int ix, int iy, int iz);
+/* Siddon trace of the line at offset off from bin b's centre line */
+int    orc_trace_off(const orc_geom* g, int plane, int a, int b, double off, int* vox, double* len, int cap);
+/* offset of sub-ray k of a bin */
+double orc_subray_offset(const orc_geom* g, int k);
+/* out = B in: separable Gaussian PSF (sigma = fwhm / (2 sqrt(2 ln 2)), taps at
+ * whole-pixel distances up to ceil(3 sigma / v), normalised to sum 1 per axis,
+ * zero outside the image: a symmetric operator).  2D. */
+void   orc_blur(const orc_geom* g, const double* in, double* out);
+int    orc_psf_radius(const orc_geom* g, double v);
 
 /* q = A_i f for the rays of subset `subset` (1..M), or of all rays if subset == 0.
  * q is natural layout; entries of other subsets are left untouched. */
