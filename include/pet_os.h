@@ -90,6 +90,18 @@ typedef struct {
     double ring_pitch;        /* 3D: == vz */
     double det_radius;        /* 3D: detector ring radius [mm], > image half-diagonal */
     int32_t n_subsets;        /* M, 1 <= M <= n_angles */
+    /* The full 2D system model of Sec. IV-A (2D only; zeros = one line per
+     * bin and no PSF).  A = diag(att) P B: P averages n_subrays parallel
+     * sub-rays per bin, spread evenly over the bin width ds (offsets
+     * ((k + 1/2)/n_subrays - 1/2) ds from the bin's line); B is a Gaussian
+     * PSF of FWHM psf_fwhm applied in image space (taps at whole-pixel
+     * distances up to ceil(3 sigma / v) <= 16 pixels, normalised per axis,
+     * zero outside the image); att are per-bin attenuation factors given at
+     * creation (pet_os_create_geometry_attenuated).  Geometries that use any
+     * of them run through states and pet_os_reconstruct, not the batched or
+     * served paths. */
+    int32_t n_subrays;        /* 0 or 1: one line per bin; else 2..64 */
+    double psf_fwhm;          /* [mm], 0: no PSF */
 } pet_os_geom_desc;
 
 /* Algorithm parameters (Sec. II, III-B, IV-A). */
@@ -118,6 +130,20 @@ const char* pet_os_version(void);
  * s = A^T 1 and the normaliser p_j = s_j/M (or 1/M where s_j = 0) of eq:pj.
  * Synchronous.  The library owns *out until pet_os_destroy_geometry. */
 int pet_os_create_geometry(const pet_os_geom_desc* desc, pet_os_geom** out);
+
+/* The same with per-bin attenuation factors (Sec. IV-A: uniform water,
+ * 0.096 / cm, over the object's support): att is a HOST array of n_bins
+ * floats (natural layout, finite, > 0), copied; the model becomes
+ * A = diag(att) P B, and the sensitivity A^T 1 includes it.  2D only. */
+int pet_os_create_geometry_attenuated(const pet_os_geom_desc* desc, const float* att,
+                                      pet_os_geom** out);
+
+/* Attenuation factors att_i = exp(-sum_j a_ij mu_j) of the geometry's rays
+ * through an attenuation map mu (DEVICE, n_voxels floats, per mm): the line
+ * integrals of the sub-ray model P, without the PSF or any attenuation the
+ * geometry already has.  att: DEVICE, n_bins floats.  Asynchronous. */
+int pet_os_attenuation_factors(const pet_os_geom* geom, const float* mu, float* att,
+                               pet_os_stream stream);
 int pet_os_destroy_geometry(pet_os_geom* geom);
 
 /* Sizes: voxels, bins (planes*angles*radial), planes. Any pointer may be NULL. */

@@ -24,6 +24,7 @@ ERRORS = {-1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "DEVICE", -4: "BUDGET", -5
 
 # every symbol declared in include/pet_os.h
 EXPORTS = ["pet_os_last_error", "pet_os_version", "pet_os_create_geometry", "pet_os_destroy_geometry",
+           "pet_os_create_geometry_attenuated", "pet_os_attenuation_factors",
            "pet_os_geometry_info", "pet_os_sensitivity", "pet_os_forward", "pet_os_back",
            "pet_os_objective", "pet_os_default_U", "pet_os_subset_gradient", "pet_os_gradient_angles",
            "pet_os_state_create", "pet_os_state_destroy",
@@ -47,7 +48,8 @@ class GeomDesc(C.Structure):
                 ("vx", C.c_double), ("vy", C.c_double), ("vz", C.c_double),
                 ("n_angles", C.c_int32), ("n_radial", C.c_int32), ("ds", C.c_double),
                 ("n_rings", C.c_int32), ("max_ring_diff", C.c_int32),
-                ("ring_pitch", C.c_double), ("det_radius", C.c_double), ("n_subsets", C.c_int32)]
+                ("ring_pitch", C.c_double), ("det_radius", C.c_double), ("n_subsets", C.c_int32),
+                ("n_subrays", C.c_int32), ("psf_fwhm", C.c_double)]
 
 
 class Params(C.Structure):
@@ -93,6 +95,8 @@ def lib():
             "pet_os_last_error": (C.c_char_p, []),
             "pet_os_version": (C.c_char_p, []),
             "pet_os_create_geometry": (C.c_int, [C.POINTER(GeomDesc), C.POINTER(_P)]),
+            "pet_os_create_geometry_attenuated": (C.c_int, [C.POINTER(GeomDesc), _P, C.POINTER(_P)]),
+            "pet_os_attenuation_factors": (C.c_int, [_P, _P, _P, _P]),
             "pet_os_destroy_geometry": (C.c_int, [_P]),
             "pet_os_geometry_info": (C.c_int, [_P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]),
             "pet_os_sensitivity": (C.c_int, [_P, _P, _P]),
@@ -176,6 +180,8 @@ def desc_struct(d: dict) -> GeomDesc:
     g.n_rings, g.max_ring_diff = int(d.get("n_rings", 1)), int(d.get("max_ring_diff", 0))
     g.ring_pitch, g.det_radius = float(d.get("ring_pitch", 1.0)), float(d.get("det_radius", 0.0))
     g.n_subsets = int(d["n_subsets"])
+    g.n_subrays = int(d.get("n_subrays", 1))
+    g.psf_fwhm = float(d.get("psf_fwhm", 0.0))
     return g
 
 
@@ -193,13 +199,21 @@ def params_struct(p: dict) -> Params:
 
 
 class Geometry:
-    """Handle of pet_os_create_geometry (sensitivity and p computed on creation)."""
+    """Handle of pet_os_create_geometry (sensitivity and p computed on creation).
+    ``att``: optional per-bin attenuation factors (host array of n_bins
+    values), for pet_os_create_geometry_attenuated."""
 
-    def __init__(self, desc: dict):
+    def __init__(self, desc: dict, att=None):
         self.desc = dict(desc)
         self._d = desc_struct(desc)
         h = _P()
-        _check(lib().pet_os_create_geometry(C.byref(self._d), C.byref(h)))
+        if att is None:
+            _check(lib().pet_os_create_geometry(C.byref(self._d), C.byref(h)))
+        else:
+            import numpy as np
+            a = np.ascontiguousarray(np.asarray(att, dtype=np.float32).reshape(-1))
+            _check(lib().pet_os_create_geometry_attenuated(C.byref(self._d), C.c_void_p(a.ctypes.data),
+                                                           C.byref(h)))
         self.handle = h
         nv, nb, npl = C.c_int64(), C.c_int64(), C.c_int32()
         _check(lib().pet_os_geometry_info(h, C.byref(nv), C.byref(nb), C.byref(npl)))
@@ -271,6 +285,14 @@ class Geometry:
                                             _dev(h_cur, self.n_voxels, "h_cur"), _dev(f, self.n_voxels, "f"),
                                             float(smooth_frac), float(var_frac), th, cnt, _stream(stream)))
         return th[0], th[1], cnt[0], cnt[1]
+
+    def attenuation_factors(self, mu, out=None, stream=None):
+        """pet_os_attenuation_factors: exp(-line integrals of mu) per bin."""
+        if out is None:
+            out = torch.empty(self.sino_shape, device="cuda", dtype=torch.float32)
+        _check(lib().pet_os_attenuation_factors(self.handle, _dev(mu, self.n_voxels, "mu"),
+                                                _dev(out, self.n_bins, "att"), _stream(stream)))
+        return out
 
     def nnz(self, subset=0) -> int:
         n = C.c_int64()

@@ -201,6 +201,8 @@ int pet_os_batch_add(pet_os_batch* B, const pet_os_geom* g, const pet_os_params*
     int rc = validate_params(p, g);
     if (rc) return rc;
     if (p->mode == PET_OS_OSEM) return fail(PET_OS_ERR_INVALID_ARG, "OSEM runs on states only, not in a batch");
+    if (g->full_model)
+        return fail(PET_OS_ERR_INVALID_ARG, "sub-rays, PSF and attenuation run on states only, not in a batch");
     int idx = -1;
     for (int s = 0; s < B->max_slots; ++s)
         if (!B->slots[s].used) { idx = s; break; }

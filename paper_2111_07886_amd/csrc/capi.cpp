@@ -42,6 +42,16 @@ int validate_desc(const pet_os_geom_desc* d) {
         return fail(PET_OS_ERR_INVALID_ARG, "n_subsets must be in [1, n_angles]");
     if ((int64_t)d->nx * d->ny * (d->dim == 3 ? d->nz : 1) > (int64_t)1 << 30)
         return fail(PET_OS_ERR_INVALID_ARG, "image too large");
+    if (d->n_subrays < 0 || d->n_subrays > 64) return fail(PET_OS_ERR_INVALID_ARG, "n_subrays must be in [0, 64]");
+    if (!(std::isfinite(d->psf_fwhm) && d->psf_fwhm >= 0.0))
+        return fail(PET_OS_ERR_INVALID_ARG, "psf_fwhm must be finite and >= 0");
+    if (d->dim == 3 && (d->n_subrays > 1 || d->psf_fwhm > 0.0))
+        return fail(PET_OS_ERR_INVALID_ARG, "sub-rays and the PSF are 2D only");
+    if (d->psf_fwhm > 0.0) {
+        const double sigma = d->psf_fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+        if (std::ceil(3.0 * sigma / d->vx) > PSF_KMAX || std::ceil(3.0 * sigma / d->vy) > PSF_KMAX)
+            return fail(PET_OS_ERR_INVALID_ARG, "PSF wider than 16 pixels (3 sigma)");
+    }
     if (d->dim == 3) {
         if (d->nz < 1 || !finite_pos(d->vz)) return fail(PET_OS_ERR_INVALID_ARG, "nz >= 1 and vz > 0 required");
         if (d->n_rings != d->nz || d->ring_pitch != d->vz)
@@ -185,11 +195,38 @@ const char* pet_os_last_error(void) { return g_last_error.c_str(); }
 
 const char* pet_os_version(void) { return "pet_os 0.1 (gfx950)"; }
 
+// taps of the Gaussian PSF along one axis: exp(-x^2 / 2 sigma^2) at whole-pixel
+// distances up to K = ceil(3 sigma / v), normalised to sum 1
+static void psf_taps(double fwhm, double v, std::vector<float>& taps, int& K) {
+    const double sigma = fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+    K = (int)std::ceil(3.0 * sigma / v);
+    std::vector<double> w(2 * K + 1);
+    double sum = 0.0;
+    for (int k = -K; k <= K; ++k) {
+        const double x = k * v;
+        w[k + K] = std::exp(-x * x / (2.0 * sigma * sigma));
+        sum += w[k + K];
+    }
+    for (double& t : w) taps.push_back((float)(t / sum));
+}
+
+static int create_geometry(const pet_os_geom_desc* desc, const float* att_host, pet_os_geom** out);
+
 int pet_os_create_geometry(const pet_os_geom_desc* desc, pet_os_geom** out) {
+    return create_geometry(desc, nullptr, out);
+}
+
+int pet_os_create_geometry_attenuated(const pet_os_geom_desc* desc, const float* att, pet_os_geom** out) {
+    if (!att) return fail(PET_OS_ERR_INVALID_ARG, "att is NULL");
+    return create_geometry(desc, att, out);
+}
+
+static int create_geometry(const pet_os_geom_desc* desc, const float* att_host, pet_os_geom** out) {
     if (!out) return fail(PET_OS_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     int rc = validate_desc(desc);
     if (rc) return rc;
+    if (att_host && desc->dim != 2) return fail(PET_OS_ERR_INVALID_ARG, "attenuation factors are 2D only");
     pet_os_geom_desc d = *desc;
     if (d.dim == 2) {
         d.nz = 1; d.vz = 1.0; d.n_rings = 1; d.max_ring_diff = 0; d.ring_pitch = 1.0;
@@ -251,6 +288,20 @@ int pet_os_create_geometry(const pet_os_geom_desc* desc, pet_os_geom** out) {
     }
     std::vector<int> all(d.n_angles);
     for (int a = 0; a < d.n_angles; ++a) all[a] = a;
+    // full 2D model: PSF taps (x then y) and attenuation factors
+    std::vector<float> taps;
+    int kx = 0, ky = 0;
+    if (d.psf_fwhm > 0.0) {
+        psf_taps(d.psf_fwhm, d.vx, taps, kx);
+        psf_taps(d.psf_fwhm, d.vy, taps, ky);
+    }
+    if (att_host) {
+        for (int64_t i = 0; i < G->n_bins; ++i)
+            if (!(std::isfinite(att_host[i]) && att_host[i] > 0.0f)) {
+                delete G;
+                return fail(PET_OS_ERR_INVALID_ARG, "attenuation factors must be finite and > 0");
+            }
+    }
 
     Carver cv;
     size_t o_ang = cv.take<AngleK>(ang.size());
@@ -264,6 +315,9 @@ int pet_os_create_geometry(const pet_os_geom_desc* desc, pet_os_geom** out) {
     size_t o_cnt = cv.take<int>(counts.size());
     size_t o_pn = cv.take<float>((size_t)G->n_vox);
     size_t o_sn = cv.take<float>((size_t)G->n_vox);
+    size_t o_tap = cv.take<float>(std::max<size_t>(taps.size(), 1));
+    size_t o_att = cv.take<float>(att_host ? (size_t)G->n_bins : 1);
+    size_t o_tmp = cv.take<float>(d.psf_fwhm > 0.0 ? (size_t)G->n_vox : 1);
     size_t total = cv.off;
     char* blk = nullptr;
     if (hipMalloc(&blk, total) != hipSuccess) {
@@ -282,7 +336,9 @@ int pet_os_create_geometry(const pet_os_geom_desc* desc, pet_os_geom** out) {
         up(o_id, inv_d.data(), inv_d.size() * sizeof(double)) != hipSuccess ||
         up(o_all, all.data(), all.size() * sizeof(int)) != hipSuccess ||
         up(o_lst, lists.data(), lists.size() * sizeof(int)) != hipSuccess ||
-        up(o_cnt, counts.data(), counts.size() * sizeof(int)) != hipSuccess) {
+        up(o_cnt, counts.data(), counts.size() * sizeof(int)) != hipSuccess ||
+        (!taps.empty() && up(o_tap, taps.data(), taps.size() * sizeof(float)) != hipSuccess) ||
+        (att_host && up(o_att, att_host, (size_t)G->n_bins * sizeof(float)) != hipSuccess)) {
         (void)hipFree(blk);
         delete G;
         return fail(PET_OS_ERR_DEVICE, "upload of geometry tables failed");
@@ -299,6 +355,16 @@ int pet_os_create_geometry(const pet_os_geom_desc* desc, pet_os_geom** out) {
     k.kappa = (const double*)(blk + o_kap);
     k.plane_base = (const int*)(blk + o_pb);
     k.inv_d = (const double*)(blk + o_id);
+    k.n_sub = std::max(1, d.n_subrays);
+    k.sub_h = (float)(d.ds / k.n_sub);
+    k.sub_x0 = (float)(0.5 * d.ds / k.n_sub - 0.5 * d.ds);
+    k.inv_nsub = (float)(1.0 / k.n_sub);
+    k.sub_half = 0.5 * d.ds - 0.5 * d.ds / k.n_sub;
+    k.psf_kx = kx;
+    k.psf_ky = ky;
+    k.psf = taps.empty() ? nullptr : (const float*)(blk + o_tap);
+    k.att = att_host ? (const float*)(blk + o_att) : nullptr;
+    G->full_model = k.n_sub > 1 || kx > 0 || att_host != nullptr;
     G->pnorm = (float*)(blk + o_pn);
     G->sens = (float*)(blk + o_sn);
     {
@@ -315,8 +381,9 @@ int pet_os_create_geometry(const pet_os_geom_desc* desc, pet_os_geom** out) {
     L.w = nullptr;
     L.angles = (const int*)(blk + o_all);
     L.n_al = d.n_angles;
-    L.out = G->sens;
+    L.out = d.psf_fwhm > 0.0 ? (float*)(blk + o_tmp) : G->sens;
     rc = launch_bp(G, L, nullptr);
+    if (!rc && d.psf_fwhm > 0.0) rc = launch_blur(G, (float*)(blk + o_tmp), G->sens, nullptr);
     if (rc) { pet_os_destroy_geometry(G); return rc; }
     std::vector<float> s((size_t)G->n_vox);
     if (hipMemcpy(s.data(), G->sens, s.size() * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) {
@@ -381,6 +448,8 @@ int work_alloc(const pet_os_geom* g, bool need_nu, Work* w) {
     const bool d3 = g->d.dim == 3;
     size_t o_fz = d3 ? cv.take<float>(nv) : 0;
     size_t o_snap = d3 ? 0 : cv.take<float>(nv);
+    const bool psf = g->k.psf_kx > 0;
+    size_t o_fb = psf ? cv.take<float>(nv) : 0;
     int caps[RED_COUNT];
     caps[RED_SUMF] = std::max(std::max(sumf_grid(g), bp_grid_max(g)), elem_grid(g->n_vox));
     caps[RED_SUMMU] = std::max(bp_grid_max(g), elem_grid(g->n_vox));
@@ -402,6 +471,7 @@ int work_alloc(const pet_os_geom* g, bool need_nu, Work* w) {
     w->nu_frozen = need_nu ? (float*)(blk + o_nu) : nullptr;
     w->fz = d3 ? (float*)(blk + o_fz) : nullptr;
     w->fsnap = d3 ? nullptr : (float*)(blk + o_snap);
+    w->fb = psf ? (float*)(blk + o_fb) : nullptr;
     for (int r = 0; r < RED_COUNT; ++r) {
         w->red[r].part = (double*)(blk + o_red[r]);
         w->red[r].total = (double*)(blk + o_tot) + r;
@@ -562,9 +632,16 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
         F.px_n_part_f = sumf_grid(g);
         F.px_red_mu = st->w.red[RED_SUMMU];
     }
+    const bool psf = !d3 && g->k.psf_kx > 0;
     hipEvent_t ev;
     if ((rc = prof_begin(st, 0, s, &ev))) return rc;
-    rc = launch_fp(g, F, s);
+    if (psf) {
+        // the projector sees the PSF-blurred iterate; the pixel pass the iterate
+        rc = launch_blur(g, f, st->w.fb, s);
+        F.f = st->w.fb;
+        F.px_f = f;
+    }
+    if (!rc) rc = launch_fp(g, F, s);
     if (rc || (rc = prof_end(ev, s))) return rc;
     BPLaunch B{};
     B.w = st->w.w; B.w_natural = 0; B.angles = angles; B.n_al = n_al;
@@ -583,7 +660,17 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
         B.osem_sens = sens_i;
         if (osem) B.beta_over_M = 0.0f;
         if ((rc = prof_begin(st, 1, s, &ev))) return rc;
-        rc = launch_bp(g, B, s);
+        if (psf) {
+            // B A_i^T w needs the neighbouring tiles' back-projection: plain
+            // back-projection, blur, then the image-space part per tile
+            BPLaunch P{};
+            P.w = st->w.w; P.w_natural = 0; P.angles = angles; P.n_al = n_al; P.out = st->w.G;
+            rc = launch_bp(g, P, s);
+            if (!rc) rc = launch_blur(g, st->w.G, st->w.fb, s);
+            if (!rc) rc = launch_upd2(g, B, st->w.fb, s);
+        } else {
+            rc = launch_bp(g, B, s);
+        }
         if (rc || (rc = prof_end(ev, s))) return rc;
     } else {
         B.f = f; B.out = st->w.G; B.mu = st->w.mu; B.want_mu = want_mu ? 1 : 0;
@@ -623,6 +710,10 @@ static int queue_objective(const pet_os_geom* g, const pet_os_params* p, Work* w
     FPLaunch F{};
     F.f = f; F.fz = w->fz; F.y = y; F.r = r; F.out = nullptr; F.angles = ex->all_angles; F.n_al = g->d.n_angles;
     F.mode = FP_OBJECTIVE; F.red = w->red[RED_FID];
+    if (g->d.dim == 2 && g->k.psf_kx > 0) {
+        if ((rc = launch_blur(g, f, w->fb, s))) return rc;
+        F.f = w->fb;
+    }
     rc = launch_fp(g, F, s);
     if (!rc) rc = launch_finalize(w->red[RED_FID], fp_grid(g, g->d.n_angles), s);
     if (!rc) rc = launch_rdp_value(g, f, (float)p->gamma_R, (float)p->eps, w->red[RED_RDP], s);
@@ -667,8 +758,12 @@ int pet_os_state_create(const pet_os_geom* g, const pet_os_params* p, pet_os_sta
             L.w = nullptr;
             L.angles = ex->subset_lists + (size_t)i * g->max_sub_angles;
             L.n_al = ex->subset_count[i];
-            L.out = st->osem_sens + (size_t)i * g->n_vox;
+            float* si = st->osem_sens + (size_t)i * g->n_vox;
+            // with a PSF: B^T P^T att, the back-projection blurred from the state's scratch
+            const bool psf = g->d.dim == 2 && g->k.psf_kx > 0;
+            L.out = psf ? st->w.fb : si;
             rc = launch_bp(g, L, nullptr);
+            if (!rc && psf) rc = launch_blur(g, st->w.fb, si, nullptr);
         }
         if (!rc && hipDeviceSynchronize() != hipSuccess) rc = fail(PET_OS_ERR_DEVICE, "subset sensitivities failed");
         if (rc) {
@@ -716,6 +811,19 @@ int pet_os_forward(const pet_os_geom* g, const float* f, int32_t subset, float* 
     F.f = f; F.out = q; F.mode = FP_PLAIN;
     F.angles = subset == 0 ? ex->all_angles : ex->subset_lists + (size_t)(subset - 1) * g->max_sub_angles;
     F.n_al = subset == 0 ? g->d.n_angles : ex->subset_count[subset - 1];
+    if (g->d.dim == 2 && g->k.psf_kx > 0) {
+        // the PSF-blurred image, in scratch released before returning
+        hipStream_t s = (hipStream_t)stream;
+        float* tmp = nullptr;
+        if (hipMalloc(&tmp, sizeof(float) * (size_t)g->n_vox) != hipSuccess)
+            return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc failed");
+        int rc = launch_blur(g, f, tmp, s);
+        F.f = tmp;
+        if (!rc) rc = launch_fp(g, F, s);
+        if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = fail(PET_OS_ERR_DEVICE, "stream synchronize failed");
+        (void)hipFree(tmp);
+        return rc;
+    }
     if (g->d.dim == 2) return launch_fp(g, F, (hipStream_t)stream);
     // 3D: the projector reads a z-fastest copy of f, made in scratch that is
     // released before returning (this call waits for the stream)
@@ -740,7 +848,35 @@ int pet_os_back(const pet_os_geom* g, const float* w, int32_t subset, float* out
     B.w = w; B.w_natural = 1; B.out = out;
     B.angles = subset == 0 ? ex->all_angles : ex->subset_lists + (size_t)(subset - 1) * g->max_sub_angles;
     B.n_al = subset == 0 ? g->d.n_angles : ex->subset_count[subset - 1];
+    if (g->d.dim == 2 && g->k.psf_kx > 0) {
+        // back-projection into scratch, then the (symmetric) PSF into out
+        hipStream_t s = (hipStream_t)stream;
+        float* tmp = nullptr;
+        if (hipMalloc(&tmp, sizeof(float) * (size_t)g->n_vox) != hipSuccess)
+            return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc failed");
+        B.out = tmp;
+        int rc = launch_bp(g, B, s);
+        if (!rc) rc = launch_blur(g, tmp, out, s);
+        if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = fail(PET_OS_ERR_DEVICE, "stream synchronize failed");
+        (void)hipFree(tmp);
+        return rc;
+    }
     return launch_bp(g, B, (hipStream_t)stream);
+}
+
+int pet_os_attenuation_factors(const pet_os_geom* g, const float* mu, float* att, pet_os_stream stream) {
+    if (!g || !mu || !att) return fail(PET_OS_ERR_INVALID_ARG, "NULL argument");
+    GeomExtra* ex = extra_of(g);
+    if (!ex) return fail(PET_OS_ERR_INVALID_ARG, "invalid geometry");
+    if (g->d.dim != 2) return fail(PET_OS_ERR_INVALID_ARG, "attenuation factors are 2D only");
+    hipStream_t s = (hipStream_t)stream;
+    // line integrals of mu through the sub-ray model, without PSF or attenuation
+    FPLaunch F{};
+    F.f = mu; F.out = att; F.mode = FP_PLAIN; F.raw = 1;
+    F.angles = ex->all_angles; F.n_al = g->d.n_angles;
+    int rc = launch_fp(g, F, s);
+    if (!rc) rc = launch_expneg(att, att, g->n_bins, s);
+    return rc;
 }
 
 int pet_os_objective(const pet_os_geom* g, const pet_os_params* p, const float* f, const float* y,
@@ -830,6 +966,11 @@ int pet_os_subset_gradient(const pet_os_geom* g, const pet_os_params* p, const f
     F.f = f; F.fz = w.fz; F.y = y; F.r = r; F.out = wsino; F.angles = angles; F.n_al = n_al;
     F.mode = FP_RATIO;
     F.seg = fp_seg_for(g, (long long)n_al * g->n_planes * g->d.n_radial, g->tuned_seg);
+    const bool psf = g->d.dim == 2 && g->k.psf_kx > 0;
+    if (psf && !rc) {
+        rc = launch_blur(g, f, w.fb, s);
+        F.f = w.fb;
+    }
     if (!rc) rc = launch_fp(g, F, s);
     BPLaunch B{};
     B.w = wsino; B.w_natural = 0; B.angles = angles; B.n_al = n_al;
@@ -840,7 +981,16 @@ int pet_os_subset_gradient(const pet_os_geom* g, const pet_os_params* p, const f
     B.part_f = w.red[RED_SUMF].part;
     B.n_part_f = sumf_grid(g);
     B.red_mu = w.red[RED_SUMMU];
-    if (!rc) rc = launch_bp(g, B, s);
+    if (psf) {
+        // B A_i^T w, then the penalty gradient per tile
+        BPLaunch P{};
+        P.w = wsino; P.w_natural = 0; P.angles = angles; P.n_al = n_al; P.out = w.G;
+        if (!rc) rc = launch_bp(g, P, s);
+        if (!rc) rc = launch_blur(g, w.G, w.fb, s);
+        if (!rc) rc = launch_upd2(g, B, w.fb, s);
+    } else if (!rc) {
+        rc = launch_bp(g, B, s);
+    }
     if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = fail(PET_OS_ERR_DEVICE, "stream synchronize failed");
     if (big) (void)hipFree(big);
     work_free(&w);

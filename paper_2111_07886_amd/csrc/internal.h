@@ -34,6 +34,8 @@ struct Reduction {
     int cap;
 };
 
+constexpr int PSF_KMAX = 16;   // largest PSF radius, in pixels, of the 2D blur
+
 enum RedSlot { RED_SUMF = 0, RED_SUMMU = 1, RED_FID = 2, RED_RDP = 3, RED_SUMY = 4, RED_SUMR = 5,
                RED_SUMS = 6, RED_COUNT = 7 };
 
@@ -53,6 +55,7 @@ struct pet_os_geom {
     int device;
     int tuned_seg = 0;                  // forward-projector segments per ray (0: heuristic)
     int tuned_bp_kind = -1;             // back-projector tile kind (-1: heuristic)
+    bool full_model = false;            // sub-rays, PSF or attenuation (2D; single-request paths only)
     std::vector<int> subset_angles(int subset) const;   // subset in 1..M, 0 = all
 };
 
@@ -66,6 +69,7 @@ struct Work {
     float* nu_frozen = nullptr;
     float* fz = nullptr;       // 3D: copy of the iterate with z fastest [(iy*nx+ix)*nz+iz]
     float* fsnap = nullptr;    // 2D: snapshot of the iterate entering the subiteration
+    float* fb = nullptr;       // 2D PSF: the blurred iterate, then the blurred back-projection
     double* red_block = nullptr;   // reductions' storage
     Reduction red[RED_COUNT];
     int* angle_list = nullptr;     // device copy of all subset angle lists [M][max_sub]
@@ -109,7 +113,9 @@ struct FPLaunch {
     int mode;
     Reduction red;           // FP_OBJECTIVE
     int seg = 0;             // threads per ray (0: tuned or heuristic)
+    int raw = 0;             // 1: no attenuation factors (line integrals of f itself)
     // 2D subiteration: pixel pass in the same launch (snapshot of f and mu)
+    const float* px_f = nullptr;   // iterate of the pixel pass when f is its PSF-blurred copy
     float* px_fsnap = nullptr;
     float* px_mu = nullptr;
     int px_want_mu = 0;
@@ -147,6 +153,12 @@ struct BPLaunch {
     const float* osem_sens = nullptr;  // 2D fused OSEM update: subset sensitivity of this subset
 };
 int launch_bp(const pet_os_geom* g, const BPLaunch& L, hipStream_t s);
+// 2D full model: out = B in (PSF), and the image-space part of a subiteration
+// (or of a gradient) after a blurred back-projection Gb = B A_i^T w
+int launch_blur(const pet_os_geom* g, const float* in, float* out, hipStream_t s);
+int launch_upd2(const pet_os_geom* g, const BPLaunch& L, const float* Gb, hipStream_t s);
+// y = exp(-x) elementwise (attenuation factors from line integrals of mu)
+int launch_expneg(const float* x, float* y, int64_t n, hipStream_t s);
 
 struct UpdLaunch {
     float* f;

@@ -40,12 +40,62 @@ struct FPArgs {
     int n_al;
     int mode;
     Reduction red;
+    const float* att;        // per-bin attenuation factors (natural), or null
 };
+
+// Sub-ray model (Sec. IV-A): the bin's projection as the mean over its
+// sub-rays, accumulated over major cells [s0, s1] of the ray.  Each pixel the
+// strip of sub-rays can cross gets the same weight the back-projector gives
+// it, so the two are an adjoint pair.
+__device__ __forceinline__ float fp_subray_acc(const GeoK& g, const FPArgs& A, const AngleK& AK, int b, int s0,
+                                               int s1) {
+    const int row_major = AK.row_major;
+    const int n_minor = row_major ? g.nx : g.ny;
+    const int sx = row_major ? 1 : g.nx;
+    const int sm = row_major ? g.nx : 1;
+    float acc = 0.0f;
+    if (AK.Q == 0.0) {
+        // axis-parallel: the sub-rays stay in a few minor cells, the same in
+        // every major cell
+        const double v = row_major ? g.vx : g.vy;
+        const double sb = bin_pos(g, b);
+        const int c_lo = max((int)floor((sb - g.sub_half + 0.5 * n_minor * v) / v) - 1, 0);
+        const int c_hi = min((int)floor((sb + g.sub_half + 0.5 * n_minor * v) / v) + 1, n_minor - 1);
+        for (int c = c_lo; c <= c_hi; ++c) {
+            const int cnt = subray_axis_count(g, b, c, n_minor, v);
+            if (cnt == 0) continue;
+            const float w = subray_axis_weight(g, AK, cnt);
+            float part = 0.0f;
+            for (int m = s0; m <= s1; ++m) {
+                if (A.mode == FP_COUNT) { part += 1.0f; continue; }
+                part = fmaf(w, A.f[(long long)m * sm + (long long)c * sx], part);
+            }
+            acc += part;
+        }
+        return acc;
+    }
+    const TxRay tx = tx_ray(g, AK, b);
+    const double hsg = fabs(AK.icv) * g.sub_half;     // strip half-width in minor cells
+    for (int m = s0; m <= s1; ++m) {
+        const double g0 = __fma_rn(tx.Q, (double)m, tx.P), g1 = g0 + tx.Q;
+        const int c0 = max((int)floor(fmin(g0, g1) - hsg) - 1, 0);
+        const int c1 = min((int)floor(fmax(g0, g1) + hsg) + 1, n_minor - 1);
+        for (int c = c0; c <= c1; ++c) {
+            const int ix = row_major ? c : m, iy = row_major ? m : c;
+            const float w = subray_weight(g, AK, pixel_ts(g, AK, ix, iy, b));
+            if (w > 0.0f) {
+                if (A.mode == FP_COUNT) { acc += 1.0f; continue; }
+                acc = fmaf(w, A.f[(long long)m * sm + (long long)c * sx], acc);
+            }
+        }
+    }
+    return acc;
+}
 
 // One ray per (thread-row of the block); SEG threads split its major cells.
 // With SEG > 1 the SEG threads of a ray are adjacent lanes of one wave and
 // their partial sums are added by a fixed shuffle tree.
-template <int DIM, int SEG>
+template <int DIM, int SEG, bool SUB = false>
 __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
     static_assert(DIM == 2, "the 3D forward projector is k_fp3");
     static_assert(SEG == 1 || (64 % SEG == 0), "segments of a ray stay in one wave");
@@ -71,7 +121,13 @@ __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
         int n_major = tx.row_major ? g.ny : g.nx;
         int n_minor = tx.row_major ? g.nx : g.ny;
         int m0, m1;
-        major_range(tx, n_major, n_minor, m0, m1);
+        if (SUB) {
+            // every major cell: the strip of sub-rays is wider than the line
+            m0 = 0;
+            m1 = n_major - 1;
+        } else {
+            major_range(tx, n_major, n_minor, m0, m1);
+        }
         int cnt = m1 - m0 + 1;
         int per = (cnt + SEG - 1) / SEG;
         int s0 = m0 + seg * per;
@@ -79,7 +135,8 @@ __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
         const int sx = tx.row_major ? 1 : g.nx;       // stride along the minor cell index
         const int sm = tx.row_major ? g.nx : 1;       // stride along the major index
         int qstep = (tx.Q > 0.0) ? 1 : -1;
-        for (int m = s0; m <= s1; ++m) {
+        if (SUB) acc = fp_subray_acc(g, A, AK, b, s0, s1);
+        else for (int m = s0; m <= s1; ++m) {
             double gm = __fma_rn(tx.Q, (double)m, tx.P);
             int c0 = (int)floor(gm);
             #pragma unroll
@@ -104,7 +161,15 @@ __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
     double term = 0.0;
     if (seg == 0 && valid) {
         long long nat = ((long long)plane * g.n_angles + a) * Nr + b;
-        if (A.mode == FP_RATIO) {
+        if (A.att != nullptr && A.mode != FP_COUNT && A.mode != FP_COMPACT) {
+            // attenuated model: q = att (P f); the back-projected weights carry att too
+            const float at = A.att[nat];
+            const float q = at * acc;
+            if (A.mode == FP_RATIO) A.out[ray] = at * (1.0f - A.y[nat] / (q + A.r[nat]));
+            else if (A.mode == FP_EM) A.out[ray] = at * (A.y[nat] / (q + A.r[nat]));
+            else if (A.mode == FP_PLAIN) A.out[nat] = q;
+            else term = (double)q - (double)A.y[nat] * log((double)q + (double)A.r[nat]);
+        } else if (A.mode == FP_RATIO) {
             float q = acc;
             A.out[ray] = 1.0f - A.y[nat] / (q + A.r[nat]);
         } else if (A.mode == FP_EM) {
@@ -121,9 +186,9 @@ __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
     if (A.mode == FP_OBJECTIVE) write_partial(term, A.red, s_red, vblock);
 }
 
-template <int DIM, int SEG>
+template <int DIM, int SEG, bool SUB>
 __global__ __launch_bounds__(NT) void k_fp(GeoK g, FPArgs A) {
-    fp_body<DIM, SEG>(g, A, blockIdx.x);
+    fp_body<DIM, SEG, SUB>(g, A, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ back projection
@@ -156,6 +221,7 @@ struct BPArgs {
     int n_part_mu;
     Reduction red_f;
     const float* osem_sens;  // OSEM (fused): f <- f * (A_i^T w) / s_i with w = y/(q+r)
+    const float* att;        // per-bin attenuation factors applied to natural-layout (or unit) w, or null
 };
 
 // nu of eq:nuki, S of eq:preconditioner, the relaxed step of Table I and P_t
@@ -173,6 +239,44 @@ __device__ __forceinline__ float sdp_update(float fj, float Gj, float pj, float 
     const float S = (fj < 0.5f * U) ? fj / pj : (U - fj) / pj;
     const float ft = fj - step * nu * S * Gj;
     return (ft <= 0.0f) ? t_clip : ((ft >= U) ? U - t_clip : ft);
+}
+
+// Image-space part of a 2D subiteration at pixel (ix, iy), from the halo
+// tile s_f of the snapshot (tile position lx, ly) and acc = the back-projected
+// weights at the pixel: grad R, G = acc + (beta/M) grad R and either mu
+// (Sec. III-B), the update of Table I, or the OSEM update.  Returns the
+// pixel's share of the tile's FP64 partial (new f, or mu).
+__device__ __forceinline__ double pixel_finish(const GeoK& g, const BPArgs& A, const float* s_f, int HX, int HY,
+                                               int lx, int ly, int ix, int iy, float acc, float meanf,
+                                               float meanmu) {
+    double part = 0.0;
+    float gradR, gmag;
+    stencil_at<2>(s_f, HX, HY, lx + 1, ly + 1, 0, ix, iy, 0, g, A.gamma_R, A.eps, gradR, gmag);
+    const long long j = (long long)iy * g.nx + ix;
+    const float Gj = fmaf(A.beta_over_M, gradR, acc);
+    if (A.fnew != nullptr && A.osem_sens != nullptr) {
+        // ordered-subsets EM (Hudson-Larkin): multiplicative update
+        const float fj = s_f[(ly + 1) * HX + lx + 1];
+        const float sj = A.osem_sens[j];
+        const float fn = (sj > 0.0f) ? fj * acc / sj : fj;
+        A.fnew[j] = fn;
+        part = (double)fn;
+    } else if (A.fnew != nullptr) {
+        const float fj = s_f[(ly + 1) * HX + lx + 1];
+        const bool need_mu = A.nu_mode == NU_COMPUTE || A.nu_mode == NU_COMPUTE_FREEZE;
+        const float fn = sdp_update(fj, Gj, A.pnorm[j], need_mu ? A.mu[j] : 1.0f, meanmu, A.nu_frozen, j,
+                                    A.nu_mode, A.step, A.nu1, A.nu2, A.U, A.t_clip);
+        A.fnew[j] = fn;
+        part = (double)fn;
+    } else {
+        A.out[j] = Gj;
+        if (A.want_mu) {
+            const float mu = fmaxf(0.01f, gmag / meanf);
+            A.mu[j] = mu;
+            part = (double)mu;
+        }
+    }
+    return part;
 }
 
 // Tile of the back-projector: X x Y pixels, AG threads per pixel (each takes
@@ -261,7 +365,8 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
                 if (col < s_nb[j]) {
                     const int al = c0 + j;
                     const int aidx = A.w_natural ? A.angles[al] : al;
-                    s_w[e] = A.w[(long long)aidx * A.w_sa + s_blo[j] + col];
+                    const long long idx = (long long)aidx * A.w_sa + s_blo[j] + col;
+                    s_w[e] = (A.att != nullptr) ? A.w[idx] * A.att[idx] : A.w[idx];
                 }
             }
             __syncthreads();
@@ -280,11 +385,36 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
                 const int aidx = A.w_natural ? a : al;
                 const int bst = s_blo[j], nbs = s_nb[j];
                 auto wval = [&](int b) -> float {
-                    if (A.w == nullptr) return 1.0f;
+                    if (A.w == nullptr) return (A.att != nullptr) ? A.att[(long long)a * Nr + b] : 1.0f;
                     const int bcol = b - bst;
-                    return (bcol >= 0 && bcol < nbs) ? s_w[j * nb_max + bcol] : A.w[(long long)aidx * A.w_sa + b];
+                    if (bcol >= 0 && bcol < nbs) return s_w[j * nb_max + bcol];
+                    const long long idx = (long long)aidx * A.w_sa + b;
+                    return (A.att != nullptr) ? A.w[idx] * A.att[idx] : A.w[idx];
                 };
-                if (AK.Q != 0.0) {
+                if (g.n_sub > 1) {
+                    // sub-ray model: the weights of the forward projector's fp_subray_acc
+                    if (AK.Q != 0.0) {
+                        const double uc = __fma_rn(xc, AK.c, yc * AK.s);
+                        const double reach = AK.e_out + g.sub_half;
+                        const int b0 = max((int)ceil((uc - reach) * inv_ds + g.h0), 0);
+                        const int b1 = min((int)floor((uc + reach) * inv_ds + g.h0), Nr - 1);
+                        for (int b = b0; b <= b1; ++b) {
+                            const float w = subray_weight(g, AK, pixel_ts(g, AK, ix, iy, b));
+                            if (w > 0.0f) acc = fmaf(w, wval(b), acc);
+                        }
+                    } else {
+                        const int mc = AK.row_major ? ix : iy;
+                        const int n = AK.row_major ? g.nx : g.ny;
+                        const double v = AK.row_major ? g.vx : g.vy;
+                        const double pc = ((double)mc - 0.5 * (double)(n - 1)) * v;
+                        const int b0 = max((int)floor((pc - 0.5 * v - g.sub_half) * inv_ds + g.h0) - 1, 0);
+                        const int b1 = min((int)ceil((pc + 0.5 * v + g.sub_half) * inv_ds + g.h0) + 1, Nr - 1);
+                        for (int b = b0; b <= b1; ++b) {
+                            const int cnt = subray_axis_count(g, b, mc, n, v);
+                            if (cnt > 0) acc = fmaf(subray_axis_weight(g, AK, cnt), wval(b), acc);
+                        }
+                    }
+                } else if (AK.Q != 0.0) {
                     const double uc = __fma_rn(xc, AK.c, yc * AK.s);
                     const int b0 = max((int)ceil((uc - AK.e_out) * inv_ds + g.h0), 0);
                     const int b1 = min((int)floor((uc + AK.e_out) * inv_ds + g.h0), Nr - 1);
@@ -326,39 +456,10 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
         return;
     }
 
-    // (4) fused image-space part: grad R, G = A_i^T w + (beta/M) grad R and
-    // either mu (Sec. III-B) or the update of the tile (the halo tile was
-    // loaded before the gather)
+    // (4) fused image-space part (the halo tile was loaded before the gather)
     __syncthreads();
     double part = 0.0;
-    if (inside && owner) {
-        float gradR, gmag;
-        stencil_at<2>(s_f, HX, HY, lx + 1, ly + 1, 0, ix, iy, 0, g, A.gamma_R, A.eps, gradR, gmag);
-        const long long j = (long long)iy * g.nx + ix;
-        const float Gj = fmaf(A.beta_over_M, gradR, acc);
-        if (A.fnew != nullptr && A.osem_sens != nullptr) {
-            // ordered-subsets EM (Hudson-Larkin): multiplicative update
-            const float fj = s_f[(ly + 1) * HX + lx + 1];
-            const float sj = A.osem_sens[j];
-            const float fn = (sj > 0.0f) ? fj * acc / sj : fj;
-            A.fnew[j] = fn;
-            part = (double)fn;
-        } else if (A.fnew != nullptr) {
-            const float fj = s_f[(ly + 1) * HX + lx + 1];
-            const bool need_mu = A.nu_mode == NU_COMPUTE || A.nu_mode == NU_COMPUTE_FREEZE;
-            const float fn = sdp_update(fj, Gj, A.pnorm[j], need_mu ? A.mu[j] : 1.0f, meanmu, A.nu_frozen, j,
-                                        A.nu_mode, A.step, A.nu1, A.nu2, A.U, A.t_clip);
-            A.fnew[j] = fn;
-            part = (double)fn;
-        } else {
-            A.out[j] = Gj;
-            if (A.want_mu) {
-                const float mu = fmaxf(0.01f, gmag / meanf);
-                A.mu[j] = mu;
-                part = (double)mu;
-            }
-        }
-    }
+    if (inside && owner) part = pixel_finish(g, A, s_f, HX, HY, lx, ly, ix, iy, acc, meanf, meanmu);
     if (A.fnew != nullptr) write_partial(part, A.red_f, s_red, vblock);
     else if (A.want_mu) write_partial(part, A.red_mu, s_red, vblock);
 }
@@ -381,6 +482,80 @@ __global__ __launch_bounds__(NT) void k_sum_tiles(GeoK g, const float* f, Reduct
 template <class T>
 __global__ __launch_bounds__(NT) void k_bp(GeoK g, BPArgs A) {
     bp_body<T>(g, A, blockIdx.x);
+}
+
+// ------------------------------------------------------------------ PSF (Sec. IV-A)
+
+constexpr int BLT = 16;         // output tile of the PSF blur
+
+// out = B in: the separable Gaussian PSF, zero outside the image (so that B
+// is symmetric).  One block per 16x16 output tile: the tile and its halo go
+// to LDS, the pass along x into LDS, then the pass along y; taps are added in
+// ascending order.
+__global__ __launch_bounds__(NT) void k_blur2(GeoK g, const float* __restrict__ in, float* __restrict__ out) {
+    __shared__ float s_in[(BLT + 2 * PSF_KMAX) * (BLT + 2 * PSF_KMAX)];
+    __shared__ float s_x[(BLT + 2 * PSF_KMAX) * BLT];
+    const int Kx = g.psf_kx, Ky = g.psf_ky;
+    const int W = BLT + 2 * Kx, H = BLT + 2 * Ky;
+    const int tiles_x = (g.nx + BLT - 1) / BLT;
+    const int tx0 = ((int)blockIdx.x % tiles_x) * BLT, ty0 = ((int)blockIdx.x / tiles_x) * BLT;
+    for (int e = threadIdx.x; e < W * H; e += NT) {
+        const int hx = e % W, hy = e / W;
+        const int x = tx0 - Kx + hx, y = ty0 - Ky + hy;
+        s_in[e] = (x >= 0 && x < g.nx && y >= 0 && y < g.ny) ? in[(long long)y * g.nx + x] : 0.0f;
+    }
+    __syncthreads();
+    const float* wx = g.psf;
+    const float* wy = g.psf + 2 * Kx + 1;
+    for (int e = threadIdx.x; e < BLT * H; e += NT) {
+        const int lx = e % BLT, hy = e / BLT;
+        float acc = 0.0f;
+        for (int k = 0; k <= 2 * Kx; ++k) acc = fmaf(wx[k], s_in[hy * W + lx + k], acc);
+        s_x[hy * BLT + lx] = acc;
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % BLT, ly = threadIdx.x / BLT;
+    const int x = tx0 + lx, y = ty0 + ly;
+    if (x < g.nx && y < g.ny) {
+        float acc = 0.0f;
+        for (int k = 0; k <= 2 * Ky; ++k) acc = fmaf(wy[k], s_x[(ly + k) * BLT + lx], acc);
+        out[(long long)y * g.nx + x] = acc;
+    }
+}
+
+// The image-space part of a 2D subiteration when the back-projection had to
+// be blurred first (PSF): Gb = B A_i^T w is given; the tiles, threads and
+// partials are those of the fused back-projector k_bp<T>.
+template <class T>
+__global__ __launch_bounds__(NT) void k_upd2(GeoK g, BPArgs A, const float* __restrict__ Gb) {
+    constexpr int NV = T::X * T::Y;
+    constexpr int HX = T::X + 2, HY = T::Y + 2;
+    __shared__ float s_f[HX * HY];
+    __shared__ double s_red[NT / 64];
+    const int vblock = blockIdx.x;
+    const int tiles_x = (g.nx + T::X - 1) / T::X;
+    const int tx0 = (vblock % tiles_x) * T::X;
+    const int ty0 = (vblock / tiles_x) * T::Y;
+    const int vox = threadIdx.x % NV, grp = threadIdx.x / NV;
+    const int lx = vox % T::X, ly = vox / T::X;
+    const int ix = tx0 + lx, iy = ty0 + ly;
+    const bool inside = ix < g.nx && iy < g.ny;
+    for (int e = threadIdx.x; e < HX * HY; e += NT) {
+        const int hx = e % HX, hy = e / HX;
+        const int gx = tx0 - 1 + hx, gy = ty0 - 1 + hy;
+        s_f[e] = (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny) ? A.f[(long long)gy * g.nx + gx] : 0.0f;
+    }
+    float meanf = 1.0f;
+    if (A.want_mu) meanf = (float)(sum_partials(A.part_f, A.n_part_f, s_red) / (double)g.nvox);
+    float meanmu = 1.0f;
+    if (A.fnew != nullptr && (A.nu_mode == NU_COMPUTE || A.nu_mode == NU_COMPUTE_FREEZE))
+        meanmu = (float)(sum_partials(A.part_mu, A.n_part_mu, s_red) / (double)g.nvox);
+    __syncthreads();
+    double part = 0.0;
+    if (inside && grp == 0)
+        part = pixel_finish(g, A, s_f, HX, HY, lx, ly, ix, iy, Gb[(long long)iy * g.nx + ix], meanf, meanmu);
+    if (A.fnew != nullptr) write_partial(part, A.red_f, s_red, vblock);
+    else if (A.want_mu) write_partial(part, A.red_mu, s_red, vblock);
 }
 
 // ------------------------------------------------------------------ update
@@ -449,9 +624,9 @@ __device__ void px_body(const GeoK& g, const PxArgs& P, long long pblock) {
 
 // First kernel of a 2D subiteration: blocks [0, n_fp) project the subset and
 // form the Poisson ratio, the rest run the pixel pass.
-template <int SEG>
+template <int SEG, bool SUB>
 __global__ __launch_bounds__(NT) void k_fp_px(GeoK g, FPArgs A, PxArgs P, int n_fp) {
-    if ((int)blockIdx.x < n_fp) fp_body<2, SEG>(g, A, blockIdx.x);
+    if ((int)blockIdx.x < n_fp) fp_body<2, SEG, SUB>(g, A, blockIdx.x);
     else px_body(g, P, (long long)blockIdx.x - n_fp);
 }
 
@@ -567,9 +742,26 @@ int launch_sum_f(const pet_os_geom* G, const float* f, float* fz, Reduction red,
     return PET_OS_OK;
 }
 
-template <int SEG>
+template <int SEG, bool SUB>
 static void fp_launch_t(const GeoK& k, const FPArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_fp<2, SEG>), dim3(grid), dim3(NT), 0, s, k, a);
+    hipLaunchKernelGGL((k_fp<2, SEG, SUB>), dim3(grid), dim3(NT), 0, s, k, a);
+}
+
+template <bool SUB>
+static void fp_launch_seg(int seg, const GeoK& k, const FPArgs& a, int grid, hipStream_t s) {
+    if (seg == 64) fp_launch_t<64, SUB>(k, a, grid, s);
+    else if (seg == 16) fp_launch_t<16, SUB>(k, a, grid, s);
+    else if (seg == 4) fp_launch_t<4, SUB>(k, a, grid, s);
+    else fp_launch_t<1, SUB>(k, a, grid, s);
+}
+
+template <bool SUB>
+static void fp_px_launch_seg(int seg, dim3 blocks, const GeoK& k, const FPArgs& a, const PxArgs& P, int grid,
+                             hipStream_t s) {
+    if (seg == 64) hipLaunchKernelGGL((k_fp_px<64, SUB>), blocks, dim3(NT), 0, s, k, a, P, grid);
+    else if (seg == 16) hipLaunchKernelGGL((k_fp_px<16, SUB>), blocks, dim3(NT), 0, s, k, a, P, grid);
+    else if (seg == 4) hipLaunchKernelGGL((k_fp_px<4, SUB>), blocks, dim3(NT), 0, s, k, a, P, grid);
+    else hipLaunchKernelGGL((k_fp_px<1, SUB>), blocks, dim3(NT), 0, s, k, a, P, grid);
 }
 
 int launch_fp(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
@@ -583,6 +775,8 @@ int launch_fp(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
     a.n_al = L.n_al;
     a.mode = L.mode;
     a.red = L.red;
+    a.att = L.raw ? nullptr : G->k.att;
+    const bool sub = G->k.n_sub > 1;
     long long nrays = (long long)L.n_al * G->n_planes * G->d.n_radial;
     if (nrays == 0) return PET_OS_OK;
     int seg = fp_seg_for(G, nrays, L.seg);
@@ -591,7 +785,7 @@ int launch_fp(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
     if (L.px_fsnap != nullptr) {
         // 2D subiteration: the pixel pass rides in the same launch
         PxArgs P;
-        P.f = L.f;
+        P.f = L.px_f != nullptr ? L.px_f : L.f;
         P.fsnap = L.px_fsnap;
         P.mu = L.px_mu;
         P.want_mu = L.px_want_mu;
@@ -601,17 +795,13 @@ int launch_fp(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
         const int npx = px_grid(G);
         if (P.want_mu && npx > P.red_mu.cap) return fail(PET_OS_ERR_DEVICE, "mu partials too small");
         const dim3 blocks(grid + npx);
-        if (seg == 64) hipLaunchKernelGGL((k_fp_px<64>), blocks, dim3(NT), 0, s, G->k, a, P, grid);
-        else if (seg == 16) hipLaunchKernelGGL((k_fp_px<16>), blocks, dim3(NT), 0, s, G->k, a, P, grid);
-        else if (seg == 4) hipLaunchKernelGGL((k_fp_px<4>), blocks, dim3(NT), 0, s, G->k, a, P, grid);
-        else hipLaunchKernelGGL((k_fp_px<1>), blocks, dim3(NT), 0, s, G->k, a, P, grid);
+        if (sub) fp_px_launch_seg<true>(seg, blocks, G->k, a, P, grid, s);
+        else fp_px_launch_seg<false>(seg, blocks, G->k, a, P, grid, s);
         PETOS_HIP(hipGetLastError());
         return PET_OS_OK;
     }
-    if (seg == 64) fp_launch_t<64>(G->k, a, grid, s);
-    else if (seg == 16) fp_launch_t<16>(G->k, a, grid, s);
-    else if (seg == 4) fp_launch_t<4>(G->k, a, grid, s);
-    else fp_launch_t<1>(G->k, a, grid, s);
+    if (sub) fp_launch_seg<true>(seg, G->k, a, grid, s);
+    else fp_launch_seg<false>(seg, G->k, a, grid, s);
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;
 }
@@ -634,9 +824,7 @@ void bp_stage_shape_kind(const pet_os_geom* G, int kind, int& nb_max, int& rows_
     lds = (size_t)chunk * nb_max * sizeof(float);
 }
 
-int launch_bp(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
-    if (G->d.dim == 3) return launch_bp3(G, L, s);
-    BPArgs a{};
+static void fill_bp_args(const pet_os_geom* G, const BPLaunch& L, BPArgs& a) {
     a.w = L.w;
     a.w_natural = L.w_natural;
     if (L.w_natural) {
@@ -671,6 +859,14 @@ int launch_bp(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
     a.n_part_mu = L.n_part_mu;
     a.red_f = L.red_f;
     a.osem_sens = L.osem_sens;
+    // compact subset weights already carry the attenuation (forward epilogue)
+    a.att = (L.w == nullptr || L.w_natural) ? G->k.att : nullptr;
+}
+
+int launch_bp(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
+    if (G->d.dim == 3) return launch_bp3(G, L, s);
+    BPArgs a{};
+    fill_bp_args(G, L, a);
     size_t lds;
     int rows_unused;
     const int kind = bp_kind_of(G);
@@ -683,6 +879,43 @@ int launch_bp(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
         hipLaunchKernelGGL((k_bp<Tile2L>), dim3(grid), dim3(NT), lds, s, G->k, a);
     else
         hipLaunchKernelGGL((k_bp<Tile2S>), dim3(grid), dim3(NT), lds, s, G->k, a);
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
+}
+
+int launch_blur(const pet_os_geom* G, const float* in, float* out, hipStream_t s) {
+    if (G->d.dim != 2 || G->k.psf_kx <= 0 || G->k.psf_ky <= 0) return fail(PET_OS_ERR_DEVICE, "no 2D PSF");
+    if (G->k.psf_kx > PSF_KMAX || G->k.psf_ky > PSF_KMAX) return fail(PET_OS_ERR_DEVICE, "PSF radius too large");
+    const int grid = ((G->d.nx + BLT - 1) / BLT) * ((G->d.ny + BLT - 1) / BLT);
+    hipLaunchKernelGGL(k_blur2, dim3(grid), dim3(NT), 0, s, G->k, in, out);
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
+}
+
+int launch_upd2(const pet_os_geom* G, const BPLaunch& L, const float* Gb, hipStream_t s) {
+    if (G->d.dim != 2) return fail(PET_OS_ERR_DEVICE, "2D only");
+    if (L.f == nullptr) return fail(PET_OS_ERR_DEVICE, "update without the snapshot");
+    BPArgs a{};
+    fill_bp_args(G, L, a);
+    const int grid = bp_grid(G);
+    if (L.want_mu && grid > L.red_mu.cap) return fail(PET_OS_ERR_DEVICE, "mu partials too small");
+    if (L.fnew != nullptr && grid > L.red_f.cap) return fail(PET_OS_ERR_DEVICE, "sum partials too small");
+    if (bp_kind_of(G) == 0)
+        hipLaunchKernelGGL((k_upd2<Tile2L>), dim3(grid), dim3(NT), 0, s, G->k, a, Gb);
+    else
+        hipLaunchKernelGGL((k_upd2<Tile2S>), dim3(grid), dim3(NT), 0, s, G->k, a, Gb);
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
+}
+
+__global__ __launch_bounds__(NT) void k_expneg(const float* __restrict__ x, float* __restrict__ y, long long n) {
+    const long long j = (long long)blockIdx.x * NT + threadIdx.x;
+    if (j < n) y[j] = expf(-x[j]);
+}
+
+int launch_expneg(const float* x, float* y, int64_t n, hipStream_t s) {
+    if (n <= 0) return PET_OS_OK;
+    hipLaunchKernelGGL(k_expneg, dim3(elem_grid(n)), dim3(NT), 0, s, x, y, (long long)n);
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;
 }

@@ -66,6 +66,16 @@ struct GeoK {
     const double* kappa;    // [n_radial][2D+1] 3D length per transaxial length
     const int* plane_base;  // [2D+1] first plane of ring difference d (index d + D)
     const double* inv_d;    // [2D+1] 1/d (0 for d = 0)
+    // full 2D system model of Sec. IV-A (defaults: one line per bin, no PSF,
+    // no attenuation)
+    int n_sub;              // parallel sub-rays per bin, spread evenly over ds
+    int psf_kx, psf_ky;     // PSF radius in pixels along x, y (0: no PSF)
+    float sub_h;            // ds / n_sub: spacing of the sub-rays
+    float sub_x0;           // offset of sub-ray 0 from the bin's line: sub_h/2 - ds/2
+    float inv_nsub;         // 1 / n_sub
+    double sub_half;        // largest |offset|: ds/2 - sub_h/2
+    const float* att;       // per-bin attenuation factors [n_bins] (natural), or null
+    const float* psf;       // PSF taps: [2 psf_kx + 1] along x, then [2 psf_ky + 1] along y
 };
 
 struct TxRay {
@@ -120,6 +130,48 @@ __device__ __forceinline__ void cell_interval(double g0, double Q, double invQ, 
     double t1 = ((double)cell + 1.0 - g0) * invQ;
     lo = fmax(0.0, fmin(t0, t1));
     hi = fmin(1.0, fmax(t0, t1));
+}
+
+// s_b - u_c for bin b and pixel (ix, iy): the bin's radial position minus
+// that of the pixel centre (2D, oblique angles)
+__device__ __forceinline__ double pixel_ts(const GeoK& g, const AngleK& A, int ix, int iy, int b) {
+    const double xc = ((double)ix - 0.5 * (double)(g.nx - 1)) * g.vx;
+    const double yc = ((double)iy - 0.5 * (double)(g.ny - 1)) * g.vy;
+    const double uc = __fma_rn(xc, A.c, yc * A.s);
+    return __fma_rn((double)b - g.h0, g.ds, -uc);
+}
+
+// Mean chord of the n_sub sub-rays of a bin through one pixel (oblique
+// angle).  Sub-ray k sits at offset sub_x0 + k sub_h from the bin's line; its
+// chord through the vx x vy pixel, as a function of the offset t of the line
+// from the pixel centre, is Lmax * clamp((e_out - |t|) / (e_out - e_in), 0, 1).
+__device__ __forceinline__ float subray_weight(const GeoK& g, const AngleK& A, double ts) {
+    const float t0 = (float)ts + g.sub_x0;
+    const float eo = (float)A.e_out, ide = (float)A.inv_de;
+    float acc = 0.0f;
+    for (int k = 0; k < g.n_sub; ++k) {
+        const float t = fmaf((float)k, g.sub_h, t0);
+        acc += fminf(1.0f, fmaxf(0.0f, (eo - fabsf(t)) * ide));
+    }
+    return (float)A.Lmax * acc * g.inv_nsub;
+}
+
+// Axis-parallel angle: the number of sub-rays of bin b whose line lies in
+// cell `cell` of the minor axis (n cells of size v; half-open cells, the
+// position in FP64 as for a single line off the grid)
+__device__ __forceinline__ int subray_axis_count(const GeoK& g, int b, int cell, int n, double v) {
+    const double sb = bin_pos(g, b);
+    int cnt = 0;
+    for (int k = 0; k < g.n_sub; ++k) {
+        const double off = (((double)k + 0.5) / (double)g.n_sub - 0.5) * g.ds;
+        const int c = (int)floor((sb + off + 0.5 * n * v) / v);
+        cnt += (c == cell) ? 1 : 0;
+    }
+    return cnt;
+}
+
+__device__ __forceinline__ float subray_axis_weight(const GeoK& g, const AngleK& A, int cnt) {
+    return (float)A.L * (float)cnt * g.inv_nsub;
 }
 
 // range of major cells [m0, m1] on which the minor coordinate can be inside

@@ -554,6 +554,8 @@ int pet_os_submit(pet_os_server* S, const pet_os_request* req, uint64_t* ticket)
     rc = validate_params(&req->params, nullptr);
     if (rc) return rc;
     if (req->params.mode == PET_OS_OSEM) return fail(PET_OS_ERR_INVALID_ARG, "OSEM runs on states only, not served");
+    if (d.n_subrays > 1 || d.psf_fwhm > 0.0)
+        return fail(PET_OS_ERR_INVALID_ARG, "sub-rays and the PSF run on states only, not served");
     if (!S->simulate && (!req->f || !req->y || !req->r)) return fail(PET_OS_ERR_INVALID_ARG, "NULL data pointer");
     if (req->n_iter < 1) return fail(PET_OS_ERR_INVALID_ARG, "n_iter must be >= 1");
     auto r = std::make_shared<Req>();
