@@ -29,6 +29,9 @@ WORKLOADS = {
           "20% background; step = 1 iteration (24 subiterations) + FP64 objective",
     "c1": "2D SDP-P2, 64x64 image (2 mm), 60 angles x 95 bins, 4 subsets, 1e5 counts, 10% background; "
           "step = 1 iteration (4 subiterations) + FP64 objective",
+    "c2full": "2D SDP-P2 with the full system model (32 sub-rays per bin, Gaussian PSF FWHM 6.59 mm, water "
+              "attenuation over the object's support), 256x256 image (1.171875 mm), 288 angles x 367 bins, "
+              "24 subsets, 5e6 counts, 20% background; step = 1 iteration (24 subiterations) + FP64 objective",
     "c3": "3D SDP-P2, 200x200x64 volume (1.5x1.5x3 mm), 224 angles x 281 bins x 1744 span-1 planes "
           "(64 rings, |d| <= 15), 28 subsets, 5e8 counts, 30% background; step = 1 iteration "
           "(28 subiterations) + FP64 objective",
@@ -39,6 +42,9 @@ KERNELS = {0: "k_fp (forward projection + Poisson ratio)",
 # 2D: two launches per subiteration (the update is fused into the back-projection)
 KERNELS_2D = {0: "k_fp_px (forward projection + Poisson ratio; snapshot of f and mu)",
               1: "k_bp (back-projection + RDP gradient + nu, S, relaxed step, P_t)"}
+# 2D with the PSF: the events bracket the blur launches with the projectors
+KERNELS_2D_PSF = {0: "k_blur2 + k_fp_px (PSF blur of f; sub-ray forward projection + ratio; snapshot, mu)",
+                  1: "k_bp + k_blur2 + k_upd2 (sub-ray back-projection; PSF blur; RDP gradient + update)"}
 
 
 def kernel_source_hash():
@@ -79,7 +85,7 @@ def traffic_from_pmc(fetch_csv, write_csv, dim):
     return {str(k): int(fetch[k] + write.get(k, 0.0)) for k in fetch}, {"fetch": sf, "write": sw}
 
 
-def algorithmic_bytes(kernel, nnz_sub, rays_sub, q, dim=3, osem=False):
+def algorithmic_bytes(kernel, nnz_sub, rays_sub, q, dim=3, osem=False, psf=False):
     """Bytes one launch must move (A is computed on the fly, never stored).
     3D: forward: 4 B image gather per nonzero + read y, r and write w per ray;
     back: 4 B w gather per nonzero + stage w once per ray + read f, write G,
@@ -89,6 +95,10 @@ def algorithmic_bytes(kernel, nnz_sub, rays_sub, q, dim=3, osem=False):
     8 nnz + 16 rays + 32 q per subiteration.  OSEM has no mu or p but reads
     the subset sensitivity: 2D forward + pixel pass 8 q, back + update 12 q;
     3D back 8 q (f, G), update 20 q (f, G, s_i in; f and its z copy out)."""
+    if psf and dim == 2 and not osem:
+        # + the blur of f (read f, write its blur) before the forward projector;
+        # the back-projection is written, blurred (read, write) and read again
+        return 4.0 * nnz_sub + (12.0 * rays_sub + 20.0 * q if kernel == 0 else 4.0 * rays_sub + 32.0 * q)
     if osem:
         if dim == 2:
             return 4.0 * nnz_sub + (12.0 * rays_sub + 8.0 * q if kernel == 0 else 4.0 * rays_sub + 12.0 * q)
@@ -114,7 +124,8 @@ def cpu_baseline_osem(w, budget_s=12.0):
     import oracle
     from oracle import osem as O
     oracle.build(force=False)
-    g = oracle.geom(w.desc)
+    att = getattr(w, "att", None)
+    g = oracle.geom(dict(w.desc, att=None if att is None else att.astype("float64")))
     M = w.desc["n_subsets"]
     sens = [O.subset_sensitivity(g, i) for i in range(1, M + 1)]
     f = w.f0
@@ -139,7 +150,8 @@ def cpu_baseline(w, p, budget_s=12.0):
     if p["mode"] == "OSEM":
         return cpu_baseline_osem(w, budget_s)
     oracle.build(force=False)
-    g = oracle.geom(w.desc)
+    att = getattr(w, "att", None)
+    g = oracle.geom(dict(w.desc, att=None if att is None else att.astype("float64")))
     rec = oracle.Recon(g, oracle.params(p), w.f0, w.y_f32, w.r_f32)
     M = w.desc["n_subsets"]
     n = 0
@@ -329,7 +341,13 @@ def bench_gradcons(args):
     torch.cuda.set_device(dev)
     y = torch.tensor(w.y, dtype=torch.float32, device=dev).contiguous()
     r = torch.tensor(w.r, dtype=torch.float32, device=dev).contiguous()
-    geom = pet.Geometry(w.desc)
+    w.att = None
+    if getattr(w, "mu", None) is not None:
+        # attenuation factors of the geometry's own rays through the mu map
+        g0 = pet.Geometry(w.desc)
+        w.att = g0.attenuation_factors(torch.tensor(w.mu, dtype=torch.float32, device=dev)).cpu().numpy()
+        g0.close()
+    geom = pet.Geometry(w.desc, att=w.att)
     M = w.desc["n_subsets"]
     steps = max(1, args.steps if not three else min(args.steps, 3))
     f = torch.tensor(w.f0, dtype=torch.float32, device=dev).contiguous()
@@ -376,7 +394,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "c4", "c5", "gradcons", "gradcons3"],
+    ap.add_argument("--workload", default="c2",
+                    choices=["c2", "c1", "c3", "c2full", "c4", "c5", "gradcons", "gradcons3"],
                     help="c2 (default, the benchmark line); c1 / c3 for additional measurements")
     ap.add_argument("--requests", type=int, default=400, help="c5: requests taken from the arrival trace")
     ap.add_argument("--mode", default=None, choices=["BSREM", "M1", "M2", "P1", "P2", "OSEM"],
@@ -419,7 +438,7 @@ def main():
     import paper_2111_07886_amd as pet
     from synth import configs
 
-    w, p, _ = {"c1": configs.c1, "c2": configs.c2, "c3": configs.c3}[args.workload]()
+    w, p, _ = {"c1": configs.c1, "c2": configs.c2, "c3": configs.c3, "c2full": configs.c2_full}[args.workload]()
     if args.mode == "OSEM":
         p = pet.osem_params(p["beta"], p["gamma_R"], p["eps"])
     elif args.mode:
@@ -461,7 +480,8 @@ def main():
     q = geom.n_voxels
     per_kernel = {}
     dim = w.desc["dim"]
-    names = KERNELS_2D if dim == 2 else KERNELS
+    psf = dim == 2 and w.desc.get("psf_fwhm", 0.0) > 0.0
+    names = (KERNELS_2D_PSF if psf else KERNELS_2D) if dim == 2 else KERNELS
     if not args.no_profile:
         for k in names:
             state.profile(k)
@@ -471,7 +491,7 @@ def main():
             if n:
                 per_kernel[k] = dict(avg_us=1e3 * ms / n, launches=n,
                                      bytes=algorithmic_bytes(k, nnz_sub, rays_sub, q, dim,
-                                                             osem=p["mode"] == "OSEM"))
+                                                             osem=p["mode"] == "OSEM", psf=psf))
     roofline = None
     if per_kernel:
         dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"])
@@ -487,7 +507,7 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                     "kernel": names[dom], "avg_launch_us": round(K["avg_us"], 3),
                     "algorithmic_bytes_per_launch": int(K["bytes"]),
-                    "per_kernel_us": {names[k].split()[0]: round(v["avg_us"], 3) for k, v in per_kernel.items()}}
+                    "per_kernel_us": {names[k].split(" (")[0]: round(v["avg_us"], 3) for k, v in per_kernel.items()}}
 
     del state
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, p)

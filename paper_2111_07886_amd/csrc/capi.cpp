@@ -142,7 +142,8 @@ static void build_angles(const pet_os_geom_desc* d, std::vector<AngleK>& out) {
         if (c != 0.0 && s != 0.0) {
             const double ex = 0.5 * d->vx * std::fabs(c), ey = 0.5 * d->vy * std::fabs(s);
             K.e_out = ex + ey;
-            K.inv_de = 1.0 / (K.e_out - std::fabs(ex - ey));
+            K.e_in = std::fabs(ex - ey);
+            K.inv_de = 1.0 / (K.e_out - K.e_in);
             K.Lmax = std::min(d->vx / std::fabs(s), d->vy / std::fabs(c));
         }
         out[a] = K;
@@ -357,6 +358,7 @@ static int create_geometry(const pet_os_geom_desc* desc, const float* att_host, 
     k.inv_d = (const double*)(blk + o_id);
     k.n_sub = std::max(1, d.n_subrays);
     k.sub_h = (float)(d.ds / k.n_sub);
+    k.inv_sub_h = (float)(k.n_sub / d.ds);
     k.sub_x0 = (float)(0.5 * d.ds / k.n_sub - 0.5 * d.ds);
     k.inv_nsub = (float)(1.0 / k.n_sub);
     k.sub_half = 0.5 * d.ds - 0.5 * d.ds / k.n_sub;
@@ -666,8 +668,7 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
             BPLaunch P{};
             P.w = st->w.w; P.w_natural = 0; P.angles = angles; P.n_al = n_al; P.out = st->w.G;
             rc = launch_bp(g, P, s);
-            if (!rc) rc = launch_blur(g, st->w.G, st->w.fb, s);
-            if (!rc) rc = launch_upd2(g, B, st->w.fb, s);
+            if (!rc) rc = launch_upd2(g, B, st->w.G, true, s);
         } else {
             rc = launch_bp(g, B, s);
         }
@@ -986,8 +987,7 @@ int pet_os_subset_gradient(const pet_os_geom* g, const pet_os_params* p, const f
         BPLaunch P{};
         P.w = wsino; P.w_natural = 0; P.angles = angles; P.n_al = n_al; P.out = w.G;
         if (!rc) rc = launch_bp(g, P, s);
-        if (!rc) rc = launch_blur(g, w.G, w.fb, s);
-        if (!rc) rc = launch_upd2(g, B, w.fb, s);
+        if (!rc) rc = launch_upd2(g, B, w.G, true, s);
     } else if (!rc) {
         rc = launch_bp(g, B, s);
     }

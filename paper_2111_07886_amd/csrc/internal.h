@@ -156,7 +156,7 @@ int launch_bp(const pet_os_geom* g, const BPLaunch& L, hipStream_t s);
 // 2D full model: out = B in (PSF), and the image-space part of a subiteration
 // (or of a gradient) after a blurred back-projection Gb = B A_i^T w
 int launch_blur(const pet_os_geom* g, const float* in, float* out, hipStream_t s);
-int launch_upd2(const pet_os_geom* g, const BPLaunch& L, const float* Gb, hipStream_t s);
+int launch_upd2(const pet_os_geom* g, const BPLaunch& L, const float* Gb, bool blur, hipStream_t s);
 // y = exp(-x) elementwise (attenuation factors from line integrals of mu)
 int launch_expneg(const float* x, float* y, int64_t n, hipStream_t s);
 

@@ -122,9 +122,24 @@ __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
         int n_minor = tx.row_major ? g.nx : g.ny;
         int m0, m1;
         if (SUB) {
-            // every major cell: the strip of sub-rays is wider than the line
-            m0 = 0;
-            m1 = n_major - 1;
+            // the major cells the strip of sub-rays can cross: the union of
+            // the ranges of its two edge lines
+            if (tx.Q == 0.0) {
+                m0 = 0;
+                m1 = n_major - 1;
+            } else {
+                const double hsg = fabs(AK.icv) * g.sub_half;
+                TxRay e = tx;
+                int a0, a1, c0, c1;
+                e.P = tx.P - hsg;
+                major_range(e, n_major, n_minor, a0, a1);
+                e.P = tx.P + hsg;
+                major_range(e, n_major, n_minor, c0, c1);
+                if (a1 < a0) { a0 = c0; a1 = c1; }
+                if (c1 < c0) { c0 = a0; c1 = a1; }
+                m0 = min(a0, c0);
+                m1 = max(a1, c1);
+            }
         } else {
             major_range(tx, n_major, n_minor, m0, m1);
         }
@@ -523,14 +538,18 @@ __global__ __launch_bounds__(NT) void k_blur2(GeoK g, const float* __restrict__ 
     }
 }
 
-// The image-space part of a 2D subiteration when the back-projection had to
-// be blurred first (PSF): Gb = B A_i^T w is given; the tiles, threads and
-// partials are those of the fused back-projector k_bp<T>.
-template <class T>
+// The image-space part of a 2D subiteration when the back-projection has to
+// be blurred (PSF): Gb = A_i^T w, blurred here over the tile's halo (BLUR) or
+// already blurred; the tiles, threads and partials are those of the fused
+// back-projector k_bp<T>.
+template <class T, bool BLUR>
 __global__ __launch_bounds__(NT) void k_upd2(GeoK g, BPArgs A, const float* __restrict__ Gb) {
     constexpr int NV = T::X * T::Y;
     constexpr int HX = T::X + 2, HY = T::Y + 2;
+    constexpr int BW = T::X + 2 * PSF_KMAX, BH = T::Y + 2 * PSF_KMAX;
     __shared__ float s_f[HX * HY];
+    __shared__ float s_b[BLUR ? BW * BH : 1];
+    __shared__ float s_bx[BLUR ? BH * T::X : 1];
     __shared__ double s_red[NT / 64];
     const int vblock = blockIdx.x;
     const int tiles_x = (g.nx + T::X - 1) / T::X;
@@ -545,6 +564,24 @@ __global__ __launch_bounds__(NT) void k_upd2(GeoK g, BPArgs A, const float* __re
         const int gx = tx0 - 1 + hx, gy = ty0 - 1 + hy;
         s_f[e] = (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny) ? A.f[(long long)gy * g.nx + gx] : 0.0f;
     }
+    const int Kx = g.psf_kx, Ky = g.psf_ky;
+    if (BLUR) {
+        // the tile of A_i^T w with a PSF-radius halo (zero outside the image),
+        // then the pass along x, as k_blur2 does
+        const int W = T::X + 2 * Kx, H = T::Y + 2 * Ky;
+        for (int e = threadIdx.x; e < W * H; e += NT) {
+            const int hx = e % W, hy = e / W;
+            const int x = tx0 - Kx + hx, y = ty0 - Ky + hy;
+            s_b[e] = (x >= 0 && x < g.nx && y >= 0 && y < g.ny) ? Gb[(long long)y * g.nx + x] : 0.0f;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < T::X * H; e += NT) {
+            const int bx = e % T::X, hy = e / T::X;
+            float acc = 0.0f;
+            for (int k = 0; k <= 2 * Kx; ++k) acc = fmaf(g.psf[k], s_b[hy * W + bx + k], acc);
+            s_bx[hy * T::X + bx] = acc;
+        }
+    }
     float meanf = 1.0f;
     if (A.want_mu) meanf = (float)(sum_partials(A.part_f, A.n_part_f, s_red) / (double)g.nvox);
     float meanmu = 1.0f;
@@ -552,8 +589,17 @@ __global__ __launch_bounds__(NT) void k_upd2(GeoK g, BPArgs A, const float* __re
         meanmu = (float)(sum_partials(A.part_mu, A.n_part_mu, s_red) / (double)g.nvox);
     __syncthreads();
     double part = 0.0;
-    if (inside && grp == 0)
-        part = pixel_finish(g, A, s_f, HX, HY, lx, ly, ix, iy, Gb[(long long)iy * g.nx + ix], meanf, meanmu);
+    if (inside && grp == 0) {
+        float b;
+        if (BLUR) {
+            const float* wy = g.psf + 2 * Kx + 1;
+            b = 0.0f;
+            for (int k = 0; k <= 2 * Ky; ++k) b = fmaf(wy[k], s_bx[(ly + k) * T::X + lx], b);
+        } else {
+            b = Gb[(long long)iy * g.nx + ix];
+        }
+        part = pixel_finish(g, A, s_f, HX, HY, lx, ly, ix, iy, b, meanf, meanmu);
+    }
     if (A.fnew != nullptr) write_partial(part, A.red_f, s_red, vblock);
     else if (A.want_mu) write_partial(part, A.red_mu, s_red, vblock);
 }
@@ -892,7 +938,7 @@ int launch_blur(const pet_os_geom* G, const float* in, float* out, hipStream_t s
     return PET_OS_OK;
 }
 
-int launch_upd2(const pet_os_geom* G, const BPLaunch& L, const float* Gb, hipStream_t s) {
+int launch_upd2(const pet_os_geom* G, const BPLaunch& L, const float* Gb, bool blur, hipStream_t s) {
     if (G->d.dim != 2) return fail(PET_OS_ERR_DEVICE, "2D only");
     if (L.f == nullptr) return fail(PET_OS_ERR_DEVICE, "update without the snapshot");
     BPArgs a{};
@@ -900,10 +946,13 @@ int launch_upd2(const pet_os_geom* G, const BPLaunch& L, const float* Gb, hipStr
     const int grid = bp_grid(G);
     if (L.want_mu && grid > L.red_mu.cap) return fail(PET_OS_ERR_DEVICE, "mu partials too small");
     if (L.fnew != nullptr && grid > L.red_f.cap) return fail(PET_OS_ERR_DEVICE, "sum partials too small");
-    if (bp_kind_of(G) == 0)
-        hipLaunchKernelGGL((k_upd2<Tile2L>), dim3(grid), dim3(NT), 0, s, G->k, a, Gb);
-    else
-        hipLaunchKernelGGL((k_upd2<Tile2S>), dim3(grid), dim3(NT), 0, s, G->k, a, Gb);
+    if (blur && (G->k.psf_kx <= 0 || G->k.psf_kx > PSF_KMAX || G->k.psf_ky > PSF_KMAX))
+        return fail(PET_OS_ERR_DEVICE, "no 2D PSF");
+    const bool large = bp_kind_of(G) == 0;
+    if (large && blur) hipLaunchKernelGGL((k_upd2<Tile2L, true>), dim3(grid), dim3(NT), 0, s, G->k, a, Gb);
+    else if (large) hipLaunchKernelGGL((k_upd2<Tile2L, false>), dim3(grid), dim3(NT), 0, s, G->k, a, Gb);
+    else if (blur) hipLaunchKernelGGL((k_upd2<Tile2S, true>), dim3(grid), dim3(NT), 0, s, G->k, a, Gb);
+    else hipLaunchKernelGGL((k_upd2<Tile2S, false>), dim3(grid), dim3(NT), 0, s, G->k, a, Gb);
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;
 }

@@ -38,6 +38,7 @@ struct AngleK {
     double e_out;       // (vx |c| + vy |s|) / 2
     double inv_de;      // 1 / (e_out - e_in), e_in = |vx |c| - vy |s|| / 2
     double Lmax;        // min(vx / |s|, vy / |c|)
+    double e_in;        // |vx |c| - vy |s|| / 2
     int row_major;      // 1: major axis = y (rows), minor = x
     int pad;
 };
@@ -71,6 +72,7 @@ struct GeoK {
     int n_sub;              // parallel sub-rays per bin, spread evenly over ds
     int psf_kx, psf_ky;     // PSF radius in pixels along x, y (0: no PSF)
     float sub_h;            // ds / n_sub: spacing of the sub-rays
+    float inv_sub_h;        // n_sub / ds
     float sub_x0;           // offset of sub-ray 0 from the bin's line: sub_h/2 - ds/2
     float inv_nsub;         // 1 / n_sub
     double sub_half;        // largest |offset|: ds/2 - sub_h/2
@@ -142,18 +144,43 @@ __device__ __forceinline__ double pixel_ts(const GeoK& g, const AngleK& A, int i
 }
 
 // Mean chord of the n_sub sub-rays of a bin through one pixel (oblique
-// angle).  Sub-ray k sits at offset sub_x0 + k sub_h from the bin's line; its
-// chord through the vx x vy pixel, as a function of the offset t of the line
-// from the pixel centre, is Lmax * clamp((e_out - |t|) / (e_out - e_in), 0, 1).
+// angle).  Sub-ray k sits at offset t_k = a + k h from the pixel centre
+// (a = ts + sub_x0, h = sub_h); its chord through the vx x vy pixel is
+// Lmax * T(t_k), T(t) = clamp((e_out - |t|) / (e_out - e_in), 0, 1), which is
+// linear on (-e_out, -e_in], 1 on (-e_in, e_in], linear on (e_in, e_out] and
+// 0 elsewhere.  The sum over k is taken piece by piece in closed form: the
+// samples in a piece (lo, hi] are k0..k1 with k0 = floor((lo - a)/h) + 1,
+// k1 = floor((hi - a)/h), and on a linear piece they add up to
+// n v0 +- h n (n - 1) / 2 (times the slope), v0 the value at sample k0.
+// Adjacent pieces share the boundary expression, so every sample is counted
+// once.
 __device__ __forceinline__ float subray_weight(const GeoK& g, const AngleK& A, double ts) {
-    const float t0 = (float)ts + g.sub_x0;
-    const float eo = (float)A.e_out, ide = (float)A.inv_de;
-    float acc = 0.0f;
-    for (int k = 0; k < g.n_sub; ++k) {
-        const float t = fmaf((float)k, g.sub_h, t0);
-        acc += fminf(1.0f, fmaxf(0.0f, (eo - fabsf(t)) * ide));
+    const float a = (float)ts + g.sub_x0;
+    const float h = g.sub_h, ih = g.inv_sub_h;
+    const int last = g.n_sub - 1;
+    const float eo = (float)A.e_out, ei = (float)A.e_in, ide = (float)A.inv_de;
+    const int b0 = (int)floorf((-eo - a) * ih);
+    const int b1 = (int)floorf((-ei - a) * ih);
+    const int b2 = (int)floorf((ei - a) * ih);
+    const int b3 = (int)floorf((eo - a) * ih);
+    float s = 0.0f;
+    int k0 = max(b0 + 1, 0), k1 = min(b1, last);
+    if (k1 >= k0) {                          // rising edge: (e_out + t) / de
+        const float n = (float)(k1 - k0 + 1);
+        const float c0 = eo + fmaf((float)k0, h, a);      // value at the first sample, times de
+        s += ide * (n * c0 + h * 0.5f * n * (n - 1.0f));
     }
-    return (float)A.Lmax * acc * g.inv_nsub;
+    k0 = max(b1 + 1, 0);
+    k1 = min(b2, last);
+    if (k1 >= k0) s += (float)(k1 - k0 + 1); // plateau
+    k0 = max(b2 + 1, 0);
+    k1 = min(b3, last);
+    if (k1 >= k0) {                          // falling edge: (e_out - t) / de
+        const float n = (float)(k1 - k0 + 1);
+        const float c0 = eo - fmaf((float)k0, h, a);
+        s += ide * (n * c0 - h * 0.5f * n * (n - 1.0f));
+    }
+    return (float)A.Lmax * s * g.inv_nsub;
 }
 
 // Axis-parallel angle: the number of sub-rays of bin b whose line lies in

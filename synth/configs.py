@@ -100,6 +100,21 @@ def c2():
     return w, params_2d(24, 5e6, U=w.U), 50
 
 
+# Sec. IV-A: 32 parallel sub-rays per detector pair, Gaussian PSF of FWHM
+# 6.59 mm, uniform water attenuation 0.096 / cm over the object's support
+N_SUBRAYS, PSF_FWHM_MM, MU_WATER_PER_MM = 32, 6.59, 0.0096
+
+
+def c2_full():
+    """C2 with the paper's full 2D system model: 32 sub-rays per bin, the PSF,
+    and attenuation by water over the phantom's support (the factors are
+    computed from ``mu`` by the geometry, pet_os_attenuation_factors)."""
+    w, p, n_iter = c2()
+    w.desc = dict(w.desc, n_subrays=N_SUBRAYS, psf_fwhm=PSF_FWHM_MM)
+    w.mu = np.where(w.f_true > 0, MU_WATER_PER_MM, 0.0)
+    return w, p, n_iter
+
+
 def c3(n=200, nz=64, n_angles=224, n_radial=281, max_rd=15, M=28, counts=5e8, seed=13):
     """Fully 3D: 200x200x64 (1.5 x 1.5 x 3 mm), 224 x 281, 64 rings, |d| <= 15, 28 subsets."""
     d = desc_3d(n, nz, n_angles, n_radial, 300.0 / n, 3.0, nz, max_rd, M)
