@@ -56,6 +56,21 @@ __device__ inline double sum_partials(const double* part, int n, double* sh) {
     return s_tot;
 }
 
+// sum_partials in two steps for n <= NT partials: the load, issued early so
+// that its latency overlaps other work, and the block sum of the loaded
+// values (the same order as sum_partials: thread t holds part[t]).
+__device__ __forceinline__ double partial_early(const double* part, int n) {
+    return ((int)threadIdx.x < n) ? part[threadIdx.x] : 0.0;
+}
+
+__device__ inline double partials_total(double v, double* sh) {
+    __shared__ double s_tot;
+    double t = block_sum(v, sh);
+    if (threadIdx.x == 0) s_tot = t;
+    __syncthreads();
+    return s_tot;
+}
+
 // RDP gradient (eqn:gradRD; in-image 8/26 neighbours, unit weights) and the
 // Matlab-style gradient magnitude of Sec. III-B at one voxel of the halo tile.
 template <int DIM>

@@ -110,12 +110,24 @@ __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
 
     float acc = 0.0f;
     int b = 0, plane = 0, al = 0, a = 0;
+    // the ray's y, r (and attenuation factor), loaded before the walk so that
+    // their latency overlaps it
+    const bool needs_data = A.mode == FP_RATIO || A.mode == FP_EM || A.mode == FP_OBJECTIVE;
+    float yv = 0.0f, rv = 0.0f, atv = 1.0f;
     if (valid) {
         b = (int)(ray % Nr);
         long long t = ray / Nr;
         plane = (int)(t % P);
         al = (int)(t / P);
         a = A.angles[al];
+        if (seg == 0) {
+            const long long nat = ((long long)plane * g.n_angles + a) * Nr + b;
+            if (needs_data) {
+                yv = A.y[nat];
+                rv = A.r[nat];
+            }
+            if (A.att != nullptr) atv = A.att[nat];
+        }
         const AngleK& AK = g.ang[a];
         TxRay tx = tx_ray(g, AK, b);
         int n_major = tx.row_major ? g.ny : g.nx;
@@ -178,24 +190,23 @@ __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
         long long nat = ((long long)plane * g.n_angles + a) * Nr + b;
         if (A.att != nullptr && A.mode != FP_COUNT && A.mode != FP_COMPACT) {
             // attenuated model: q = att (P f); the back-projected weights carry att too
-            const float at = A.att[nat];
-            const float q = at * acc;
-            if (A.mode == FP_RATIO) A.out[ray] = at * (1.0f - A.y[nat] / (q + A.r[nat]));
-            else if (A.mode == FP_EM) A.out[ray] = at * (A.y[nat] / (q + A.r[nat]));
+            const float q = atv * acc;
+            if (A.mode == FP_RATIO) A.out[ray] = atv * (1.0f - yv / (q + rv));
+            else if (A.mode == FP_EM) A.out[ray] = atv * (yv / (q + rv));
             else if (A.mode == FP_PLAIN) A.out[nat] = q;
-            else term = (double)q - (double)A.y[nat] * log((double)q + (double)A.r[nat]);
+            else term = (double)q - (double)yv * log((double)q + (double)rv);
         } else if (A.mode == FP_RATIO) {
             float q = acc;
-            A.out[ray] = 1.0f - A.y[nat] / (q + A.r[nat]);
+            A.out[ray] = 1.0f - yv / (q + rv);
         } else if (A.mode == FP_EM) {
-            A.out[ray] = A.y[nat] / (acc + A.r[nat]);
+            A.out[ray] = yv / (acc + rv);
         } else if (A.mode == FP_COUNT || A.mode == FP_COMPACT) {
             A.out[ray] = acc;
         } else if (A.mode == FP_PLAIN) {
             A.out[nat] = acc;
         } else {
             double q = (double)acc;
-            term = q - (double)A.y[nat] * log(q + (double)A.r[nat]);
+            term = q - (double)yv * log(q + (double)rv);
         }
     }
     if (A.mode == FP_OBJECTIVE) write_partial(term, A.red, s_red, vblock);
@@ -349,8 +360,12 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
     float meanf = 1.0f;
     if (A.f != nullptr && A.want_mu) meanf = (float)(sum_partials(A.part_f, A.n_part_f, s_red) / (double)g.nvox);
     float meanmu = 1.0f;
-    if (A.fnew != nullptr && (A.nu_mode == NU_COMPUTE || A.nu_mode == NU_COMPUTE_FREEZE))
-        meanmu = (float)(sum_partials(A.part_mu, A.n_part_mu, s_red) / (double)g.nvox);
+    const bool want_meanmu = A.fnew != nullptr && (A.nu_mode == NU_COMPUTE || A.nu_mode == NU_COMPUTE_FREEZE);
+    // the mu partials: with at most NT of them, loaded now and added after the
+    // gather, so that the load overlaps the staging
+    const bool mu_early = want_meanmu && A.n_part_mu <= NT;
+    const double mu_part = mu_early ? partial_early(A.part_mu, A.n_part_mu) : 0.0;
+    if (want_meanmu && !mu_early) meanmu = (float)(sum_partials(A.part_mu, A.n_part_mu, s_red) / (double)g.nvox);
 
     float acc = 0.0f;
     for (int c0 = 0; c0 < A.n_al; c0 += A.chunk) {
@@ -470,6 +485,8 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
         if (inside && owner) A.out[(long long)iy * g.nx + ix] = acc;
         return;
     }
+
+    if (mu_early) meanmu = (float)(partials_total(mu_part, s_red) / (double)g.nvox);
 
     // (4) fused image-space part (the halo tile was loaded before the gather)
     __syncthreads();
