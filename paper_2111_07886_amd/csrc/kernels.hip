@@ -317,7 +317,7 @@ using Tile2S = Tile<8, 8, 4>;     // small images: 4 angle groups
 
 constexpr int MAXCH = 16;    // angles per staging chunk
 
-template <class T>
+template <class T, bool SUB = false, bool ATT = false>
 __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
     constexpr int NV = T::X * T::Y;                 // pixels per tile
     constexpr int HX = T::X + 2, HY = T::Y + 2;
@@ -396,7 +396,7 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
                     const int al = c0 + j;
                     const int aidx = A.w_natural ? A.angles[al] : al;
                     const long long idx = (long long)aidx * A.w_sa + s_blo[j] + col;
-                    s_w[e] = (A.att != nullptr) ? A.w[idx] * A.att[idx] : A.w[idx];
+                    s_w[e] = ATT ? A.w[idx] * A.att[idx] : A.w[idx];
                 }
             }
             __syncthreads();
@@ -415,13 +415,13 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
                 const int aidx = A.w_natural ? a : al;
                 const int bst = s_blo[j], nbs = s_nb[j];
                 auto wval = [&](int b) -> float {
-                    if (A.w == nullptr) return (A.att != nullptr) ? A.att[(long long)a * Nr + b] : 1.0f;
+                    if (A.w == nullptr) return ATT ? A.att[(long long)a * Nr + b] : 1.0f;
                     const int bcol = b - bst;
                     if (bcol >= 0 && bcol < nbs) return s_w[j * nb_max + bcol];
                     const long long idx = (long long)aidx * A.w_sa + b;
-                    return (A.att != nullptr) ? A.w[idx] * A.att[idx] : A.w[idx];
+                    return ATT ? A.w[idx] * A.att[idx] : A.w[idx];
                 };
-                if (g.n_sub > 1) {
+                if (SUB) {
                     // sub-ray model: the weights of the forward projector's fp_subray_acc
                     if (AK.Q != 0.0) {
                         const double uc = __fma_rn(xc, AK.c, yc * AK.s);
@@ -511,9 +511,9 @@ __global__ __launch_bounds__(NT) void k_sum_tiles(GeoK g, const float* f, Reduct
     write_partial(v, R, s_red, blockIdx.x);
 }
 
-template <class T>
+template <class T, bool SUB, bool ATT>
 __global__ __launch_bounds__(NT) void k_bp(GeoK g, BPArgs A) {
-    bp_body<T>(g, A, blockIdx.x);
+    bp_body<T, SUB, ATT>(g, A, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ PSF (Sec. IV-A)
@@ -938,10 +938,21 @@ int launch_bp(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
     int grid = bp_grid(G);
     if (L.want_mu && grid > L.red_mu.cap) return fail(PET_OS_ERR_DEVICE, "mu partials too small");
     if (L.fnew != nullptr && grid > L.red_f.cap) return fail(PET_OS_ERR_DEVICE, "sum partials too small");
-    if (kind == 0)
-        hipLaunchKernelGGL((k_bp<Tile2L>), dim3(grid), dim3(NT), lds, s, G->k, a);
-    else
-        hipLaunchKernelGGL((k_bp<Tile2S>), dim3(grid), dim3(NT), lds, s, G->k, a);
+    // the sub-ray gather and the attenuation of user or unit weights are
+    // compiled only into the kernels that need them
+    const bool sub = G->k.n_sub > 1, att = a.att != nullptr;
+    const dim3 gr(grid), bl(NT);
+    if (kind == 0) {
+        if (sub && att) hipLaunchKernelGGL((k_bp<Tile2L, true, true>), gr, bl, lds, s, G->k, a);
+        else if (sub) hipLaunchKernelGGL((k_bp<Tile2L, true, false>), gr, bl, lds, s, G->k, a);
+        else if (att) hipLaunchKernelGGL((k_bp<Tile2L, false, true>), gr, bl, lds, s, G->k, a);
+        else hipLaunchKernelGGL((k_bp<Tile2L, false, false>), gr, bl, lds, s, G->k, a);
+    } else {
+        if (sub && att) hipLaunchKernelGGL((k_bp<Tile2S, true, true>), gr, bl, lds, s, G->k, a);
+        else if (sub) hipLaunchKernelGGL((k_bp<Tile2S, true, false>), gr, bl, lds, s, G->k, a);
+        else if (att) hipLaunchKernelGGL((k_bp<Tile2S, false, true>), gr, bl, lds, s, G->k, a);
+        else hipLaunchKernelGGL((k_bp<Tile2S, false, false>), gr, bl, lds, s, G->k, a);
+    }
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;
 }
