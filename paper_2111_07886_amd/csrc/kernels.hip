@@ -1054,7 +1054,7 @@ __device__ void fp_dispatch(const GeoK& g, const FPArgs& A, int seg, long long v
     }
 }
 
-__global__ __launch_bounds__(NT) void k_fp_batch(const SlotDev* S, const Item* items, const int* count) {
+__global__ __launch_bounds__(NT) void k_fp_batch(const SlotDev* __restrict__ S, const Item* __restrict__ items, const int* __restrict__ count) {
     const int n = *count;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const Item I = items[it];
@@ -1095,7 +1095,7 @@ __global__ __launch_bounds__(NT) void k_fp_batch(const SlotDev* S, const Item* i
 }
 
 template <class T>
-__global__ __launch_bounds__(NT) void k_bp_batch(const SlotDev* S, const Item* items, const int* count) {
+__global__ __launch_bounds__(NT) void k_bp_batch(const SlotDev* __restrict__ S, const Item* __restrict__ items, const int* __restrict__ count) {
     const int n = *count;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const Item I = items[it];

@@ -843,7 +843,7 @@ __device__ __forceinline__ bool slot_live3(const SlotDev& d) { return d.active &
 // is a multiple of 8.
 __device__ __forceinline__ int xcd_item(int block, int grid) { return (block % 8) * (grid / 8) + block / 8; }
 
-__global__ __launch_bounds__(NT) void k_fp3_batch(const SlotDev* S, const Item* items, const int* count) {
+__global__ __launch_bounds__(NT) void k_fp3_batch(const SlotDev* __restrict__ S, const Item* __restrict__ items, const int* __restrict__ count) {
     const int n = *count;
     for (int it = xcd_item(blockIdx.x, gridDim.x); it < n; it += gridDim.x) {
         const Item I = items[it];
@@ -864,7 +864,7 @@ __global__ __launch_bounds__(NT) void k_fp3_batch(const SlotDev* S, const Item* 
 }
 
 template <int ZB, int NBS>
-__global__ __launch_bounds__(NT) void k_bp3_batch(const SlotDev* S, const Item* items, const int* count) {
+__global__ __launch_bounds__(NT) void k_bp3_batch(const SlotDev* __restrict__ S, const Item* __restrict__ items, const int* __restrict__ count) {
     __shared__ BP3Shared sh;
     const int n = *count;
     for (int it = xcd_item(blockIdx.x, gridDim.x); it < n; it += gridDim.x) {
@@ -901,7 +901,7 @@ __global__ __launch_bounds__(NT) void k_bp3_batch(const SlotDev* S, const Item* 
     }
 }
 
-__global__ __launch_bounds__(NT) void k_upd3_batch(const SlotDev* S, const Item* items, const int* count) {
+__global__ __launch_bounds__(NT) void k_upd3_batch(const SlotDev* __restrict__ S, const Item* __restrict__ items, const int* __restrict__ count) {
     const int n = *count;
     for (int it = xcd_item(blockIdx.x, gridDim.x); it < n; it += gridDim.x) {
         const Item I = items[it];
