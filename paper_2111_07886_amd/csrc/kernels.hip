@@ -1094,8 +1094,10 @@ __global__ __launch_bounds__(NT) void k_fp_batch(const SlotDev* __restrict__ S, 
     }
 }
 
+// at most 72 VGPRs (7 waves per SIMD): measured 2 % faster than the
+// unbounded 77, and 6 % faster than 64 with its spills
 template <class T>
-__global__ __launch_bounds__(NT) void k_bp_batch(const SlotDev* __restrict__ S, const Item* __restrict__ items, const int* __restrict__ count) {
+__global__ __launch_bounds__(NT, 7) void k_bp_batch(const SlotDev* __restrict__ S, const Item* __restrict__ items, const int* __restrict__ count) {
     const int n = *count;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const Item I = items[it];
