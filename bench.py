@@ -349,6 +349,9 @@ def bench_gradcons(args):
         w.att = g0.attenuation_factors(torch.tensor(w.mu, dtype=torch.float32, device=dev)).cpu().numpy()
         g0.close()
     geom = pet.Geometry(w.desc, att=w.att)
+    if w.desc["dim"] == 2 and not args.no_autotune:
+        # the library's own tuner: projector shapes timed on the first subset
+        pet.autotune(geom)
     M = w.desc["n_subsets"]
     steps = max(1, args.steps if not three else min(args.steps, 3))
     f = torch.tensor(w.f0, dtype=torch.float32, device=dev).contiguous()
@@ -395,6 +398,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="2D: keep the heuristic projector shapes")
     ap.add_argument("--workload", default="c2",
                     choices=["c2", "c1", "c3", "c2full", "c4", "c5", "gradcons", "gradcons3"],
                     help="c2 (default, the benchmark line); c1 / c3 for additional measurements")
@@ -542,7 +546,8 @@ def main():
         "config": {"workload": WORKLOADS[args.workload] if not args.mode else
                    WORKLOADS[args.workload].replace("SDP-P2", "OSEM" if args.mode == "OSEM" else "SDP-" + args.mode),
                    "subsets": M, "nnz_per_subset": int(nnz_sub), "rays_per_subset": int(rays_sub),
-                   "voxels": q, "objective_last": obj[-1] if obj else None,
+                   "voxels": q, "autotuned": w.desc["dim"] == 2 and not args.no_autotune,
+                   "objective_last": obj[-1] if obj else None,
                    "objective_ms": None if obj_ms is None else round(obj_ms, 4)},
         "roofline": roofline,
         "cpu_baseline": cpu,
