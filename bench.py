@@ -149,7 +149,7 @@ def cpu_baseline(w, p, budget_s=12.0):
     work is done."""
     import oracle
     if p["mode"] == "OSEM":
-        return cpu_baseline_osem(w, budget_s)
+        return cpu_baseline_osem(w, budget_s), None
     oracle.build(force=False)
     att = getattr(w, "att", None)
     g = oracle.geom(dict(w.desc, att=None if att is None else att.astype("float64")))
@@ -163,10 +163,38 @@ def cpu_baseline(w, p, budget_s=12.0):
         if n % M == 0:
             rec.objective()
     dt = time.perf_counter() - t0
-    return {"value": round(n / dt, 3), "unit": "subiterations/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"first {n} subiterations (objective after each of the {n // M} full iterations) "
-                      f"of the same workload from f0, FP64 C oracle, {dt:.1f} s wall"}
+    out = {"value": round(n / dt, 3), "unit": "subiterations/s", "cores": oracle.num_threads(),
+           "kind": "oracle",
+           "sample": f"first {n} subiterations (objective after each of the {n // M} full iterations) "
+                     f"of the same workload from f0, FP64 C oracle, {dt:.1f} s wall"}
+    return out, rec
+
+
+def one_step_error(rec, geom, p, w):
+    """Error of the GPU path against the oracle where the baseline stopped:
+    one GPU subiteration and one oracle subiteration from the oracle's own
+    state (iterate cast to FP32, position, Nesterov t, frozen nu); rel-L2."""
+    import numpy as np
+    import torch
+
+    import paper_2111_07886_amd as pet
+    fin = np.asarray(rec.f, dtype=np.float32).astype(np.float64)
+    ref = rec.clone_with(fin)
+    ref.frozen = np.asarray(rec.frozen, dtype=np.float32).astype(np.float64)
+    ref.subiteration()
+    st = pet.State(geom, p)
+    nu = None
+    if rec.st.have_frozen:
+        nu = torch.tensor(ref.frozen.reshape(geom.img_shape), dtype=torch.float32, device="cuda")
+    st.seek(rec.st.k, rec.st.i, rec.st.t_nest, nu)
+    fg = torch.tensor(fin.reshape(geom.img_shape), dtype=torch.float32, device="cuda")
+    st.subiteration(fg, torch.tensor(w.y_f32, dtype=torch.float32, device="cuda").reshape(geom.sino_shape),
+                    torch.tensor(w.r_f32, dtype=torch.float32, device="cuda").reshape(geom.sino_shape))
+    torch.cuda.synchronize()
+    st.close()
+    g = fg.cpu().double().numpy().reshape(-1)
+    o = ref.image().reshape(-1)
+    return float(np.linalg.norm(g - o) / np.linalg.norm(o)), int(rec.st.k), int(rec.st.i)
 
 
 def bench_batched(args):
@@ -528,7 +556,14 @@ def main():
                     "per_kernel_us": {names[k].split(" (")[0]: round(v["avg_us"], 3) for k, v in per_kernel.items()}}
 
     del state
-    cpu = None if args.no_cpu_baseline else cpu_baseline(w, p)
+    cpu, parity = None, None
+    if not args.no_cpu_baseline:
+        cpu, rec = cpu_baseline(w, p)
+        if rec is not None:
+            e, k_at, i_at = one_step_error(rec, geom, p, w)
+            parity = {"one_subiteration_rel_l2": e, "at_k": k_at, "at_i": i_at,
+                      "what": "one GPU subiteration vs one FP64 oracle subiteration from the oracle's state "
+                              "where the CPU baseline stopped (FP32-cast iterate)"}
 
     out = {
         "metric": "subiterations/s",
@@ -551,6 +586,7 @@ def main():
                    "objective_ms": None if obj_ms is None else round(obj_ms, 4)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "parity": parity,
     }
     print(json.dumps(out), flush=True)
 
