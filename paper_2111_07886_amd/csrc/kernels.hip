@@ -251,20 +251,41 @@ struct BPArgs {
 };
 
 // nu of eq:nuki, S of eq:preconditioner, the relaxed step of Table I and P_t
-// of eq:OperatorPt at one voxel; meanmu is mean(mu) when nu is recomputed
-__device__ __forceinline__ float sdp_update(float fj, float Gj, float pj, float muj, float meanmu, float* nu_frozen,
-                                            long long j, int nu_mode, float step, float nu1, float nu2, float U,
-                                            float t_clip) {
+// of eq:OperatorPt at one voxel; meanmu is mean(mu) when nu is recomputed,
+// nu_in the frozen nu of the voxel when it is reused
+__device__ __forceinline__ float sdp_update(float fj, float Gj, float pj, float muj, float meanmu, float nu_in,
+                                            float* nu_frozen, long long j, int nu_mode, float step, float nu1,
+                                            float nu2, float U, float t_clip) {
     float nu = 1.0f;
     if (nu_mode == NU_COMPUTE || nu_mode == NU_COMPUTE_FREEZE) {
         nu = fminf(nu2, fmaxf(nu1, meanmu / muj));
         if (nu_mode == NU_COMPUTE_FREEZE) nu_frozen[j] = nu;
     } else if (nu_mode == NU_FROZEN) {
-        nu = nu_frozen[j];
+        nu = nu_in;
     }
     const float S = (fj < 0.5f * U) ? fj / pj : (U - fj) / pj;
     const float ft = fj - step * nu * S * Gj;
     return (ft <= 0.0f) ? t_clip : ((ft >= U) ? U - t_clip : ft);
+}
+
+// Per-pixel inputs of the update (p, mu, frozen nu, OSEM sensitivity), read
+// by the owner thread of an inside pixel before the gather so that their
+// latency overlaps it.
+struct PixPre {
+    float p, mu, nu, sens;
+};
+
+__device__ __forceinline__ PixPre pixel_prefetch(const BPArgs& A, bool active, long long j) {
+    PixPre r{1.0f, 1.0f, 1.0f, 0.0f};
+    if (!active || A.fnew == nullptr) return r;
+    if (A.osem_sens != nullptr) {
+        r.sens = A.osem_sens[j];
+        return r;
+    }
+    r.p = A.pnorm[j];
+    if (A.nu_mode == NU_COMPUTE || A.nu_mode == NU_COMPUTE_FREEZE) r.mu = A.mu[j];
+    else if (A.nu_mode == NU_FROZEN) r.nu = A.nu_frozen[j];
+    return r;
 }
 
 // Image-space part of a 2D subiteration at pixel (ix, iy), from the halo
@@ -274,7 +295,7 @@ __device__ __forceinline__ float sdp_update(float fj, float Gj, float pj, float 
 // pixel's share of the tile's FP64 partial (new f, or mu).
 __device__ __forceinline__ double pixel_finish(const GeoK& g, const BPArgs& A, const float* s_f, int HX, int HY,
                                                int lx, int ly, int ix, int iy, float acc, float meanf,
-                                               float meanmu) {
+                                               float meanmu, const PixPre& pre) {
     double part = 0.0;
     float gradR, gmag;
     stencil_at<2>(s_f, HX, HY, lx + 1, ly + 1, 0, ix, iy, 0, g, A.gamma_R, A.eps, gradR, gmag);
@@ -283,15 +304,14 @@ __device__ __forceinline__ double pixel_finish(const GeoK& g, const BPArgs& A, c
     if (A.fnew != nullptr && A.osem_sens != nullptr) {
         // ordered-subsets EM (Hudson-Larkin): multiplicative update
         const float fj = s_f[(ly + 1) * HX + lx + 1];
-        const float sj = A.osem_sens[j];
+        const float sj = pre.sens;
         const float fn = (sj > 0.0f) ? fj * acc / sj : fj;
         A.fnew[j] = fn;
         part = (double)fn;
     } else if (A.fnew != nullptr) {
         const float fj = s_f[(ly + 1) * HX + lx + 1];
-        const bool need_mu = A.nu_mode == NU_COMPUTE || A.nu_mode == NU_COMPUTE_FREEZE;
-        const float fn = sdp_update(fj, Gj, A.pnorm[j], need_mu ? A.mu[j] : 1.0f, meanmu, A.nu_frozen, j,
-                                    A.nu_mode, A.step, A.nu1, A.nu2, A.U, A.t_clip);
+        const float fn = sdp_update(fj, Gj, pre.p, pre.mu, meanmu, pre.nu, A.nu_frozen, j, A.nu_mode, A.step,
+                                    A.nu1, A.nu2, A.U, A.t_clip);
         A.fnew[j] = fn;
         part = (double)fn;
     } else {
@@ -316,14 +336,20 @@ using Tile2L = Tile<16, 16, 1>;   // large images
 using Tile2S = Tile<8, 8, 4>;     // small images: 4 angle groups
 
 constexpr int MAXCH = 16;    // angles per staging chunk
+constexpr int ANG_W = (int)(sizeof(AngleK) / sizeof(double));   // 8-byte words of an angle record
+static_assert(sizeof(AngleK) % sizeof(double) == 0, "angle records are copied in 8-byte words");
 
-template <class T, bool SUB = false, bool ATT = false>
+// LEAN (the batched kernel, whose occupancy is register-bound) reads the
+// angle records from the geometry table in the gather and the pixel's update
+// inputs after it; otherwise both are fetched before the gather.
+template <class T, bool SUB = false, bool ATT = false, bool LEAN = false>
 __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
     constexpr int NV = T::X * T::Y;                 // pixels per tile
     constexpr int HX = T::X + 2, HY = T::Y + 2;
     extern __shared__ float s_w[];
     __shared__ float s_f[HX * HY];
-    __shared__ int s_blo[MAXCH], s_nb[MAXCH];
+    __shared__ int s_blo[MAXCH], s_nb[MAXCH], s_a[MAXCH];
+    __shared__ AngleK s_ang[MAXCH];
     __shared__ double s_red[NT / 64];
     __shared__ float s_acc[T::AG > 1 ? T::AG * NV : 1];
 
@@ -346,17 +372,24 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
     const double X0 = ((double)tx0 - 0.5 * g.nx) * g.vx, X1 = X0 + T::X * g.vx;
     const double Y0 = ((double)ty0 - 0.5 * g.ny) * g.vy, Y1 = Y0 + T::Y * g.vy;
 
-    // halo tile of f (fused stencil) and mean f: independent of the gather,
-    // so issued first
+    // halo tile of f (fused stencil), the pixel's update inputs and mean f:
+    // independent of the gather, so issued first; the halo goes to LDS once
+    // the first chunk's angle records are on their way
+    constexpr int HALO_PT = (HX * HY + NT - 1) / NT;
+    float hv[HALO_PT];
     if (A.f != nullptr) {
-        for (int e = threadIdx.x; e < HX * HY; e += NT) {
+#pragma unroll
+        for (int k = 0; k < HALO_PT; ++k) {
+            const int e = threadIdx.x + k * NT;
             const int hx = e % HX, hy = e / HX;
             const int gx = tx0 - 1 + hx, gy = ty0 - 1 + hy;
             float v = 0.0f;
-            if (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny) v = A.f[(long long)gy * g.nx + gx];
-            s_f[e] = v;
+            if (e < HX * HY && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny) v = A.f[(long long)gy * g.nx + gx];
+            hv[k] = v;
+            if (LEAN && e < HX * HY) s_f[e] = v;
         }
     }
+    const PixPre pre_early = LEAN ? PixPre{} : pixel_prefetch(A, inside && grp == 0, (long long)iy * g.nx + ix);
     float meanf = 1.0f;
     if (A.f != nullptr && A.want_mu) meanf = (float)(sum_partials(A.part_f, A.n_part_f, s_red) / (double)g.nvox);
     float meanmu = 1.0f;
@@ -370,11 +403,19 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
     float acc = 0.0f;
     for (int c0 = 0; c0 < A.n_al; c0 += A.chunk) {
         const int nch = min(A.chunk, A.n_al - c0);
-        if (A.w != nullptr) {
-            // (1) per-angle bin footprint of the tile (+1 bin margin)
-            if (threadIdx.x < nch) {
-                const int j = threadIdx.x;
-                const AngleK& AK = g.ang[A.angles[c0 + j]];
+        // (1) the chunk's angle records into LDS and, with a sinogram, the
+        // per-angle bin footprint of the tile (+1 bin margin)
+        if (!LEAN) for (int e = threadIdx.x; e < nch * ANG_W; e += NT) {
+            const int j = e / ANG_W, q = e - j * ANG_W;
+            const unsigned long long* src = reinterpret_cast<const unsigned long long*>(&g.ang[A.angles[c0 + j]]);
+            reinterpret_cast<unsigned long long*>(&s_ang[j])[q] = src[q];
+        }
+        if (threadIdx.x < nch) {
+            const int j = threadIdx.x;
+            const int a = A.angles[c0 + j];
+            const AngleK& AK = g.ang[a];
+            if (!LEAN) s_a[j] = a;
+            if (A.w != nullptr) {
                 double umin = 1e300, umax = -1e300;
                 for (int k = 0; k < 4; ++k) {
                     const double x = (k & 1) ? X1 : X0, y = (k & 2) ? Y1 : Y0;
@@ -387,14 +428,23 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
                 s_blo[j] = blo;
                 s_nb[j] = max(0, min(bhi - blo + 1, nb_max));
             }
-            __syncthreads();
+        }
+        if (!LEAN && c0 == 0 && A.f != nullptr) {
+#pragma unroll
+            for (int k = 0; k < HALO_PT; ++k) {
+                const int e = threadIdx.x + k * NT;
+                if (e < HX * HY) s_f[e] = hv[k];
+            }
+        }
+        __syncthreads();
+        if (A.w != nullptr) {
             // (2) stage the footprint rows into LDS
             const int nel = nch * nb_max;
             for (int e = threadIdx.x; e < nel; e += NT) {
                 const int j = e / nb_max, col = e - j * nb_max;
                 if (col < s_nb[j]) {
                     const int al = c0 + j;
-                    const int aidx = A.w_natural ? A.angles[al] : al;
+                    const int aidx = A.w_natural ? (LEAN ? A.angles[al] : s_a[j]) : al;
                     const long long idx = (long long)aidx * A.w_sa + s_blo[j] + col;
                     s_w[e] = ATT ? A.w[idx] * A.att[idx] : A.w[idx];
                 }
@@ -410,8 +460,8 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
         if (inside) {
             for (int j = grp; j < nch; j += T::AG) {
                 const int al = c0 + j;
-                const int a = A.angles[al];
-                const AngleK& AK = g.ang[a];
+                const int a = LEAN ? A.angles[al] : s_a[j];
+                const AngleK& AK = LEAN ? g.ang[a] : s_ang[j];
                 const int aidx = A.w_natural ? a : al;
                 const int bst = s_blo[j], nbs = s_nb[j];
                 auto wval = [&](int b) -> float {
@@ -487,11 +537,21 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
     }
 
     if (mu_early) meanmu = (float)(partials_total(mu_part, s_red) / (double)g.nvox);
+    if (!LEAN && A.n_al <= 0) {
+#pragma unroll
+        for (int k = 0; k < HALO_PT; ++k) {
+            const int e = threadIdx.x + k * NT;
+            if (e < HX * HY) s_f[e] = hv[k];
+        }
+    }
 
     // (4) fused image-space part (the halo tile was loaded before the gather)
     __syncthreads();
     double part = 0.0;
-    if (inside && owner) part = pixel_finish(g, A, s_f, HX, HY, lx, ly, ix, iy, acc, meanf, meanmu);
+    if (inside && owner) {
+        const PixPre pre = LEAN ? pixel_prefetch(A, true, (long long)iy * g.nx + ix) : pre_early;
+        part = pixel_finish(g, A, s_f, HX, HY, lx, ly, ix, iy, acc, meanf, meanmu, pre);
+    }
     if (A.fnew != nullptr) write_partial(part, A.red_f, s_red, vblock);
     else if (A.want_mu) write_partial(part, A.red_mu, s_red, vblock);
 }
@@ -576,6 +636,7 @@ __global__ __launch_bounds__(NT) void k_upd2(GeoK g, BPArgs A, const float* __re
     const int lx = vox % T::X, ly = vox / T::X;
     const int ix = tx0 + lx, iy = ty0 + ly;
     const bool inside = ix < g.nx && iy < g.ny;
+    const PixPre pre = pixel_prefetch(A, inside && grp == 0, (long long)iy * g.nx + ix);
     for (int e = threadIdx.x; e < HX * HY; e += NT) {
         const int hx = e % HX, hy = e / HX;
         const int gx = tx0 - 1 + hx, gy = ty0 - 1 + hy;
@@ -615,7 +676,7 @@ __global__ __launch_bounds__(NT) void k_upd2(GeoK g, BPArgs A, const float* __re
         } else {
             b = Gb[(long long)iy * g.nx + ix];
         }
-        part = pixel_finish(g, A, s_f, HX, HY, lx, ly, ix, iy, b, meanf, meanmu);
+        part = pixel_finish(g, A, s_f, HX, HY, lx, ly, ix, iy, b, meanf, meanmu, pre);
     }
     if (A.fnew != nullptr) write_partial(part, A.red_f, s_red, vblock);
     else if (A.want_mu) write_partial(part, A.red_mu, s_red, vblock);
@@ -1135,7 +1196,7 @@ __global__ __launch_bounds__(NT, 7) void k_bp_batch(const SlotDev* __restrict__ 
         A.red_f.part = d.part_f;
         A.red_f.total = nullptr;
         A.red_f.cap = d.n_part_f;
-        bp_body<T>(d.g, A, I.block);
+        bp_body<T, false, false, true>(d.g, A, I.block);
         __syncthreads();
     }
 }
