@@ -167,7 +167,29 @@ def cpu_baseline(w, p, budget_s=12.0):
            "kind": "oracle",
            "sample": f"first {n} subiterations (objective after each of the {n // M} full iterations) "
                      f"of the same workload from f0, FP64 C oracle, {dt:.1f} s wall"}
+    out["one_thread"] = one_thread_rate(g, p, w, n / dt)
     return out, rec
+
+
+def one_thread_rate(g, p, w, rate_all, budget_s=4.0):
+    """The same oracle on one host thread, from f0, for about budget_s (at
+    least one subiteration; skipped where one would take over 20 s)."""
+    import oracle
+    nt = oracle.num_threads()
+    if nt > 1 and nt / rate_all > 20.0:
+        return None
+    oracle.set_num_threads(1)
+    try:
+        rec = oracle.Recon(g, oracle.params(p), w.f0, w.y_f32, w.r_f32)
+        n = 0
+        t0 = time.perf_counter()
+        while n == 0 or time.perf_counter() - t0 < budget_s:
+            rec.subiteration()
+            n += 1
+        dt = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(nt)
+    return {"value": round(n / dt, 3), "unit": "subiterations/s", "sample": f"first {n} subiterations, {dt:.1f} s"}
 
 
 def one_step_error(rec, geom, p, w):
@@ -377,7 +399,7 @@ def bench_gradcons(args):
         w.att = g0.attenuation_factors(torch.tensor(w.mu, dtype=torch.float32, device=dev)).cpu().numpy()
         g0.close()
     geom = pet.Geometry(w.desc, att=w.att)
-    if w.desc["dim"] == 2 and not args.no_autotune:
+    if not args.no_autotune:
         # the library's own tuner: projector shapes timed on the first subset
         pet.autotune(geom)
     M = w.desc["n_subsets"]
@@ -426,7 +448,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true", help="2D: keep the heuristic projector shapes")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default projector shapes")
     ap.add_argument("--workload", default="c2",
                     choices=["c2", "c1", "c3", "c2full", "c4", "c5", "gradcons", "gradcons3"],
                     help="c2 (default, the benchmark line); c1 / c3 for additional measurements")
@@ -484,7 +506,16 @@ def main():
     r = torch.tensor(w.r, dtype=torch.float32, device=dev).contiguous()
     w.y_f32 = y.cpu().double().numpy()
     w.r_f32 = r.cpu().double().numpy()
-    geom = pet.Geometry(w.desc)
+    w.att = None
+    if getattr(w, "mu", None) is not None:
+        # attenuation factors of the geometry's own rays through the mu map
+        g0 = pet.Geometry(w.desc)
+        w.att = g0.attenuation_factors(torch.tensor(w.mu, dtype=torch.float32, device=dev)).cpu().numpy()
+        g0.close()
+    geom = pet.Geometry(w.desc, att=w.att)
+    if not args.no_autotune:
+        # the library's own tuner: projector shapes timed on the first subset
+        pet.autotune(geom)
     M = w.desc["n_subsets"]
     state = pet.State(geom, p)
 
@@ -517,6 +548,22 @@ def main():
     ev[2].record()
     torch.cuda.synchronize()
     obj_ms = max(0.0, ev[0].elapsed_time(ev[1]) - ev[1].elapsed_time(ev[2]))
+
+    # the spread of the step time: HIP events around each of `steps` more
+    # steps (outside the timed region)
+    sev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    sev[0].record()
+    for k in range(args.steps):
+        state.run(f, y, r, 1)
+        sev[k + 1].record()
+    torch.cuda.synchronize()
+    step_ms = sorted(sev[k].elapsed_time(sev[k + 1]) for k in range(args.steps))
+
+    def pct(v, q):
+        return v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
+
+    step_spread = {"p10": round(pct(step_ms, 0.1), 4), "p50": round(pct(step_ms, 0.5), 4),
+                   "p90": round(pct(step_ms, 0.9), 4), "n": len(step_ms)}
 
     # per-kernel device time: HIP events on the launch stream around every
     # launch of one kernel, over a pass of the same steps (kept out of the
@@ -581,9 +628,11 @@ def main():
         "config": {"workload": WORKLOADS[args.workload] if not args.mode else
                    WORKLOADS[args.workload].replace("SDP-P2", "OSEM" if args.mode == "OSEM" else "SDP-" + args.mode),
                    "subsets": M, "nnz_per_subset": int(nnz_sub), "rays_per_subset": int(rays_sub),
-                   "voxels": q, "autotuned": w.desc["dim"] == 2 and not args.no_autotune,
+                   "voxels": q, "autotuned": not args.no_autotune,
+                   "attenuation": w.att is not None,
                    "objective_last": obj[-1] if obj else None,
-                   "objective_ms": None if obj_ms is None else round(obj_ms, 4)},
+                   "objective_ms": None if obj_ms is None else round(obj_ms, 4),
+                   "step_ms_spread": step_spread},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,

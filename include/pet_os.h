@@ -310,7 +310,10 @@ int pet_os_reconstruct_batch(int32_t n, const pet_os_geom* const* geoms, const p
 /* Autotuner: times the forward projector's threads per ray (1, 4, 16, 64) and,
  * in 2D, the back-projector's tile (16x16, or 8x8 with four angle groups) on
  * this geometry's first subset and keeps the fastest for all later launches
- * with this geometry (plain and batched).  flags bit 0: ignore the cache.
+ * with this geometry (plain and batched).  In 3D it times the single-request
+ * back-projector's slices per block (16, 32, 64) and ring differences staged
+ * together (4, 8) instead; batched 3D launches keep their fixed shape.
+ * flags bit 0: ignore the cache.
  * When the environment variable PET_OS_TUNE_CACHE names a file, results are
  * read from / appended to it keyed by the geometry descriptor.  Synchronous. */
 int pet_os_autotune(pet_os_geom* geom, int32_t flags, pet_os_stream stream);

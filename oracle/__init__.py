@@ -101,6 +101,7 @@ def _load():
             "orc_subiteration": (C.c_int, [G, P, S, _D, _D, _D, _D, _D, _D]),
             "orc_reconstruct": (C.c_int, [G, P, _D, _D, _D, C.c_int, _D]),
             "orc_num_threads": (C.c_int, []),
+            "orc_set_num_threads": (None, [C.c_int]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -161,6 +162,7 @@ def n_planes(g): return _load().orc_n_planes(C.byref(g))
 def n_voxels(g): return _load().orc_n_voxels(C.byref(g))
 def n_bins(g): return _load().orc_n_bins(C.byref(g))
 def num_threads(): return _load().orc_num_threads()
+def set_num_threads(n): _load().orc_set_num_threads(int(n))
 
 
 def sino_shape(g):

@@ -24,6 +24,16 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Thread count of later parallel regions.  For timing: the back-projector
+   adds thread-private images, so its last bits depend on the count. */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* Geometry (Sec. IV-A set-up; readings listed in the header)          */
 /* ------------------------------------------------------------------ */

@@ -127,6 +127,7 @@ int    orc_reconstruct(const orc_geom* g, const orc_params* p, double* f,
                        const double* y, const double* r, int n_iter, double* obj);
 
 int    orc_num_threads(void);
+void   orc_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

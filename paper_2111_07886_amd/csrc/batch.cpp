@@ -92,7 +92,7 @@ int rebuild_lists(pet_os_batch* B) {
         const int nfp = d3 ? fp3_grid(S.g, S.g->max_sub_angles)
                            : fp_grid_seg(S.g, S.g->max_sub_angles, S.fp_seg) + px_items(S.g);
         for (int b = 0; b < nfp; ++b) L[d3 ? WL_FP3 : WL_FP].push_back({s, b});
-        const int nbp = bp_grid_kind(S.g, S.bp_kind);
+        const int nbp = d3 ? bp3_grid_batch(S.g) : bp_grid_kind(S.g, S.bp_kind);
         const int zi = d3 ? (bp3_zb(S.g) == 16 ? 0 : (bp3_zb(S.g) == 32 ? 1 : 2)) : 0;
         const int wbp = d3 ? WL_BP3 + 2 * zi + (bp3_nbs_of(S.g) == 40 ? 1 : 0) : WL_BP0 + S.bp_kind;
         for (int b = 0; b < nbp; ++b) L[wbp].push_back({s, b});
@@ -260,7 +260,7 @@ int pet_os_batch_add(pet_os_batch* B, const pet_os_geom* g, const pet_os_params*
     D.part_f = S.w.red[RED_SUMF].part;
     D.part_mu = S.w.red[RED_SUMMU].part;
     D.n_part_f = sumf_grid(g);
-    D.n_part_mu = g->d.dim == 3 ? bp_grid_kind(g, S.bp_kind) : px_grid(g);
+    D.n_part_mu = g->d.dim == 3 ? bp3_grid_batch(g) : px_grid(g);
     D.subset_lists = ex->subset_lists;
     D.subset_count = ex->d_subset_count;
     D.max_sub = g->max_sub_angles;
@@ -436,11 +436,71 @@ int time_launch(hipStream_t s, int reps, Fn fn, float* ms_out) {
 
 }  // namespace
 
+// 3D: the single-request back-projector's slices per block (16, 32, 64, at
+// most the default) and ring differences per staging group (4, 8), timed on
+// the first subset; the forward projector has a single shape.  Cached as
+// "0 <zb * 16 + dpg>".
+static int autotune3(pet_os_geom* g, GeomExtra* ex, int32_t flags, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const std::string key = tune_key(g->d);
+    int seg = 0, code = -1;
+    if (!(flags & 1) && cache_lookup(key, seg, code) && code > 0) {
+        // a cached shape is taken if it is one the tuner could have chosen
+        const int zb = code / 16, dpg = code % 16;
+        int nb, rw, dq, half, lds;
+        if ((zb == 16 || zb == 32 || zb == 64) && zb <= bp3_zb(g) && (dpg == 4 || dpg == 8) &&
+            bp3_shape_single(g, zb, dpg, nb, rw, dq, half, lds) == PET_OS_OK) {
+            g->tuned_zb = zb;
+            g->tuned_dpg = dpg;
+            return PET_OS_OK;
+        }
+    }
+    const size_t nw = (size_t)g->max_sub_angles * g->n_planes * g->d.n_radial;
+    float *w = nullptr, *img = nullptr;
+    if (hipMalloc(&w, nw * sizeof(float)) != hipSuccess || hipMalloc(&img, (size_t)g->n_vox * sizeof(float)) != hipSuccess) {
+        if (w) (void)hipFree(w);
+        return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc failed in autotune");
+    }
+    int rc = launch_fill(w, (int64_t)nw, 0.5f, s);
+    const int saved_zb = g->tuned_zb, saved_dpg = g->tuned_dpg;
+    float best = 1e30f;
+    int best_zb = 0, best_dpg = 0;
+    const int zbs[] = {16, 32, 64};
+    const int dpgs[] = {4, 8};
+    for (int zb : zbs) {
+        if (zb > bp3_zb(g)) continue;
+        for (int dpg : dpgs) {
+            if (rc) break;
+            int nb, rw, dq, half, lds;
+            if (bp3_shape_single(g, zb, dpg, nb, rw, dq, half, lds)) continue;   // does not fit
+            g->tuned_zb = zb;
+            g->tuned_dpg = dpg;
+            BPLaunch L{};
+            L.w = w; L.w_natural = 0; L.angles = ex->subset_lists; L.n_al = ex->subset_count[0]; L.out = img;
+            float ms = 0;
+            rc = time_launch(s, 5, [&]() { return launch_bp(g, L, s); }, &ms);
+            if (!rc && ms < best) { best = ms; best_zb = zb; best_dpg = dpg; }
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(w);
+    (void)hipFree(img);
+    if (rc || best_zb == 0) {
+        g->tuned_zb = saved_zb;
+        g->tuned_dpg = saved_dpg;
+        return rc ? rc : fail(PET_OS_ERR_INVALID_ARG, "3D geometry: no back-projector shape fits");
+    }
+    g->tuned_zb = best_zb;
+    g->tuned_dpg = best_dpg;
+    cache_store(key, 0, best_zb * 16 + best_dpg);
+    return PET_OS_OK;
+}
+
 extern "C" int pet_os_autotune(pet_os_geom* g, int32_t flags, pet_os_stream stream) {
     if (!g) return fail(PET_OS_ERR_INVALID_ARG, "geom is NULL");
     GeomExtra* ex = extra_of(g);
     if (!ex) return fail(PET_OS_ERR_INVALID_ARG, "invalid geometry");
-    if (g->d.dim == 3) return PET_OS_OK;     // the 3D projectors have a single shape
+    if (g->d.dim == 3) return autotune3(g, ex, flags, (hipStream_t)stream);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     const std::string key = tune_key(g->d);
     int seg = 0, kind = -1;

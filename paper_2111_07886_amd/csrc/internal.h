@@ -55,6 +55,8 @@ struct pet_os_geom {
     int device;
     int tuned_seg = 0;                  // forward-projector segments per ray (0: heuristic)
     int tuned_bp_kind = -1;             // back-projector tile kind (-1: heuristic)
+    int tuned_zb = 0;                   // 3D back-projector slices per block (0: default)
+    int tuned_dpg = 0;                  // 3D ring differences per staging group (0: default)
     bool full_model = false;            // sub-rays, PSF or attenuation (2D; single-request paths only)
     std::vector<int> subset_angles(int subset) const;   // subset in 1..M, 0 = all
 };
@@ -209,8 +211,11 @@ int launch_sum_f(const pet_os_geom* g, const float* f, float* fz, Reduction red,
 
 // 3D projectors and update (kernels3d.hip)
 int fp3_grid(const pet_os_geom* g, int n_al);
-int bp3_grid(const pet_os_geom* g);
+int bp3_grid(const pet_os_geom* g);          // single-request launch (autotuned shape)
+int bp3_grid_batch(const pet_os_geom* g);    // batched launch (default shape)
+int bp3_grid_zb(const pet_os_geom* g, int zb);
 int bp3_zb(const pet_os_geom* g);
+int bp3_shape_single(const pet_os_geom* G, int zb, int dpg_req, int& nb, int& rw, int& dpg, int& half, int& lds);
 int upd3_grid(const pet_os_geom* g);
 int bp3_shape(const pet_os_geom* g, int& nb, int& zb, int& rw, int& dpg);
 int launch_fp3(const pet_os_geom* g, const FPLaunch& L, hipStream_t s);

@@ -844,7 +844,7 @@ int bp_grid_kind(const pet_os_geom* G, int kind) {
 int bp_grid(const pet_os_geom* G) { return bp_grid_kind(G, bp_kind_of(G)); }
 
 int bp_grid_max(const pet_os_geom* G) {
-    if (G->d.dim == 3) return bp3_grid(G);
+    if (G->d.dim == 3) return bp3_grid_zb(G, 16);   // the most blocks any 3D shape launches
     return std::max(bp_grid_kind(G, 0), bp_grid_kind(G, 1));
 }
 

@@ -244,20 +244,23 @@ struct BP3Args {
     int zb;                  // slices per block: 16, 32 or 64
     int rw;                  // staged rows per (ring difference, bin)
     int dpg;                 // ring differences staged together: 4 or 8
+    int half;                // floats of one staging buffer (>= dpg * row stride * rw)
+    int lds;                 // floats of the staging area (two buffers; the finish reuses it)
 };
 
 constexpr int BP3_T = 8;         // columns per tile side
 constexpr int BP3_ZMAX = 64;
 constexpr int BP3_HMAX = 2;      // candidate bins of a column handled per pass
-constexpr int BP3_LDS = 12288;   // floats of the staging area (48 KB)
+constexpr int BP3_LDS = 12288;   // floats of the largest staging area (48 KB)
 constexpr int BP3_MAXND = 63;    // ring differences -31..31
 
 // LDS row stride of the staged footprint: 20 bins (3 rows per wave load) or 40
 __host__ __device__ inline int bp3_nbs(int nb) { return nb <= 20 ? 20 : 40; }
 
-// LDS shared by the back-projector's phases (declared once per kernel)
+// LDS shared by the back-projector's phases (declared once per kernel); the
+// staging area is separate (dynamic in the single-request kernel, sized to
+// the geometry's footprint)
 struct BP3Shared {
-    float w[BP3_LDS];
     double tau[2];
     int blo, nb, npass;
     int omin[BP3_MAXND], omax[BP3_MAXND];
@@ -288,12 +291,11 @@ __device__ __forceinline__ void bp3_apply(float (&acc)[BP3_ZMAX], const float* s
 // s_fin[lz][column] (top of the LDS area), then either store the
 // back-projection or compute the RDP gradient, mu and G of the tile's voxels.
 template <int ZB>
-__device__ void bp3_finish(const GeoK& g, const BP3Args& A, float (&acc)[BP3_ZMAX], BP3Shared& sh, float meanf,
-                           int vblock, int tx0, int ty0, int z0) {
+__device__ void bp3_finish(const GeoK& g, const BP3Args& A, float (&acc)[BP3_ZMAX], BP3Shared& sh, float* s_w,
+                           float meanf, int vblock, int tx0, int ty0, int z0) {
     constexpr int QS = ZB / 4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    float* s_w = sh.w;
-    float* s_fin = s_w + (BP3_LDS - ZB * 64);
+    float* s_fin = s_w + (A.lds - ZB * 64);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         __syncthreads();
@@ -320,9 +322,9 @@ __device__ void bp3_finish(const GeoK& g, const BP3Args& A, float (&acc)[BP3_ZMA
         }
         return;
     }
-    // halo tile of f: (8+2) x (8+2) x (ZB+2), below s_fin
+    // halo tile of f: (8+2) x (8+2) x (ZB+2), below s_fin (the host sizes the
+    // staging area to hold both)
     constexpr int HX = BP3_T + 2, HY = BP3_T + 2, HZ = ZB + 2;
-    static_assert(HX * HY * HZ <= BP3_LDS - ZB * 64, "halo and sums share the staging area");
     for (int e = threadIdx.x; e < HX * HY * HZ; e += NT) {
         const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
         const int gx = tx0 - 1 + hx, gy = ty0 - 1 + hy, gz = z0 - 1 + hz;
@@ -438,7 +440,7 @@ __device__ __forceinline__ int col_hits(const GeoK& g, const AngleK& AK, int m, 
 }
 
 template <int ZB, int NBS>
-__device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared& sh) {
+__device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared& sh, float* s_w) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tiles_x = (g.nx + BP3_T - 1) / BP3_T, tiles_y = (g.ny + BP3_T - 1) / BP3_T;
     int t = vblock;
@@ -529,14 +531,14 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared&
             // the loads of group k+1 run while group k is gathered
             const int ngr = (ND + dpg - 1) / dpg;
             __syncthreads();
-            bp3_stage<NBS>(g, A, sh, sh.w, 0, z0, aidx, blo, nbv);
+            bp3_stage<NBS>(g, A, sh, s_w, 0, z0, aidx, blo, nbv);
             for (int gi = 0; gi < ngr; ++gi) {
                 const int dg = gi * dpg;
-                float* buf = sh.w + (gi & 1) * (BP3_LDS / 2);
+                float* buf = s_w + (gi & 1) * A.half;
                 __builtin_amdgcn_s_waitcnt(0);      // this thread's loads into buf have landed
                 __syncthreads();                    // ... everyone's; the other buffer is free
                 if (gi + 1 < ngr)
-                    bp3_stage<NBS>(g, A, sh, sh.w + ((gi + 1) & 1) * (BP3_LDS / 2), dg + dpg, z0, aidx, blo, nbv);
+                    bp3_stage<NBS>(g, A, sh, s_w + ((gi + 1) & 1) * A.half, dg + dpg, z0, aidx, blo, nbv);
                 // (6) gather: wave v takes the group's ring differences v, v+4, ...
                 for (int ds = wave; ds < dpg; ds += 4) {
                     const int di = dg + ds;
@@ -572,15 +574,18 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared&
         }
         __syncthreads();    // the angle's shared values are read no more
     }
-    bp3_finish<ZB>(g, A, acc, sh, meanf, vblock, tx0, ty0, z0);
+    bp3_finish<ZB>(g, A, acc, sh, s_w, meanf, vblock, tx0, ty0, z0);
 }
 
+// dynamic LDS: the staging area, A.lds floats.  Up to 32 slices per block the
+// register budget is held to four waves per SIMD.
 template <int ZB, int NBS>
-__global__ __launch_bounds__(NT) void k_bp3(GeoK g, BP3Args A, int n_tiles) {
+__global__ __launch_bounds__(NT, ZB <= 32 ? 4 : 1) void k_bp3(GeoK g, BP3Args A, int n_tiles) {
     __shared__ BP3Shared sh;
+    extern __shared__ float bp3_stage_area[];
     const int tile = (int)xcd_block(blockIdx.x, n_tiles);
     if (tile >= n_tiles) return;
-    bp3_body<ZB, NBS>(g, A, tile, sh);
+    bp3_body<ZB, NBS>(g, A, tile, sh, bp3_stage_area);
 }
 
 // ------------------------------------------------------------------ update and z-fastest copy
@@ -676,28 +681,32 @@ int fp3_grid(const pet_os_geom* G, int n_al) {
     return (int)((n + FP3_W - 1) / FP3_W);
 }
 
+// Slices per block of the batched back-projector, and the default of the
+// single-request one: the smallest of 16, 32, 64 that holds the volume's depth.
 int bp3_zb(const pet_os_geom* G) { return G->d.nz <= 16 ? 16 : (G->d.nz <= 32 ? 32 : 64); }
 
-
-int bp3_grid(const pet_os_geom* G) {
-    const int zb = bp3_zb(G);
+int bp3_grid_zb(const pet_os_geom* G, int zb) {
     return ((G->d.nx + BP3_T - 1) / BP3_T) * ((G->d.ny + BP3_T - 1) / BP3_T) * ((G->d.nz + zb - 1) / zb);
 }
+
+// the single-request back-projector's slices per block: the autotuned value
+// when there is one
+static int bp3_zb_single(const pet_os_geom* G) { return G->tuned_zb > 0 ? G->tuned_zb : bp3_zb(G); }
+
+int bp3_grid(const pet_os_geom* G) { return bp3_grid_zb(G, bp3_zb_single(G)); }
+int bp3_grid_batch(const pet_os_geom* G) { return bp3_grid_zb(G, bp3_zb(G)); }
 
 int upd3_grid(const pet_os_geom* G) {
     return ((G->d.nx + U3X - 1) / U3X) * G->d.ny * ((G->d.nz + U3Z - 1) / U3Z);
 }
 
-// Staging shape of the 3D back-projector: bins per angle (bound on the
-// tile's radial extent), rows per (ring difference, bin) = slices + slice
-// offset span + 1 pad row (odd, for conflict-free LDS writes), and the ring
-// differences staged together.  Fails if the footprint cannot fit in LDS.
-int bp3_shape(const pet_os_geom* G, int& nb, int& zb, int& rw, int& dpg) {
+// Bins staged per angle (bound on an 8x8 tile's radial extent) and rows per
+// (ring difference, bin) for zb slices: zb + slice-offset span + 1 pad row.
+static int bp3_rows(const pet_os_geom* G, int zb, int& nb, int& rw) {
     const auto& d = G->d;
     nb = (int)std::ceil(BP3_T * (d.vx + d.vy) / d.ds) + 4;
     if (nb > d.n_radial) nb = d.n_radial;
     if (nb > 40) return fail(PET_OS_ERR_INVALID_ARG, "3D geometry: more than 40 bins per 8x8 voxel tile (ds too small)");
-    zb = bp3_zb(G);
     const double smax = 0.5 * (d.n_radial - 1) * d.ds;
     const double hmin = std::sqrt(d.det_radius * d.det_radius - smax * smax);
     const double hmax = d.det_radius;
@@ -706,12 +715,40 @@ int bp3_shape(const pet_os_geom* G, int& nb, int& zb, int& rw, int& dpg) {
     const double dtau_h = vhalf * (hmax - hmin) / (2.0 * hmin * hmin);
     const int span = (int)std::ceil(d.max_ring_diff * (dtau_tile + dtau_h) + 1e-9) + 3;
     rw = zb + span + 1;
+    return PET_OS_OK;
+}
+
+// Staging shape of the batched back-projector (a fixed BP3_LDS-float area):
+// the default slices per block and 8 ring differences staged together when
+// two such buffers fit, else 4.  Fails if the footprint cannot fit in LDS.
+int bp3_shape(const pet_os_geom* G, int& nb, int& zb, int& rw, int& dpg) {
+    zb = bp3_zb(G);
+    int rc = bp3_rows(G, zb, nb, rw);
+    if (rc) return rc;
     const int nbs = bp3_nbs(nb);
-    // two staging buffers of BP3_LDS/2 floats
     dpg = 8;
     if ((long long)dpg * nbs * rw > BP3_LDS / 2) dpg = 4;
     if ((long long)dpg * nbs * rw > BP3_LDS / 2)
         return fail(PET_OS_ERR_INVALID_ARG, "3D geometry: back-projection footprint does not fit in LDS");
+    return PET_OS_OK;
+}
+
+// Shape of the single-request back-projector for zb slices per block and dpg
+// ring differences per staging group (0: 8 if it fits, else 4): the staging
+// area holds two buffers of dpg x row stride x rw floats and, for the finish,
+// the halo tile of f and the block's sums; at most BP3_LDS floats.
+int bp3_shape_single(const pet_os_geom* G, int zb, int dpg_req, int& nb, int& rw, int& dpg, int& half, int& lds) {
+    int rc = bp3_rows(G, zb, nb, rw);
+    if (rc) return rc;
+    const long long nbs = bp3_nbs(nb);
+    dpg = dpg_req > 0 ? dpg_req : ((8LL * nbs * rw <= BP3_LDS / 2) ? 8 : 4);
+    const long long h = (long long)dpg * nbs * rw;
+    const long long fin = (long long)(BP3_T + 2) * (BP3_T + 2) * (zb + 2) + (long long)zb * 64;
+    const long long total = std::max(2 * h, fin);
+    if (total > BP3_LDS)
+        return fail(PET_OS_ERR_INVALID_ARG, "3D geometry: back-projection footprint does not fit in LDS");
+    half = (int)h;
+    lds = (int)total;
     return PET_OS_OK;
 }
 
@@ -763,25 +800,29 @@ int launch_bp3(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
     if (2 * G->d.max_ring_diff + 1 > BP3_MAXND) return fail(PET_OS_ERR_INVALID_ARG, "max_ring_diff too large");
     BP3Args a;
     fill_bp3(G, L, a);
-    int rc = bp3_shape(G, a.nb, a.zb, a.rw, a.dpg);
+    a.zb = bp3_zb_single(G);
+    int rc = bp3_shape_single(G, a.zb, G->tuned_dpg, a.nb, a.rw, a.dpg, a.half, a.lds);
     if (rc) return rc;
     const int grid = bp3_grid(G);
     if (L.want_mu && grid > L.red_mu.cap) return fail(PET_OS_ERR_DEVICE, "mu partials too small");
     const bool wide = bp3_nbs(a.nb) == 40;
     const dim3 blocks(8 * ((grid + 7) / 8));
+    const size_t lds = (size_t)a.lds * sizeof(float);
     switch (a.zb) {
         case 16:
-            if (wide) hipLaunchKernelGGL((k_bp3<16, 40>), blocks, dim3(NT), 0, s, G->k, a, grid);
-            else hipLaunchKernelGGL((k_bp3<16, 20>), blocks, dim3(NT), 0, s, G->k, a, grid);
+            if (wide) hipLaunchKernelGGL((k_bp3<16, 40>), blocks, dim3(NT), lds, s, G->k, a, grid);
+            else hipLaunchKernelGGL((k_bp3<16, 20>), blocks, dim3(NT), lds, s, G->k, a, grid);
             break;
         case 32:
-            if (wide) hipLaunchKernelGGL((k_bp3<32, 40>), blocks, dim3(NT), 0, s, G->k, a, grid);
-            else hipLaunchKernelGGL((k_bp3<32, 20>), blocks, dim3(NT), 0, s, G->k, a, grid);
+            if (wide) hipLaunchKernelGGL((k_bp3<32, 40>), blocks, dim3(NT), lds, s, G->k, a, grid);
+            else hipLaunchKernelGGL((k_bp3<32, 20>), blocks, dim3(NT), lds, s, G->k, a, grid);
+            break;
+        case 64:
+            if (wide) hipLaunchKernelGGL((k_bp3<64, 40>), blocks, dim3(NT), lds, s, G->k, a, grid);
+            else hipLaunchKernelGGL((k_bp3<64, 20>), blocks, dim3(NT), lds, s, G->k, a, grid);
             break;
         default:
-            if (wide) hipLaunchKernelGGL((k_bp3<64, 40>), blocks, dim3(NT), 0, s, G->k, a, grid);
-            else hipLaunchKernelGGL((k_bp3<64, 20>), blocks, dim3(NT), 0, s, G->k, a, grid);
-            break;
+            return fail(PET_OS_ERR_DEVICE, "3D back-projector: slices per block must be 16, 32 or 64");
     }
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;
@@ -866,6 +907,7 @@ __global__ __launch_bounds__(NT) void k_fp3_batch(const SlotDev* __restrict__ S,
 template <int ZB, int NBS>
 __global__ __launch_bounds__(NT) void k_bp3_batch(const SlotDev* __restrict__ S, const Item* __restrict__ items, const int* __restrict__ count) {
     __shared__ BP3Shared sh;
+    __shared__ float s_w[BP3_LDS];
     const int n = *count;
     for (int it = xcd_item(blockIdx.x, gridDim.x); it < n; it += gridDim.x) {
         const Item I = items[it];
@@ -896,7 +938,9 @@ __global__ __launch_bounds__(NT) void k_bp3_batch(const SlotDev* __restrict__ S,
         A.zb = d.zb;
         A.rw = d.rows_max;
         A.dpg = d.chunk;
-        bp3_body<ZB, NBS>(d.g, A, I.block, sh);
+        A.half = BP3_LDS / 2;
+        A.lds = BP3_LDS;
+        bp3_body<ZB, NBS>(d.g, A, I.block, sh, s_w);
         __syncthreads();
     }
 }

@@ -124,7 +124,9 @@ struct HipExecutor : Executor {
         pet_os_geom* G = nullptr;
         int rc = pet_os_create_geometry(&d, &G);
         if (rc) return rc;
-        rc = pet_os_autotune(G, 0, stream);
+        // the served lanes run the batched kernels, whose 2D shapes the
+        // autotuner picks (the 3D batched shape is fixed)
+        if (d.dim == 2) rc = pet_os_autotune(G, 0, stream);
         if (rc) { pet_os_destroy_geometry(G); return rc; }
         *g = G;
         *bytes = geometry_bytes(d, G->n_planes);

@@ -153,11 +153,13 @@ def workload(name, orc):
     return w, configs.params_2d(d["n_subsets"], 3e5, U=w.U), 4
 
 
-def stepwise(pet, orc, w, p, samples, tol=1e-5):
+def stepwise(pet, orc, w, p, samples, tol=1e-5, tune=False):
     """One GPU subiteration from the oracle's own state (iterate cast to FP32,
     position, Nesterov t, frozen nu) at each sampled J, against one oracle
-    subiteration from the same FP32 input."""
+    subiteration from the same FP32 input (tune: shapes from the autotuner)."""
     G = pet.Geometry(full_desc(w.desc))
+    if tune:
+        pet.autotune(G)
     st = pet.State(G, p)
     y, r = dev(w.y), dev(w.r)
     rec = orc.Recon(orc.geom(w.desc), orc.params(p), w.f0, host(y), host(r))
@@ -402,3 +404,41 @@ def test_c3_full_size(pet, orc):
     del wv, b, bo
     say("C3 stepwise J = 1, 2")
     stepwise(pet, orc, w, p, {1, 2})
+
+
+# 3D with ragged 8x8 column tiles (27 x 21) and a depth (40) that no z-block
+# size divides; span of slice offsets 4, so every staging shape but
+# (64 slices, 8 ring differences) fits the back-projector's LDS
+GEOM_Z = dict(dim=3, nx=27, ny=21, nz=40, vx=2.0, vy=2.0, vz=2.5, n_angles=16, n_radial=39, ds=2.0,
+              n_rings=40, max_ring_diff=2, ring_pitch=2.5, det_radius=150.0, n_subsets=4)
+
+
+def tune_key(d):
+    """The tuning cache's key of a descriptor (the library's format)."""
+    return "%d %d %d %d %.17g %.17g %.17g %d %d %.17g %d %d %.17g %.17g %d" % (
+        d["dim"], d["nx"], d["ny"], d["nz"], d["vx"], d["vy"], d["vz"], d["n_angles"], d["n_radial"], d["ds"],
+        d["n_rings"], d["max_ring_diff"], d["ring_pitch"], d["det_radius"], d["n_subsets"])
+
+
+@pytest.mark.parametrize("zb,dpg", [(16, 4), (16, 8), (32, 4), (32, 8), (64, 4)])
+def test_bp3_shapes(pet, orc, tmp_path, monkeypatch, zb, dpg):
+    """Every slices-per-block / ring-differences-per-group shape the 3D
+    autotuner can choose, pinned through its cache file: the subset
+    back-projection and fused subiterations against the oracle."""
+    from synth import configs, phantoms
+    d = full_desc(GEOM_Z)
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{tune_key(d)}|0 {zb * 16 + dpg}\n")
+    monkeypatch.setenv("PET_OS_TUNE_CACHE", str(cache))
+    say(f"bp3 shape zb={zb} dpg={dpg}")
+    G = pet.Geometry(d)
+    pet.autotune(G)
+    assert cache.read_text().count("|") == 1          # the cached shape was taken, not retuned
+    g = orc.geom(d)
+    rng = np.random.default_rng(zb + dpg)
+    wv = f32(rng.uniform(-1.0, 1.0, G.sino_shape))
+    assert rel(host(G.back(dev(wv), 2)), orc.back(g, wv, 2)) <= 1e-5
+    ones = np.ones(G.sino_shape)
+    assert rel(host(G.back(dev(ones), 0)), orc.back(g, ones, 0)) <= 1e-5     # every angle
+    w = phantoms.make_3d(d, seed=31, n_ell=4, counts=2e6, bg_uniform=0.15, bg_scatter=0.15, scatter_sigma_bins=4.0)
+    stepwise(pet, orc, w, configs.params_3d(U=w.U), {1, 2, 5}, tune=True)
