@@ -66,7 +66,9 @@ def traffic_from_pmc(fetch_csv, write_csv, dim):
     """Measured memory-side bytes per launch from two rocprofv3 --pmc runs
     (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
     same counter reads for the plain copy of COPY_BYTES (--calibrate-copy);
-    the median over the launches of each kernel."""
+    the median over the launches of each kernel's most launched variant (the
+    per-subiteration one: the autotuner's trial shapes run a few times)."""
+    import collections
     import csv
     import statistics
 
@@ -76,9 +78,12 @@ def traffic_from_pmc(fetch_csv, write_csv, dim):
         scale = COPY_BYTES / (copy * 1024.0)
         out = {}
         for k, prefix in TRAFFIC_KERNELS[dim].items():
-            vals = [float(r["Counter_Value"]) * 1024.0 * scale for r in rows if r["Kernel_Name"].startswith(prefix)]
-            if vals:
-                out[k] = statistics.median(vals)
+            by_name = collections.defaultdict(list)
+            for r in rows:
+                if r["Kernel_Name"].startswith(prefix):
+                    by_name[r["Kernel_Name"]].append(float(r["Counter_Value"]) * 1024.0 * scale)
+            if by_name:
+                out[k] = statistics.median(max(by_name.values(), key=len))
         return out, scale
 
     fetch, sf = per_kernel(fetch_csv)

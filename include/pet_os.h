@@ -312,8 +312,9 @@ int pet_os_reconstruct_batch(int32_t n, const pet_os_geom* const* geoms, const p
  * this geometry's first subset and keeps the fastest for all later launches
  * with this geometry (plain and batched).  In 3D it times the single-request
  * back-projector's slices per block (16, 32, 64) and ring differences staged
- * together (4, 8) instead; batched 3D launches keep their fixed shape.
- * flags bit 0: ignore the cache.
+ * together (4, 8) instead; batched 3D launches keep their fixed shape.  The
+ * default shape is timed first and another replaces it only when at least
+ * 3 % faster.  flags bit 0: ignore the cache.
  * When the environment variable PET_OS_TUNE_CACHE names a file, results are
  * read from / appended to it keyed by the geometry descriptor.  Synchronous. */
 int pet_os_autotune(pet_os_geom* geom, int32_t flags, pet_os_stream stream);

@@ -409,6 +409,20 @@ void cache_store(const std::string& key, int seg, int kind) {
     std::fclose(fh);
 }
 
+// The tuner's choice among shapes timed in turn, the default first: another
+// shape replaces the current pick only when at least 3 % faster, so that
+// shapes within timing noise of each other do not flip from run to run.
+struct TunePick {
+    int value = -1;
+    float ms = 0.0f;
+    void offer(int v, float t) {
+        if (value < 0 || t < 0.97f * ms) {
+            value = v;
+            ms = t;
+        }
+    }
+};
+
 // median device time in ms of `reps` launches of fn on stream s
 template <class Fn>
 int time_launch(hipStream_t s, int reps, Fn fn, float* ms_out) {
@@ -463,36 +477,41 @@ static int autotune3(pet_os_geom* g, GeomExtra* ex, int32_t flags, hipStream_t s
     }
     int rc = launch_fill(w, (int64_t)nw, 0.5f, s);
     const int saved_zb = g->tuned_zb, saved_dpg = g->tuned_dpg;
-    float best = 1e30f;
-    int best_zb = 0, best_dpg = 0;
+    // the default shape first (its staging group as the default rule picks it)
+    int nb, rw, dpg0, half, lds;
+    const int zb0 = bp3_zb(g);
+    if (!rc) rc = bp3_shape_single(g, zb0, 0, nb, rw, dpg0, half, lds);
+    TunePick pick;
+    std::vector<int> codes{zb0 * 16 + dpg0};
     const int zbs[] = {16, 32, 64};
     const int dpgs[] = {4, 8};
-    for (int zb : zbs) {
-        if (zb > bp3_zb(g)) continue;
-        for (int dpg : dpgs) {
-            if (rc) break;
-            int nb, rw, dq, half, lds;
-            if (bp3_shape_single(g, zb, dpg, nb, rw, dq, half, lds)) continue;   // does not fit
-            g->tuned_zb = zb;
-            g->tuned_dpg = dpg;
-            BPLaunch L{};
-            L.w = w; L.w_natural = 0; L.angles = ex->subset_lists; L.n_al = ex->subset_count[0]; L.out = img;
-            float ms = 0;
-            rc = time_launch(s, 5, [&]() { return launch_bp(g, L, s); }, &ms);
-            if (!rc && ms < best) { best = ms; best_zb = zb; best_dpg = dpg; }
-        }
+    for (int zb : zbs)
+        for (int dpg : dpgs)
+            if (zb <= zb0 && zb * 16 + dpg != codes[0]) codes.push_back(zb * 16 + dpg);
+    for (int code : codes) {
+        if (rc) break;
+        const int zb = code / 16, dpg = code % 16;
+        int dq;
+        if (bp3_shape_single(g, zb, dpg, nb, rw, dq, half, lds)) continue;   // does not fit
+        g->tuned_zb = zb;
+        g->tuned_dpg = dpg;
+        BPLaunch L{};
+        L.w = w; L.w_natural = 0; L.angles = ex->subset_lists; L.n_al = ex->subset_count[0]; L.out = img;
+        float ms = 0;
+        rc = time_launch(s, 5, [&]() { return launch_bp(g, L, s); }, &ms);
+        if (!rc) pick.offer(code, ms);
     }
     (void)hipStreamSynchronize(s);
     (void)hipFree(w);
     (void)hipFree(img);
-    if (rc || best_zb == 0) {
+    if (rc || pick.value <= 0) {
         g->tuned_zb = saved_zb;
         g->tuned_dpg = saved_dpg;
         return rc ? rc : fail(PET_OS_ERR_INVALID_ARG, "3D geometry: no back-projector shape fits");
     }
-    g->tuned_zb = best_zb;
-    g->tuned_dpg = best_dpg;
-    cache_store(key, 0, best_zb * 16 + best_dpg);
+    g->tuned_zb = pick.value / 16;
+    g->tuned_dpg = pick.value % 16;
+    cache_store(key, 0, pick.value);
     return PET_OS_OK;
 }
 
@@ -522,33 +541,40 @@ extern "C" int pet_os_autotune(pet_os_geom* g, int32_t flags, pet_os_stream stre
     if (!rc) rc = launch_fill(w, (int64_t)nw, 0.5f, s);
     const int* angles = ex->subset_lists;
     const int n_al = ex->subset_count[0];
-    // forward projector: threads per ray
-    float best = 1e30f;
-    int best_seg = 1;
-    const int segs2[] = {1, 4, 16, 64};
-    for (int sg : segs2) {
-        if (rc) break;
+    // forward projector: threads per ray, the default shape first
+    const int seg0 = fp_seg_for(g, (long long)g->max_sub_angles * g->n_planes * g->d.n_radial, 0);
+    TunePick seg_pick;
+    const int segs2[] = {seg0, 1, 4, 16, 64};
+    for (int k = 0; k < 5 && !rc; ++k) {
+        const int sg = segs2[k];
+        if (k > 0 && sg == seg0) continue;
         FPLaunch F{};
         F.f = f; F.out = w; F.angles = angles; F.n_al = n_al; F.mode = FP_COMPACT; F.seg = sg;
         float ms = 0;
         rc = time_launch(s, 5, [&]() { return launch_fp(g, F, s); }, &ms);
-        if (!rc && ms < best) { best = ms; best_seg = sg; }
+        if (!rc) seg_pick.offer(sg, ms);
     }
-    // back-projector tile (2D only)
+    // back-projector tile (2D only), the default tile first
     int best_kind = -1;
     if (!rc && g->d.dim == 2) {
-        float bbest = 1e30f;
         const int saved = g->tuned_bp_kind;
-        for (int kd = 0; kd < 2 && !rc; ++kd) {
+        g->tuned_bp_kind = -1;
+        const int kind0 = bp_kind_of(g);
+        TunePick kind_pick;
+        const int kinds[] = {kind0, 1 - kind0};
+        for (int kd : kinds) {
+            if (rc) break;
             g->tuned_bp_kind = kd;
             BPLaunch L{};
             L.w = w; L.w_natural = 0; L.angles = angles; L.n_al = n_al; L.out = img;
             float ms = 0;
             rc = time_launch(s, 5, [&]() { return launch_bp(g, L, s); }, &ms);
-            if (!rc && ms < bbest) { bbest = ms; best_kind = kd; }
+            if (!rc) kind_pick.offer(kd, ms);
         }
         g->tuned_bp_kind = saved;
+        best_kind = kind_pick.value;
     }
+    const int best_seg = seg_pick.value;
     (void)hipStreamSynchronize(s);
     (void)hipFree(f);
     (void)hipFree(w);
