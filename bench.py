@@ -49,10 +49,16 @@ KERNELS_2D_PSF = {0: "k_blur2 + k_fp_px (PSF blur of f; sub-ray forward projecti
 
 
 def kernel_source_hash():
+    """Hash of the device sources with comments and whitespace removed: a
+    stored traffic measurement stays valid across comment-only edits."""
+    import re
     h = hashlib.sha256()
     for name in ("kernels.hip", "kernels3d.hip", "devutil.h", "raygeom.h"):
-        with open(os.path.join(ROOT, "paper_2111_07886_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2111_07886_amd", "csrc", name), encoding="utf-8") as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

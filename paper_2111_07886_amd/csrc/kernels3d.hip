@@ -23,8 +23,10 @@
 //            or two slice offsets o1, o1+1 with their lengths a1, a2; these
 //            apply to every slice of the column:
 //                acc[iz] += a1 w[r1 = iz - o1] + a2 w[r1 = iz - o1 - 1],
-//            with w staged in LDS as [d][bin][r1] (r1 fastest, zero outside
-//            the valid rings).  The four waves' partial sums are added in a
+//            with w staged in LDS as [d][row][bin] (bins fastest; row = r1
+//            relative to the block, zero outside the valid rings), in a
+//            staging area sized to the geometry's footprint (dynamic LDS in
+//            the single-request kernel).  The four waves' partial sums are added in a
 //            fixed order, then the RDP gradient, mu and G of the column tile
 //            are computed from an LDS halo of f.  No atomics.
 //   k_upd3   the update of k_update on 64 x 32 (x, z) tiles, also writing
