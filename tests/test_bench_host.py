@@ -1,0 +1,111 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU contract, the
+algorithmic byte model, the memory-side traffic from PMC counter CSVs, the
+kernel-source key of stored traffic, and the oracle baseline record."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+@pytest.fixture(scope="module")
+def bench():
+    saved = sys.argv
+    sys.argv = ["bench.py"]
+    try:
+        import bench as b
+    finally:
+        sys.argv = saved
+    return b
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+@pytest.mark.parametrize("osem", [False, True])
+def test_byte_model_totals(bench, osem):
+    """Per subiteration the launches move 8 nnz + 16 rays + 32 q bytes (OSEM:
+    no mu or p, but the subset sensitivity; 2D 8 nnz + 16 rays + 20 q, 3D
+    8 nnz + 16 rays + 28 q)."""
+    nnz, rays, q = 1_001_276.0, 4404.0, 65536.0
+    two = sum(bench.algorithmic_bytes(k, nnz, rays, q, dim=2, osem=osem) for k in (0, 1))
+    three = sum(bench.algorithmic_bytes(k, nnz, rays, q, dim=3, osem=osem) for k in (0, 1, 2))
+    if not osem:
+        assert two == three == 8 * nnz + 16 * rays + 32 * q
+    else:
+        assert two == 8 * nnz + 16 * rays + 20 * q
+        assert three == 8 * nnz + 16 * rays + 28 * q
+    # the full model adds the blur of f and of the back-projection
+    full = sum(bench.algorithmic_bytes(k, nnz, rays, q, dim=2, psf=True) for k in (0, 1))
+    assert full == 8 * nnz + 16 * rays + 52 * q
+
+
+def _pmc_csv(path, counter, rows):
+    fields = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=fields)
+        w.writeheader()
+        for i, (name, val) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i, "Kernel_Name": name, "Counter_Name": counter, "Counter_Value": val})
+
+
+def test_traffic_from_counters(bench, tmp_path):
+    """Counters scaled by what they read for the plain copy, the median over
+    the most launched variant of each kernel (trial shapes left out)."""
+    copy_kib = bench.COPY_BYTES / 1024.0
+    fp = "void petos::k_fp_px<64, false>(petos::GeoK, petos::FPArgs, petos::PxArgs, int)"
+    bp = "void petos::k_bp<petos::Tile<8, 8, 4>, false, false>(petos::GeoK, petos::BPArgs)"
+    trial = "void petos::k_bp<petos::Tile<16, 16, 1>, false, false>(petos::GeoK, petos::BPArgs)"
+    # FETCH_SIZE reads half of the copy's bytes (x2), WRITE_SIZE all of them (x1)
+    _pmc_csv(tmp_path / "f.csv", "FETCH_SIZE",
+             [("__amd_rocclr_copyBuffer", copy_kib / 2), (fp, 100.0), (fp, 110.0), (fp, 120.0),
+              (bp, 200.0), (bp, 210.0), (bp, 220.0), (trial, 9999.0)])
+    _pmc_csv(tmp_path / "w.csv", "WRITE_SIZE",
+             [("__amd_rocclr_copyBuffer", copy_kib), (fp, 10.0), (fp, 10.0), (fp, 10.0),
+              (bp, 20.0), (bp, 20.0), (bp, 20.0), (trial, 1.0), (trial, 1.0)])
+    per, scale = bench.traffic_from_pmc(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), 2)
+    assert scale == {"fetch": 2.0, "write": 1.0}
+    assert per["0"] == int((2 * 110.0 + 10.0) * 1024)
+    assert per["1"] == int((2 * 210.0 + 20.0) * 1024)
+
+
+def test_source_key_ignores_comments(bench, tmp_path, monkeypatch):
+    csrc = tmp_path / "paper_2111_07886_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    names = ("kernels.hip", "kernels3d.hip", "devutil.h", "raygeom.h")
+    for n in names:
+        (csrc / n).write_text("int f(int x) { return x + 1; }  // one\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    k0 = bench.kernel_source_hash()
+    (csrc / "kernels.hip").write_text("/* header */\nint f(int x)\n{\n    return x + 1;  // other words\n}\n")
+    assert bench.kernel_source_hash() == k0
+    (csrc / "kernels.hip").write_text("int f(int x) { return x + 2; }\n")
+    assert bench.kernel_source_hash() != k0
+
+
+def test_cpu_baseline_record(bench):
+    """The oracle leg on the 64x64 case: rate, host threads, the one-thread
+    rate and the oracle state handed to the parity check."""
+    import oracle
+    from synth import configs
+    oracle.build(force=False)
+    w, p, _ = configs.c1()
+    w.y_f32 = w.y.astype("float32").astype("float64")
+    w.r_f32 = w.r.astype("float32").astype("float64")
+    out, rec = bench.cpu_baseline(w, p, budget_s=0.5)
+    assert out["kind"] == "oracle" and out["unit"] == "subiterations/s" and out["value"] > 0
+    assert out["cores"] == oracle.num_threads() >= 1
+    one = out["one_thread"]
+    assert one is not None and one["value"] > 0
+    assert oracle.num_threads() == out["cores"]       # the thread count is restored
+    assert rec is not None and rec.st.k * w.desc["n_subsets"] + rec.st.i - 1 >= 1
