@@ -9,6 +9,13 @@ namespace petos {
 
 constexpr int NT = 256;   // threads per block everywhere
 
+// img[idx] of an image of at most 2^30 voxels (the geometry's limit): the
+// base pointer is uniform and the byte offset fits 32 bits, so the load takes
+// one 32-bit address add per lane instead of 64-bit index arithmetic
+__device__ __forceinline__ float img_at(const float* img, int idx) {
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(img) + 4u * (unsigned)idx);
+}
+
 // ------------------------------------------------------------------ reductions
 
 __device__ __forceinline__ double wave_sum(double v) {

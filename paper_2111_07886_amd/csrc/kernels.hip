@@ -68,7 +68,7 @@ __device__ __forceinline__ float fp_subray_acc(const GeoK& g, const FPArgs& A, c
             float part = 0.0f;
             for (int m = s0; m <= s1; ++m) {
                 if (A.mode == FP_COUNT) { part += 1.0f; continue; }
-                part = fmaf(w, A.f[(long long)m * sm + (long long)c * sx], part);
+                part = fmaf(w, img_at(A.f, m * sm + c * sx), part);
             }
             acc += part;
         }
@@ -85,7 +85,7 @@ __device__ __forceinline__ float fp_subray_acc(const GeoK& g, const FPArgs& A, c
             const float w = subray_weight(g, AK, pixel_ts(g, AK, ix, iy, b));
             if (w > 0.0f) {
                 if (A.mode == FP_COUNT) { acc += 1.0f; continue; }
-                acc = fmaf(w, A.f[(long long)m * sm + (long long)c * sx], acc);
+                acc = fmaf(w, img_at(A.f, m * sm + c * sx), acc);
             }
         }
     }
@@ -176,7 +176,7 @@ __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
                 if (hi > lo) {
                     if (A.mode == FP_COUNT) { acc += 1.0f; continue; }
                     float aij = (float)(tx.L * (hi - lo));
-                    acc = fmaf(aij, A.f[(long long)m * sm + (long long)c * sx], acc);
+                    acc = fmaf(aij, img_at(A.f, m * sm + c * sx), acc);
                 }
             }
         }

@@ -178,11 +178,10 @@ __device__ void fp3_body(const GeoK& g, const FP3Args& A, long long vblock) {
                 if (counting) {
                     for (int j = 0; j < total; ++j) acc += s_pc[wave][j].len;
                 } else {
-                    const float* fr = A.fz + r1;
 #pragma unroll 4
                     for (int j = 0; j < total; ++j) {
                         const Piece p = s_pc[wave][j];
-                        acc = fmaf(p.len, fr[p.off], acc);
+                        acc = fmaf(p.len, img_at(A.fz, p.off + r1), acc);
                     }
                 }
             }
