@@ -471,7 +471,8 @@ def main():
                     help="also run a plain 256 MiB device copy (for PMC byte-counter scaling)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic_<workload>.json from two rocprofv3 --pmc counter CSVs "
-                         "(FETCH_SIZE, WRITE_SIZE) of this workload run with --calibrate-copy, and exit")
+                         "(FETCH_SIZE, WRITE_SIZE) of this workload run with --calibrate-copy --no-autotune "
+                         "(the default projector shapes), and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -482,10 +483,11 @@ def main():
     if args.traffic_from:
         dim = 3 if args.workload == "c3" else 2
         per, scale = traffic_from_pmc(args.traffic_from[0], args.traffic_from[1], dim)
-        out = {"workload": args.workload, "kernel_source": kernel_source_hash(), "bytes_per_launch": per,
-               "counter_scale": scale,
-               "note": "memory-side bytes (FETCH_SIZE + WRITE_SIZE) per launch, median over launches, "
-                       "scaled by the counters of a plain 256 MiB copy"}
+        out = {"workload": args.workload, "kernel_source": kernel_source_hash(), "shapes": "default",
+               "bytes_per_launch": per, "counter_scale": scale,
+               "note": "memory-side bytes (FETCH_SIZE + WRITE_SIZE) per launch, median over the launches of "
+                       "each kernel's per-subiteration variant, scaled by the counters of a plain 256 MiB copy; "
+                       "counter runs with the default projector shapes (--no-autotune)"}
         path = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
         with open(path, "w") as fh:
             json.dump(out, fh, indent=1)
@@ -527,6 +529,7 @@ def main():
     if not args.no_autotune:
         # the library's own tuner: projector shapes timed on the first subset
         pet.autotune(geom)
+    shapes = geom.shapes()
     M = w.desc["n_subsets"]
     state = pet.State(geom, p)
 
@@ -604,8 +607,11 @@ def main():
         traffic = None
         tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
         if os.path.exists(tpath):
+            # measured with the default projector shapes (counter runs take
+            # --no-autotune): valid while the sources and the shapes match
             t = json.load(open(tpath))
-            if t.get("kernel_source") == kernel_source_hash() and str(dom) in t.get("bytes_per_launch", {}):
+            if (t.get("kernel_source") == kernel_source_hash() and t.get("shapes") == "default"
+                    and shapes["current"] == shapes["default"] and str(dom) in t.get("bytes_per_launch", {})):
                 traffic = t["bytes_per_launch"][str(dom)]
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
@@ -639,7 +645,7 @@ def main():
         "config": {"workload": WORKLOADS[args.workload] if not args.mode else
                    WORKLOADS[args.workload].replace("SDP-P2", "OSEM" if args.mode == "OSEM" else "SDP-" + args.mode),
                    "subsets": M, "nnz_per_subset": int(nnz_sub), "rays_per_subset": int(rays_sub),
-                   "voxels": q, "autotuned": not args.no_autotune,
+                   "voxels": q, "autotuned": not args.no_autotune, "shapes": shapes["current"],
                    "attenuation": w.att is not None,
                    "objective_last": obj[-1] if obj else None,
                    "objective_ms": None if obj_ms is None else round(obj_ms, 4),

@@ -318,6 +318,13 @@ int pet_os_reconstruct_batch(int32_t n, const pet_os_geom* const* geoms, const p
  * When the environment variable PET_OS_TUNE_CACHE names a file, results are
  * read from / appended to it keyed by the geometry descriptor.  Synchronous. */
 int pet_os_autotune(pet_os_geom* geom, int32_t flags, pet_os_stream stream);
+/* The projector shapes the single-request launches of this geometry use now
+ * (current[4], after any autotuning) and the defaults they start from
+ * (defaults[4]), each as {forward-projector threads per ray (2D; 0 in 3D),
+ * back-projector tile kind (2D: 0 = 16x16, 1 = 8x8 with four angle groups;
+ * 3D: 2), 3D slices per block, 3D ring differences per staging group (0 in
+ * 2D)}.  Host only; either array may be NULL. */
+int pet_os_geometry_shapes(const pet_os_geom* geom, int32_t* current, int32_t* defaults);
 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of reconstruction requests.  2D and 3D

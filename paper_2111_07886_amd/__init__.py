@@ -34,7 +34,8 @@ EXPORTS = ["pet_os_last_error", "pet_os_version", "pet_os_create_geometry", "pet
            "pet_os_batch_destroy", "pet_os_batch_add", "pet_os_batch_remove", "pet_os_batch_step",
            "pet_os_batch_run", "pet_os_batch_slot_status", "pet_os_batch_bytes", "pet_os_reconstruct_batch",
            "pet_os_autotune", "pet_os_server_create", "pet_os_server_destroy", "pet_os_submit", "pet_os_wait",
-           "pet_os_cancel", "pet_os_server_stats", "pet_os_server_create_simulated", "pet_os_server_inject"]
+           "pet_os_cancel", "pet_os_server_stats", "pet_os_server_create_simulated", "pet_os_server_inject",
+           "pet_os_geometry_shapes"]
 
 
 class PetOSError(RuntimeError):
@@ -131,6 +132,7 @@ def lib():
             "pet_os_reconstruct_batch": (C.c_int, [i32, C.POINTER(_P), C.POINTER(Params), C.POINTER(_P),
                                                    C.POINTER(_P), C.POINTER(_P), C.POINTER(i32), _P]),
             "pet_os_autotune": (C.c_int, [_P, i32, _P]),
+            "pet_os_geometry_shapes": (C.c_int, [_P, C.POINTER(i32), C.POINTER(i32)]),
             "pet_os_server_create": (C.c_int, [C.c_size_t, i32, C.POINTER(_P)]),
             "pet_os_server_destroy": (C.c_int, [_P]),
             "pet_os_submit": (C.c_int, [_P, C.POINTER(Request), C.POINTER(C.c_uint64)]),
@@ -293,6 +295,14 @@ class Geometry:
         _check(lib().pet_os_attenuation_factors(self.handle, _dev(mu, self.n_voxels, "mu"),
                                                 _dev(out, self.n_bins, "att"), _stream(stream)))
         return out
+
+    def shapes(self) -> dict:
+        """pet_os_geometry_shapes: {"current": ..., "default": ...}, each
+        {"fp_seg", "bp_kind", "bp3_zb", "bp3_dpg"}."""
+        cur, dft = (C.c_int32 * 4)(), (C.c_int32 * 4)()
+        _check(lib().pet_os_geometry_shapes(self.handle, cur, dft))
+        keys = ("fp_seg", "bp_kind", "bp3_zb", "bp3_dpg")
+        return {"current": dict(zip(keys, list(cur))), "default": dict(zip(keys, list(dft)))}
 
     def nnz(self, subset=0) -> int:
         n = C.c_int64()

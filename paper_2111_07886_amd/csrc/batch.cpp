@@ -450,6 +450,31 @@ int time_launch(hipStream_t s, int reps, Fn fn, float* ms_out) {
 
 }  // namespace
 
+extern "C" int pet_os_geometry_shapes(const pet_os_geom* g, int32_t* current, int32_t* defaults) {
+    if (!g) return fail(PET_OS_ERR_INVALID_ARG, "geom is NULL");
+    const bool d3 = g->d.dim == 3;
+    const long long nrays = (long long)g->max_sub_angles * g->n_planes * g->d.n_radial;
+    int32_t cur[4] = {0, 0, 0, 0}, def[4] = {0, 0, 0, 0};
+    if (d3) {
+        int nb, rw, dpg, half, lds;
+        def[1] = cur[1] = 2;
+        def[2] = bp3_zb(g);
+        if (bp3_shape_single(g, def[2], 0, nb, rw, dpg, half, lds) == PET_OS_OK) def[3] = dpg;
+        cur[2] = g->tuned_zb > 0 ? g->tuned_zb : def[2];
+        if (bp3_shape_single(g, cur[2], g->tuned_dpg, nb, rw, dpg, half, lds) == PET_OS_OK) cur[3] = dpg;
+    } else {
+        def[0] = fp_seg_for(g, nrays, 0);
+        cur[0] = fp_seg_for(g, nrays, g->tuned_seg);
+        cur[1] = bp_kind_of(g);
+        def[1] = bp_kind_default(g);
+    }
+    for (int k = 0; k < 4; ++k) {
+        if (current) current[k] = cur[k];
+        if (defaults) defaults[k] = def[k];
+    }
+    return PET_OS_OK;
+}
+
 // 3D: the single-request back-projector's slices per block (16, 32, 64, at
 // most the default) and ring differences per staging group (4, 8), timed on
 // the first subset; the forward projector has a single shape.  Cached as
@@ -558,8 +583,7 @@ extern "C" int pet_os_autotune(pet_os_geom* g, int32_t flags, pet_os_stream stre
     int best_kind = -1;
     if (!rc && g->d.dim == 2) {
         const int saved = g->tuned_bp_kind;
-        g->tuned_bp_kind = -1;
-        const int kind0 = bp_kind_of(g);
+        const int kind0 = bp_kind_default(g);
         TunePick kind_pick;
         const int kinds[] = {kind0, 1 - kind0};
         for (int kd : kinds) {

@@ -199,6 +199,7 @@ int fp_seg_for(const pet_os_geom* g, long long nrays, int requested);
 int fp_grid_seg(const pet_os_geom* g, int n_al, int seg);
 int fp_grid(const pet_os_geom* g, int n_al);
 int bp_kind_of(const pet_os_geom* g);
+int bp_kind_default(const pet_os_geom* g);   // the heuristic, before any autotuning
 int bp_grid_kind(const pet_os_geom* g, int kind);
 int bp_grid(const pet_os_geom* g);
 int bp_grid_max(const pet_os_geom* g);

@@ -828,11 +828,15 @@ int fp_grid(const pet_os_geom* G, int n_al) {
 
 // 2D tile kinds 0: 16x16, 1: 8x8 with four angle groups; 3D geometries use
 // kind 2, the column tiles of k_bp3
-int bp_kind_of(const pet_os_geom* G) {
+int bp_kind_default(const pet_os_geom* G) {
     if (G->d.dim == 3) return 2;
-    if (G->tuned_bp_kind >= 0) return G->tuned_bp_kind;
     long long tiles16 = (long long)((G->d.nx + 15) / 16) * ((G->d.ny + 15) / 16);
     return tiles16 < 1024 ? 1 : 0;
+}
+
+int bp_kind_of(const pet_os_geom* G) {
+    if (G->d.dim == 2 && G->tuned_bp_kind >= 0) return G->tuned_bp_kind;
+    return bp_kind_default(G);
 }
 
 int bp_grid_kind(const pet_os_geom* G, int kind) {

@@ -434,6 +434,9 @@ def test_bp3_shapes(pet, orc, tmp_path, monkeypatch, zb, dpg):
     G = pet.Geometry(d)
     pet.autotune(G)
     assert cache.read_text().count("|") == 1          # the cached shape was taken, not retuned
+    sh = G.shapes()
+    assert (sh["current"]["bp3_zb"], sh["current"]["bp3_dpg"]) == (zb, dpg)
+    assert sh["current"]["bp_kind"] == sh["default"]["bp_kind"] == 2 and sh["default"]["bp3_zb"] == 64
     g = orc.geom(d)
     rng = np.random.default_rng(zb + dpg)
     wv = f32(rng.uniform(-1.0, 1.0, G.sino_shape))
