@@ -476,8 +476,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU sharding is "
-                                   "described in DESIGN.md and is not measured", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "runs on one GPU only: sharding across GPUs is designed but neither "
+                                   "built nor measured", "n_gpus": args.gpus}))
         sys.exit(2)
 
     if args.traffic_from:
