@@ -3,6 +3,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace petos {
@@ -18,10 +20,65 @@ __device__ __forceinline__ float img_at(const float* img, int idx) {
 
 // ------------------------------------------------------------------ reductions
 
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+// Sums across lanes by DPP moves (no LDS crossbar): the partner lane of each
+// step is i^1, i^2 (quad permutations), then the mirror within each half
+// row and within each row of 16.  After step k every lane of its group of
+// 2^(k+1) lanes holds the group's sum (the two addends of a step are the
+// same pair on both sides, so the values agree exactly).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+constexpr int DPP_XOR1 = 0xB1;          // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4E;          // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7 - i within each half row
+constexpr int DPP_MIRROR = 0x140;       // lane i <-> 15 - i within each row
+
+// Sum over aligned groups of W lanes (W = 1, 4, 16 or 64; every lane of the
+// wave active), valid in every lane of the group.  W = 64 adds the four row
+// sums, read from lanes 0, 16, 32, 48, in row order.
+template <int W, class V>
+__device__ __forceinline__ V group_sum(V v) {
+    static_assert(W == 1 || W == 4 || W == 16 || W == 64, "group of 1, 4, 16 or 64 lanes");
+    auto step = [](V x, auto ctrl) -> V {
+        constexpr int C = decltype(ctrl)::value;
+        if constexpr (sizeof(V) == 8) return x + dpp_f64<C>(x);
+        else return x + dpp_f32<C>(x);
+    };
+    if constexpr (W >= 4) {
+        v = step(v, std::integral_constant<int, DPP_XOR1>{});
+        v = step(v, std::integral_constant<int, DPP_XOR2>{});
+    }
+    if constexpr (W >= 16) {
+        v = step(v, std::integral_constant<int, DPP_HALF_MIRROR>{});
+        v = step(v, std::integral_constant<int, DPP_MIRROR>{});
+    }
+    if constexpr (W == 64) {
+        if constexpr (sizeof(V) == 8) {
+            V r[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                r[k] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 16 * k),
+                                        __builtin_amdgcn_readlane(__double2loint(v), 16 * k));
+            v = ((r[0] + r[1]) + r[2]) + r[3];
+        } else {
+            V r[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) r[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16 * k));
+            v = ((r[0] + r[1]) + r[2]) + r[3];
+        }
+    }
     return v;
 }
+
+// Sum over the wave (every lane active), valid in every lane.
+__device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
 
 // Sum of v over the block in a fixed order; valid in thread 0.
 __device__ inline double block_sum(double v, double* sh /* >= NT/64 */) {

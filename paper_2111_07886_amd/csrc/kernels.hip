@@ -181,10 +181,9 @@ __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
             }
         }
     }
-    if (SEG > 1) {
-        #pragma unroll
-        for (int off = SEG / 2; off > 0; off >>= 1) acc += __shfl_down(acc, off, SEG);
-    }
+    // the segments' sums of a ray (SEG adjacent lanes, every lane of the
+    // wave takes part), valid in each of its lanes
+    acc = group_sum<SEG>(acc);
     double term = 0.0;
     if (seg == 0 && valid) {
         long long nat = ((long long)plane * g.n_angles + a) * Nr + b;
