@@ -156,15 +156,17 @@ __device__ void fp3_body(const GeoK& g, const FP3Args& A, long long vblock) {
                 }
             }
             // (2) compact the pieces of the 64 cells, in cell order, into LDS
+            // (each lane has 0..4 pieces: the exclusive prefix of the counts
+            // is the sum over their three bits of 2^k x the lanes below with
+            // bit k set, counted from the wave's ballots)
             const int cnt = __popc(present);
-            int incl = cnt;
+            int pos = 0, total = 0;
 #pragma unroll
-            for (int s = 1; s < 64; s <<= 1) {
-                const int t = __shfl_up(incl, s, 64);
-                if (lane >= s) incl += t;
+            for (int k = 0; k < 3; ++k) {
+                const unsigned long long m = __ballot((cnt >> k) & 1);
+                pos += __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u)) << k;
+                total += __popcll(m) << k;
             }
-            const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
-            int pos = incl - cnt;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (present & (1 << k)) {
