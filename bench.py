@@ -244,7 +244,8 @@ def bench_batched(args):
     geoms, ys, rs = [], [], []
     for w, p, n in reqs:
         G = pet.Geometry(w.desc)
-        pet.autotune(G)
+        if not args.no_autotune:
+            pet.autotune(G)
         geoms.append(G)
         ys.append(torch.tensor(w.y, dtype=torch.float32, device=dev))
         rs.append(torch.tensor(w.r, dtype=torch.float32, device=dev))
@@ -328,7 +329,8 @@ def bench_served(args):
     plain_geoms = {}
     for k, (desc, p, f0, y, r) in keys.items():
         G = pet.Geometry(desc)
-        pet.autotune(G)
+        if not args.no_autotune:
+            pet.autotune(G)
         plain_geoms[k] = G
     torch.cuda.synchronize()
 
@@ -459,7 +461,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default projector shapes")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default projector shapes (the served workload's server still tunes its "
+                         "2D geometries)")
     ap.add_argument("--workload", default="c2",
                     choices=["c2", "c1", "c3", "c2full", "c4", "c5", "gradcons", "gradcons3"],
                     help="c2 (default, the benchmark line); c1 / c3 for additional measurements")
