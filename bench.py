@@ -323,7 +323,7 @@ def bench_served(args):
     keys = {}
     for desc, p, n, at, f0, y, r in reqs:
         keys.setdefault(json.dumps(desc, sort_keys=True), (desc, p, f0, y, r))
-    S = pet.Server(64 << 30, 128)
+    S = pet.Server(64 << 30, args.slots)
     for desc, p, f0, y, r in keys.values():
         S.wait(S.submit(desc, p, f0.clone(), y, r, 1))
     plain_geoms = {}
@@ -376,7 +376,8 @@ def bench_served(args):
            "config": {"workload": f"served: {n} requests, Poisson arrivals at 200/s, 98% 2D (128..320 px) / "
                                   f"2% 3D (128x128x32, 180x185x424 planes), 30 iterations each",
                       "completed": ok, "p50_latency_ms": round(1e3 * pct(lat_s, 50), 2),
-                      "p99_latency_ms": round(1e3 * pct(lat_s, 99), 2), "max_active": st["max_active"],
+                      "p99_latency_ms": round(1e3 * pct(lat_s, 99), 2), "slots": args.slots,
+                      "max_active": st["max_active"],
                       "plain_recons_per_s": round(n / span_p, 3),
                       "plain_p50_latency_ms": round(1e3 * pct(lat_p, 50), 2),
                       "plain_p99_latency_ms": round(1e3 * pct(lat_p, 99), 2),
@@ -468,6 +469,7 @@ def main():
                     choices=["c2", "c1", "c3", "c2full", "c4", "c5", "gradcons", "gradcons3"],
                     help="c2 (default, the benchmark line); c1 / c3 for additional measurements")
     ap.add_argument("--requests", type=int, default=400, help="c5: requests taken from the arrival trace")
+    ap.add_argument("--slots", type=int, default=128, help="c5: requests the server runs at once")
     ap.add_argument("--mode", default=None, choices=["BSREM", "M1", "M2", "P1", "P2", "OSEM"],
                     help="c1/c2/c3: run this algorithm instead of the workload's SDP-P2 (OSEM: the "
                          "initialisation of Sec. IV-C)")
