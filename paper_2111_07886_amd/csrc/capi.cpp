@@ -22,6 +22,8 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+thread_local LaunchEvents g_launch_events;
+
 int fail(int code, const std::string& msg) {
     set_error(msg);
     return code;
@@ -580,7 +582,10 @@ static Sched schedule_step(pet_os_state* st) {
 }
 
 // events around launches of the profiled kernel
-static int prof_begin(pet_os_state* st, int kernel, hipStream_t s, hipEvent_t* end) {
+// Per-kernel profiling: a bracket of one launch hands its events to that
+// launch (recorded by the dispatch: the kernel's own duration); a bracket of
+// several launches records them around the launches.
+static int prof_begin(pet_os_state* st, int kernel, hipStream_t s, hipEvent_t* end, bool single) {
     *end = nullptr;
     if (st->prof_kernel != kernel) return PET_OS_OK;
     if (st->prof_used == st->prof_ev.size()) {
@@ -590,12 +595,23 @@ static int prof_begin(pet_os_state* st, int kernel, hipStream_t s, hipEvent_t* e
         st->prof_ev.emplace_back(a, b);
     }
     auto& pr = st->prof_ev[st->prof_used++];
-    PETOS_HIP(hipEventRecord(pr.first, s));
-    *end = pr.second;
+    if (single) {
+        g_launch_events = LaunchEvents{pr.first, pr.second};
+    } else {
+        PETOS_HIP(hipEventRecord(pr.first, s));
+        *end = pr.second;
+    }
     return PET_OS_OK;
 }
 
 static int prof_end(hipEvent_t end, hipStream_t s) {
+    if (g_launch_events.start != nullptr) {
+        // nothing was launched (an empty subset): a zero-length interval
+        const LaunchEvents e = g_launch_events;
+        g_launch_events = LaunchEvents{};
+        PETOS_HIP(hipEventRecord(e.start, s));
+        PETOS_HIP(hipEventRecord(e.stop, s));
+    }
     if (end) PETOS_HIP(hipEventRecord(end, s));
     return PET_OS_OK;
 }
@@ -636,7 +652,7 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
     }
     const bool psf = !d3 && g->k.psf_kx > 0;
     hipEvent_t ev;
-    if ((rc = prof_begin(st, 0, s, &ev))) return rc;
+    if ((rc = prof_begin(st, 0, s, &ev, !psf))) return rc;
     if (psf) {
         // the projector sees the PSF-blurred iterate; the pixel pass the iterate
         rc = launch_blur(g, f, st->w.fb, s);
@@ -661,7 +677,7 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
         B.red_f = st->w.red[RED_SUMF];
         B.osem_sens = sens_i;
         if (osem) B.beta_over_M = 0.0f;
-        if ((rc = prof_begin(st, 1, s, &ev))) return rc;
+        if ((rc = prof_begin(st, 1, s, &ev, !psf))) return rc;
         if (psf) {
             // B A_i^T w needs the neighbouring tiles' back-projection: plain
             // back-projection, blur, then the image-space part per tile
@@ -679,7 +695,7 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
         B.n_part_f = sumf_grid(g);
         B.red_mu = st->w.red[RED_SUMMU];
         if (osem) B.beta_over_M = 0.0f;
-        if ((rc = prof_begin(st, 1, s, &ev))) return rc;
+        if ((rc = prof_begin(st, 1, s, &ev, true))) return rc;
         rc = launch_bp(g, B, s);
         if (rc || (rc = prof_end(ev, s))) return rc;
         UpdLaunch U{};
@@ -692,7 +708,7 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
         U.part_mu = st->w.red[RED_SUMMU].part;
         U.n_part_mu = bp_grid(g);
         U.red_f = st->w.red[RED_SUMF];
-        if ((rc = prof_begin(st, 2, s, &ev))) return rc;
+        if ((rc = prof_begin(st, 2, s, &ev, true))) return rc;
         rc = launch_update(g, U, s);
         if (rc || (rc = prof_end(ev, s))) return rc;
     }

@@ -1,5 +1,6 @@
 // internal.h -- private structures of the pet_os library (not part of the ABI).
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -14,6 +15,23 @@ namespace petos {
 // ---------------------------------------------------------------- errors
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
+
+// Timing events of the next kernel launched on this thread through
+// petos_launch: the per-kernel profiler hands them over for a bracket that
+// holds a single launch, and the dispatch itself records them (no separate
+// event packets around the kernel).  Consumed by that launch.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchEvents g_launch_events;
+
+template <typename... KArgs, typename... Args>
+inline void petos_launch(void (*kernel)(KArgs...), dim3 grid, dim3 block, uint32_t shmem, hipStream_t s,
+                         Args... args) {
+    const LaunchEvents e = g_launch_events;
+    g_launch_events = LaunchEvents{};
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, e.start, e.stop, 0u, args...);
+}
 
 #define PETOS_HIP(call)                                                              \
     do {                                                                             \

@@ -871,7 +871,7 @@ int launch_sum_f(const pet_os_geom* G, const float* f, float* fz, Reduction red,
 
 template <int SEG, bool SUB>
 static void fp_launch_t(const GeoK& k, const FPArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_fp<2, SEG, SUB>), dim3(grid), dim3(NT), 0, s, k, a);
+    petos_launch(k_fp<2, SEG, SUB>, dim3(grid), dim3(NT), 0, s, k, a);
 }
 
 template <bool SUB>
@@ -885,10 +885,10 @@ static void fp_launch_seg(int seg, const GeoK& k, const FPArgs& a, int grid, hip
 template <bool SUB>
 static void fp_px_launch_seg(int seg, dim3 blocks, const GeoK& k, const FPArgs& a, const PxArgs& P, int grid,
                              hipStream_t s) {
-    if (seg == 64) hipLaunchKernelGGL((k_fp_px<64, SUB>), blocks, dim3(NT), 0, s, k, a, P, grid);
-    else if (seg == 16) hipLaunchKernelGGL((k_fp_px<16, SUB>), blocks, dim3(NT), 0, s, k, a, P, grid);
-    else if (seg == 4) hipLaunchKernelGGL((k_fp_px<4, SUB>), blocks, dim3(NT), 0, s, k, a, P, grid);
-    else hipLaunchKernelGGL((k_fp_px<1, SUB>), blocks, dim3(NT), 0, s, k, a, P, grid);
+    if (seg == 64) petos_launch(k_fp_px<64, SUB>, blocks, dim3(NT), 0, s, k, a, P, grid);
+    else if (seg == 16) petos_launch(k_fp_px<16, SUB>, blocks, dim3(NT), 0, s, k, a, P, grid);
+    else if (seg == 4) petos_launch(k_fp_px<4, SUB>, blocks, dim3(NT), 0, s, k, a, P, grid);
+    else petos_launch(k_fp_px<1, SUB>, blocks, dim3(NT), 0, s, k, a, P, grid);
 }
 
 int launch_fp(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
@@ -1007,15 +1007,15 @@ int launch_bp(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
     const bool sub = G->k.n_sub > 1, att = a.att != nullptr;
     const dim3 gr(grid), bl(NT);
     if (kind == 0) {
-        if (sub && att) hipLaunchKernelGGL((k_bp<Tile2L, true, true>), gr, bl, lds, s, G->k, a);
-        else if (sub) hipLaunchKernelGGL((k_bp<Tile2L, true, false>), gr, bl, lds, s, G->k, a);
-        else if (att) hipLaunchKernelGGL((k_bp<Tile2L, false, true>), gr, bl, lds, s, G->k, a);
-        else hipLaunchKernelGGL((k_bp<Tile2L, false, false>), gr, bl, lds, s, G->k, a);
+        if (sub && att) petos_launch(k_bp<Tile2L, true, true>, gr, bl, lds, s, G->k, a);
+        else if (sub) petos_launch(k_bp<Tile2L, true, false>, gr, bl, lds, s, G->k, a);
+        else if (att) petos_launch(k_bp<Tile2L, false, true>, gr, bl, lds, s, G->k, a);
+        else petos_launch(k_bp<Tile2L, false, false>, gr, bl, lds, s, G->k, a);
     } else {
-        if (sub && att) hipLaunchKernelGGL((k_bp<Tile2S, true, true>), gr, bl, lds, s, G->k, a);
-        else if (sub) hipLaunchKernelGGL((k_bp<Tile2S, true, false>), gr, bl, lds, s, G->k, a);
-        else if (att) hipLaunchKernelGGL((k_bp<Tile2S, false, true>), gr, bl, lds, s, G->k, a);
-        else hipLaunchKernelGGL((k_bp<Tile2S, false, false>), gr, bl, lds, s, G->k, a);
+        if (sub && att) petos_launch(k_bp<Tile2S, true, true>, gr, bl, lds, s, G->k, a);
+        else if (sub) petos_launch(k_bp<Tile2S, true, false>, gr, bl, lds, s, G->k, a);
+        else if (att) petos_launch(k_bp<Tile2S, false, true>, gr, bl, lds, s, G->k, a);
+        else petos_launch(k_bp<Tile2S, false, false>, gr, bl, lds, s, G->k, a);
     }
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;

@@ -769,7 +769,7 @@ int launch_fp3(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
     if (L.mode != FP_COUNT && L.fz == nullptr) return fail(PET_OS_ERR_DEVICE, "3D forward projection without z copy");
     const int grid = fp3_grid(G, L.n_al);
     if (L.mode == FP_OBJECTIVE && grid > L.red.cap) return fail(PET_OS_ERR_DEVICE, "objective partials too small");
-    hipLaunchKernelGGL(k_fp3, dim3(8 * ((grid + 7) / 8)), dim3(NT), 0, s, G->k, a, (long long)grid);
+    petos_launch(k_fp3, dim3(8 * ((grid + 7) / 8)), dim3(NT), 0, s, G->k, a, (long long)grid);
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;
 }
@@ -813,16 +813,16 @@ int launch_bp3(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
     const size_t lds = (size_t)a.lds * sizeof(float);
     switch (a.zb) {
         case 16:
-            if (wide) hipLaunchKernelGGL((k_bp3<16, 40>), blocks, dim3(NT), lds, s, G->k, a, grid);
-            else hipLaunchKernelGGL((k_bp3<16, 20>), blocks, dim3(NT), lds, s, G->k, a, grid);
+            if (wide) petos_launch(k_bp3<16, 40>, blocks, dim3(NT), lds, s, G->k, a, grid);
+            else petos_launch(k_bp3<16, 20>, blocks, dim3(NT), lds, s, G->k, a, grid);
             break;
         case 32:
-            if (wide) hipLaunchKernelGGL((k_bp3<32, 40>), blocks, dim3(NT), lds, s, G->k, a, grid);
-            else hipLaunchKernelGGL((k_bp3<32, 20>), blocks, dim3(NT), lds, s, G->k, a, grid);
+            if (wide) petos_launch(k_bp3<32, 40>, blocks, dim3(NT), lds, s, G->k, a, grid);
+            else petos_launch(k_bp3<32, 20>, blocks, dim3(NT), lds, s, G->k, a, grid);
             break;
         case 64:
-            if (wide) hipLaunchKernelGGL((k_bp3<64, 40>), blocks, dim3(NT), lds, s, G->k, a, grid);
-            else hipLaunchKernelGGL((k_bp3<64, 20>), blocks, dim3(NT), lds, s, G->k, a, grid);
+            if (wide) petos_launch(k_bp3<64, 40>, blocks, dim3(NT), lds, s, G->k, a, grid);
+            else petos_launch(k_bp3<64, 20>, blocks, dim3(NT), lds, s, G->k, a, grid);
             break;
         default:
             return fail(PET_OS_ERR_DEVICE, "3D back-projector: slices per block must be 16, 32 or 64");
@@ -859,7 +859,7 @@ int launch_update3(const pet_os_geom* G, const UpdLaunch& L, hipStream_t s) {
     const int grid = upd3_grid(G);
     if (grid > L.red_f.cap) return fail(PET_OS_ERR_DEVICE, "sum partials too small");
     if (L.fz == nullptr) return fail(PET_OS_ERR_DEVICE, "3D update without z copy");
-    hipLaunchKernelGGL(k_upd3, dim3(grid), dim3(NT), 0, s, a);
+    petos_launch(k_upd3, dim3(grid), dim3(NT), 0, s, a);
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;
 }
