@@ -548,7 +548,9 @@ extern "C" int pet_os_autotune(pet_os_geom* g, int32_t flags, pet_os_stream stre
     std::lock_guard<std::mutex> lk(g_tune_mu);
     const std::string key = tune_key(g->d);
     int seg = 0, kind = -1;
-    if (!(flags & 1) && cache_lookup(key, seg, kind)) {
+    // a cached shape is taken if it is one the tuner could have chosen
+    if (!(flags & 1) && cache_lookup(key, seg, kind) && (seg == 1 || seg == 4 || seg == 16 || seg == 64) &&
+        (kind == 0 || kind == 1)) {
         g->tuned_seg = seg;
         g->tuned_bp_kind = kind;
         return PET_OS_OK;

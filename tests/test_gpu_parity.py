@@ -445,3 +445,43 @@ def test_bp3_shapes(pet, orc, tmp_path, monkeypatch, zb, dpg):
     assert rel(host(G.back(dev(ones), 0)), orc.back(g, ones, 0)) <= 1e-5     # every angle
     w = phantoms.make_3d(d, seed=31, n_ell=4, counts=2e6, bg_uniform=0.15, bg_scatter=0.15, scatter_sigma_bins=4.0)
     stepwise(pet, orc, w, configs.params_3d(U=w.U), {1, 2, 5}, tune=True)
+
+
+@pytest.mark.parametrize("seg", [1, 4, 16, 64])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_2d_shapes(pet, orc, tmp_path, monkeypatch, seg, kind):
+    """Every 2D shape the autotuner can choose (forward threads per ray x
+    back-projector tile), pinned through its cache file, against the oracle
+    on a ragged anisotropic geometry: subset forward and back-projection and
+    fused subiterations."""
+    from synth import phantoms, configs
+    d = full_desc(GEOMS["ragged_aniso"])
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{tune_key(d)}|{seg} {kind}\n")
+    monkeypatch.setenv("PET_OS_TUNE_CACHE", str(cache))
+    say(f"2d shape seg={seg} kind={kind}")
+    G = pet.Geometry(d)
+    pet.autotune(G)
+    assert cache.read_text().count("|") == 1          # the cached shape was taken, not retuned
+    assert G.shapes()["current"]["fp_seg"] == seg and G.shapes()["current"]["bp_kind"] == kind
+    g = orc.geom(d)
+    rng = np.random.default_rng(seg * 2 + kind)
+    f = f32(rng.uniform(0.5, 2.0, G.img_shape))
+    sub = [a for a in range(g.n_angles) if a % g.n_subsets == 2]
+    assert rel(host(G.forward(dev(f), 3))[:, sub], orc.forward(g, f, 3)[:, sub]) <= 1e-5
+    wv = f32(rng.uniform(-1.0, 1.0, G.sino_shape))
+    assert rel(host(G.back(dev(wv), 3)), orc.back(g, wv, 3)) <= 1e-5
+    w = phantoms.make_2d(d, seed=23, n_ell=5, counts=3e5, bg_frac=0.1)
+    stepwise(pet, orc, w, configs.params_2d(d["n_subsets"], 3e5, U=w.U), {1, 2, 7}, tune=True)
+
+
+def test_invalid_cached_shape_is_retuned(pet, tmp_path, monkeypatch):
+    """A cache entry naming a shape the tuner cannot choose is ignored."""
+    d = full_desc(GEOMS["ragged_aniso"])
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{tune_key(d)}|7 1\n")
+    monkeypatch.setenv("PET_OS_TUNE_CACHE", str(cache))
+    G = pet.Geometry(d)
+    pet.autotune(G)
+    assert G.shapes()["current"]["fp_seg"] in (1, 4, 16, 64)
+    assert cache.read_text().count("|") == 2          # retuned and stored
