@@ -151,7 +151,7 @@ def cpu_baseline_osem(w, budget_s=12.0):
     return {"value": round(n / dt, 3), "unit": "subiterations/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"first {n} OSEM subiterations of the same workload from f0 (subset sensitivities "
-                      f"precomputed), FP64 oracle, {dt:.1f} s wall"}
+                      f"precomputed), FP64 oracle, {dt:.1f} s wall", "host": host_cpu()}
 
 
 def cpu_baseline(w, p, budget_s=12.0):
@@ -179,7 +179,22 @@ def cpu_baseline(w, p, budget_s=12.0):
            "sample": f"first {n} subiterations (objective after each of the {n // M} full iterations) "
                      f"of the same workload from f0, FP64 C oracle, {dt:.1f} s wall"}
     out["one_thread"] = one_thread_rate(g, p, w, n / dt)
+    out["host"] = host_cpu()
     return out, rec
+
+
+def host_cpu():
+    """The host the oracle ran on: logical CPUs visible and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu": model}
 
 
 def one_thread_rate(g, p, w, rate_all, budget_s=4.0):

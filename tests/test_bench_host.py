@@ -109,3 +109,4 @@ def test_cpu_baseline_record(bench):
     assert one is not None and one["value"] > 0
     assert oracle.num_threads() == out["cores"]       # the thread count is restored
     assert rec is not None and rec.st.k * w.desc["n_subsets"] + rec.st.i - 1 >= 1
+    assert out["host"]["nproc"] >= 1 and "cpu" in out["host"]
