@@ -504,7 +504,8 @@ def main():
     if args.traffic_from:
         dim = 3 if args.workload == "c3" else 2
         per, scale = traffic_from_pmc(args.traffic_from[0], args.traffic_from[1], dim)
-        out = {"workload": args.workload, "kernel_source": kernel_source_hash(), "shapes": "default",
+        out = {"workload": args.workload, "mode": args.mode or "P2", "kernel_source": kernel_source_hash(),
+               "shapes": "default",
                "bytes_per_launch": per, "counter_scale": scale,
                "note": "memory-side bytes (FETCH_SIZE + WRITE_SIZE) per launch, median over the launches of "
                        "each kernel's per-subiteration variant, scaled by the counters of a plain 256 MiB copy; "
@@ -629,9 +630,11 @@ def main():
         tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
         if os.path.exists(tpath):
             # measured with the default projector shapes (counter runs take
-            # --no-autotune): valid while the sources and the shapes match
+            # --no-autotune) in one algorithm mode: valid while the sources,
+            # the shapes and the mode match
             t = json.load(open(tpath))
             if (t.get("kernel_source") == kernel_source_hash() and t.get("shapes") == "default"
+                    and t.get("mode") == p["mode"]
                     and shapes["current"] == shapes["default"] and str(dom) in t.get("bytes_per_launch", {})):
                 traffic = t["bytes_per_launch"][str(dom)]
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
