@@ -68,6 +68,23 @@ TRAFFIC_KERNELS = {2: {0: "void petos::k_fp_px<", 1: "void petos::k_bp<"},
 COPY_BYTES = 64 * 1024 * 1024 * 4      # the --calibrate-copy transfer
 
 
+def stored_traffic(workload, mode, shapes, kernel):
+    """Memory-side bytes per launch of `kernel` (0 forward, 1 back, 2 3D
+    update) from profiles/traffic_<workload>.json, or None.  The counts were
+    taken with the default projector shapes (counter runs take --no-autotune)
+    in one algorithm mode: they hold while the kernel sources, the shapes and
+    the mode are the same."""
+    tpath = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(tpath):
+        return None
+    t = json.load(open(tpath))
+    if (t.get("kernel_source") == kernel_source_hash() and t.get("shapes") == "default"
+            and t.get("mode") == mode and shapes["current"] == shapes["default"]
+            and str(kernel) in t.get("bytes_per_launch", {})):
+        return t["bytes_per_launch"][str(kernel)]
+    return None
+
+
 def traffic_from_pmc(fetch_csv, write_csv, dim):
     """Measured memory-side bytes per launch from two rocprofv3 --pmc runs
     (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
@@ -626,17 +643,7 @@ def main():
         dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"])
         K = per_kernel[dom]
         achieved = K["bytes"] / (K["avg_us"] * 1e-6) / 1e9
-        traffic = None
-        tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
-        if os.path.exists(tpath):
-            # measured with the default projector shapes (counter runs take
-            # --no-autotune) in one algorithm mode: valid while the sources,
-            # the shapes and the mode match
-            t = json.load(open(tpath))
-            if (t.get("kernel_source") == kernel_source_hash() and t.get("shapes") == "default"
-                    and t.get("mode") == p["mode"]
-                    and shapes["current"] == shapes["default"] and str(dom) in t.get("bytes_per_launch", {})):
-                traffic = t["bytes_per_launch"][str(dom)]
+        traffic = stored_traffic(args.workload, p["mode"], shapes, dom)
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                     "kernel": names[dom], "avg_launch_us": round(K["avg_us"], 3),

@@ -110,3 +110,24 @@ def test_cpu_baseline_record(bench):
     assert oracle.num_threads() == out["cores"]       # the thread count is restored
     assert rec is not None and rec.st.k * w.desc["n_subsets"] + rec.st.i - 1 >= 1
     assert out["host"]["nproc"] >= 1 and "cpu" in out["host"]
+
+
+def test_stored_traffic_needs_same_sources_shapes_and_mode(bench, tmp_path, monkeypatch):
+    """The counted bytes of a kernel are reported only for the sources, the
+    default shapes and the algorithm mode they were counted with."""
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "k1")
+    rec = {"workload": "c2", "mode": "P2", "kernel_source": "k1", "shapes": "default",
+           "bytes_per_launch": {"0": 111, "1": 222}}
+    (tmp_path / "profiles" / "traffic_c2.json").write_text(json.dumps(rec))
+    dflt = {"fp_seg": 64, "bp_kind": 1}
+    same = {"current": dict(dflt), "default": dict(dflt)}
+    assert bench.stored_traffic("c2", "P2", same, 1) == 222
+    assert bench.stored_traffic("c2", "P2", same, 2) is None          # kernel not counted
+    assert bench.stored_traffic("c2", "OSEM", same, 1) is None        # other mode
+    tuned = {"current": dict(dflt, fp_seg=16), "default": dict(dflt)}
+    assert bench.stored_traffic("c2", "P2", tuned, 1) is None         # other shapes
+    assert bench.stored_traffic("c3", "P2", same, 1) is None          # nothing stored
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "k2")
+    assert bench.stored_traffic("c2", "P2", same, 1) is None          # sources changed
