@@ -396,7 +396,25 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
     // the mu partials: with at most NT of them, loaded now and added after the
     // gather, so that the load overlaps the staging
     const bool mu_early = want_meanmu && A.n_part_mu <= NT;
-    const double mu_part = mu_early ? partial_early(A.part_mu, A.n_part_mu) : 0.0;
+    // With one wave of pixels (NV == 64) only wave 0 needs the totals: it
+    // loads all the mu partials (lane l: partials l, l+64, l+128, l+192) and
+    // adds them without the block's barriers, in block_sum's order.
+    constexpr bool WAVE0_TOTALS = NV == 64 && !LEAN;
+    double mu_q[WAVE0_TOTALS ? 4 : 1] = {};
+    double mu_part = 0.0;
+    if (mu_early) {
+        if constexpr (WAVE0_TOTALS) {
+            if (grp == 0) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int t = (int)threadIdx.x + 64 * k;
+                    mu_q[k] = t < A.n_part_mu ? A.part_mu[t] : 0.0;
+                }
+            }
+        } else {
+            mu_part = partial_early(A.part_mu, A.n_part_mu);
+        }
+    }
     if (want_meanmu && !mu_early) meanmu = (float)(sum_partials(A.part_mu, A.n_part_mu, s_red) / (double)g.nvox);
 
     float acc = 0.0f;
@@ -535,7 +553,18 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
         return;
     }
 
-    if (mu_early) meanmu = (float)(partials_total(mu_part, s_red) / (double)g.nvox);
+    if (mu_early) {
+        if constexpr (WAVE0_TOTALS) {
+            if (grp == 0) {
+                double t = wave_sum(mu_q[0]);
+#pragma unroll
+                for (int k = 1; k < 4; ++k) t += wave_sum(mu_q[k]);
+                meanmu = (float)(t / (double)g.nvox);
+            }
+        } else {
+            meanmu = (float)(partials_total(mu_part, s_red) / (double)g.nvox);
+        }
+    }
     if (!LEAN && A.n_al <= 0) {
 #pragma unroll
         for (int k = 0; k < HALO_PT; ++k) {
@@ -551,8 +580,17 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
         const PixPre pre = LEAN ? pixel_prefetch(A, true, (long long)iy * g.nx + ix) : pre_early;
         part = pixel_finish(g, A, s_f, HX, HY, lx, ly, ix, iy, acc, meanf, meanmu, pre);
     }
-    if (A.fnew != nullptr) write_partial(part, A.red_f, s_red, vblock);
-    else if (A.want_mu) write_partial(part, A.red_mu, s_red, vblock);
+    if (A.fnew == nullptr && !A.want_mu) return;
+    const Reduction R = A.fnew != nullptr ? A.red_f : A.red_mu;
+    if constexpr (WAVE0_TOTALS) {
+        // waves 1..3 hold no pixel: the block's sum is wave 0's
+        if (grp == 0) {
+            const double bs = wave_sum(part);
+            if (threadIdx.x == 0) R.part[vblock] = bs;
+        }
+    } else {
+        write_partial(part, R, s_red, vblock);
+    }
 }
 
 // Partials of sum f over the same tiles, threads and order as the fused
