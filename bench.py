@@ -1,16 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the SDP-BSREM hot path on one MI355X.
 
-Workload: the 2D 256x256 reconstruction (300 mm FOV, 288 angles x 367 bins,
-24 interleaved subsets, SDP-P2 with the Table II high-count row, seeded
-12-ellipse phantom with hot lesions, 5e6 counts, 20 % background).
-One step = one full iteration: 24 subiterations (forward projection +
-ratio, back-projection + RDP/smoothness stencil, preconditioned update).
-The FP64 objective, which no subiteration needs, is timed on its own
-(config.objective_ms).  Inputs are resident in HBM before timing.
+Default workload: the fully 3D reconstruction (200x200x64 volume, 224 angles x
+281 bins x 1744 span-1 planes, 64 rings with ring difference <= 15, 28
+interleaved subsets, SDP-P2 with the Table III non-TOF row, seeded ellipsoid
+phantom, 5e8 counts, 30 % randoms + scatter).  One step = one full
+iteration: 28 subiterations (forward projection + ratio, back-projection +
+RDP/smoothness stencil, preconditioned update).  The FP64 objective, which no
+subiteration needs, is timed on its own (config.objective_ms).  Inputs are
+resident in HBM before timing.
+
+The same run measures the metric's batched and served half: 96 uneven 2D
+reconstructions advanced by one captured launch per batched subiteration
+against the same requests one at a time ("batched"), and a Poisson arrival
+trace served by the continuous-batching server against the plain path
+("served", recons/s with p50/p99 latency).  --workload c2 / c1 / c2full give
+the 2D single-request lines, c4 / c5 the two legs alone.
 
 Prints ONE JSON line (metric, value = subiterations/s, roofline of the
-dominant kernel from HIP events, CPU oracle baseline).
+dominant kernel, CPU oracle baselines).
 """
 from __future__ import annotations
 
@@ -25,6 +33,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def progress(msg):
+    """A progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"# {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
 WORKLOADS = {
     "c2": "2D SDP-P2, 256x256 image (1.171875 mm), 288 angles x 367 bins, 24 subsets, 5e6 counts, "
           "20% background; step = 1 iteration (24 subiterations); the FP64 objective is timed on its own",
@@ -173,8 +186,8 @@ def cpu_baseline_osem(w, budget_s=12.0):
 
 def cpu_baseline(w, p, budget_s=12.0):
     """The FP64 oracle, as it stands, on the same workload: subiterations from
-    f0 with the objective after every full iteration, until ~budget_s of CPU
-    work is done."""
+    f0 until ~budget_s of CPU work is done.  Like the GPU's timed region it
+    evaluates no objective (the paper's Table I subiteration only)."""
     import oracle
     if p["mode"] == "OSEM":
         return cpu_baseline_osem(w, budget_s), None
@@ -188,13 +201,11 @@ def cpu_baseline(w, p, budget_s=12.0):
     while time.perf_counter() - t0 < budget_s and n < 50 * M and (n == 0 or budget_s > 0):
         rec.subiteration()
         n += 1
-        if n % M == 0:
-            rec.objective()
     dt = time.perf_counter() - t0
     out = {"value": round(n / dt, 3), "unit": "subiterations/s", "cores": oracle.num_threads(),
            "kind": "oracle",
-           "sample": f"first {n} subiterations (objective after each of the {n // M} full iterations) "
-                     f"of the same workload from f0, FP64 C oracle, {dt:.1f} s wall"}
+           "sample": f"first {n} subiterations of the same workload from f0 (no objective evaluations, as in "
+                     f"the GPU's timed region), FP64 C oracle, {dt:.1f} s wall"}
     out["one_thread"] = one_thread_rate(g, p, w, n / dt)
     out["host"] = host_cpu()
     return out, rec
@@ -262,15 +273,47 @@ def one_step_error(rec, geom, p, w):
     return float(np.linalg.norm(g - o) / np.linalg.norm(o)), int(rec.st.k), int(rec.st.i)
 
 
-def bench_batched(args):
+def oracle_recons_rate(items, budget_s=15.0, note=""):
+    """The FP64 oracle, as it stands, on a bounded sample of reconstruction
+    requests: (geometry descriptor, params, f0, y, r, n_iter) items taken in
+    order, subiteration by subiteration (no objective evaluations, as in the
+    GPU's timed region), until ~budget_s of CPU work is done.  A request cut
+    short counts by the fraction of its subiterations done."""
+    import oracle
+    oracle.build(force=False)
+    done, subs, started = 0.0, 0, 0
+    t0 = time.perf_counter()
+    for desc, p, f0, y, r, n_iter in items:
+        if time.perf_counter() - t0 >= budget_s:
+            break
+        started += 1
+        g = oracle.geom(desc)
+        rec = oracle.Recon(g, oracle.params(p), f0, y, r)
+        total = n_iter * desc["n_subsets"]
+        k = 0
+        while k < total and time.perf_counter() - t0 < budget_s:
+            rec.subiteration()
+            k += 1
+        done += k / total
+        subs += k
+    dt = time.perf_counter() - t0
+    return {"value": round(done / dt, 4), "unit": "recons/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{note}: {started} requests started, {done:.2f} reconstructions' worth ({subs} "
+                      f"subiterations, no objective) in {dt:.1f} s, FP64 C oracle",
+            "subiterations_per_s": round(subs / dt, 3), "host": host_cpu()}
+
+
+def bench_batched(args, cpu=True):
     """96 uneven 2D reconstructions (10 iterations each): one batch, one
     captured step per subiteration, vs the same requests one at a time."""
+    import numpy as np
     import torch
 
     import paper_2111_07886_amd as pet
     from synth import configs
 
     specs = configs.c4_specs()
+    progress("batched: generating 96 requests")
     reqs = [configs.c4_workload(sp) for sp in specs]
     dev = torch.device("cuda:0")
     geoms, ys, rs = [], [], []
@@ -289,6 +332,7 @@ def bench_batched(args):
     params = [p for _, p, _ in reqs]
     iters = [n for _, _, n in reqs]
     # warm-up (graph capture, caches)
+    progress("batched: geometries ready, timing")
     fs = [torch.tensor(w.f0, dtype=torch.float32, device=dev) for w, _, _ in reqs]
     pet.reconstruct_batch(geoms, params, fs, ys, rs, [1] * len(reqs))
     fs = [torch.tensor(w.f0, dtype=torch.float32, device=dev) for w, _, _ in reqs]
@@ -305,23 +349,29 @@ def bench_batched(args):
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
     same = all(torch.equal(a, b) for a, b in zip(fs, fs2))
-    out = {"metric": "recons/s", "value": round(len(reqs) / tb, 3), "unit": "recons/s", "n_gpus": 1,
-           "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * tb, 3), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "batched: 96 uneven 2D SDP-P2 reconstructions (64..320 px, 60..360 angles, "
-                                  "4..32 subsets, 1e5..1e7 counts), 10 iterations each; step = all 96 to the end",
-                      "subiterations": n_sub, "subiterations_per_s": round(n_sub / tb, 1),
-                      "plain_one_at_a_time_s": round(tp, 4), "plain_recons_per_s": round(len(reqs) / tp, 3),
-                      "speedup_vs_plain": round(tp / tb, 3), "batched_equals_plain_bitwise": same},
-           "roofline": {"bound": "hbm", "achieved": round(bytes_total / tb / 1e9, 2), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(bytes_total / tb / 1e9 / HBM_PEAK_GBS, 5), "traffic": None,
-                        "kernel": "whole batched step (all kernels), algorithmic bytes 8 nnz + 16 rays + 32 q "
-                                  "per subiteration"},
-           "cpu_baseline": None}
-    print(json.dumps(out), flush=True)
+    cpu_base = None
+    if cpu:
+        progress("batched: oracle sample")
+        # every 8th request (a spread of sizes), data as the GPU sees them (FP32)
+        f32 = lambda t: t.cpu().double().numpy()
+        items = [(w.desc, p, w.f0, f32(ys[k]), f32(rs[k]), n) for k, (w, p, n) in enumerate(reqs) if k % 8 == 0]
+        cpu_base = oracle_recons_rate(items, note="every 8th of the 96 batched requests")
+    return {"metric": "recons/s", "value": round(len(reqs) / tb, 3), "unit": "recons/s", "n_gpus": 1,
+            "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * tb, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "batched: 96 uneven 2D SDP-P2 reconstructions (64..320 px, 60..360 angles, "
+                                   "4..32 subsets, 1e5..1e7 counts), 10 iterations each; step = all 96 to the end",
+                       "subiterations": n_sub, "subiterations_per_s": round(n_sub / tb, 1),
+                       "plain_one_at_a_time_s": round(tp, 4), "plain_recons_per_s": round(len(reqs) / tp, 3),
+                       "speedup_vs_plain": round(tp / tb, 3), "batched_equals_plain_bitwise": same},
+            "roofline": {"bound": "hbm", "achieved": round(bytes_total / tb / 1e9, 2), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(bytes_total / tb / 1e9 / HBM_PEAK_GBS, 5), "traffic": None,
+                         "kernel": "whole batched step (all kernels), algorithmic bytes 8 nnz + 16 rays + 32 q "
+                                   "per subiteration"},
+            "cpu_baseline": cpu_base}
 
 
-def bench_served(args):
+def bench_served(args, cpu=True):
     """Poisson arrivals (200 req/s) of 2D (128..320 px) and 3D (128x128x32)
     requests, 30 iterations each: the continuous-batching server vs the same
     trace served one request at a time (FIFO) by pet_os_reconstruct."""
@@ -339,7 +389,10 @@ def bench_served(args):
     trace = configs.c5_trace(n_requests=args.requests)
     dev = torch.device("cuda:0")
     reqs = []
-    for q in trace:
+    progress(f"served: generating {len(trace)} requests")
+    for qi, q in enumerate(trace):
+        if qi % 50 == 49:
+            progress(f"served: {qi + 1} requests generated")
         d = q["desc"]
         if d["dim"] == 3:
             w = phantoms.make_3d(d, seed=q["seed"], n_ell=11, counts=q["counts"], bg_uniform=0.1, bg_scatter=0.1)
@@ -370,6 +423,7 @@ def bench_served(args):
         return float(np.percentile(np.asarray(v), q))
 
     # served
+    progress("served: geometries warm, serving the trace")
     fs = [f0.clone() for *_, f0, y, r in reqs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -386,6 +440,7 @@ def bench_served(args):
     span_s = max(r_["t_finish"] for r_ in res) - min(r_["t_submit"] for r_ in res)
     ok = sum(r_["status"] == 0 for r_ in res)
     # plain: one at a time, arrival order, same arrival times
+    progress("served: the same trace one request at a time")
     fs2 = [f0.clone() for *_, f0, y, r in reqs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -402,6 +457,13 @@ def bench_served(args):
     span_p = fin[-1] - reqs[0][3]
     same = sum(torch.equal(a, b) for a, b in zip(fs, fs2))
     n = len(reqs)
+    cpu_base = None
+    if cpu:
+        progress("served: oracle sample")
+        f32 = lambda t: t.cpu().double().numpy()
+        items = [(desc, p, f32(f0), f32(y), f32(r), nn) for k, (desc, p, nn, at, f0, y, r) in enumerate(reqs)
+                 if k % 20 == 0]
+        cpu_base = oracle_recons_rate(items, note="every 20th request of the arrival trace, one at a time")
     out = {"metric": "served recons/s", "value": round(n / span_s, 3), "unit": "recons/s", "n_gpus": 1,
            "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * span_s, 2), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -414,8 +476,8 @@ def bench_served(args):
                       "plain_p50_latency_ms": round(1e3 * pct(lat_p, 50), 2),
                       "plain_p99_latency_ms": round(1e3 * pct(lat_p, 99), 2),
                       "results_equal_to_plain": f"{same}/{n}"},
-           "roofline": None, "cpu_baseline": None}
-    print(json.dumps(out), flush=True)
+           "roofline": None, "cpu_baseline": cpu_base}
+    return out
 
 
 def bench_gradcons(args):
@@ -497,9 +559,12 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default projector shapes (the served workload's server still tunes its "
                          "2D geometries)")
-    ap.add_argument("--workload", default="c2",
-                    choices=["c2", "c1", "c3", "c2full", "c4", "c5", "gradcons", "gradcons3"],
-                    help="c2 (default, the benchmark line); c1 / c3 for additional measurements")
+    ap.add_argument("--workload", default="c3",
+                    choices=["c3", "c2", "c1", "c2full", "c4", "c5", "gradcons", "gradcons3"],
+                    help="c3 (default: the benchmark line, with the batched and served legs); c1 / c2 / c2full "
+                         "for the 2D single-request measurements; c4 / c5 for the batched / served legs alone")
+    ap.add_argument("--no-batched", action="store_true", help="c3: leave out the batched leg (c4)")
+    ap.add_argument("--no-served", action="store_true", help="c3: leave out the served leg (c5)")
     ap.add_argument("--requests", type=int, default=400, help="c5: requests taken from the arrival trace")
     ap.add_argument("--slots", type=int, default=128, help="c5: requests the server runs at once")
     ap.add_argument("--mode", default=None, choices=["BSREM", "M1", "M2", "P1", "P2", "OSEM"],
@@ -533,9 +598,11 @@ def main():
         print(json.dumps(out))
         return
     if args.workload == "c4":
-        return bench_batched(args)
+        print(json.dumps(bench_batched(args, cpu=not args.no_cpu_baseline)), flush=True)
+        return
     if args.workload == "c5":
-        return bench_served(args)
+        print(json.dumps(bench_served(args, cpu=not args.no_cpu_baseline)), flush=True)
+        return
     if args.workload in ("gradcons", "gradcons3"):
         return bench_gradcons(args)
 
@@ -545,7 +612,9 @@ def main():
     import paper_2111_07886_amd as pet
     from synth import configs
 
+    progress(f"{args.workload}: generating the workload")
     w, p, _ = {"c1": configs.c1, "c2": configs.c2, "c3": configs.c3, "c2full": configs.c2_full}[args.workload]()
+    progress(f"{args.workload}: workload ready")
     if args.mode == "OSEM":
         p = pet.osem_params(p["beta"], p["gamma_R"], p["eps"])
     elif args.mode:
@@ -589,6 +658,7 @@ def main():
     state.run(f, y, r, args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    progress(f"{args.workload}: {args.steps} timed steps in {elapsed:.3f} s")
     sub_per_s = args.steps * M / elapsed
     # the FP64 objective of the iterate, as a state evaluates it after an
     # iteration (device time of one more iteration with and without it)
@@ -653,6 +723,7 @@ def main():
     del state
     cpu, parity = None, None
     if not args.no_cpu_baseline:
+        progress(f"{args.workload}: oracle baseline")
         cpu, rec = cpu_baseline(w, p)
         if rec is not None:
             e, k_at, i_at = one_step_error(rec, geom, p, w)
@@ -685,7 +756,32 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
     }
+    if args.workload == "c3":
+        # the metric's batched and served half, measured in the same run
+        if not args.no_batched:
+            out["batched"] = leg_summary(bench_batched(args, cpu=not args.no_cpu_baseline))
+            progress(f"batched leg done: {out['batched']['recons_per_s']} recons/s")
+        if not args.no_served:
+            out["served"] = leg_summary(bench_served(args, cpu=not args.no_cpu_baseline))
+            progress(f"served leg done: {out['served']['recons_per_s']} recons/s")
     print(json.dumps(out), flush=True)
+
+
+def leg_summary(line):
+    """The batched or served measurement as keys of the benchmark line."""
+    c = line["config"]
+    out = {"workload": c["workload"], "recons_per_s": line["value"], "wall_s": round(line["ms_per_step"] / 1e3, 4)}
+    for k in ("subiterations_per_s", "plain_recons_per_s", "speedup_vs_plain", "batched_equals_plain_bitwise",
+              "p50_latency_ms", "p99_latency_ms", "plain_p50_latency_ms", "plain_p99_latency_ms", "slots",
+              "max_active", "completed", "results_equal_to_plain"):
+        if k in c:
+            out[k] = c[k]
+    if "speedup_vs_plain" not in out and "plain_recons_per_s" in c:
+        out["speedup_vs_plain"] = round(line["value"] / c["plain_recons_per_s"], 3)
+    if line.get("roofline"):
+        out["roofline"] = line["roofline"]
+    out["cpu_baseline"] = line.get("cpu_baseline")
+    return out
 
 
 if __name__ == "__main__":

@@ -35,6 +35,17 @@
  *   - Every call returns PET_OS_OK (0) or a negative PET_OS_ERR_* code and sets
  *     a thread-local message readable with pet_os_last_error().  Arguments are
  *     validated before anything is queued: a failing call changes nothing.
+ *   - Data check (the problem statement of Sec. II-A and eq:BoundedSet): the
+ *     reconstruction entry points (pet_os_subiteration, pet_os_run,
+ *     pet_os_reconstruct, pet_os_batch_add, served admission) reject with
+ *     PET_OS_ERR_INVALID_ARG data in which a count y is negative or not
+ *     finite, a background value r is not > 0 or not finite (gamma in
+ *     R^p_{++}), or an image value f lies outside [0, U] or is not finite
+ *     (OSEM: f >= 0); with P1/P2 and J0 = 0 f must also have a positive
+ *     entry (its mean divides the gradient magnitude of mu).  The check is
+ *     one device pass over y, r and f followed by a synchronisation of
+ *     `stream`; a state makes it when it first sees a (f, y, r) triple of
+ *     buffers, not again while the same buffers come back.
  *   - Calls are asynchronous on `stream` unless stated otherwise.
  */
 #ifndef PET_OS_H
@@ -213,14 +224,17 @@ int pet_os_state_position(const pet_os_state* state, int64_t* k, int32_t* i);
  *   f~ = f - lambda_k alpha_{k,i} nu^{k,i} S(f) grad Phi_i;  f = P_t(f~)
  * then advances (k, i).  nu^{k,i} is computed from the iterate entering the
  * subiteration.  y, r: n_bins floats (natural layout, r > 0).  Asynchronous;
- * the FP64 scalars lambda_k, alpha_{k,i} are evaluated on the host. */
+ * the FP64 scalars lambda_k, alpha_{k,i} are evaluated on the host.  The
+ * first call with a (f, y, r) triple makes the data check (conventions). */
 int pet_os_subiteration(pet_os_state* state, float* f, const float* y, const float* r,
                         pet_os_stream stream);
 
 /* n_iter iterations (n_iter * M subiterations) of SDP-BSREM from f (in/out).
  * obj: NULL, or a HOST array of n_iter+1 doubles receiving Phi(f^k) for
  * k = 0, objective_every, 2*objective_every, ... (other entries NaN); the
- * call then blocks at the end.  With obj == NULL it is asynchronous. */
+ * call then blocks at the end.  The data check (conventions) runs first and
+ * waits for `stream`; with obj == NULL the iterations are queued
+ * asynchronously after it. */
 int pet_os_reconstruct(const pet_os_geom* geom, const pet_os_params* params, float* f,
                        const float* y, const float* r, int32_t n_iter, double* obj,
                        pet_os_stream stream);
@@ -256,7 +270,11 @@ int pet_os_state_seek(pet_os_state* state, int64_t k, int32_t i, double t_nest, 
  * export: buf == NULL queries the size into *len; otherwise *len must be at
  * least that size.  Synchronous (copies the frozen nu to the host).
  * import: the target state must have the same geometry descriptor and mode,
- * else PET_OS_ERR_STATE_MISMATCH. */
+ * else PET_OS_ERR_STATE_MISMATCH; the checkpoint's parameters, position and
+ * Nesterov t must pass the checks of pet_os_state_create and
+ * pet_os_state_seek, and a frozen nu is accepted only by a P1/P2 state
+ * (INVALID_ARG, with the state unchanged).  The next subiteration makes the
+ * data check again (U may have changed). */
 int pet_os_state_export(const pet_os_state* state, void* buf, size_t* len);
 int pet_os_state_import(pet_os_state* state, const void* buf, size_t len);
 
@@ -281,7 +299,8 @@ int pet_os_batch_destroy(pet_os_batch* batch);
  * with data y, r (device, natural layout) on `geom` (must outlive the slot).
  * Allocates the request's scratch and schedule, queues sum(f) on `stream`;
  * synchronises `stream` first (the slot table is read by queued steps).
- * Errors: INVALID_ARG, BUDGET (no free slot), OUT_OF_MEMORY. */
+ * Errors: INVALID_ARG (also data that fail the check of the conventions),
+ * BUDGET (no free slot), OUT_OF_MEMORY. */
 int pet_os_batch_add(pet_os_batch* batch, const pet_os_geom* geom, const pet_os_params* params, float* f,
                      const float* y, const float* r, int32_t n_iter, pet_os_stream stream, int32_t* slot);
 /* Release a slot (synchronises `stream`); its f holds the last iterate. */
@@ -371,7 +390,9 @@ int pet_os_server_create(size_t hbm_budget_bytes, int32_t max_slots, pet_os_serv
 /* Finishes every queued and running request, then stops. */
 int pet_os_server_destroy(pet_os_server* server);
 /* Queue a request; returns at once with a ticket.  Invalid descriptors,
- * parameters or pointers are rejected synchronously (INVALID_ARG). */
+ * parameters or pointers are rejected synchronously (INVALID_ARG).  The data
+ * (y, r, f0) are checked at admission (conventions); a request whose data
+ * fail ends with status INVALID_ARG and the others are not affected. */
 int pet_os_submit(pet_os_server* server, const pet_os_request* req, uint64_t* ticket);
 /* Wait up to timeout_us (< 0: forever) for a ticket; fills *out and releases
  * the ticket.  PET_OS_ERR_TIMEOUT if it is still running. */
@@ -387,6 +408,7 @@ int pet_os_server_create_simulated(size_t budget_bytes, int32_t max_slots, int64
 #define PET_OS_INJECT_ADMIT_OOM 1      /* the next admissions fail with OUT_OF_MEMORY */
 #define PET_OS_INJECT_STEP_FAILURE 2   /* the next batched steps fail (DEVICE) */
 #define PET_OS_INJECT_NAN_OBJECTIVE 3  /* the next objectives come back NaN */
+#define PET_OS_INJECT_BAD_DATA 4       /* the next admissions fail the data check (INVALID_ARG) */
 int pet_os_server_inject(pet_os_server* server, int32_t kind, int32_t count);
 
 #ifdef __cplusplus

@@ -78,7 +78,7 @@ class ServerStats(C.Structure):
                 ("bytes_in_use", C.c_size_t), ("geometries_cached", C.c_int64)]
 
 
-INJECT = {"admit_oom": 1, "step_failure": 2, "nan_objective": 3}
+INJECT = {"admit_oom": 1, "step_failure": 2, "nan_objective": 3, "bad_data": 4}
 
 _lib = None
 _P = C.c_void_p

@@ -76,9 +76,15 @@ def full_model_geometry(desc, img):
 
 
 def run_case(phantom="uniform", n=256, M=24, count_level="high", modes=("BSREM", "P1", "P2"), n_iter=100,
-             ref_iter=1000, seed=21, targets=(10, 20, 50), full_model=False):
+             ref_iter=1000, seed=21, targets=(10, 20, 50), full_model=False, data=None, keep_images=False):
     """One data set, the given algorithms for n_iter iterations each, against
-    f_inf = BSREM(24) after ref_iter iterations."""
+    f_inf = BSREM(24) after ref_iter iterations.
+
+    data: None (simulate: the phantom projected by this geometry, then the
+    counts model of simulate_sdp_counts), or a dict with the counts ``y``,
+    the background ``r`` (numpy, natural layout) and the bound ``U`` to
+    reconstruct instead.  keep_images: the result also holds ``f_inf`` and
+    each mode's final image (numpy) under ``images``."""
     from synth import configs
     TC = configs.TC_HIGH if count_level == "high" else configs.TC_LOW
     desc, img, rois, rng = make_data(phantom, n, M, TC, seed)
@@ -87,13 +93,16 @@ def run_case(phantom="uniform", n=256, M=24, count_level="high", modes=("BSREM",
         desc, att = full_model_geometry(desc, img)
     G = Geometry(desc, att=att)
     dev = torch.device("cuda")
-    Af = G.forward(torch.tensor(img, dtype=torch.float32, device=dev)).cpu().double().numpy()
-    from synth import phantoms
-    y_np, r_np, scale = phantoms.simulate_sdp_counts(Af, TC, rng, configs.SF, configs.RF)
-    y = torch.tensor(y_np, dtype=torch.float32, device=dev)
-    r = torch.tensor(r_np, dtype=torch.float32, device=dev)
+    if data is None:
+        Af = G.forward(torch.tensor(img, dtype=torch.float32, device=dev)).cpu().double().numpy()
+        from synth import phantoms
+        y_np, r_np, scale = phantoms.simulate_sdp_counts(Af, TC, rng, configs.SF, configs.RF)
+    else:
+        y_np, r_np = data["y"], data["r"]
+    y = torch.tensor(np.asarray(y_np).reshape(G.sino_shape), dtype=torch.float32, device=dev)
+    r = torch.tensor(np.asarray(r_np).reshape(G.sino_shape), dtype=torch.float32, device=dev)
     ones = torch.ones(G.img_shape, dtype=torch.float32, device=dev)
-    U = G.default_U(ones, y, r)
+    U = G.default_U(ones, y, r) if data is None else float(data["U"])
 
     def params(mode, m):
         if phantom == "uniform" and m == 24 and mode in ("BSREM", "P1", "P2") and count_level == "high":
@@ -140,6 +149,8 @@ def run_case(phantom="uniform", n=256, M=24, count_level="high", modes=("BSREM",
                 nr[k].append(nrmsd(fh, f_inf_np, m))
         st.close()
         out["modes"][mode] = {"params": p, "ms_per_iteration": ms_it, "objective": phi, "nrmsd": nr}
+        if keep_images:
+            out.setdefault("images", {"f_inf": f_inf_np})[mode] = f.cpu().double().numpy()
     # iterations to reach BSREM's objective after K iterations
     if "BSREM" in out["modes"]:
         ref = out["modes"]["BSREM"]["objective"]

@@ -222,6 +222,10 @@ int pet_os_batch_add(pet_os_batch* B, const pet_os_geom* g, const pet_os_params*
     const bool need_nu = p->mode == PET_OS_P1 || p->mode == PET_OS_P2;
     rc = work_alloc(g, need_nu, &S.w);
     if (rc) return rc;
+    if ((rc = check_data(g, p, &S.w, f, y, r, st))) {
+        work_free(&S.w);
+        return rc;
+    }
     std::vector<float> step;
     std::vector<int> nu;
     schedule_table(*p, M, S.J_end, step, nu);
@@ -273,8 +277,7 @@ int pet_os_batch_add(pet_os_batch* B, const pet_os_geom* g, const pet_os_params*
     D.eps = (float)p->eps;
     D.nu1 = (float)p->nu1;
     D.nu2 = (float)p->nu2;
-    D.U = (float)p->U;
-    D.t_clip = (float)p->t_clip;
+    D.box = make_box(p->U, p->t_clip);
     D.fp_seg = S.fp_seg;
     D.bp_kind = S.bp_kind;
     if (g->d.dim == 3) {
@@ -503,7 +506,7 @@ static int autotune3(pet_os_geom* g, GeomExtra* ex, int32_t flags, hipStream_t s
     int rc = launch_fill(w, (int64_t)nw, 0.5f, s);
     const int saved_zb = g->tuned_zb, saved_dpg = g->tuned_dpg;
     // the default shape first (its staging group as the default rule picks it)
-    int nb, rw, dpg0, half, lds;
+    int nb = 0, rw = 0, dpg0 = 0, half = 0, lds = 0;
     const int zb0 = bp3_zb(g);
     if (!rc) rc = bp3_shape_single(g, zb0, 0, nb, rw, dpg0, half, lds);
     TunePick pick;

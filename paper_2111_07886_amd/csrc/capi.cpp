@@ -465,6 +465,8 @@ int work_alloc(const pet_os_geom* g, bool need_nu, Work* w) {
     size_t o_red[RED_COUNT];
     for (int r = 0; r < RED_COUNT; ++r) o_red[r] = cv.take<double>((size_t)caps[r]);
     size_t o_tot = cv.take<double>(RED_COUNT);
+    size_t o_chk = cv.take<unsigned>((size_t)CHECK_GRID * 4);
+    size_t o_chkt = cv.take<unsigned long long>(4);
     char* blk = nullptr;
     if (hipMalloc(&blk, cv.off) != hipSuccess) return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc of scratch failed");
     w->bytes = cv.off;
@@ -476,6 +478,8 @@ int work_alloc(const pet_os_geom* g, bool need_nu, Work* w) {
     w->fz = d3 ? (float*)(blk + o_fz) : nullptr;
     w->fsnap = d3 ? nullptr : (float*)(blk + o_snap);
     w->fb = psf ? (float*)(blk + o_fb) : nullptr;
+    w->check_part = (unsigned*)(blk + o_chk);
+    w->check_total = (unsigned long long*)(blk + o_chkt);
     for (int r = 0; r < RED_COUNT; ++r) {
         w->red[r].part = (double*)(blk + o_red[r]);
         w->red[r].total = (double*)(blk + o_tot) + r;
@@ -528,6 +532,52 @@ int validate_params(const pet_os_params* p, const pet_os_geom* g) {
         if (p->J0 < 0 || p->J1 < p->J0) return fail(PET_OS_ERR_INVALID_ARG, "need 0 <= J0 <= J1");
     }
     (void)g;
+    return PET_OS_OK;
+}
+
+// smallest float not below x (x finite, > 0)
+static float float_at_or_above(double x) {
+    float v = (float)x;
+    if ((double)v < x) v = std::nextafter(v, std::numeric_limits<float>::infinity());
+    return v;
+}
+
+BoxK make_box(double U, double t) {
+    BoxK b;
+    b.half_up = float_at_or_above(0.5 * U);
+    b.U_up = float_at_or_above(U);
+    b.U = (float)U;
+    b.t_lo = (float)t;
+    b.t_hi = (float)(U - t);
+    return b;
+}
+
+// The data of the problem statement (Sec. II-A, eq:BoundedSet): counts
+// y >= 0, background r > 0 (gamma in R^p_{++}), initial image f in
+// B = [0, U]^q (OSEM: f >= 0), every entry finite; with the adaptive nu of
+// eq:nuki from the first subiteration (P1/P2, J0 = 0) the mean of f must be
+// > 0 (it divides the gradient magnitude in mu).
+int check_data(const pet_os_geom* g, const pet_os_params* p, Work* w, const float* f, const float* y,
+               const float* r, hipStream_t s) {
+    float f_lim = std::numeric_limits<float>::infinity();
+    if (p->mode != PET_OS_OSEM) {
+        f_lim = (float)p->U;
+        if ((double)f_lim <= p->U) f_lim = std::nextafter(f_lim, std::numeric_limits<float>::infinity());
+    }
+    int rc = launch_check_data(y, r, g->n_bins, f, g->n_vox, f_lim, w->check_part, w->check_total, s);
+    if (rc) return rc;
+    unsigned long long c[4] = {0, 0, 0, 0};
+    PETOS_HIP(hipMemcpyAsync(c, w->check_total, sizeof(c), hipMemcpyDeviceToHost, s));
+    PETOS_HIP(hipStreamSynchronize(s));
+    if (c[0]) return fail(PET_OS_ERR_INVALID_ARG, "y: " + std::to_string(c[0]) + " entries negative or not finite");
+    if (c[1])
+        return fail(PET_OS_ERR_INVALID_ARG, "r: " + std::to_string(c[1]) + " entries not > 0 or not finite");
+    if (c[2])
+        return fail(PET_OS_ERR_INVALID_ARG, "f: " + std::to_string(c[2]) +
+                                                (p->mode == PET_OS_OSEM ? " entries negative or not finite"
+                                                                        : " entries outside [0, U] or not finite"));
+    if ((p->mode == PET_OS_P1 || p->mode == PET_OS_P2) && p->J0 == 0 && c[3] == 0)
+        return fail(PET_OS_ERR_INVALID_ARG, "f: mean must be > 0 when nu is adaptive from the first subiteration");
     return PET_OS_OK;
 }
 
@@ -672,7 +722,7 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
         B.f = st->w.fsnap; B.out = nullptr; B.mu = st->w.mu; B.want_mu = 0;
         B.fnew = f; B.pnorm = g->pnorm; B.nu_frozen = st->w.nu_frozen; B.nu_mode = sc.nu_mode;
         B.step = step; B.nu1 = (float)st->p.nu1; B.nu2 = (float)st->p.nu2;
-        B.U = (float)st->p.U; B.t_clip = (float)st->p.t_clip;
+        B.box = make_box(st->p.U, st->p.t_clip);
         B.part_mu = st->w.red[RED_SUMMU].part; B.n_part_mu = px_grid(g);
         B.red_f = st->w.red[RED_SUMF];
         B.osem_sens = sens_i;
@@ -704,7 +754,7 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
         U.nu_mode = sc.nu_mode;
         U.step = step;
         U.nu1 = (float)st->p.nu1; U.nu2 = (float)st->p.nu2;
-        U.U = (float)st->p.U; U.t_clip = (float)st->p.t_clip;
+        U.box = make_box(st->p.U, st->p.t_clip);
         U.part_mu = st->w.red[RED_SUMMU].part;
         U.n_part_mu = bp_grid(g);
         U.red_f = st->w.red[RED_SUMF];
@@ -814,8 +864,22 @@ int pet_os_state_position(const pet_os_state* st, int64_t* k, int32_t* i) {
     return PET_OS_OK;
 }
 
+// the data check of a state's (f, y, r) buffers, made when they differ from
+// the last ones it accepted
+static int check_state_data(pet_os_state* st, const float* f, const float* y, const float* r, hipStream_t s) {
+    if (st->checked_f == f && st->checked_y == y && st->checked_r == r) return PET_OS_OK;
+    int rc = check_data(st->g, &st->p, &st->w, f, y, r, s);
+    if (rc) return rc;
+    st->checked_f = f;
+    st->checked_y = y;
+    st->checked_r = r;
+    return PET_OS_OK;
+}
+
 int pet_os_subiteration(pet_os_state* st, float* f, const float* y, const float* r, pet_os_stream stream) {
     if (!st || !f || !y || !r) return fail(PET_OS_ERR_INVALID_ARG, "NULL argument");
+    int rc = check_state_data(st, f, y, r, (hipStream_t)stream);
+    if (rc) return rc;
     return run_subiteration(st, f, y, r, (hipStream_t)stream, false);
 }
 
@@ -1097,7 +1161,8 @@ int pet_os_run(pet_os_state* st, float* f, const float* y, const float* r, int32
     if (n_iter < 0) return fail(PET_OS_ERR_INVALID_ARG, "n_iter must be >= 0");
     if (obj && st->p.objective_every < 1) return fail(PET_OS_ERR_INVALID_ARG, "objective_every must be >= 1");
     hipStream_t s = (hipStream_t)stream;
-    int rc;
+    int rc = check_state_data(st, f, y, r, s);
+    if (rc) return rc;
     if (obj && (rc = ensure_obj(st, n_iter + 1))) return rc;
     std::vector<char> have((size_t)n_iter + 1, 0);
     rc = run_iterations(st, f, y, r, n_iter, obj != nullptr, std::max(1, st->p.objective_every), 0, s, have);
@@ -1120,6 +1185,10 @@ int pet_os_reconstruct(const pet_os_geom* g, const pet_os_params* p, float* f, c
     int rc = pet_os_state_create(g, p, &st);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
+    if ((rc = check_state_data(st, f, y, r, s))) {
+        pet_os_state_destroy(st);
+        return rc;
+    }
     std::vector<char> have((size_t)n_iter + 1, 0);
     if (obj) {
         rc = ensure_obj(st, n_iter + 1);
@@ -1264,6 +1333,12 @@ int pet_os_state_import(pet_os_state* st, const void* buf, size_t len) {
     if (len < sizeof(CkptHeader) + (has_nu ? nv * sizeof(float) : 0))
         return fail(PET_OS_ERR_INVALID_ARG, "checkpoint too short");
     if (h.i < 1 || h.i > st->g->d.n_subsets || h.k < 0) return fail(PET_OS_ERR_INVALID_ARG, "bad position");
+    // every value is checked before any field of the state is written
+    int rc = validate_params(&h.params, st->g);
+    if (rc) return rc;
+    if (!(std::isfinite(h.t_nest) && h.t_nest >= 1.0)) return fail(PET_OS_ERR_INVALID_ARG, "t_nest must be >= 1");
+    if (h.have_frozen > 1 || (h.have_frozen && !has_nu))
+        return fail(PET_OS_ERR_INVALID_ARG, "checkpoint marks a frozen nu the state cannot hold");
     if (has_nu) {
         PETOS_HIP(hipDeviceSynchronize());
         PETOS_HIP(hipMemcpy(st->w.nu_frozen, (const char*)buf + sizeof(h), nv * sizeof(float),
@@ -1274,6 +1349,7 @@ int pet_os_state_import(pet_os_state* st, const void* buf, size_t len) {
     st->i = h.i;
     st->t_nest = h.t_nest;
     st->have_frozen = (int)h.have_frozen;
+    st->checked_f = st->checked_y = st->checked_r = nullptr;   // U may differ: check the data again
     return PET_OS_OK;
 }
 

@@ -93,6 +93,8 @@ struct Work {
     double* red_block = nullptr;   // reductions' storage
     Reduction red[RED_COUNT];
     int* angle_list = nullptr;     // device copy of all subset angle lists [M][max_sub]
+    unsigned* check_part = nullptr;            // data check: per-block counts [CHECK_GRID][4]
+    unsigned long long* check_total = nullptr; // data check: the four totals
     size_t bytes = 0;
 };
 
@@ -117,6 +119,8 @@ Sched sched_next(const pet_os_params& p, int M, int64_t k, int i, double* t_nest
 // (float)(lambda alpha) and nu mode of subiterations J = 1..n_sub from the start
 void schedule_table(const pet_os_params& p, int M, int64_t n_sub, std::vector<float>& step, std::vector<int>& nu);
 int validate_params(const pet_os_params* p, const pet_os_geom* g);
+// FP32 thresholds and clamp values of the box B for bound U and clamp t
+BoxK make_box(double U, double t);
 int validate_desc(const pet_os_geom_desc* d);
 
 // ---------------------------------------------------------------- launchers (kernels.hip)
@@ -166,7 +170,8 @@ struct BPLaunch {
     const float* pnorm = nullptr;
     float* nu_frozen = nullptr;
     int nu_mode = 0;
-    float step = 0, nu1 = 0, nu2 = 0, U = 0, t_clip = 0;
+    float step = 0, nu1 = 0, nu2 = 0;
+    BoxK box{};
     const double* part_mu = nullptr;   // partials of sum mu from the pixel pass
     int n_part_mu = 0;
     Reduction red_f{};                 // partials of sum of the new iterate
@@ -189,7 +194,8 @@ struct UpdLaunch {
     float* nu_frozen;
     int nu_mode;
     float step;              // lambda_k * alpha_{k,i}
-    float nu1, nu2, U, t_clip;
+    float nu1, nu2;
+    BoxK box;
     const double* part_mu;   // partials of sum mu (from the back-projection)
     int n_part_mu;
     Reduction red_f;         // sum of the new iterate
@@ -198,6 +204,17 @@ struct UpdLaunch {
 int launch_update(const pet_os_geom* g, const UpdLaunch& L, hipStream_t s);
 
 int launch_sum(const float* x, int64_t n, Reduction red, hipStream_t s);
+// data check of Sec. II-A (kernels.hip): counts of y entries that are negative
+// or not finite, r entries not > 0 or not finite, f entries outside [0, U]
+// (f_lim: the smallest float above U) or not finite, and positive f entries,
+// into total[4]; part holds CHECK_GRID * 4 block counts
+constexpr int CHECK_GRID = 1024;
+int launch_check_data(const float* y, const float* r, int64_t nb, const float* f, int64_t nv, float f_lim,
+                      unsigned* part, unsigned long long* total, hipStream_t s);
+// the data check of one request on its scratch; synchronises the stream and
+// returns INVALID_ARG with the rule that failed (capi.cpp)
+int check_data(const pet_os_geom* g, const pet_os_params* p, Work* w, const float* f, const float* y,
+               const float* r, hipStream_t s);
 int launch_rdp_value(const pet_os_geom* g, const float* f, float gamma_R, float eps, Reduction red,
                      hipStream_t s);
 int launch_fill(float* x, int64_t n, float v, hipStream_t s);
@@ -269,7 +286,8 @@ struct SlotDev {
     const float* sched_step;   // [J_end] lambda_k alpha_{k,i} of subiteration J (index J-1)
     const int* sched_nu;       // [J_end] nu mode of subiteration J
     int J, J_end;              // next subiteration (device-advanced), last one
-    float beta_over_M, gamma_R, eps, nu1, nu2, U, t_clip;
+    float beta_over_M, gamma_R, eps, nu1, nu2;
+    BoxK box;
     int fp_seg, bp_kind;
     int nb_max, rows_max, chunk;   // back-projector staging (3D: bins, rows, ring differences per group)
     int zb;                        // 3D: slices per back-projection block
@@ -316,5 +334,9 @@ struct pet_os_state {
     int prof_kernel = -1;               // kernel bracketed by events, -1 = none
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
     size_t prof_used = 0;
+    // the (f, y, r) buffers whose data last passed the check of Sec. II-A
+    const float* checked_f = nullptr;
+    const float* checked_y = nullptr;
+    const float* checked_r = nullptr;
 };
 

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 
 #include "devutil.h"
@@ -241,7 +242,8 @@ struct BPArgs {
     const float* pnorm;
     float* nu_frozen;
     int nu_mode;
-    float step, nu1, nu2, U, t_clip;
+    float step, nu1, nu2;
+    BoxK box;
     const double* part_mu;
     int n_part_mu;
     Reduction red_f;
@@ -254,7 +256,7 @@ struct BPArgs {
 // nu_in the frozen nu of the voxel when it is reused
 __device__ __forceinline__ float sdp_update(float fj, float Gj, float pj, float muj, float meanmu, float nu_in,
                                             float* nu_frozen, long long j, int nu_mode, float step, float nu1,
-                                            float nu2, float U, float t_clip) {
+                                            float nu2, const BoxK& box) {
     float nu = 1.0f;
     if (nu_mode == NU_COMPUTE || nu_mode == NU_COMPUTE_FREEZE) {
         nu = fminf(nu2, fmaxf(nu1, meanmu / muj));
@@ -262,9 +264,7 @@ __device__ __forceinline__ float sdp_update(float fj, float Gj, float pj, float 
     } else if (nu_mode == NU_FROZEN) {
         nu = nu_in;
     }
-    const float S = (fj < 0.5f * U) ? fj / pj : (U - fj) / pj;
-    const float ft = fj - step * nu * S * Gj;
-    return (ft <= 0.0f) ? t_clip : ((ft >= U) ? U - t_clip : ft);
+    return box_step(box, fj, pj, step, nu, Gj);
 }
 
 // Per-pixel inputs of the update (p, mu, frozen nu, OSEM sensitivity), read
@@ -310,7 +310,7 @@ __device__ __forceinline__ double pixel_finish(const GeoK& g, const BPArgs& A, c
     } else if (A.fnew != nullptr) {
         const float fj = s_f[(ly + 1) * HX + lx + 1];
         const float fn = sdp_update(fj, Gj, pre.p, pre.mu, meanmu, pre.nu, A.nu_frozen, j, A.nu_mode, A.step,
-                                    A.nu1, A.nu2, A.U, A.t_clip);
+                                    A.nu1, A.nu2, A.box);
         A.fnew[j] = fn;
         part = (double)fn;
     } else {
@@ -1018,8 +1018,7 @@ static void fill_bp_args(const pet_os_geom* G, const BPLaunch& L, BPArgs& a) {
     a.step = L.step;
     a.nu1 = L.nu1;
     a.nu2 = L.nu2;
-    a.U = L.U;
-    a.t_clip = L.t_clip;
+    a.box = L.box;
     a.part_mu = L.part_mu;
     a.n_part_mu = L.n_part_mu;
     a.red_f = L.red_f;
@@ -1083,6 +1082,63 @@ int launch_upd2(const pet_os_geom* G, const BPLaunch& L, const float* Gb, bool b
     else if (large) hipLaunchKernelGGL((k_upd2<Tile2L, false>), dim3(grid), dim3(NT), 0, s, G->k, a, Gb);
     else if (blur) hipLaunchKernelGGL((k_upd2<Tile2S, true>), dim3(grid), dim3(NT), 0, s, G->k, a, Gb);
     else hipLaunchKernelGGL((k_upd2<Tile2S, false>), dim3(grid), dim3(NT), 0, s, G->k, a, Gb);
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
+}
+
+// ------------------------------------------------------------------ data check
+// The data of the problem statement (Sec. II-A): counts g >= 0, background
+// gamma > 0 elementwise, and an initial image in the box B of eq:BoundedSet,
+// every value finite.  Each block counts the entries that break a rule
+// ([0] y, [1] r, [2] f) and the positive entries of f ([3]) over a
+// grid-stride range; k_check_total adds the block counts in block order.
+// f_lim is the smallest float above U (f <= U exactly when f < f_lim).
+__global__ __launch_bounds__(NT) void k_check_data(const float* __restrict__ y, const float* __restrict__ r,
+                                                   long long nb, const float* __restrict__ f, long long nv,
+                                                   float f_lim, unsigned* __restrict__ part) {
+    __shared__ unsigned s_c[4];
+    if (threadIdx.x < 4) s_c[threadIdx.x] = 0u;
+    __syncthreads();
+    unsigned c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+    const long long stride = (long long)gridDim.x * NT;
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < nb; i += stride) {
+        const float yv = y[i], rv = r[i];
+        c0 += (yv >= 0.0f && yv <= FLT_MAX) ? 0u : 1u;     // false for NaN
+        c1 += (rv > 0.0f && rv <= FLT_MAX) ? 0u : 1u;
+    }
+    for (long long j = (long long)blockIdx.x * NT + threadIdx.x; j < nv; j += stride) {
+        const float fv = f[j];
+        c2 += (fv >= 0.0f && fv < f_lim && fv <= FLT_MAX) ? 0u : 1u;
+        c3 += (fv > 0.0f) ? 1u : 0u;
+    }
+    atomicAdd(&s_c[0], c0);
+    atomicAdd(&s_c[1], c1);
+    atomicAdd(&s_c[2], c2);
+    atomicAdd(&s_c[3], c3);
+    __syncthreads();
+    if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = s_c[threadIdx.x];
+}
+
+__global__ __launch_bounds__(NT) void k_check_total(const unsigned* __restrict__ part, int n_blocks,
+                                                    unsigned long long* __restrict__ total) {
+    __shared__ unsigned long long s_t[4];
+    if (threadIdx.x < 4) s_t[threadIdx.x] = 0ull;
+    __syncthreads();
+    unsigned long long t[4] = {0ull, 0ull, 0ull, 0ull};
+    for (int b = threadIdx.x; b < n_blocks; b += NT)
+        for (int k = 0; k < 4; ++k) t[k] += part[b * 4 + k];
+    for (int k = 0; k < 4; ++k) atomicAdd(&s_t[k], t[k]);
+    __syncthreads();
+    if (threadIdx.x < 4) total[threadIdx.x] = s_t[threadIdx.x];
+}
+
+int launch_check_data(const float* y, const float* r, int64_t nb, const float* f, int64_t nv, float f_lim,
+                      unsigned* part, unsigned long long* total, hipStream_t s) {
+    const int64_t n = std::max(nb, nv);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(CHECK_GRID, (n + NT - 1) / NT));
+    hipLaunchKernelGGL(k_check_data, dim3(grid), dim3(NT), 0, s, y, r, (long long)nb, f, (long long)nv, f_lim,
+                       part);
+    hipLaunchKernelGGL(k_check_total, dim3(1), dim3(NT), 0, s, (const unsigned*)part, grid, total);
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;
 }
@@ -1230,8 +1286,7 @@ __global__ __launch_bounds__(NT, 7) void k_bp_batch(const SlotDev* __restrict__ 
         A.step = d.sched_step[d.J - 1];
         A.nu1 = d.nu1;
         A.nu2 = d.nu2;
-        A.U = d.U;
-        A.t_clip = d.t_clip;
+        A.box = d.box;
         A.part_mu = d.part_mu;
         A.n_part_mu = d.n_part_mu;
         A.red_f.part = d.part_f;

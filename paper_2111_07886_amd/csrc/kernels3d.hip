@@ -601,7 +601,8 @@ struct Upd3Args {
     const float* pnorm;
     float* nu_frozen;
     int nu_mode;
-    float step, nu1, nu2, U, t_clip;
+    float step, nu1, nu2;
+    BoxK box;
     const double* part_mu;
     int n_part_mu;
     Reduction red_f;
@@ -651,9 +652,7 @@ __device__ void upd3_body(const Upd3Args& A, long long vblock, bool update) {
                 } else if (A.nu_mode == NU_FROZEN) {
                     nu = A.nu_frozen[j];
                 }
-                const float S = (fj < 0.5f * A.U) ? fj / pj : (A.U - fj) / pj;
-                const float ft = fj - A.step * nu * S * Gj;
-                const float fn = (ft <= 0.0f) ? A.t_clip : ((ft >= A.U) ? A.U - A.t_clip : ft);
+                const float fn = box_step(A.box, fj, pj, A.step, nu, Gj);
                 A.f[j] = fn;
                 v = fn;
             } else {
@@ -842,8 +841,7 @@ static void fill_upd3(const pet_os_geom* G, const UpdLaunch& L, Upd3Args& a) {
     a.step = L.step;
     a.nu1 = L.nu1;
     a.nu2 = L.nu2;
-    a.U = L.U;
-    a.t_clip = L.t_clip;
+    a.box = L.box;
     a.part_mu = L.part_mu;
     a.n_part_mu = L.n_part_mu;
     a.red_f = L.red_f;
@@ -965,8 +963,7 @@ __global__ __launch_bounds__(NT) void k_upd3_batch(const SlotDev* __restrict__ S
         A.step = d.sched_step[d.J - 1];
         A.nu1 = d.nu1;
         A.nu2 = d.nu2;
-        A.U = d.U;
-        A.t_clip = d.t_clip;
+        A.box = d.box;
         A.part_mu = d.part_mu;
         A.n_part_mu = d.n_part_mu;
         A.red_f.part = d.part_f;

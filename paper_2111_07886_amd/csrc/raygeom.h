@@ -80,6 +80,30 @@ struct GeoK {
     const float* psf;       // PSF taps: [2 psf_kx + 1] along x, then [2 psf_ky + 1] along y
 };
 
+// The box B = {0 <= f <= U} of eq:BoundedSet as the FP32 update applies it.
+// The branch of S (eq:preconditioner: f < U/2 or not) and of P_t
+// (eq:OperatorPt: f~ >= U or not) is taken by comparing an FP32 value with
+// U/2 and with U.  half_up and U_up are the smallest floats not below U/2 and
+// U, so that for every float x, x < half_up exactly when x < U/2 and
+// x >= U_up exactly when x >= U: both comparisons decide as they would
+// against the FP64 bound (made on the host by make_box).
+struct BoxK {
+    float half_up;   // smallest float >= U/2
+    float U_up;      // smallest float >= U
+    float U;         // U rounded to nearest: the value in (U - f) / p
+    float t_lo;      // t of P_t (0 < t < U)
+    float t_hi;      // U - t, formed in FP64 and rounded once
+};
+
+// S_jj of eq:preconditioner, the relaxed step f~ = f - c nu S G of Table I
+// (c = lambda_k alpha_{k,i}) and the projection P_t of eq:OperatorPt at one
+// voxel: f~ <= 0 gives t, f~ >= U gives U - t, anything else is kept.
+__device__ __forceinline__ float box_step(const BoxK& B, float fj, float pj, float c, float nu, float Gj) {
+    const float S = (fj < B.half_up) ? fj / pj : (B.U - fj) / pj;
+    const float ft = fj - c * nu * S * Gj;
+    return (ft <= 0.0f) ? B.t_lo : ((ft >= B.U_up) ? B.t_hi : ft);
+}
+
 struct TxRay {
     double P, Q, invQ, L;
     int row_major;

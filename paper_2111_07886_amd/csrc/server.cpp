@@ -159,7 +159,7 @@ struct SimExecutor : Executor {
     int max_slots;
     std::vector<int> used;
     int64_t step_us = 50;
-    int fail_add = 0, fail_step = 0, nan_objective = 0;
+    int fail_add = 0, fail_step = 0, nan_objective = 0, bad_data = 0;
     explicit SimExecutor(int ms) : max_slots(ms), used(ms, 0) {}
     int geometry(const pet_os_geom_desc& d, void** g, size_t* bytes) override {
         *g = new pet_os_geom_desc(d);
@@ -169,6 +169,7 @@ struct SimExecutor : Executor {
     void drop_geometry(void* g) override { delete (pet_os_geom_desc*)g; }
     int add(void*, const pet_os_request&, int* slot) override {
         if (fail_add > 0) { --fail_add; return fail(PET_OS_ERR_OUT_OF_MEMORY, "injected: out of memory on admission"); }
+        if (bad_data > 0) { --bad_data; return fail(PET_OS_ERR_INVALID_ARG, "injected: r: 1 entries not > 0 or not finite"); }
         for (int s = 0; s < max_slots; ++s)
             if (!used[s]) { used[s] = 1; *slot = s; return PET_OS_OK; }
         return fail(PET_OS_ERR_BUDGET, "no free slot");
@@ -526,6 +527,7 @@ int pet_os_server_inject(pet_os_server* S, int32_t kind, int32_t count) {
         case PET_OS_INJECT_ADMIT_OOM: S->sim->fail_add += count; break;
         case PET_OS_INJECT_STEP_FAILURE: S->sim->fail_step += count; break;
         case PET_OS_INJECT_NAN_OBJECTIVE: S->sim->nan_objective += count; break;
+        case PET_OS_INJECT_BAD_DATA: S->sim->bad_data += count; break;
         default: return fail(PET_OS_ERR_INVALID_ARG, "unknown fault kind");
     }
     return PET_OS_OK;

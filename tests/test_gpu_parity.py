@@ -153,10 +153,14 @@ def workload(name, orc):
     return w, configs.params_2d(d["n_subsets"], 3e5, U=w.U), 4
 
 
-def stepwise(pet, orc, w, p, samples, tol=1e-5, tune=False):
+def stepwise(pet, orc, w, p, samples, tol=1e-5, tune=False, branches=None, label=None):
     """One GPU subiteration from the oracle's own state (iterate cast to FP32,
     position, Nesterov t, frozen nu) at each sampled J, against one oracle
-    subiteration from the same FP32 input (tune: shapes from the autotuner)."""
+    subiteration from the same FP32 input (tune: shapes from the autotuner).
+    branches: a dict that receives, over the samples, the number of voxels
+    whose entering value takes the upper branch of S (f >= U/2,
+    eq:preconditioner) and the number the oracle's P_t sends to U - t or to t
+    (eq:OperatorPt)."""
     G = pet.Geometry(full_desc(w.desc))
     if tune:
         pet.autotune(G)
@@ -164,6 +168,7 @@ def stepwise(pet, orc, w, p, samples, tol=1e-5, tune=False):
     y, r = dev(w.y), dev(w.r)
     rec = orc.Recon(orc.geom(w.desc), orc.params(p), w.f0, host(y), host(r))
     worst = 0.0
+    U, t = p["U"], p["t_clip"]
     for J in range(1, max(samples) + 1):
         if J in samples:
             fin = f32(rec.f)
@@ -174,10 +179,33 @@ def stepwise(pet, orc, w, p, samples, tol=1e-5, tune=False):
             st.seek(rec.st.k, rec.st.i, rec.st.t_nest, nu)
             fg = dev(fin.reshape(G.img_shape))
             st.subiteration(fg, y, r)
-            e = rel(host(fg), ref.image())
+            got = host(fg)
+            e = rel(got, ref.image())
             worst = max(worst, e)
             assert e <= tol, (J, e)
+            if branches is not None:
+                fo = ref.image().reshape(-1)
+                branches["upper"] = branches.get("upper", 0) + int((fin >= 0.5 * U).sum())
+                branches["clamp_hi"] = branches.get("clamp_hi", 0) + int((fo == U - t).sum())
+                branches["clamp_lo"] = branches.get("clamp_lo", 0) + int((fo == t).sum())
+                # the voxels the GPU sends to U - t (FP32 value of U - t); P_t
+                # decides on f~, which FP32 and FP64 round differently, so a
+                # voxel may be clamped on one side only when the other side's
+                # value lies within rounding of the threshold U
+                hi = float(np.float32(U - t))
+                gv = got.reshape(-1)
+                gh = gv == hi
+                oh = fo == U - t
+                branches["clamp_hi_gpu"] = branches.get("clamp_hi_gpu", 0) + int(gh.sum())
+                branches["clamp_hi_differ"] = branches.get("clamp_hi_differ", 0) + int((gh != oh).sum())
+                near = 1e-5 * U
+                assert np.all(fo[gh & ~oh] >= U - t - near), (J, fo[gh & ~oh])
+                assert np.all(gv[oh & ~gh] >= U - t - near), (J, gv[oh & ~gh])
         rec.subiteration()
+    from parity_record import record
+    label = label or f"{w.desc['dim']}D {w.desc['nx']}x{w.desc['ny']}x{w.desc.get('nz', 1)} {p['mode']}"
+    record("stepwise", label,
+           samples=len(samples), worst_rel_l2=worst, tol=tol, U=U, **(branches or {}))
     return worst
 
 
@@ -190,8 +218,79 @@ def test_stepwise_c1_every_subiteration(pet, orc, mode):
     p = configs.params_2d(4, 1e5, mode=mode, U=w.U)
     p.update(J0=2, J1=6)
     say(f"stepwise C1 {mode}")
-    worst = stepwise(pet, orc, w, p, set(range(1, 4 * n_iter + 1)))
+    worst = stepwise(pet, orc, w, p, set(range(1, 4 * n_iter + 1)), label=f"C1 {mode}")
     say(f"stepwise C1 {mode}: worst one-step rel-L2 {worst:.2e}")
+
+
+SMALL_U = 2.0   # U as a multiple of max f_true: iterates cross U/2 and reach U
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_stepwise_small_U_2d(pet, orc, tmp_path, monkeypatch, kind):
+    """The upper branch of S (eq:preconditioner: (U - f)/p for f >= U/2) and
+    the upper clamp of P_t (eq:OperatorPt: f~ >= U gives U - t) on the GPU:
+    the 64^2 workload in SDP-P2 with U = 2 max f_true, every subiteration of
+    its 10 iterations from the oracle's state, with each back-projector tile
+    (16x16; 8x8 with four angle groups) pinned through the tuning cache."""
+    from synth import configs
+    w, _, n_iter = configs.c1()
+    U = SMALL_U * float(w.f_true.max())
+    p = configs.params_2d(4, 1e5, mode="P2", U=U)
+    p.update(J0=2, J1=6)
+    d = full_desc(w.desc)
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{tune_key(d)}|16 {kind}\n")
+    monkeypatch.setenv("PET_OS_TUNE_CACHE", str(cache))
+    say(f"stepwise small U 2D kind {kind}")
+    br = {}
+    worst = stepwise(pet, orc, w, p, set(range(1, 4 * n_iter + 1)), tune=True, branches=br,
+                     label=f"C1 P2 U = 2 max f, tile kind {kind}")
+    say(f"stepwise small U 2D kind {kind}: worst {worst:.2e}, branches {br}")
+    assert br["upper"] > 100 and br["clamp_hi"] > 10 and br["clamp_hi_gpu"] > 10
+
+
+@pytest.mark.parametrize("name", ["3d_small", "3d_ragged"])
+def test_stepwise_small_U_3d(pet, orc, name):
+    """As above on the 3D update kernel (U = 2 max f_true, SDP-P2 of Table III)."""
+    from synth import configs
+    w, _, n_iter = workload(name, orc)
+    p = configs.params_3d(U=SMALL_U * float(w.f_true.max()))
+    M = w.desc["n_subsets"]
+    say(f"stepwise small U {name}")
+    br = {}
+    worst = stepwise(pet, orc, w, p, set(range(1, n_iter * M + 1)), branches=br, label=f"{name} P2 U = 2 max f")
+    say(f"stepwise small U {name}: worst {worst:.2e}, branches {br}")
+    assert br["upper"] > 100 and br["clamp_hi"] > 5 and br["clamp_hi_gpu"] > 5
+
+
+def test_box_clamps_decide_as_fp64(pet, orc):
+    """P_t (eq:OperatorPt) compares the FP32 step result with U as the FP64
+    comparison does, also for a U that is not a float.  With a vanishing
+    step (lambda0 = 1e-30) f~ = f exactly on both sides, so a voxel at the
+    float 3.0 just below U = 3 + 2^-30 is kept (rounding U to the nearest
+    float would clamp it to U - t), a voxel at 0 goes to t, and every voxel
+    of the GPU result equals the oracle's rounded to FP32."""
+    from synth import configs
+    w, _, _ = configs.c1()
+    U = 3.0 + 2.0 ** -30
+    assert float(np.float32(U)) == 3.0 < U
+    p = configs.params_2d(4, 1e5, mode="BSREM", U=U)
+    p.update(lambda0=1e-30)
+    f0 = np.full(w.f0.shape, 1.0)
+    f0[20:40, 10:50] = 3.0
+    f0[41:44, 10:50] = 0.0
+    f0[45:48, 10:50] = float(np.nextafter(np.float32(1.5), np.float32(0)))
+    G = pet.Geometry(full_desc(w.desc))
+    y, r = dev(w.y), dev(w.r)
+    st = pet.State(G, p)
+    fg = dev(f0)
+    st.subiteration(fg, y, r)
+    ref = orc.Recon(orc.geom(w.desc), orc.params(p), f32(f0), host(y), host(r))
+    ref.subiteration()
+    got, fo = host(fg).reshape(-1), ref.f
+    assert np.all(fo[(f0 == 3.0).reshape(-1)] == 3.0)
+    assert np.all(fo[(f0 == 0.0).reshape(-1)] == p["t_clip"])
+    assert np.array_equal(got, f32(fo))
 
 
 def test_stepwise_c2_full_size(pet, orc):
@@ -202,7 +301,7 @@ def test_stepwise_c2_full_size(pet, orc):
     w, p, n_iter = configs.c2()
     samples = set(range(1, 49)) | {97, 240, 480, 720, 960, 999, 1000, 1001, 1002, 1100, 1199, 1200}
     say("stepwise C2")
-    worst = stepwise(pet, orc, w, p, samples)
+    worst = stepwise(pet, orc, w, p, samples, label="C2 256^2 P2")
     say(f"stepwise C2: worst one-step rel-L2 {worst:.2e}")
 
 
@@ -217,36 +316,54 @@ def test_stepwise_other_geometries(pet, orc, name):
 NOISE = 5e-7   # size of the FP32 evaluation error of one subiteration (stepwise tests: 1e-7 .. 1e-6)
 
 
-def intrinsic_spread(orc, w, p, n_iter, seeds=(0, 1)):
+def intrinsic_spread(orc, w, p, n_iter, seeds=(0, 1), per_iteration=False):
     """Sensitivity of the method itself: the FP64 oracle against the same FP64
     oracle perturbed after every subiteration by relative noise of the size of
     one FP32 subiteration's evaluation error.  Returns the largest image
-    rel-L2 and objective relative difference."""
+    rel-L2 and objective relative difference after n_iter iterations (with
+    per_iteration, the objective's after each of the n_iter iterations, as a
+    list)."""
     g, P = orc.geom(w.desc), orc.params(p)
     y, r = f32(w.y), f32(w.r)
     M = w.desc["n_subsets"]
     clean = orc.Recon(g, P, w.f0, y, r)
-    for _ in range(n_iter * M):
-        clean.subiteration()
-    phi = clean.objective()
-    e_img, e_obj = 0.0, 0.0
+    phis = []
+    for k in range(n_iter):
+        for _ in range(M):
+            clean.subiteration()
+        if per_iteration or k == n_iter - 1:
+            phis.append(clean.objective())
+    e_img, e_obj = 0.0, [0.0] * len(phis)
     for sd in seeds:
         rng = np.random.default_rng(sd)
         noisy = orc.Recon(g, P, w.f0, y, r)
-        for _ in range(n_iter * M):
-            noisy.subiteration()
-            noisy.f *= 1.0 + NOISE * rng.standard_normal(noisy.f.shape)
+        n_obj = 0
+        for k in range(n_iter):
+            for _ in range(M):
+                noisy.subiteration()
+                noisy.f *= 1.0 + NOISE * rng.standard_normal(noisy.f.shape)
+            if per_iteration or k == n_iter - 1:
+                e_obj[n_obj] = max(e_obj[n_obj], abs(noisy.objective() - phis[n_obj]) / abs(phis[n_obj]))
+                n_obj += 1
         e_img = max(e_img, rel(noisy.f, clean.f))
-        e_obj = max(e_obj, abs(noisy.objective() - phi) / abs(phi))
-    return e_img, e_obj
+    return e_img, (e_obj if per_iteration else e_obj[-1])
+
+
+TOL_IMG, TOL_OBJ = 1e-4, 1e-6    # stated: image after the configured iterations, objective
+IMG_PARITY_LIMIT = 1e-2           # above this a widened image tolerance pins nothing: not asserted
 
 
 def check_trajectory(pet, orc, w, p, n_iter, label):
-    """Image after the configured iterations and the objective trace against
-    the oracle: within the stated 1e-4 (image) / 1e-6 (objective) where the
-    method is well conditioned, else within 5x the method's own sensitivity
-    to perturbations of the size of one FP32 subiteration (measured on the
-    oracle)."""
+    """Image after the configured iterations and the objective against the
+    oracle's trajectory.  The tolerance applied is the stated one (1e-4 image,
+    1e-6 objective) or, where the method itself separates two trajectories
+    by more (measured on the oracle: FP64 against FP64 perturbed by noise of
+    the size of one FP32 subiteration's error), 5x that spread.  An image
+    tolerance widened beyond 1e-2 would pin nothing, so such an image is only
+    recorded (the stepwise tests are that workload's parity evidence); the
+    objective is asserted in every case.  Each case is recorded
+    (parity_record) with its errors, spreads and applied tolerances."""
+    from parity_record import record
     G = pet.Geometry(full_desc(w.desc))
     f = dev(w.f0)
     y, r = dev(w.y), dev(w.r)
@@ -256,11 +373,17 @@ def check_trajectory(pet, orc, w, p, n_iter, label):
     e = rel(host(f), fo)
     eo = abs(obj[-1] - objo[-1]) / abs(objo[-1])
     s_img, s_obj = intrinsic_spread(orc, w, p, n_iter)
-    tol_img = 1e-4 if s_img < 1e-5 else 5.0 * s_img
-    tol_obj = 1e-6 if s_obj < 1e-7 else 5.0 * s_obj
-    say(f"trajectory {label}: image rel-L2 {e:.2e} (spread {s_img:.2e}, tol {tol_img:.1e}); "
-        f"objective {eo:.2e} (spread {s_obj:.2e}, tol {tol_obj:.1e})")
-    assert e <= tol_img
+    tol_img = max(TOL_IMG, 5.0 * s_img)
+    tol_obj = max(TOL_OBJ, 5.0 * s_obj)
+    img_asserted = tol_img <= IMG_PARITY_LIMIT
+    say(f"trajectory {label}: image rel-L2 {e:.2e} (spread {s_img:.2e}, tol {tol_img:.1e}"
+        f"{'' if img_asserted else ', not asserted'}); objective {eo:.2e} (spread {s_obj:.2e}, tol {tol_obj:.1e})")
+    record("trajectory", label, n_iter=n_iter, image_rel_l2=e, image_spread=s_img, image_tol=tol_img,
+           image_face_value=tol_img == TOL_IMG, image_asserted=img_asserted, objective_rel=eo,
+           objective_spread=s_obj, objective_tol=tol_obj, objective_face_value=tol_obj == TOL_OBJ,
+           mode=p["mode"])
+    if img_asserted:
+        assert e <= tol_img
     assert eo <= tol_obj
     return e, s_img
 

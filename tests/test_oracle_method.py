@@ -342,3 +342,33 @@ def test_objective_decreases_to_minimum(orc):
     assert obj[-1] >= phistar - 1e-9 * abs(phistar)
     assert abs(obj[-1] - phistar) <= 1e-8 * abs(phistar)
     assert np.all(np.diff(obj[200:]) <= 1e-9 * abs(phistar))
+
+
+# ---------------------------------------------------------------- default U
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_default_U_by_hand(orc, dim):
+    """The default box bound (the paper only proves U exists, eq:BoundedSet)
+    is 1e3 max(max f0, (sum y - sum r)_+ / sum_j (A^T 1)_j), the sensitivity
+    summed over every ray, computed here from the brute-force matrix: each
+    branch of the max, and the clipped count excess."""
+    g = g2(orc, n=6, na=8, nr=9, M=4) if dim == 2 else g3(orc, n=4, nz=3, na=4, nr=7, M=2)
+    A = dense_A(orc, g)
+    s_tot = A.sum()                      # sum_j (A^T 1)_j over every ray of every subset
+    rng = np.random.default_rng(17)
+    nb, nv = A.shape
+    r = rng.uniform(0.5, 1.5, nb)
+    # count excess dominates: (sum y - sum r) / sum s exceeds max f0
+    f0 = rng.uniform(0.1, 0.5, nv)
+    y = rng.uniform(20.0, 40.0, nb)
+    chat = (y.sum() - r.sum()) / s_tot
+    assert chat > f0.max()
+    assert abs(orc.default_U(g, f0, y, r) - 1e3 * chat) <= 1e-12 * 1e3 * chat
+    # max f0 dominates
+    f0b = f0.copy()
+    f0b[3] = 10.0 * chat
+    assert orc.default_U(g, f0b, y, r) == 1e3 * f0b.max()
+    # fewer counts than background: the excess is clipped at 0
+    y0 = 0.1 * r
+    assert orc.default_U(g, f0, y0, r) == 1e3 * f0.max()

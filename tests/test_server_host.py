@@ -123,6 +123,27 @@ def test_injected_admission_failure_hits_one_request(pet):
     S.close()
 
 
+def test_bad_data_fails_only_its_request(pet):
+    """A request whose data fail the admission check of Sec. II-A (here an
+    injected r <= 0) ends with INVALID_ARG; requests queued before and after
+    it, and those running beside it, complete."""
+    S = pet.Server(1 << 40, 2, simulate=True, step_us=500)
+    d, p = req(64, M=4)
+    a = S.submit(d, p, n_iter=3)
+    while S.stats()["active"] == 0:
+        time.sleep(0.001)
+    S.inject("bad_data", 1)
+    ts = [S.submit(d, p, n_iter=1) for _ in range(3)]
+    ra = S.wait(a)
+    res = [S.wait(t) for t in ts]
+    assert ra["status"] == 0 and ra["subiterations"] == 12
+    assert [r["status"] for r in res] == [-1, 0, 0]
+    assert "r:" in res[0]["message"] and res[0]["subiterations"] == 0
+    st = S.stats()
+    assert st["active"] == 0 and st["queued"] == 0
+    S.close()
+
+
 def test_injected_step_failure_fails_running_only(pet):
     S = pet.Server(1 << 40, 4, simulate=True, step_us=5000)
     d, p = req(64, M=4)
