@@ -35,7 +35,7 @@ EXPORTS = ["pet_os_last_error", "pet_os_version", "pet_os_create_geometry", "pet
            "pet_os_batch_run", "pet_os_batch_slot_status", "pet_os_batch_bytes", "pet_os_reconstruct_batch",
            "pet_os_autotune", "pet_os_server_create", "pet_os_server_destroy", "pet_os_submit", "pet_os_wait",
            "pet_os_cancel", "pet_os_server_stats", "pet_os_server_create_simulated", "pet_os_server_inject",
-           "pet_os_geometry_shapes"]
+           "pet_os_geometry_shapes", "pet_os_reconstruct_noalloc"]
 
 
 class PetOSError(RuntimeError):
@@ -114,6 +114,7 @@ def lib():
             "pet_os_subiteration": (C.c_int, [_P, _P, _P, _P, _P]),
             "pet_os_reconstruct": (C.c_int, [_P, C.POINTER(Params), _P, _P, _P, i32,
                                              C.POINTER(C.c_double), _P]),
+            "pet_os_reconstruct_noalloc": (C.c_int, [_P, C.POINTER(Params), _P, _P, _P, i32, _P]),
             "pet_os_state_export": (C.c_int, [_P, _P, C.POINTER(C.c_size_t)]),
             "pet_os_state_import": (C.c_int, [_P, _P, C.c_size_t]),
             "pet_os_run": (C.c_int, [_P, _P, _P, _P, i32, C.POINTER(C.c_double), _P]),
@@ -411,6 +412,19 @@ def reconstruct(geom: Geometry, params: dict, f, y, r, n_iter: int, want_objecti
                                     _dev(y, geom.n_bins, "y"), _dev(r, geom.n_bins, "r"), int(n_iter),
                                     obj, _stream(stream)))
     return list(obj) if want_objective else None
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20      # PET_OS_NOALLOC_SCRATCH_BYTES
+
+
+def reconstruct_noalloc(geom: Geometry, params: dict, f, y, r, n_iter: int, stream=None):
+    """pet_os_reconstruct_noalloc: pet_os_reconstruct without objectives, with
+    the request's scratch in the library's static device array (no device
+    allocation); n_iter iterations in place on f."""
+    p = params_struct(params)
+    _check(lib().pet_os_reconstruct_noalloc(geom.handle, C.byref(p), _dev(f, geom.n_voxels, "f"),
+                                            _dev(y, geom.n_bins, "y"), _dev(r, geom.n_bins, "r"), int(n_iter),
+                                            _stream(stream)))
 
 
 class Batch:

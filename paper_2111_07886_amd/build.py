@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpet_os.so")
-SOURCES = ["kernels.hip", "kernels3d.hip", "diag.hip", "capi.cpp", "batch.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "kernels3d.hip", "diag.hip", "capi.cpp", "batch.cpp", "server.cpp", "noalloc.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

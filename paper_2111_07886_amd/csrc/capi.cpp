@@ -441,55 +441,92 @@ int pet_os_sensitivity(const pet_os_geom* g, float* out, pet_os_stream stream) {
 
 namespace petos {
 
-int work_alloc(const pet_os_geom* g, bool need_nu, Work* w) {
-    *w = Work{};
+// Layout of one request's scratch in a single block: the offsets of every
+// buffer from the block's start, and its size.
+struct WorkLayout {
+    size_t o_w, o_G, o_mu, o_nu, o_fz, o_snap, o_fb, o_red[RED_COUNT], o_tot, o_chk, o_chkt, bytes;
+    int caps[RED_COUNT];
+    bool need_nu, d3, psf;
+};
+
+static WorkLayout work_layout(const pet_os_geom* g, bool need_nu) {
+    WorkLayout L{};
     Carver cv;
     size_t nv = (size_t)g->n_vox;
-    size_t o_w = cv.take<float>((size_t)g->max_sub_angles * g->n_planes * g->d.n_radial);
-    size_t o_G = cv.take<float>(nv);
-    size_t o_mu = cv.take<float>(nv);
-    size_t o_nu = need_nu ? cv.take<float>(nv) : 0;
-    const bool d3 = g->d.dim == 3;
-    size_t o_fz = d3 ? cv.take<float>(nv) : 0;
-    size_t o_snap = d3 ? 0 : cv.take<float>(nv);
-    const bool psf = g->k.psf_kx > 0;
-    size_t o_fb = psf ? cv.take<float>(nv) : 0;
-    int caps[RED_COUNT];
-    caps[RED_SUMF] = std::max(std::max(sumf_grid(g), bp_grid_max(g)), elem_grid(g->n_vox));
-    caps[RED_SUMMU] = std::max(bp_grid_max(g), elem_grid(g->n_vox));
-    caps[RED_FID] = fp_grid(g, g->d.n_angles);
-    caps[RED_RDP] = elem_grid(g->n_vox);
-    caps[RED_SUMY] = elem_grid(g->n_bins);
-    caps[RED_SUMR] = elem_grid(g->n_bins);
-    caps[RED_SUMS] = 1;
-    size_t o_red[RED_COUNT];
-    for (int r = 0; r < RED_COUNT; ++r) o_red[r] = cv.take<double>((size_t)caps[r]);
-    size_t o_tot = cv.take<double>(RED_COUNT);
-    size_t o_chk = cv.take<unsigned>((size_t)CHECK_GRID * 4);
-    size_t o_chkt = cv.take<unsigned long long>(4);
-    char* blk = nullptr;
-    if (hipMalloc(&blk, cv.off) != hipSuccess) return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc of scratch failed");
-    w->bytes = cv.off;
+    L.need_nu = need_nu;
+    L.d3 = g->d.dim == 3;
+    L.psf = g->k.psf_kx > 0;
+    L.o_w = cv.take<float>((size_t)g->max_sub_angles * g->n_planes * g->d.n_radial);
+    L.o_G = cv.take<float>(nv);
+    L.o_mu = cv.take<float>(nv);
+    L.o_nu = need_nu ? cv.take<float>(nv) : 0;
+    L.o_fz = L.d3 ? cv.take<float>(nv) : 0;
+    L.o_snap = L.d3 ? 0 : cv.take<float>(nv);
+    L.o_fb = L.psf ? cv.take<float>(nv) : 0;
+    L.caps[RED_SUMF] = std::max(std::max(sumf_grid(g), bp_grid_max(g)), elem_grid(g->n_vox));
+    L.caps[RED_SUMMU] = std::max(bp_grid_max(g), elem_grid(g->n_vox));
+    L.caps[RED_FID] = fp_grid(g, g->d.n_angles);
+    L.caps[RED_RDP] = elem_grid(g->n_vox);
+    L.caps[RED_SUMY] = elem_grid(g->n_bins);
+    L.caps[RED_SUMR] = elem_grid(g->n_bins);
+    L.caps[RED_SUMS] = 1;
+    for (int r = 0; r < RED_COUNT; ++r) L.o_red[r] = cv.take<double>((size_t)L.caps[r]);
+    L.o_tot = cv.take<double>(RED_COUNT);
+    L.o_chk = cv.take<unsigned>((size_t)CHECK_GRID * 4);
+    L.o_chkt = cv.take<unsigned long long>(4);
+    L.bytes = cv.off;
+    return L;
+}
+
+// point the buffers of w into the block at blk (laid out by L)
+static void work_carve(const WorkLayout& L, char* blk, Work* w) {
+    *w = Work{};
+    w->bytes = L.bytes;
     w->red_block = (double*)blk;
-    w->w = (float*)(blk + o_w);
-    w->G = (float*)(blk + o_G);
-    w->mu = (float*)(blk + o_mu);
-    w->nu_frozen = need_nu ? (float*)(blk + o_nu) : nullptr;
-    w->fz = d3 ? (float*)(blk + o_fz) : nullptr;
-    w->fsnap = d3 ? nullptr : (float*)(blk + o_snap);
-    w->fb = psf ? (float*)(blk + o_fb) : nullptr;
-    w->check_part = (unsigned*)(blk + o_chk);
-    w->check_total = (unsigned long long*)(blk + o_chkt);
+    w->w = (float*)(blk + L.o_w);
+    w->G = (float*)(blk + L.o_G);
+    w->mu = (float*)(blk + L.o_mu);
+    w->nu_frozen = L.need_nu ? (float*)(blk + L.o_nu) : nullptr;
+    w->fz = L.d3 ? (float*)(blk + L.o_fz) : nullptr;
+    w->fsnap = L.d3 ? nullptr : (float*)(blk + L.o_snap);
+    w->fb = L.psf ? (float*)(blk + L.o_fb) : nullptr;
+    w->check_part = (unsigned*)(blk + L.o_chk);
+    w->check_total = (unsigned long long*)(blk + L.o_chkt);
     for (int r = 0; r < RED_COUNT; ++r) {
-        w->red[r].part = (double*)(blk + o_red[r]);
-        w->red[r].total = (double*)(blk + o_tot) + r;
-        w->red[r].cap = caps[r];
+        w->red[r].part = (double*)(blk + L.o_red[r]);
+        w->red[r].total = (double*)(blk + L.o_tot) + r;
+        w->red[r].cap = L.caps[r];
     }
-    if (hipMemset(blk + o_tot, 0, RED_COUNT * sizeof(double)) != hipSuccess) {
+}
+
+size_t work_bytes(const pet_os_geom* g, bool need_nu) { return work_layout(g, need_nu).bytes; }
+
+int work_alloc(const pet_os_geom* g, bool need_nu, Work* w) {
+    *w = Work{};
+    const WorkLayout L = work_layout(g, need_nu);
+    char* blk = nullptr;
+    if (hipMalloc(&blk, L.bytes) != hipSuccess) return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc of scratch failed");
+    work_carve(L, blk, w);
+    if (hipMemset(blk + L.o_tot, 0, RED_COUNT * sizeof(double)) != hipSuccess) {
         (void)hipFree(blk);
+        *w = Work{};
         return fail(PET_OS_ERR_DEVICE, "scratch init failed");
     }
     return PET_OS_OK;
+}
+
+int work_place(const pet_os_geom* g, bool need_nu, void* base, size_t cap, Work* w, hipStream_t s) {
+    *w = Work{};
+    const WorkLayout L = work_layout(g, need_nu);
+    if (L.bytes > cap)
+        return fail(PET_OS_ERR_INVALID_ARG, "the reconstruction needs " + std::to_string(L.bytes) +
+                                                " bytes of scratch; the static area holds " + std::to_string(cap));
+    work_carve(L, (char*)base, w);
+    // the totals start at zero, as in a fresh allocation (a fill kernel, so
+    // that no memset is recorded if the caller captures the stream)
+    int rc = launch_fill((float*)w->red[0].total, (int64_t)(RED_COUNT * sizeof(double) / sizeof(float)), 0.0f, s);
+    if (rc) *w = Work{};
+    return rc;
 }
 
 void work_free(Work* w) {
@@ -1130,6 +1167,15 @@ static int run_iterations(pet_os_state* st, float* f, const float* y, const floa
     }
     return rc;
 }
+
+}  // extern "C"
+
+int petos::run_plain(pet_os_state* st, float* f, const float* y, const float* r, int n_iter, hipStream_t s) {
+    std::vector<char> none;
+    return run_iterations(st, f, y, r, n_iter, false, 1, 0, s, none);
+}
+
+extern "C" {
 
 static int ensure_obj(pet_os_state* st, int n) {
     if (st->obj_cap >= n) return PET_OS_OK;

@@ -100,6 +100,11 @@ struct Work {
 
 int work_alloc(const pet_os_geom* g, bool need_nu, Work* w);
 void work_free(Work* w);
+// bytes of one request's scratch, and the same scratch placed in caller
+// memory at base (cap bytes, 256-byte aligned): no allocation; the reduction
+// totals are cleared by a fill kernel on s
+size_t work_bytes(const pet_os_geom* g, bool need_nu);
+int work_place(const pet_os_geom* g, bool need_nu, void* base, size_t cap, Work* w, hipStream_t s);
 
 // device angle lists of a geometry
 struct GeomExtra {
@@ -317,6 +322,11 @@ void launch_batch3_bp(const SlotDev* d_slots, const Item* list, const int* cnt, 
 int bp3_nbs_of(const pet_os_geom* g);   // LDS row stride of the 3D back-projector (20 or 40)
 void launch_batch3_upd(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, hipStream_t s);
 
+}  // namespace petos
+
+namespace petos {
+// n_iter iterations of Table I on a state (no objective evaluations), queued on s
+int run_plain(pet_os_state* st, float* f, const float* y, const float* r, int n_iter, hipStream_t s);
 }  // namespace petos
 
 // per-request state of the plain path
