@@ -50,9 +50,9 @@ WORKLOADS = {
           "(64 rings, |d| <= 15), 28 subsets, 5e8 counts, 30% background; step = 1 iteration "
           "(28 subiterations); the FP64 objective is timed on its own",
 }
-KERNELS = {0: "k_fp (forward projection + Poisson ratio)",
-           1: "k_bp (back-projection + RDP gradient + mu)",
-           2: "k_update (nu, S, relaxed step, P_t)"}
+KERNELS = {0: "k_fp3 (forward projection + Poisson ratio)",
+           1: "k_bp3 (back-projection + RDP gradient + mu)",
+           2: "k_upd3 (nu, S, relaxed step, P_t; z-fastest copy)"}
 # 2D: two launches per subiteration (the update is fused into the back-projection)
 KERNELS_2D = {0: "k_fp_px (forward projection + Poisson ratio; snapshot of f and mu)",
               1: "k_bp (back-projection + RDP gradient + nu, S, relaxed step, P_t)"}
@@ -125,6 +125,81 @@ def traffic_from_pmc(fetch_csv, write_csv, dim):
     fetch, sf = per_kernel(fetch_csv)
     write, sw = per_kernel(write_csv)
     return {str(k): int(fetch[k] + write.get(k, 0.0)) for k in fetch}, {"fetch": sf, "write": sw}
+
+
+# MI355X on-chip ceilings (256 CUs of 4 SIMDs, 8 XCDs of 16 L2 channels, at
+# 2.4 GHz): a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles;
+# the LDS returns 128 bytes per clock per CU; an L2 channel takes one
+# request per clock
+CLOCK_HZ = 2.4e9
+VALU_WAVE_INSTR_PEAK = 256 * 4 * CLOCK_HZ / 4          # 614.4e9 wave64 instructions / s
+LDS_PEAK_BYTES = 256 * 128 * CLOCK_HZ                  # 78.6e12 B/s
+L2_REQ_PEAK = 8 * 16 * CLOCK_HZ                        # 307.2e9 requests / s
+COUNTERS = ["SQ_INSTS_VALU", "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_LDS", "SQ_INSTS_LDS_LOAD_BANDWIDTH",
+            "TCC_HIT_sum", "TCC_MISS_sum", "SQ_INSTS_SALU", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64",
+            "SQ_INSTS_VALU_MUL_F64", "SQ_LDS_BANK_CONFLICT", "SQ_WAVES", "GRBM_GUI_ACTIVE"]
+
+
+def counters_from_pmc(csv_paths, dim):
+    """Per-launch medians of the rocprofv3 --pmc counters in csv_paths for
+    each kernel of the per-subiteration launches (its most launched variant),
+    keyed by kernel index as in TRAFFIC_KERNELS."""
+    import collections
+    import csv
+    import statistics
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in csv_paths:
+        for r in csv.DictReader(open(path)):
+            vals[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    out = {}
+    for k, prefix in TRAFFIC_KERNELS[dim].items():
+        names = [n for n in vals if n.startswith(prefix)]
+        if not names:
+            continue
+        main = max(names, key=lambda n: max(len(v) for v in vals[n].values()))
+        out[str(k)] = {c: statistics.median(v) for c, v in vals[main].items()}
+    return out
+
+
+def stored_counters(workload, mode, shapes, kernel):
+    """Per-launch counters of `kernel` from profiles/counters_<workload>.json
+    while the kernel sources, the shapes and the mode are those profiled."""
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if (t.get("kernel_source") == kernel_source_hash() and t.get("shapes") == "default"
+            and t.get("mode") == mode and shapes["current"] == shapes["default"]):
+        return t.get("per_launch", {}).get(str(kernel))
+    return None
+
+
+def onchip_ceilings(c, avg_us, traffic):
+    """Fractions of the on-chip ceilings one launch reaches, from its
+    counters c (per launch) and its duration: VALU issue, LDS bandwidth, L2
+    request rate, and the counted HBM bytes against 8 TB/s."""
+    t = avg_us * 1e-6
+    out = {}
+    if traffic is not None:
+        out["hbm_counted"] = {"achieved_GBs": round(traffic / t / 1e9, 1), "peak_GBs": HBM_PEAK_GBS,
+                              "frac": round(traffic / t / 1e9 / HBM_PEAK_GBS, 4)}
+    if c is None:
+        return out or None
+    if "SQ_INSTS_VALU" in c:
+        r = c["SQ_INSTS_VALU"] / t
+        out["valu_issue"] = {"achieved_G_instr_s": round(r / 1e9, 1), "peak_G_instr_s": VALU_WAVE_INSTR_PEAK / 1e9,
+                             "frac": round(r / VALU_WAVE_INSTR_PEAK, 4)}
+        if "SQ_INSTS_VALU_FMA_F32" in c:
+            out["valu_issue"]["fma_f32_share"] = round(c["SQ_INSTS_VALU_FMA_F32"] / c["SQ_INSTS_VALU"], 4)
+    if "SQ_INSTS_LDS_LOAD_BANDWIDTH" in c:
+        r = 64.0 * c["SQ_INSTS_LDS_LOAD_BANDWIDTH"] / t
+        out["lds_load"] = {"achieved_TBs": round(r / 1e12, 2), "peak_TBs": round(LDS_PEAK_BYTES / 1e12, 1),
+                           "frac": round(r / LDS_PEAK_BYTES, 4)}
+    if "TCC_HIT_sum" in c and "TCC_MISS_sum" in c:
+        req = c["TCC_HIT_sum"] + c["TCC_MISS_sum"]
+        out["l2_requests"] = {"achieved_G_req_s": round(req / t / 1e9, 1), "peak_G_req_s": L2_REQ_PEAK / 1e9,
+                              "frac": round(req / t / L2_REQ_PEAK, 4), "hit_rate": round(c["TCC_HIT_sum"] / req, 4)}
+    return out
 
 
 def algorithmic_bytes(kernel, nnz_sub, rays_sub, q, dim=3, osem=False, psf=False):
@@ -572,6 +647,9 @@ def main():
                          "initialisation of Sec. IV-C)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (for PMC byte-counter scaling)")
+    ap.add_argument("--counters-from", nargs="+", metavar="PMC_CSV",
+                    help="write profiles/counters_<workload>.json from rocprofv3 --pmc counter CSVs of this "
+                         "workload run with --no-autotune (the default projector shapes), and exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic_<workload>.json from two rocprofv3 --pmc counter CSVs "
                          "(FETCH_SIZE, WRITE_SIZE) of this workload run with --calibrate-copy --no-autotune "
@@ -583,6 +661,17 @@ def main():
                                    "built nor measured", "n_gpus": args.gpus}))
         sys.exit(2)
 
+    if args.counters_from:
+        dim = 3 if args.workload == "c3" else 2
+        out = {"workload": args.workload, "mode": args.mode or "P2", "kernel_source": kernel_source_hash(),
+               "shapes": "default", "per_launch": counters_from_pmc(args.counters_from, dim),
+               "note": "rocprofv3 --pmc counters per launch (median over the launches of each kernel's "
+                       "per-subiteration variant), runs with the default projector shapes (--no-autotune)"}
+        path = os.path.join(ROOT, "profiles", f"counters_{args.workload}.json")
+        with open(path, "w") as fh:
+            json.dump(out, fh, indent=1)
+        print(json.dumps(out))
+        return
     if args.traffic_from:
         dim = 3 if args.workload == "c3" else 2
         per, scale = traffic_from_pmc(args.traffic_from[0], args.traffic_from[1], dim)
@@ -718,7 +807,12 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                     "kernel": names[dom], "avg_launch_us": round(K["avg_us"], 3),
                     "algorithmic_bytes_per_launch": int(K["bytes"]),
-                    "per_kernel_us": {names[k].split(" (")[0]: round(v["avg_us"], 3) for k, v in per_kernel.items()}}
+                    "per_kernel_us": {names[k].split(" (")[0]: round(v["avg_us"], 3) for k, v in per_kernel.items()},
+                    # achieved/frac above: algorithmic bytes (4 B per nonzero, most served by LDS or
+                    # L2) per launch over its duration; below, what the launch reaches of each
+                    # ceiling it meets on the chip, from the counters on record and the same duration
+                    "ceilings": onchip_ceilings(stored_counters(args.workload, p["mode"], shapes, dom),
+                                                K["avg_us"], traffic)}
 
     del state
     cpu, parity = None, None

@@ -45,6 +45,14 @@ int validate_desc(const pet_os_geom_desc* d) {
     if ((int64_t)d->nx * d->ny * (d->dim == 3 ? d->nz : 1) > (int64_t)1 << 30)
         return fail(PET_OS_ERR_INVALID_ARG, "image too large");
     if (d->n_subrays < 0 || d->n_subrays > 64) return fail(PET_OS_ERR_INVALID_ARG, "n_subrays must be in [0, 64]");
+    // the projectors index one pass (all angles at most) in 32-bit integers:
+    // 2D rays, and 3D forward work items (angle, bin, ring difference, ring chunk)
+    {
+        const int64_t D = d->dim == 3 ? std::max(0, d->max_ring_diff) : 0;
+        const int64_t chunks = d->dim == 3 ? (std::max(1, d->n_rings) + 63) / 64 : 1;
+        const int64_t per_pass = (int64_t)d->n_angles * d->n_radial * (2 * D + 1) * chunks;
+        if (per_pass >= ((int64_t)1 << 31)) return fail(PET_OS_ERR_INVALID_ARG, "sinogram too large");
+    }
     if (!(std::isfinite(d->psf_fwhm) && d->psf_fwhm >= 0.0))
         return fail(PET_OS_ERR_INVALID_ARG, "psf_fwhm must be finite and >= 0");
     if (d->dim == 3 && (d->n_subrays > 1 || d->psf_fwhm > 0.0))

@@ -77,6 +77,49 @@ __device__ __forceinline__ V group_sum(V v) {
     return v;
 }
 
+// Sum over aligned groups of W lanes by a balanced binary tree of the lanes
+// (adjacent pairs, then pairs of pairs, ...): group_sum, except that W = 64
+// adds its four row sums as (r0 + r1) + (r2 + r3).
+template <int W>
+__device__ __forceinline__ float group_sum_balanced(float v) {
+    if constexpr (W < 64) {
+        return group_sum<W>(v);
+    } else {
+        v = group_sum<16>(v);
+        float r[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16 * k));
+        return (r[0] + r[1]) + (r[2] + r[3]);
+    }
+}
+
+// Balanced binary tree over L leaves (L a power of two) added in leaf order:
+// add() takes leaves 0, 1, ..., L-1; after the last one total() holds
+// (...((l0 + l1) + (l2 + l3)) + ...).  A pending left subtree is kept per
+// level, so the association is that of the full tree whatever the leaves.
+template <int L>
+struct LeafTree {
+    static constexpr int LOG = L >= 64 ? 6 : L >= 32 ? 5 : L >= 16 ? 4 : L >= 8 ? 3 : L >= 4 ? 2 : L >= 2 ? 1 : 0;
+    static_assert((1 << LOG) == L, "a power of two of leaves");
+    float pend[LOG > 0 ? LOG : 1];
+    float sum = 0.0f;
+    __device__ __forceinline__ void add(int k, float s) {
+        bool carry = true;
+#pragma unroll
+        for (int l = 0; l < LOG; ++l) {
+            if (carry) {
+                if ((k >> l) & 1) {
+                    s = pend[l] + s;
+                } else {
+                    pend[l] = s;
+                    carry = false;
+                }
+            }
+        }
+        if (carry) sum = s;
+    }
+};
+
 // Sum over the wave (every lane active), valid in every lane.
 __device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
 

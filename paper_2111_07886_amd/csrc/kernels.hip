@@ -94,8 +94,13 @@ __device__ __forceinline__ float fp_subray_acc(const GeoK& g, const FPArgs& A, c
 }
 
 // One ray per (thread-row of the block); SEG threads split its major cells.
-// With SEG > 1 the SEG threads of a ray are adjacent lanes of one wave and
-// their partial sums are added by a fixed shuffle tree.
+// The ray's sum does not depend on SEG: its major cells [m0, m1] are cut
+// into 64 leaves of ceil(count / 64) consecutive cells, each leaf is summed
+// in cell order, and the 64 leaf sums are added by a balanced binary tree.
+// A thread takes 64 / SEG consecutive leaves and adds them by that tree's
+// subtree (LeafTree); the SEG threads of a ray are adjacent lanes of one
+// wave and add their subtrees by its top levels (group_sum_balanced).  So
+// every SEG, and the batched kernels' choice of it, give the same bits.
 template <int DIM, int SEG, bool SUB = false>
 __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
     static_assert(DIM == 2, "the 3D forward projector is k_fp3");
@@ -116,10 +121,13 @@ __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
     const bool needs_data = A.mode == FP_RATIO || A.mode == FP_EM || A.mode == FP_OBJECTIVE;
     float yv = 0.0f, rv = 0.0f, atv = 1.0f;
     if (valid) {
-        b = (int)(ray % Nr);
-        long long t = ray / Nr;
-        plane = (int)(t % P);
-        al = (int)(t / P);
+        // a 2D pass holds fewer than 2^31 rays (checked with the descriptor):
+        // 32-bit index arithmetic
+        const int r32 = (int)ray;
+        b = r32 % Nr;
+        const int t = r32 / Nr;
+        plane = t % P;
+        al = t / P;
         a = A.angles[al];
         if (seg == 0) {
             const long long nat = ((long long)plane * g.n_angles + a) * Nr + b;
@@ -156,35 +164,61 @@ __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
         } else {
             major_range(tx, n_major, n_minor, m0, m1);
         }
-        int cnt = m1 - m0 + 1;
-        int per = (cnt + SEG - 1) / SEG;
-        int s0 = m0 + seg * per;
-        int s1 = min(m1, s0 + per - 1);
+        const int cnt = m1 - m0 + 1;
+        const int per = (cnt + 63) / 64;              // cells per leaf
+        constexpr int LPT = 64 / SEG;                 // leaves per thread
         const int sx = tx.row_major ? 1 : g.nx;       // stride along the minor cell index
         const int sm = tx.row_major ? g.nx : 1;       // stride along the major index
-        int qstep = (tx.Q > 0.0) ? 1 : -1;
-        if (SUB) acc = fp_subray_acc(g, A, AK, b, s0, s1);
-        else for (int m = s0; m <= s1; ++m) {
-            double gm = __fma_rn(tx.Q, (double)m, tx.P);
-            int c0 = (int)floor(gm);
-            #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                if (k == 1 && tx.Q == 0.0) break;
-                int c = c0 + k * qstep;
-                if (c < 0 || c >= n_minor) continue;
-                double lo, hi;
-                cell_interval(gm, tx.Q, tx.invQ, c, lo, hi);
-                if (hi > lo) {
-                    if (A.mode == FP_COUNT) { acc += 1.0f; continue; }
-                    float aij = (float)(tx.L * (hi - lo));
-                    acc = fmaf(aij, img_at(A.f, m * sm + c * sx), acc);
+        const int qstep = (tx.Q > 0.0) ? 1 : -1;
+        LeafTree<LPT> tree;
+        for (int k = 0; k < LPT; ++k) {
+            const int s0 = m0 + (seg * LPT + k) * per;
+            const int s1 = min(m1, s0 + per - 1);
+            float leaf = 0.0f;
+            if (SUB) {
+                if (s0 <= s1) leaf = fp_subray_acc(g, A, AK, b, s0, s1);
+            } else {
+                // Over major cell m the ray's minor coordinate runs from
+                // gm = P + Q m to gm + Q (|Q| <= 1): it stays in cell c0 =
+                // floor(gm), or crosses once into c0 + qstep at the fraction
+                // t of the cell's length, t = (c0 + 1 - gm)/Q (Q > 0) or
+                // (c0 - gm)/Q (Q < 0).  The cell and the crossing are decided
+                // in FP64; t and the two lengths are formed in FP32 from the
+                // FP64 distance to the crossed edge.
+                const float Lf = (float)tx.L;
+                const float invQf = (float)tx.invQ;
+                const bool up = tx.Q >= 0.0;
+                for (int m = s0; m <= s1; ++m) {
+                    const double gm = __fma_rn(tx.Q, (double)m, tx.P);
+                    const double cf = floor(gm);
+                    const int c0 = (int)cf;
+                    const double edge = up ? cf + 1.0 : cf;             // the edge the ray may cross
+                    const double ge = gm + tx.Q;
+                    const bool cross = up ? (ge > edge) : (ge < edge);
+                    float a1 = Lf, a2 = 0.0f;
+                    if (cross) {
+                        a1 = Lf * ((float)(edge - gm) * invQf);
+                        a2 = Lf - a1;
+                    }
+                    const int c1 = c0 + qstep;
+                    const bool in0 = c0 >= 0 && c0 < n_minor && a1 > 0.0f;
+                    const bool in1 = cross && c1 >= 0 && c1 < n_minor && a2 > 0.0f;
+                    if (A.mode == FP_COUNT) {
+                        leaf += (in0 ? 1.0f : 0.0f) + (in1 ? 1.0f : 0.0f);
+                        continue;
+                    }
+                    const int base = m * sm;
+                    if (in0) leaf = fmaf(a1, img_at(A.f, base + c0 * sx), leaf);
+                    if (in1) leaf = fmaf(a2, img_at(A.f, base + c1 * sx), leaf);
                 }
             }
+            tree.add(k, leaf);
         }
+        acc = tree.sum;
     }
-    // the segments' sums of a ray (SEG adjacent lanes, every lane of the
-    // wave takes part), valid in each of its lanes
-    acc = group_sum<SEG>(acc);
+    // the subtrees of a ray's SEG threads (adjacent lanes; every lane of the
+    // wave takes part), added by the tree's top levels, valid in each lane
+    acc = group_sum_balanced<SEG>(acc);
     double term = 0.0;
     if (seg == 0 && valid) {
         long long nat = ((long long)plane * g.n_angles + a) * Nr + b;
@@ -515,10 +549,16 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
                     const double uc = __fma_rn(xc, AK.c, yc * AK.s);
                     const int b0 = max((int)ceil((uc - AK.e_out) * inv_ds + g.h0), 0);
                     const int b1 = min((int)floor((uc + AK.e_out) * inv_ds + g.h0), Nr - 1);
+                    // the radial offset of bin b0's line from the pixel centre
+                    // in FP64, the window's later bins (|t| < e_out, at most
+                    // three) in FP32 steps of ds from it
+                    const float t0 = (float)__fma_rn((double)b0 - g.h0, g.ds, -uc);
+                    const float dsf = (float)g.ds, eo = (float)AK.e_out, ide = (float)AK.inv_de;
+                    const float lmax = (float)AK.Lmax;
                     for (int b = b0; b <= b1; ++b) {
-                        const double tt = fabs(__fma_rn((double)b - g.h0, g.ds, -uc));
-                        const double len = AK.Lmax * fmin(1.0, (AK.e_out - tt) * AK.inv_de);
-                        if (len > 0.0) acc = fmaf((float)len, wval(b), acc);
+                        const float tt = fabsf(fmaf((float)(b - b0), dsf, t0));
+                        const float len = lmax * fminf(1.0f, (eo - tt) * ide);
+                        if (len > 0.0f) acc = fmaf(len, wval(b), acc);
                     }
                 } else {
                     const int m = AK.row_major ? iy : ix;

@@ -85,13 +85,15 @@ __device__ void fp3_body(const GeoK& g, const FP3Args& A, long long vblock) {
     bool live = item < fp3_items(A.n_al, Nr, D, R);
     int ch = 0, di = 0, b = 0, al = 0;
     if (live) {
-        long long t = item;
-        ch = (int)(t % nch);
+        // fewer than 2^31 items per pass (checked with the descriptor): the
+        // wave-uniform decode in 32-bit integers
+        int t = (int)item;
+        ch = t % nch;
         t /= nch;
-        di = (int)(t % ND);
+        di = t % ND;
         t /= ND;
-        b = (int)(t % Nr);
-        al = (int)(t / Nr);
+        b = t % Nr;
+        al = t / Nr;
     }
     const int d = di - D;
     const int r1lo = max(0, -d), r1hi = min(R - 1, R - 1 - d);

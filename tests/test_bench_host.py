@@ -131,3 +131,32 @@ def test_stored_traffic_needs_same_sources_shapes_and_mode(bench, tmp_path, monk
     assert bench.stored_traffic("c3", "P2", same, 1) is None          # nothing stored
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "k2")
     assert bench.stored_traffic("c2", "P2", same, 1) is None          # sources changed
+
+
+def test_counters_and_onchip_ceilings(bench, tmp_path):
+    """Per-launch counters are the medians over the most launched variant of
+    each kernel; the ceilings divide them by the launch's duration against
+    the chip's VALU issue (256 CUs x 4 SIMDs, a wave64 instruction every 4
+    cycles at 2.4 GHz), LDS (128 B per clock per CU) and L2 request
+    (8 x 16 channels, one per clock) rates."""
+    a, b = tmp_path / "a.csv", tmp_path / "b.csv"
+    bp = "void petos::k_bp3<64, 20>(petos::GeoK, petos::BP3Args, int)"
+    trial = "void petos::k_bp3<32, 20>(petos::GeoK, petos::BP3Args, int)"
+    _pmc_csv(a, "SQ_INSTS_VALU", [(bp, 100.0), (bp, 300.0), (bp, 200.0), (trial, 7.0)])
+    _pmc_csv(b, "TCC_HIT_sum", [(bp, 90.0), (bp, 90.0), (bp, 90.0)])
+    with open(b, "a", newline="") as fh:
+        w = csv.writer(fh)
+        for i in range(3):
+            w.writerow([10 + i, bp, "TCC_MISS_sum", 10.0])
+    per = bench.counters_from_pmc([str(a), str(b)], 3)
+    assert per["1"] == {"SQ_INSTS_VALU": 200.0, "TCC_HIT_sum": 90.0, "TCC_MISS_sum": 10.0}
+    assert bench.VALU_WAVE_INSTR_PEAK == 614.4e9
+    assert abs(bench.LDS_PEAK_BYTES - 78.6432e12) < 1e6 and bench.L2_REQ_PEAK == 307.2e9
+    c = {"SQ_INSTS_VALU": 614.4e3, "SQ_INSTS_VALU_FMA_F32": 153.6e3, "SQ_INSTS_LDS_LOAD_BANDWIDTH": 1e6,
+         "TCC_HIT_sum": 2.4576e5, "TCC_MISS_sum": 6.144e4}
+    out = bench.onchip_ceilings(c, 2.0, 8e6)          # a 2 us launch
+    assert abs(out["valu_issue"]["frac"] - 0.5) < 1e-9 and out["valu_issue"]["fma_f32_share"] == 0.25
+    assert abs(out["lds_load"]["achieved_TBs"] - 32.0) < 1e-9
+    assert abs(out["l2_requests"]["frac"] - 0.5) < 1e-9 and out["l2_requests"]["hit_rate"] == 0.8
+    assert out["hbm_counted"]["achieved_GBs"] == 4000.0 and out["hbm_counted"]["frac"] == 0.5
+    assert bench.onchip_ceilings(None, 2.0, None) is None

@@ -598,6 +598,28 @@ def test_2d_shapes(pet, orc, tmp_path, monkeypatch, seg, kind):
     stepwise(pet, orc, w, configs.params_2d(d["n_subsets"], 3e5, U=w.U), {1, 2, 7}, tune=True)
 
 
+@pytest.mark.parametrize("name", ["ragged_aniso", "c2"])
+def test_forward_sum_independent_of_threads_per_ray(pet, tmp_path, monkeypatch, name):
+    """A ray's sum is cut into fixed leaves added by a fixed tree, so every
+    threads-per-ray shape gives the same bits (which lets a batch choose its
+    own shape and still compute what each request computes alone)."""
+    d = full_desc(GEOMS[name])
+    rng = np.random.default_rng(9)
+    f = dev(rng.uniform(0.5, 2.0, (d["ny"], d["nx"])))
+    out = []
+    for seg in (1, 4, 16, 64):
+        cache = tmp_path / f"tune{seg}.txt"
+        cache.write_text(f"{tune_key(d)}|{seg} 0\n")
+        monkeypatch.setenv("PET_OS_TUNE_CACHE", str(cache))
+        G = pet.Geometry(d)
+        pet.autotune(G)
+        assert G.shapes()["current"]["fp_seg"] == seg
+        out.append(G.forward(f, 0))
+    torch.cuda.synchronize()
+    for k in range(1, 4):
+        assert torch.equal(out[0], out[k]), k
+
+
 def test_invalid_cached_shape_is_retuned(pet, tmp_path, monkeypatch):
     """A cache entry naming a shape the tuner cannot choose is ignored."""
     d = full_desc(GEOMS["ragged_aniso"])
