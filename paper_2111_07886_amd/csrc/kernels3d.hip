@@ -269,6 +269,7 @@ struct BP3Shared {
     double tau[2];
     int blo, nb, npass;
     int omin[BP3_MAXND], omax[BP3_MAXND];
+    int pbase[BP3_MAXND];    // plane of ring r1 = 0 of ring difference index di (plane_base - first ring)
     double red[NT / 64];
 };
 
@@ -362,9 +363,12 @@ __device__ void bp3_finish(const GeoK& g, const BP3Args& A, float (&acc)[BP3_ZMA
 // Stage w of ring differences dg .. dg+dpg-1 into buf as [d][row][bin], row r
 // of d holding r1 = z0 - omax(d) + r - 1 (row 0 and invalid rings: zeros;
 // unit weights: ones).  NBS is the row stride; one wave instruction copies
-// 64/NBS consecutive rows straight from device memory into LDS.  Returns
-// without waiting: the caller waits for the loads before the barrier that
-// publishes the buffer.
+// 64/NBS consecutive rows straight from device memory into LDS.  Per ring
+// difference the rows of valid rings form one range [rlo, rhi]: the rows
+// outside it are zero-filled by the block, the range is copied in chunks of
+// 64/NBS rows whose only per-lane work is the range test and the address.
+// Returns without waiting: the caller waits for the loads before the barrier
+// that publishes the buffer.
 template <int NBS>
 __device__ __forceinline__ void bp3_stage(const GeoK& g, const BP3Args& A, const BP3Shared& sh, float* buf, int dg,
                                           int z0, int aidx, int blo, int nbv) {
@@ -373,27 +377,40 @@ __device__ __forceinline__ void bp3_stage(const GeoK& g, const BP3Args& A, const
     const int lane = threadIdx.x & 63;
     const int sub = lane / NBS, col = lane - sub * NBS;
     const int D = g.max_rd, ND = 2 * D + 1, R = g.n_rings, rw = A.rw, dpg = A.dpg;
-    const int nchunk = (rw + LPI - 1) / LPI;
+    const bool lane_ok = sub < LPI && col < nbv;
+    // a lane's element of a chunk: row (chunk start + sub), bin (blo + col);
+    // its offset from the chunk's first element is the same in every chunk
+    const long long lane_off = (long long)sub * A.w_sp + col;
     for (int ds = 0; ds < dpg; ++ds) {
         const int di = dg + ds;
         if (di >= ND) break;
         const int d = di - D;
         const int lo = max(0, -d), hi = min(R - 1, R - 1 - d);
         const int om = __builtin_amdgcn_readfirstlane(sh.omax[di]);
-        const long long plane0 = (long long)g.plane_base[di] - lo;
-        for (int ch = wave; ch < nchunk; ch += 4) {
-            const int row0 = ch * LPI;
-            float* dst = buf + (ds * rw + row0) * NBS;
-            const int row = row0 + sub;
-            const int r1 = z0 - om + row - 1;
-            const bool in_rows = sub < LPI && row < rw && col < nbv;
-            const bool ring_ok = row >= 1 && r1 >= lo && r1 <= hi;
-            if (A.w != nullptr && in_rows && ring_ok) {
-                const float* src = A.w + (plane0 + r1) * A.w_sp + (long long)aidx * A.w_sa + blo + col;
-                __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 4, 0, 0);
-            } else if (in_rows) {
-                dst[sub * NBS + col] = (A.w == nullptr && ring_ok) ? 1.0f : 0.0f;
-            }
+        const int r1_row0 = z0 - om - 1;            // ring r1 of row 0
+        // rows of valid rings (row 0 stays zero): [rlo, rhi], possibly empty
+        const int rlo = max(1, lo - r1_row0), rhi = min(rw - 1, hi - r1_row0);
+        float* bd = buf + ds * rw * NBS;
+        // zeros below the range ([0, nzlo)) and above it ([top0, rw))
+        const int nzlo = min(rlo, rw), top0 = max(rhi, rlo - 1) + 1, nzhi = max(rw - top0, 0);
+        for (int e = threadIdx.x; e < (nzlo + nzhi) * NBS; e += NT) {
+            const int rr = e / NBS, cc = e - rr * NBS;
+            const int row = rr < nzlo ? rr : top0 + (rr - nzlo);
+            bd[row * NBS + cc] = 0.0f;
+        }
+        if (rhi < rlo) continue;
+        if (A.w == nullptr) {
+            for (int e = threadIdx.x; e < (rhi - rlo + 1) * NBS; e += NT) bd[rlo * NBS + e] = 1.0f;
+            continue;
+        }
+        // (uniform) element of row rlo, bin blo: plane pbase[di] + r1
+        const float* wr = A.w + ((long long)sh.pbase[di] + r1_row0 + rlo) * A.w_sp + (long long)aidx * A.w_sa + blo;
+        const long long wstep = (long long)(4 * LPI) * A.w_sp;
+        wr += (long long)(wave * LPI) * A.w_sp;
+        for (int r0 = rlo + wave * LPI; r0 <= rhi; r0 += 4 * LPI, wr += wstep) {
+            if (lane_ok && r0 + sub <= rhi)
+                __builtin_amdgcn_global_load_lds(wr + lane_off, (__attribute__((address_space(3))) void*)(bd + r0 * NBS),
+                                                 4, 0, 0);
         }
     }
 }
@@ -469,6 +486,12 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared&
     float acc[BP3_ZMAX];
 #pragma unroll
     for (int i = 0; i < BP3_ZMAX; ++i) acc[i] = 0.0f;
+    // plane of ring 0 per ring difference, read by the staging (published by
+    // the first barrier of the angle loop)
+    if ((int)threadIdx.x < ND) {
+        const int d = (int)threadIdx.x - D;
+        sh.pbase[threadIdx.x] = g.plane_base[threadIdx.x] - max(0, -d);
+    }
 
     for (int al = 0; al < A.n_al; ++al) {
         const int a = A.angles[al];
