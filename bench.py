@@ -51,8 +51,9 @@ WORKLOADS = {
           "(28 subiterations); the FP64 objective is timed on its own",
 }
 KERNELS = {0: "k_fp3 (forward projection + Poisson ratio)",
-           1: "k_bp3 (back-projection + RDP gradient + mu)",
-           2: "k_upd3 (nu, S, relaxed step, P_t; z-fastest copy)"}
+           1: "k_bp3 (back-projection)",
+           2: "k_upd3 (nu, S, relaxed step, P_t; z-fastest copy)",
+           3: "k_pen3 (RDP gradient, G, mu)"}
 # 2D: two launches per subiteration (the update is fused into the back-projection)
 KERNELS_2D = {0: "k_fp_px (forward projection + Poisson ratio; snapshot of f and mu)",
               1: "k_bp (back-projection + RDP gradient + nu, S, relaxed step, P_t)"}
@@ -77,7 +78,7 @@ def kernel_source_hash():
 
 # kernel-name prefixes of the per-subiteration launches, by kernel index
 TRAFFIC_KERNELS = {2: {0: "void petos::k_fp_px<", 1: "void petos::k_bp<"},
-                   3: {0: "petos::k_fp3(", 1: "void petos::k_bp3<", 2: "petos::k_upd3("}}
+                   3: {0: "petos::k_fp3(", 1: "void petos::k_bp3<", 2: "petos::k_upd3(", 3: "petos::k_pen3("}}
 COPY_BYTES = 64 * 1024 * 1024 * 4      # the --calibrate-copy transfer
 
 
@@ -204,14 +205,15 @@ def onchip_ceilings(c, avg_us, traffic):
 
 def algorithmic_bytes(kernel, nnz_sub, rays_sub, q, dim=3, osem=False, psf=False):
     """Bytes one launch must move (A is computed on the fly, never stored).
-    3D: forward: 4 B image gather per nonzero + read y, r and write w per ray;
-    back: 4 B w gather per nonzero + stage w once per ray + read f, write G,
-    mu; update: read f, G, mu, p and write f per voxel.  2D, two launches:
-    forward + pixel pass (read f, write its snapshot and mu), and
-    back-projection + update (read the snapshot, mu, p, write f).  Either way
-    8 nnz + 16 rays + 32 q per subiteration.  OSEM has no mu or p but reads
+    3D, four launches: forward: 4 B image gather per nonzero + read y, r and
+    write w per ray; back: 4 B w gather per nonzero + stage w once per ray +
+    write A_i^T w per voxel; penalty (kernel 3): read A_i^T w and f, write G
+    and mu; update: read f, G, mu, p and write f: 8 nnz + 16 rays + 40 q per
+    subiteration.  2D, two launches: forward + pixel pass (read f, write its
+    snapshot and mu), and back-projection + update (read the snapshot, mu, p,
+    write f): 8 nnz + 16 rays + 32 q.  OSEM has no mu, p or penalty but reads
     the subset sensitivity: 2D forward + pixel pass 8 q, back + update 12 q;
-    3D back 8 q (f, G), update 20 q (f, G, s_i in; f and its z copy out)."""
+    3D back 4 q, update 20 q (f, G, s_i in; f and its z copy out)."""
     if psf and dim == 2 and not osem:
         # + the blur of f (read f, write its blur) before the forward projector;
         # the back-projection is written, blurred (read, write) and read again
@@ -222,7 +224,7 @@ def algorithmic_bytes(kernel, nnz_sub, rays_sub, q, dim=3, osem=False, psf=False
         if kernel == 0:
             return 4.0 * nnz_sub + 12.0 * rays_sub
         if kernel == 1:
-            return 4.0 * nnz_sub + 4.0 * rays_sub + 8.0 * q
+            return 4.0 * nnz_sub + 4.0 * rays_sub + 4.0 * q
         return 20.0 * q
     if dim == 2:
         if kernel == 0:
@@ -231,7 +233,9 @@ def algorithmic_bytes(kernel, nnz_sub, rays_sub, q, dim=3, osem=False, psf=False
     if kernel == 0:
         return 4.0 * nnz_sub + 12.0 * rays_sub
     if kernel == 1:
-        return 4.0 * nnz_sub + 4.0 * rays_sub + 12.0 * q
+        return 4.0 * nnz_sub + 4.0 * rays_sub + 4.0 * q
+    if kernel == 3:
+        return 16.0 * q
     return 20.0 * q
 
 

@@ -269,8 +269,8 @@ int pet_os_run(pet_os_state* state, float* f, const float* y, const float* r, in
 
 /* Kernel timing with HIP events on the state's stream (tracing, Sec. IV
  * reports CPU time; this reports device time).  kernel: 0 = forward
- * projection + ratio, 1 = back-projection + RDP/mu stencil, 2 = update,
- * -1 = off.  Events bracket every launch of that kernel until switched off.
+ * projection + ratio, 1 = back-projection (2D: with the RDP/mu stencil and
+ * the update), 2 = 3D update, 3 = 3D RDP gradient and mu, -1 = off.  Events bracket every launch of that kernel until switched off.
  * read: synchronises, returns the summed milliseconds and launch count since
  * the last read, and resets them. */
 int pet_os_state_profile(pet_os_state* state, int32_t kernel);

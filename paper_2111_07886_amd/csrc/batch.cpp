@@ -133,6 +133,8 @@ int rebuild_lists(pet_os_batch* B) {
         const int wbp = d3 ? WL_BP3 + 2 * zi + (bp3_nbs_of(S.g) == 40 ? 1 : 0) : WL_BP0 + S.bp_kind;
         for (int b = 0; b < nbp; ++b) L[wbp].push_back({s, b});
         if (d3) {
+            const int npen = pen3_grid(S.g);
+            for (int b = 0; b < npen; ++b) L[WL_PEN3].push_back({s, b});
             const int nup = upd3_grid(S.g);
             for (int b = 0; b < nup; ++b) L[WL_UPD3].push_back({s, b});
         }
@@ -300,7 +302,7 @@ int pet_os_batch_add(pet_os_batch* B, const pet_os_geom* g, const pet_os_params*
     D.part_f = S.w.red[RED_SUMF].part;
     D.part_mu = S.w.red[RED_SUMMU].part;
     D.n_part_f = sumf_grid(g);
-    D.n_part_mu = g->d.dim == 3 ? bp3_grid_batch(g) : px_grid(g);
+    D.n_part_mu = g->d.dim == 3 ? pen3_grid(g) : px_grid(g);
     D.subset_lists = ex->subset_lists;
     D.subset_count = ex->d_subset_count;
     D.max_sub = g->max_sub_angles;

@@ -472,7 +472,7 @@ static WorkLayout work_layout(const pet_os_geom* g, bool need_nu) {
     L.o_snap = L.d3 ? 0 : cv.take<float>(nv);
     L.o_fb = L.psf ? cv.take<float>(nv) : 0;
     L.caps[RED_SUMF] = std::max(std::max(sumf_grid(g), bp_grid_max(g)), elem_grid(g->n_vox));
-    L.caps[RED_SUMMU] = std::max(bp_grid_max(g), elem_grid(g->n_vox));
+    L.caps[RED_SUMMU] = std::max(std::max(bp_grid_max(g), elem_grid(g->n_vox)), g->d.dim == 3 ? pen3_grid(g) : 0);
     L.caps[RED_FID] = fp_grid(g, g->d.n_angles);
     L.caps[RED_RDP] = elem_grid(g->n_vox);
     L.caps[RED_SUMY] = elem_grid(g->n_bins);
@@ -785,14 +785,22 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
         }
         if (rc || (rc = prof_end(ev, s))) return rc;
     } else {
-        B.f = f; B.out = st->w.G; B.mu = st->w.mu; B.want_mu = want_mu ? 1 : 0;
-        B.part_f = st->w.red[RED_SUMF].part;
-        B.n_part_f = sumf_grid(g);
-        B.red_mu = st->w.red[RED_SUMMU];
-        if (osem) B.beta_over_M = 0.0f;
+        // 3D: the back-projection into G, then (SDP-BSREM) the penalty
+        // gradient added to it and mu, then the update
+        B.out = st->w.G;
         if ((rc = prof_begin(st, 1, s, &ev, true))) return rc;
         rc = launch_bp(g, B, s);
         if (rc || (rc = prof_end(ev, s))) return rc;
+        if (!osem) {
+            BPLaunch P = B;
+            P.f = f; P.mu = st->w.mu; P.want_mu = want_mu ? 1 : 0;
+            P.part_f = st->w.red[RED_SUMF].part;
+            P.n_part_f = sumf_grid(g);
+            P.red_mu = st->w.red[RED_SUMMU];
+            if ((rc = prof_begin(st, 3, s, &ev, true))) return rc;
+            rc = launch_pen3(g, P, s);
+            if (rc || (rc = prof_end(ev, s))) return rc;
+        }
         UpdLaunch U{};
         U.osem_sens = sens_i;
         U.f = f; U.fz = st->w.fz; U.G = st->w.G; U.mu = st->w.mu; U.pnorm = g->pnorm; U.nu_frozen = st->w.nu_frozen;
@@ -801,7 +809,7 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
         U.nu1 = (float)st->p.nu1; U.nu2 = (float)st->p.nu2;
         U.box = make_box(st->p.U, st->p.t_clip);
         U.part_mu = st->w.red[RED_SUMMU].part;
-        U.n_part_mu = bp_grid(g);
+        U.n_part_mu = pen3_grid(g);
         U.red_f = st->w.red[RED_SUMF];
         if ((rc = prof_begin(st, 2, s, &ev, true))) return rc;
         rc = launch_update(g, U, s);
@@ -1113,6 +1121,12 @@ int pet_os_subset_gradient(const pet_os_geom* g, const pet_os_params* p, const f
         P.w = wsino; P.w_natural = 0; P.angles = angles; P.n_al = n_al; P.out = w.G;
         if (!rc) rc = launch_bp(g, P, s);
         if (!rc) rc = launch_upd2(g, B, w.G, true, s);
+    } else if (!rc && g->d.dim == 3) {
+        // the back-projection into grad, then the penalty gradient added to it
+        BPLaunch P = B;
+        P.f = nullptr;
+        rc = launch_bp(g, P, s);
+        if (!rc) rc = launch_pen3(g, B, s);
     } else if (!rc) {
         rc = launch_bp(g, B, s);
     }
@@ -1279,7 +1293,7 @@ int pet_os_state_seek(pet_os_state* st, int64_t k, int32_t i, double t_nest, con
 
 int pet_os_state_profile(pet_os_state* st, int32_t kernel) {
     if (!st) return fail(PET_OS_ERR_INVALID_ARG, "state is NULL");
-    if (kernel < -1 || kernel > 2) return fail(PET_OS_ERR_INVALID_ARG, "kernel must be -1..2");
+    if (kernel < -1 || kernel > 3) return fail(PET_OS_ERR_INVALID_ARG, "kernel must be -1..3");
     st->prof_kernel = kernel;
     return PET_OS_OK;
 }

@@ -262,6 +262,11 @@ int bp3_shape(const pet_os_geom* g, int& nb, int& zb, int& rw, int& dpg);
 int launch_fp3(const pet_os_geom* g, const FPLaunch& L, hipStream_t s);
 int launch_bp3(const pet_os_geom* g, const BPLaunch& L, hipStream_t s);
 int launch_update3(const pet_os_geom* g, const UpdLaunch& L, hipStream_t s);
+// 3D: G = out + (beta/M) grad R(f) in place over the back-projection in
+// L.out, mu and the partials of sum mu (L.f, mu, want_mu, beta_over_M,
+// gamma_R, eps, part_f, n_part_f, red_mu); one partial per block of pen3_grid
+int launch_pen3(const pet_os_geom* g, const BPLaunch& L, hipStream_t s);
+int pen3_grid(const pet_os_geom* g);
 // z-fastest copy of f and the partials of sum f (same tiles and order as the 3D update)
 int launch_prep3(const pet_os_geom* g, const float* f, float* fz, Reduction red, hipStream_t s);
 void bp_stage_shape_kind(const pet_os_geom* G, int kind, int& nb_max, int& rows_max, int& chunk, size_t& lds);
@@ -305,11 +310,11 @@ struct Item {
 };
 
 // work lists: 2D forward + pixel pass, 2D back-projection + update per tile
-// kind, and the 3D forward, back-projection per z-block size (16/32/64) and
-// update
+// kind, and the 3D forward, back-projection per z-block size (16/32/64),
+// penalty gradient and mu, and update
 // (lists WL_BP3 + 2 * zi + wi: z-block 16/32/64 for zi = 0/1/2, LDS row
 // stride 20/40 bins for wi = 0/1)
-enum { WL_FP = 0, WL_BP0 = 1, WL_BP1 = 2, WL_FP3 = 3, WL_BP3 = 4, WL_UPD3 = 10, WL_COUNT = 11 };
+enum { WL_FP = 0, WL_BP0 = 1, WL_BP1 = 2, WL_FP3 = 3, WL_BP3 = 4, WL_UPD3 = 10, WL_PEN3 = 11, WL_COUNT = 12 };
 
 // Queue one batched subiteration (every active slot advances by one):
 // forward, back-projection (one launch per tile kind), update, advance.
@@ -321,6 +326,7 @@ void launch_batch3_bp(const SlotDev* d_slots, const Item* list, const int* cnt, 
                       hipStream_t s);
 int bp3_nbs_of(const pet_os_geom* g);   // LDS row stride of the 3D back-projector (20 or 40)
 void launch_batch3_upd(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, hipStream_t s);
+void launch_batch3_pen(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, hipStream_t s);
 
 }  // namespace petos
 

@@ -1360,6 +1360,7 @@ int launch_batch_step(SlotDev* d_slots, int n_slots, Item* const lists[WL_COUNT]
         if (live(WL_BP3 + k))
             launch_batch3_bp(d_slots, lists[WL_BP3 + k], d_counts + WL_BP3 + k, grids[WL_BP3 + k], zbs[k / 2],
                              (k & 1) ? 40 : 20, s);
+    if (live(WL_PEN3)) launch_batch3_pen(d_slots, lists[WL_PEN3], d_counts + WL_PEN3, grids[WL_PEN3], s);
     if (live(WL_UPD3)) launch_batch3_upd(d_slots, lists[WL_UPD3], d_counts + WL_UPD3, grids[WL_UPD3], s);
     hipLaunchKernelGGL(k_advance, dim3((n_slots + NT - 1) / NT), dim3(NT), 0, s, d_slots, n_slots);
     PETOS_HIP(hipGetLastError());

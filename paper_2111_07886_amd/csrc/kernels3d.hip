@@ -27,8 +27,13 @@
 //            relative to the block, zero outside the valid rings), in a
 //            staging area sized to the geometry's footprint (dynamic LDS in
 //            the single-request kernel).  The four waves' partial sums are added in a
-//            fixed order, then the RDP gradient, mu and G of the column tile
-//            are computed from an LDS halo of f.  No atomics.
+//            fixed order and the tile's back-projection is stored.  No
+//            atomics.
+//   k_pen3   the image-space part of a subiteration on 32 x 8 x 8 voxel
+//            tiles with an LDS halo of f: G = A_i^T w + (beta/M) grad R(f)
+//            (eqn:gradRD), mu (Sec. III-B) and FP64 partials of sum mu.
+//            Apart from the back-projector, it runs at the occupancy of a
+//            small kernel instead of at the end of every column tile.
 //   k_upd3   the update of k_update on 64 x 32 (x, z) tiles, also writing
 //            the z-fastest copy through LDS; FP64 partials of sum f.
 //   k_prep3  the z-fastest copy and the sum-f partials of a caller's image
@@ -57,7 +62,7 @@ struct FP3Args {
 };
 
 constexpr int FP3_W = NT / 64;      // waves per block: one (angle, bin, ring difference) each
-constexpr int FP3_CAP = 4 * 64;     // pieces of a stretch of 64 major cells (<= 4 per cell)
+constexpr int FP3_CAP = 3 * 64;     // pieces of a stretch of 64 major cells (<= 3 per cell)
 
 struct Piece {
     int off;      // (iy * nx + ix) * nz + o
@@ -117,60 +122,67 @@ __device__ void fp3_body(const GeoK& g, const FP3Args& A, long long vblock) {
         const double Qz = (double)d * zb.tauQ;
         const double invQz = (d == 0) ? 0.0 : g.inv_d[di] * zb.inv_tauQ;
         const double Lk = tx.L * g.kappa[(long long)b * ND + di];
-        const int qstep = (tx.Q > 0.0) ? 1 : -1;
-        const int zstep = (Qz > 0.0) ? 1 : -1;
+        const int qstep = (tx.Q >= 0.0) ? 1 : -1;
+        const int zstep = (Qz >= 0.0) ? 1 : -1;
+        const float Lkf = (float)Lk, invQf = (float)tx.invQ, invQzf = (float)invQz;
         // a LOR between rings r1 and r1 + d stays in slices r1 + [min(0,d), max(0,d)]
         const int olo = min(0, d), ohi = max(0, d);
         for (int mb = m0; mb <= m1; mb += 64) {
-            // (1) the lane's major cell: up to four pieces (minor cell c0 or
-            // its neighbour) x (slice offset o0 or its neighbour)
+            // (1) the lane's major cell: up to three pieces.  Over the cell
+            // the ray's transaxial minor coordinate runs from gm to gm + Q
+            // and its axial coordinate from zm to zm + Qz; each crosses at
+            // most one edge, at the fraction tx or tz of the cell's length
+            // (decided in FP64, the fractions formed in FP32 from the FP64
+            // distances).  The pieces, in order along the ray: up to the
+            // first crossing in (c0, o0), then up to the second in the cell
+            // the first crossing leads to, then in (c0 + qstep, o0 + zstep).
             const int m = mb + lane;
-            int off[4] = {0, 0, 0, 0};
-            float len[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            int off[3] = {0, 0, 0};
+            float len[3] = {0.0f, 0.0f, 0.0f};
             int present = 0;
             if (m <= m1) {
                 const double gm = __fma_rn(tx.Q, (double)m, tx.P);
                 const double zm = __fma_rn(Qz, (double)m, zeta0);
-                const int c0 = (int)floor(gm), o0 = (int)floor(zm);
+                const double cf = floor(gm), of = floor(zm);
+                const int c0 = (int)cf, o0 = (int)of;
+                const double ce = (tx.Q >= 0.0) ? cf + 1.0 : cf;    // the edges the ray may cross
+                const double oe = (Qz >= 0.0) ? of + 1.0 : of;
+                const double ge = gm + tx.Q, ze = zm + Qz;
+                const bool xc = (tx.Q >= 0.0) ? (ge > ce) : (ge < ce);
+                const bool zc = (Qz >= 0.0) ? (ze > oe) : (ze < oe);
+                const float tX = xc ? (float)(ce - gm) * invQf : 1.0f;
+                const float tZ = zc ? (float)(oe - zm) * invQzf : 1.0f;
+                const bool x_first = tX <= tZ;
+                const float t1 = fminf(tX, tZ), t2 = fmaxf(tX, tZ);
+                const int c1 = c0 + qstep, o1 = o0 + zstep;
+                const float frac[3] = {t1, t2 - t1, 1.0f - t2};
+                const int pc[3] = {c0, x_first ? c1 : c0, c1};
+                const int po[3] = {o0, x_first ? o0 : o1, o1};
+                const bool exists[3] = {true, xc || zc, xc && zc};
 #pragma unroll
-                for (int kx = 0; kx < 2; ++kx) {
-                    const int c = c0 + kx * qstep;
-                    if ((kx == 1 && tx.Q == 0.0) || c < 0 || c >= n_minor) continue;
-                    double lx, hx;
-                    cell_interval(gm, tx.Q, tx.invQ, c, lx, hx);
-                    if (!(hx > lx)) continue;
+                for (int k = 0; k < 3; ++k) {
+                    const int c = pc[k], o = po[k];
+                    if (!exists[k] || !(frac[k] > 0.0f) || c < 0 || c >= n_minor || o < olo || o > ohi) continue;
                     const int ix = tx.row_major ? c : m, iy = tx.row_major ? m : c;
-                    const int col = (iy * g.nx + ix) * g.nz;
-#pragma unroll
-                    for (int kz = 0; kz < 2; ++kz) {
-                        if (kz == 1 && Qz == 0.0) continue;
-                        const int o = o0 + kz * zstep;
-                        if (o < olo || o > ohi) continue;
-                        double lz, hz;
-                        cell_interval(zm, Qz, invQz, o, lz, hz);
-                        const double l = fmin(hx, hz) - fmax(lx, lz);
-                        if (l > 0.0) {
-                            off[2 * kx + kz] = col + o;
-                            len[2 * kx + kz] = counting ? 1.0f : (float)(Lk * l);
-                            present |= 1 << (2 * kx + kz);
-                        }
-                    }
+                    off[k] = (iy * g.nx + ix) * g.nz + o;
+                    len[k] = counting ? 1.0f : Lkf * frac[k];
+                    present |= 1 << k;
                 }
             }
             // (2) compact the pieces of the 64 cells, in cell order, into LDS
-            // (each lane has 0..4 pieces: the exclusive prefix of the counts
-            // is the sum over their three bits of 2^k x the lanes below with
+            // (each lane has 0..3 pieces: the exclusive prefix of the counts
+            // is the sum over their two bits of 2^k x the lanes below with
             // bit k set, counted from the wave's ballots)
             const int cnt = __popc(present);
             int pos = 0, total = 0;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
+            for (int k = 0; k < 2; ++k) {
                 const unsigned long long m = __ballot((cnt >> k) & 1);
                 pos += __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u)) << k;
                 total += __popcll(m) << k;
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < 3; ++k) {
                 if (present & (1 << k)) {
                     s_pc[wave][pos] = Piece{off[k], len[k]};
                     ++pos;
@@ -237,14 +249,7 @@ struct BP3Args {
     int w_natural;           // angle_index = natural angle (1) or position in the list (0)
     const int* angles;
     int n_al;
-    float* out;
-    const float* f;          // non-null => fused stencil, out = G
-    float* mu;
-    int want_mu;
-    float beta_over_M, gamma_R, eps;
-    const double* part_f;
-    int n_part_f;
-    Reduction red_mu;
+    float* out;              // the back-projection A_i^T w
     int nb;                  // staged bins per angle
     int zb;                  // slices per block: 16, 32 or 64
     int rw;                  // staged rows per (ring difference, bin)
@@ -294,11 +299,12 @@ __device__ __forceinline__ void bp3_apply(float (&acc)[BP3_ZMAX], const float* s
 }
 
 // After all angles: add the four waves' partial sums in wave order into
-// s_fin[lz][column] (top of the LDS area), then either store the
-// back-projection or compute the RDP gradient, mu and G of the tile's voxels.
+// s_fin[lz][column] (top of the LDS area) and store the tile's
+// back-projection.  The penalty gradient, mu and G of a subiteration follow
+// in k_pen3.
 template <int ZB>
-__device__ void bp3_finish(const GeoK& g, const BP3Args& A, float (&acc)[BP3_ZMAX], BP3Shared& sh, float* s_w,
-                           float meanf, int vblock, int tx0, int ty0, int z0) {
+__device__ void bp3_finish(const GeoK& g, const BP3Args& A, float (&acc)[BP3_ZMAX], float* s_w, int tx0, int ty0,
+                           int z0) {
     constexpr int QS = ZB / 4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     float* s_fin = s_w + (A.lds - ZB * 64);
@@ -320,44 +326,11 @@ __device__ void bp3_finish(const GeoK& g, const BP3Args& A, float (&acc)[BP3_ZMA
         }
     }
     __syncthreads();
-    if (A.f == nullptr) {
-        for (int e = threadIdx.x; e < ZB * 64; e += NT) {
-            const int c = e & 63, lz = e >> 6;
-            const int ix = tx0 + (c & 7), iy = ty0 + (c >> 3), iz = z0 + lz;
-            if (ix < g.nx && iy < g.ny && iz < g.nz) A.out[((long long)iz * g.ny + iy) * g.nx + ix] = s_fin[e];
-        }
-        return;
-    }
-    // halo tile of f: (8+2) x (8+2) x (ZB+2), below s_fin (the host sizes the
-    // staging area to hold both)
-    constexpr int HX = BP3_T + 2, HY = BP3_T + 2, HZ = ZB + 2;
-    for (int e = threadIdx.x; e < HX * HY * HZ; e += NT) {
-        const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
-        const int gx = tx0 - 1 + hx, gy = ty0 - 1 + hy, gz = z0 - 1 + hz;
-        float v = 0.0f;
-        if (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz)
-            v = A.f[((long long)gz * g.ny + gy) * g.nx + gx];
-        s_w[e] = v;
-    }
-    __syncthreads();
-    double mu_part = 0.0;
     for (int e = threadIdx.x; e < ZB * 64; e += NT) {
         const int c = e & 63, lz = e >> 6;
-        const int lx = c & 7, ly = c >> 3;
-        const int ix = tx0 + lx, iy = ty0 + ly, iz = z0 + lz;
-        if (ix < g.nx && iy < g.ny && iz < g.nz) {
-            float gradR, gmag;
-            stencil_at<3>(s_w, HX, HY, lx + 1, ly + 1, lz + 1, ix, iy, iz, g, A.gamma_R, A.eps, gradR, gmag);
-            const long long j = ((long long)iz * g.ny + iy) * g.nx + ix;
-            A.out[j] = fmaf(A.beta_over_M, gradR, s_fin[e]);
-            if (A.want_mu) {
-                const float mu = fmaxf(0.01f, gmag / meanf);
-                A.mu[j] = mu;
-                mu_part += (double)mu;
-            }
-        }
+        const int ix = tx0 + (c & 7), iy = ty0 + (c >> 3), iz = z0 + lz;
+        if (ix < g.nx && iy < g.ny && iz < g.nz) A.out[((long long)iz * g.ny + iy) * g.nx + ix] = s_fin[e];
     }
-    if (A.want_mu) write_partial(mu_part, A.red_mu, sh.red, vblock);
 }
 
 // Stage w of ring differences dg .. dg+dpg-1 into buf as [d][row][bin], row r
@@ -480,8 +453,6 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared&
     const double X0 = ((double)tx0 - 0.5 * g.nx) * g.vx, X1 = X0 + BP3_T * g.vx;
     const double Y0 = ((double)ty0 - 0.5 * g.ny) * g.vy, Y1 = Y0 + BP3_T * g.vy;
 
-    float meanf = 1.0f;
-    if (A.f != nullptr && A.want_mu) meanf = (float)(sum_partials(A.part_f, A.n_part_f, sh.red) / (double)g.nvox);
 
     float acc[BP3_ZMAX];
 #pragma unroll
@@ -602,7 +573,7 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared&
         }
         __syncthreads();    // the angle's shared values are read no more
     }
-    bp3_finish<ZB>(g, A, acc, sh, s_w, meanf, vblock, tx0, ty0, z0);
+    bp3_finish<ZB>(g, A, acc, s_w, tx0, ty0, z0);
 }
 
 // dynamic LDS: the staging area, A.lds floats.  Up to 32 slices per block the
@@ -614,6 +585,92 @@ __global__ __launch_bounds__(NT, ZB <= 32 ? 4 : 1) void k_bp3(GeoK g, BP3Args A,
     const int tile = (int)xcd_block(blockIdx.x, n_tiles);
     if (tile >= n_tiles) return;
     bp3_body<ZB, NBS>(g, A, tile, sh, bp3_stage_area);
+}
+
+// ------------------------------------------------------------------ penalty gradient and mu
+
+// The image-space part of a 3D subiteration after the back-projection b =
+// A_i^T w: G = b + (beta/M) grad R(f) (eqn:gradRD, 26 in-image neighbours)
+// in place over b, and with want_mu the smoothness measure mu = max(0.01,
+// |grad f| / mean f) (Sec. III-B) with the block's FP64 partial of sum mu.
+// One block per 32 (x) x 8 (y) x 8 (z) voxels (a thread per (x, y), eight
+// slices each); f with a one-voxel halo in LDS.
+constexpr int PEN3_X = 32, PEN3_Y = 8, PEN3_Z = 8;
+
+struct Pen3Args {
+    const float* f;
+    float* G;                // in: b, out: G
+    float* mu;
+    int want_mu;
+    float beta_over_M, gamma_R, eps;
+    const double* part_f;    // partials of sum f of the entering iterate (mean f)
+    int n_part_f;
+    Reduction red_mu;
+};
+
+__host__ __device__ inline int pen3_tiles(int n, int t) { return (n + t - 1) / t; }
+
+__device__ void pen3_body(const GeoK& g, const Pen3Args& A, int vblock) {
+    constexpr int HX = PEN3_X + 2, HY = PEN3_Y + 2, HZ = PEN3_Z + 2;
+    __shared__ float s_f[HX * HY * HZ];
+    __shared__ double s_red[NT / 64];
+    const int tx = pen3_tiles(g.nx, PEN3_X), ty = pen3_tiles(g.ny, PEN3_Y);
+    const int x0 = (vblock % tx) * PEN3_X, y0 = ((vblock / tx) % ty) * PEN3_Y, z0 = (vblock / (tx * ty)) * PEN3_Z;
+    for (int e = threadIdx.x; e < HX * HY * HZ; e += NT) {
+        const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
+        const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+        float v = 0.0f;
+        if (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz)
+            v = A.f[((long long)gz * g.ny + gy) * g.nx + gx];
+        s_f[e] = v;
+    }
+    float meanf = 1.0f;
+    if (A.want_mu) meanf = (float)(sum_partials(A.part_f, A.n_part_f, s_red) / (double)g.nvox);
+    __syncthreads();
+    const int lx = threadIdx.x % PEN3_X, ly = threadIdx.x / PEN3_X;
+    const int ix = x0 + lx, iy = y0 + ly;
+    double mu_part = 0.0;
+    if (ix < g.nx && iy < g.ny) {
+        for (int lz = 0; lz < PEN3_Z; ++lz) {
+            const int iz = z0 + lz;
+            if (iz >= g.nz) break;
+            float gradR, gmag;
+            stencil_at<3>(s_f, HX, HY, lx + 1, ly + 1, lz + 1, ix, iy, iz, g, A.gamma_R, A.eps, gradR, gmag);
+            const long long j = ((long long)iz * g.ny + iy) * g.nx + ix;
+            A.G[j] = fmaf(A.beta_over_M, gradR, A.G[j]);
+            if (A.want_mu) {
+                const float mu = fmaxf(0.01f, gmag / meanf);
+                A.mu[j] = mu;
+                mu_part += (double)mu;
+            }
+        }
+    }
+    if (A.want_mu) write_partial(mu_part, A.red_mu, s_red, vblock);
+}
+
+__global__ __launch_bounds__(NT) void k_pen3(GeoK g, Pen3Args A) { pen3_body(g, A, blockIdx.x); }
+
+int pen3_grid(const pet_os_geom* G) {
+    return pen3_tiles(G->d.nx, PEN3_X) * pen3_tiles(G->d.ny, PEN3_Y) * pen3_tiles(G->d.nz, PEN3_Z);
+}
+
+int launch_pen3(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
+    Pen3Args a{};
+    a.f = L.f;
+    a.G = L.out;
+    a.mu = L.mu;
+    a.want_mu = L.want_mu;
+    a.beta_over_M = L.beta_over_M;
+    a.gamma_R = L.gamma_R;
+    a.eps = L.eps;
+    a.part_f = L.part_f;
+    a.n_part_f = L.n_part_f;
+    a.red_mu = L.red_mu;
+    const int grid = pen3_grid(G);
+    if (L.want_mu && grid > L.red_mu.cap) return fail(PET_OS_ERR_DEVICE, "mu partials too small");
+    petos_launch(k_pen3, dim3(grid), dim3(NT), 0, s, G->k, a);
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
 }
 
 // ------------------------------------------------------------------ update and z-fastest copy
@@ -770,7 +827,7 @@ int bp3_shape_single(const pet_os_geom* G, int zb, int dpg_req, int& nb, int& rw
     const long long nbs = bp3_nbs(nb);
     dpg = dpg_req > 0 ? dpg_req : ((8LL * nbs * rw <= BP3_LDS / 2) ? 8 : 4);
     const long long h = (long long)dpg * nbs * rw;
-    const long long fin = (long long)(BP3_T + 2) * (BP3_T + 2) * (zb + 2) + (long long)zb * 64;
+    const long long fin = 2LL * zb * 64;     // the finish: the waves' partial sums and their total
     const long long total = std::max(2 * h, fin);
     if (total > BP3_LDS)
         return fail(PET_OS_ERR_INVALID_ARG, "3D geometry: back-projection footprint does not fit in LDS");
@@ -812,15 +869,6 @@ static void fill_bp3(const pet_os_geom* G, const BPLaunch& L, BP3Args& a) {
     a.angles = L.angles;
     a.n_al = L.n_al;
     a.out = L.out;
-    a.f = L.f;
-    a.mu = L.mu;
-    a.want_mu = L.want_mu;
-    a.beta_over_M = L.beta_over_M;
-    a.gamma_R = L.gamma_R;
-    a.eps = L.eps;
-    a.part_f = L.part_f;
-    a.n_part_f = L.n_part_f;
-    a.red_mu = L.red_mu;
 }
 
 int launch_bp3(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
@@ -830,8 +878,8 @@ int launch_bp3(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
     a.zb = bp3_zb_single(G);
     int rc = bp3_shape_single(G, a.zb, G->tuned_dpg, a.nb, a.rw, a.dpg, a.half, a.lds);
     if (rc) return rc;
+    if (L.f != nullptr) return fail(PET_OS_ERR_DEVICE, "the 3D penalty gradient is k_pen3's (launch_pen3)");
     const int grid = bp3_grid(G);
-    if (L.want_mu && grid > L.red_mu.cap) return fail(PET_OS_ERR_DEVICE, "mu partials too small");
     const bool wide = bp3_nbs(a.nb) == 40;
     const dim3 blocks(8 * ((grid + 7) / 8));
     const size_t lds = (size_t)a.lds * sizeof(float);
@@ -940,7 +988,6 @@ __global__ __launch_bounds__(NT) void k_bp3_batch(const SlotDev* __restrict__ S,
         const SlotDev& d = S[I.slot];
         if (!slot_live3(d) || d.zb != ZB) continue;
         const int i = (d.J - 1) % d.g.n_subsets;
-        const int nu_mode = d.sched_nu[d.J - 1];
         BP3Args A{};
         A.w = d.w;
         A.w_natural = 0;
@@ -949,7 +996,27 @@ __global__ __launch_bounds__(NT) void k_bp3_batch(const SlotDev* __restrict__ S,
         A.angles = d.subset_lists + (long long)i * d.max_sub;
         A.n_al = d.subset_count[i];
         A.out = d.G;
+        A.nb = d.nb_max;
+        A.zb = d.zb;
+        A.rw = d.rows_max;
+        A.dpg = d.chunk;
+        A.half = BP3_LDS / 2;
+        A.lds = BP3_LDS;
+        bp3_body<ZB, NBS>(d.g, A, I.block, sh, s_w);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_pen3_batch(const SlotDev* __restrict__ S, const Item* __restrict__ items, const int* __restrict__ count) {
+    const int n = *count;
+    for (int it = xcd_item(blockIdx.x, gridDim.x); it < n; it += gridDim.x) {
+        const Item I = items[it];
+        const SlotDev& d = S[I.slot];
+        if (!slot_live3(d)) continue;
+        const int nu_mode = d.sched_nu[d.J - 1];
+        Pen3Args A{};
         A.f = d.f;
+        A.G = d.G;
         A.mu = d.mu;
         A.want_mu = (nu_mode == NU_COMPUTE || nu_mode == NU_COMPUTE_FREEZE) ? 1 : 0;
         A.beta_over_M = d.beta_over_M;
@@ -960,13 +1027,7 @@ __global__ __launch_bounds__(NT) void k_bp3_batch(const SlotDev* __restrict__ S,
         A.red_mu.part = d.part_mu;
         A.red_mu.total = nullptr;
         A.red_mu.cap = d.n_part_mu;
-        A.nb = d.nb_max;
-        A.zb = d.zb;
-        A.rw = d.rows_max;
-        A.dpg = d.chunk;
-        A.half = BP3_LDS / 2;
-        A.lds = BP3_LDS;
-        bp3_body<ZB, NBS>(d.g, A, I.block, sh, s_w);
+        pen3_body(d.g, A, I.block);
         __syncthreads();
     }
 }
@@ -1002,7 +1063,7 @@ __global__ __launch_bounds__(NT) void k_upd3_batch(const SlotDev* __restrict__ S
     }
 }
 
-// the 3D part of one batched subiteration (lists WL_FP3, WL_BP3_*, WL_UPD3)
+// the 3D part of one batched subiteration (lists WL_FP3, WL_BP3_*, WL_PEN3, WL_UPD3)
 void launch_batch3_fp(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_fp3_batch, dim3(grid), dim3(NT), 0, s, d_slots, list, cnt);
 }
@@ -1021,6 +1082,10 @@ int bp3_nbs_of(const pet_os_geom* G) {
     int nb, zb, rw, dpg;
     if (bp3_shape(G, nb, zb, rw, dpg)) return 40;
     return bp3_nbs(nb);
+}
+
+void launch_batch3_pen(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_pen3_batch, dim3(grid), dim3(NT), 0, s, d_slots, list, cnt);
 }
 
 void launch_batch3_upd(const SlotDev* d_slots, const Item* list, const int* cnt, int grid, hipStream_t s) {
