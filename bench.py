@@ -203,6 +203,28 @@ def onchip_ceilings(c, avg_us, traffic):
     return out
 
 
+# FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2 (packed
+# FP32) x 2.4 GHz = 157.3 TFLOP/s, the published figure; the kernels are
+# built without packed FP32, which halves what they can issue (78.6)
+FP32_VECTOR_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2 * CLOCK_HZ / 1e12
+FP32_UNPACKED_PEAK_TFLOPS = FP32_VECTOR_PEAK_TFLOPS / 2
+
+
+def algorithmic_flops(kernel, nnz_sub, rays_sub, q):
+    """Floating-point work one 3D launch must do: one FMA (2 flops) per
+    nonzero in either projector; the Poisson ratio (add, divide, subtract)
+    per ray; the penalty (kernel 3) 26 neighbour terms of 10 flops plus the
+    gradient magnitude and mu (about 280 per voxel); the update (kernel 2)
+    about 12 per voxel (nu, S, step, P_t)."""
+    if kernel == 0:
+        return 2.0 * nnz_sub + 3.0 * rays_sub
+    if kernel == 1:
+        return 2.0 * nnz_sub
+    if kernel == 3:
+        return 280.0 * q
+    return 12.0 * q
+
+
 def algorithmic_bytes(kernel, nnz_sub, rays_sub, q, dim=3, osem=False, psf=False):
     """Bytes one launch must move (A is computed on the fly, never stored).
     3D, four launches: forward: 4 B image gather per nonzero + read y, r and
@@ -382,6 +404,18 @@ def oracle_recons_rate(items, budget_s=15.0, note=""):
             "subiterations_per_s": round(subs / dt, 3), "host": host_cpu()}
 
 
+def calibrate_copy(dev):
+    """A plain device copy of COPY_BYTES, the reference for scaling the
+    FETCH_SIZE / WRITE_SIZE counters of the same process."""
+    import torch
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
 def bench_batched(args, cpu=True):
     """96 uneven 2D reconstructions (10 iterations each): one batch, one
     captured step per subiteration, vs the same requests one at a time."""
@@ -410,6 +444,8 @@ def bench_batched(args, cpu=True):
         bytes_total += n * (8.0 * G.nnz(0) + 16.0 * G.n_bins + 32.0 * M * G.n_voxels)
     params = [p for _, p, _ in reqs]
     iters = [n for _, _, n in reqs]
+    if getattr(args, "calibrate_copy", False):
+        calibrate_copy(dev)
     # warm-up (graph capture, caches)
     progress("batched: geometries ready, timing")
     fs = [torch.tensor(w.f0, dtype=torch.float32, device=dev) for w, _, _ in reqs]
@@ -735,12 +771,7 @@ def main():
     state = pet.State(geom, p)
 
     if args.calibrate_copy:
-        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+        calibrate_copy(dev)
 
     # warm-up, then exactly `steps` timed iterations bracketed by synchronisation
     # the timed steps are subiterations only: the objective (not part of a
@@ -804,19 +835,9 @@ def main():
     roofline = None
     if per_kernel:
         dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"])
-        K = per_kernel[dom]
-        achieved = K["bytes"] / (K["avg_us"] * 1e-6) / 1e9
-        traffic = stored_traffic(args.workload, p["mode"], shapes, dom)
-        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                    "kernel": names[dom], "avg_launch_us": round(K["avg_us"], 3),
-                    "algorithmic_bytes_per_launch": int(K["bytes"]),
-                    "per_kernel_us": {names[k].split(" (")[0]: round(v["avg_us"], 3) for k, v in per_kernel.items()},
-                    # achieved/frac above: algorithmic bytes (4 B per nonzero, most served by LDS or
-                    # L2) per launch over its duration; below, what the launch reaches of each
-                    # ceiling it meets on the chip, from the counters on record and the same duration
-                    "ceilings": onchip_ceilings(stored_counters(args.workload, p["mode"], shapes, dom),
-                                                K["avg_us"], traffic)}
+        roofline = roofline_of(per_kernel, dom, names, dim, nnz_sub, rays_sub, q,
+                               stored_traffic(args.workload, p["mode"], shapes, dom),
+                               stored_counters(args.workload, p["mode"], shapes, dom))
 
     del state
     cpu, parity = None, None
@@ -863,6 +884,37 @@ def main():
             out["served"] = leg_summary(bench_served(args, cpu=not args.no_cpu_baseline))
             progress(f"served leg done: {out['served']['recons_per_s']} recons/s")
     print(json.dumps(out), flush=True)
+
+
+def roofline_of(per_kernel, dom, names, dim, nnz_sub, rays_sub, q, traffic, counters):
+    """The roofline record of the dominant kernel `dom`.  2D: HBM-bound,
+    achieved = its algorithmic bytes over its average launch.  3D: the
+    projectors' gathers are served by LDS and L2, not HBM (their algorithmic
+    byte rate exceeds what HBM delivers), so the bound is the VALU: achieved
+    = algorithmic flops over the launch against FP32 FMA issue; the byte
+    rate is kept under its own key.  `ceilings`: what the launch reaches of
+    each on-chip ceiling, from the counters on record and the same
+    duration."""
+    K = per_kernel[dom]
+    t = K["avg_us"] * 1e-6
+    rate_gbs = K["bytes"] / t / 1e9
+    common = {"traffic": traffic, "kernel": names[dom], "avg_launch_us": round(K["avg_us"], 3),
+              "algorithmic_bytes_per_launch": int(K["bytes"]),
+              "per_kernel_us": {names[k].split(" (")[0]: round(v["avg_us"], 3) for k, v in per_kernel.items()},
+              "ceilings": onchip_ceilings(counters, K["avg_us"], traffic)}
+    if dim == 3:
+        fl = algorithmic_flops(dom, nnz_sub, rays_sub, q)
+        achieved = fl / t / 1e12
+        out = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(FP32_VECTOR_PEAK_TFLOPS, 1),
+               "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5),
+               "frac_of_unpacked_fp32": round(achieved / FP32_UNPACKED_PEAK_TFLOPS, 5),
+               "algorithmic_flops_per_launch": int(fl),
+               "algorithmic_bytes_GBs": round(rate_gbs, 1)}
+    else:
+        out = {"bound": "hbm", "achieved": round(rate_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(rate_gbs / HBM_PEAK_GBS, 5)}
+    out.update(common)
+    return out
 
 
 def leg_summary(line):

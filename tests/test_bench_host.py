@@ -163,3 +163,27 @@ def test_counters_and_onchip_ceilings(bench, tmp_path):
     assert abs(out["l2_requests"]["frac"] - 0.5) < 1e-9 and out["l2_requests"]["hit_rate"] == 0.8
     assert out["hbm_counted"]["achieved_GBs"] == 4000.0 and out["hbm_counted"]["frac"] == 0.5
     assert bench.onchip_ceilings(None, 2.0, None) is None
+
+
+def test_roofline_bound_by_dimension(bench):
+    """2D: the dominant kernel's algorithmic bytes over its launch against
+    8 TB/s.  3D: the gathers are served on chip, so the record is the VALU
+    bound: 2 flops per nonzero over the launch against the published FP32
+    vector peak (157.3 TFLOP/s; 78.6 without packed FP32), with the byte
+    rate under its own key."""
+    assert abs(bench.FP32_VECTOR_PEAK_TFLOPS - 157.2864) < 1e-9
+    assert abs(bench.FP32_UNPACKED_PEAK_TFLOPS - 78.6432) < 1e-9
+    names = {0: "k_fp3 (x)", 1: "k_bp3 (y)"}
+    nnz, rays, q = 1e9, 4e6, 2.5e6
+    per = {0: {"avg_us": 100.0, "bytes": bench.algorithmic_bytes(0, nnz, rays, q, 3)},
+           1: {"avg_us": 400.0, "bytes": bench.algorithmic_bytes(1, nnz, rays, q, 3)}}
+    r3 = bench.roofline_of(per, 1, names, 3, nnz, rays, q, None, None)
+    assert r3["bound"] == "alu" and r3["unit"] == "TFLOP/s"
+    assert abs(r3["achieved"] - 2e9 / 400e-6 / 1e12) < 1e-3            # 5 TFLOP/s
+    assert abs(r3["frac"] - 5.0 / 157.2864) < 1e-5
+    assert abs(r3["algorithmic_bytes_GBs"] - (4 * nnz + 4 * rays + 4 * q) / 400e-6 / 1e9) < 0.1
+    assert r3["kernel"] == "k_bp3 (y)" and r3["traffic"] is None
+    per2 = {1: {"avg_us": 10.0, "bytes": 5e6}}
+    r2 = bench.roofline_of(per2, 1, {1: "k_bp (z)"}, 2, nnz, rays, q, 4e6, None)
+    assert r2["bound"] == "hbm" and r2["achieved"] == 500.0 and r2["frac"] == 0.0625
+    assert r2["ceilings"]["hbm_counted"]["achieved_GBs"] == 400.0
