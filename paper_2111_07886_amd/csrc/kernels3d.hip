@@ -278,22 +278,18 @@ struct BP3Shared {
     double red[NT / 64];
 };
 
-// acc[i] += a1 w(r1 = iz - o1) + a2 w(r1 = iz - o1 - 1) for the ZB slices of
-// the block; sp[(i + 1) * NBS] holds w(r1 = z0 + i - o1), sp[i * NBS] the
-// row before it.  Loads go in batches of 16 to bound the live registers.
+// acc[i] += a w(r1 = iz - o) for the ZB slices of the block, with
+// sp[(i + 1) * NBS] holding w(r1 = z0 + i - o).  Loads go in batches of 16
+// to bound the live registers.
 template <int ZB, int NBS>
-__device__ __forceinline__ void bp3_apply(float (&acc)[BP3_ZMAX], const float* sp, float a1, float a2) {
-    float prev = sp[0];
+__device__ __forceinline__ void bp3_apply(float (&acc)[BP3_ZMAX], const float* sp, float a) {
 #pragma unroll
     for (int c = 0; c < ZB; c += 16) {
         float v[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) v[i] = sp[(c + i + 1) * NBS];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            acc[c + i] = fmaf(a1, v[i], fmaf(a2, prev, acc[c + i]));
-            prev = v[i];
-        }
+        for (int i = 0; i < 16; ++i) acc[c + i] = fmaf(a, v[i], acc[c + i]);
         __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -333,15 +329,17 @@ __device__ void bp3_finish(const GeoK& g, const BP3Args& A, float (&acc)[BP3_ZMA
     }
 }
 
-// Stage w of ring differences dg .. dg+dpg-1 into buf as [d][row][bin], row r
-// of d holding r1 = z0 - omax(d) + r - 1 (row 0 and invalid rings: zeros;
-// unit weights: ones).  NBS is the row stride; one wave instruction copies
-// 64/NBS consecutive rows straight from device memory into LDS.  Per ring
-// difference the rows of valid rings form one range [rlo, rhi]: the rows
-// outside it are zero-filled by the block, the range is copied in chunks of
-// 64/NBS rows whose only per-lane work is the range test and the address.
-// Returns without waiting: the caller waits for the loads before the barrier
-// that publishes the buffer.
+// Stage w of the calling wave's ring differences of group dg (slots ds =
+// wave, wave + 4, ... < dpg: the ones it gathers) into buf as [ds][row][bin],
+// row r of slot ds holding r1 = z0 - omax(d) + r - 1 (row 0 and invalid
+// rings: zeros; unit weights: ones).  NBS is the row stride; one wave
+// instruction copies 64/NBS consecutive rows straight from device memory into
+// LDS.  Per ring difference the rows of valid rings form one range [rlo,
+// rhi]: the rows outside it are zero-filled by the wave, the range is copied
+// in chunks of 64/NBS rows whose only per-lane work is the range test and the
+// address.  A slot's rows are written and read by the same wave, so no block
+// barrier orders them: the wave waits for its own loads.  Returns without
+// waiting.
 template <int NBS>
 __device__ __forceinline__ void bp3_stage(const GeoK& g, const BP3Args& A, const BP3Shared& sh, float* buf, int dg,
                                           int z0, int aidx, int blo, int nbv) {
@@ -354,7 +352,7 @@ __device__ __forceinline__ void bp3_stage(const GeoK& g, const BP3Args& A, const
     // a lane's element of a chunk: row (chunk start + sub), bin (blo + col);
     // its offset from the chunk's first element is the same in every chunk
     const long long lane_off = (long long)sub * A.w_sp + col;
-    for (int ds = 0; ds < dpg; ++ds) {
+    for (int ds = wave; ds < dpg; ds += 4) {
         const int di = dg + ds;
         if (di >= ND) break;
         const int d = di - D;
@@ -366,21 +364,20 @@ __device__ __forceinline__ void bp3_stage(const GeoK& g, const BP3Args& A, const
         float* bd = buf + ds * rw * NBS;
         // zeros below the range ([0, nzlo)) and above it ([top0, rw))
         const int nzlo = min(rlo, rw), top0 = max(rhi, rlo - 1) + 1, nzhi = max(rw - top0, 0);
-        for (int e = threadIdx.x; e < (nzlo + nzhi) * NBS; e += NT) {
+        for (int e = lane; e < (nzlo + nzhi) * NBS; e += 64) {
             const int rr = e / NBS, cc = e - rr * NBS;
             const int row = rr < nzlo ? rr : top0 + (rr - nzlo);
             bd[row * NBS + cc] = 0.0f;
         }
         if (rhi < rlo) continue;
         if (A.w == nullptr) {
-            for (int e = threadIdx.x; e < (rhi - rlo + 1) * NBS; e += NT) bd[rlo * NBS + e] = 1.0f;
+            for (int e = lane; e < (rhi - rlo + 1) * NBS; e += 64) bd[rlo * NBS + e] = 1.0f;
             continue;
         }
         // (uniform) element of row rlo, bin blo: plane pbase[di] + r1
         const float* wr = A.w + ((long long)sh.pbase[di] + r1_row0 + rlo) * A.w_sp + (long long)aidx * A.w_sa + blo;
-        const long long wstep = (long long)(4 * LPI) * A.w_sp;
-        wr += (long long)(wave * LPI) * A.w_sp;
-        for (int r0 = rlo + wave * LPI; r0 <= rhi; r0 += 4 * LPI, wr += wstep) {
+        const long long wstep = (long long)LPI * A.w_sp;
+        for (int r0 = rlo; r0 <= rhi; r0 += LPI, wr += wstep) {
             if (lane_ok && r0 + sub <= rhi)
                 __builtin_amdgcn_global_load_lds(wr + lane_off, (__attribute__((address_space(3))) void*)(bd + r0 * NBS),
                                                  4, 0, 0);
@@ -390,47 +387,76 @@ __device__ __forceinline__ void bp3_stage(const GeoK& g, const BP3Args& A, const
 
 // Hits of one column for one angle: the transaxial psi-interval [ax, bx] of
 // the column's cell in major cell m, for every bin b0..b1 whose ray crosses it,
-// kept as the tau values at its ends, the transaxial length and the axial
-// slope ck = ring_pitch / (2 h_b) per unit ring difference.  Slots take hits
+// kept as tau at its smaller end (t0) and its tau extent (dt >= 0, from the
+// FP64 difference), the transaxial length and the axial slope ck =
+// ring_pitch / (2 h_b) per unit ring difference.  Over ring difference d the
+// piece runs axially over zeta in 1/2 + d [t0, t0 + dt].  Slots take hits
 // first .. first + BP3_HMAX - 1 (in bin order); returns the number of hits.
 struct Hits {
     int b[BP3_HMAX];
-    double tA[BP3_HMAX], tB[BP3_HMAX];
+    float t0[BP3_HMAX], dt[BP3_HMAX];
     float L[BP3_HMAX], ck[BP3_HMAX];
     bool v[BP3_HMAX];
 };
 
+// One candidate bin b of col_hits, with h and 1 / (2 h) of its table row
+// already loaded.
+__device__ __forceinline__ void col_hit_one(const GeoK& g, const AngleK& AK, double h, double inv2h, int m, int mc,
+                                            int b, int first, float ck0, int& n, Hits& H) {
+    double P;
+    if (AK.Q == 0.0) P = AK.row_major ? g.bin[b].axis_pos_x : g.bin[b].axis_pos_y;
+    else P = __fma_rn(bin_pos(g, b), AK.icv, AK.K);
+    const double gm = __fma_rn(AK.Q, (double)m, P);
+    double ax, bx;
+    cell_interval(gm, AK.Q, AK.invQ, mc, ax, bx);
+    if (!(bx > ax)) return;
+    const int slot = n - first;
+#pragma unroll
+    for (int k = 0; k < BP3_HMAX; ++k) {
+        if (slot == k) {
+            // z_bin: tau at the start of major cell 0 and per major cell
+            const double u0 = __fma_rn(bin_pos(g, b), AK.Au, AK.Bu);
+            const double tau0 = (u0 + h) * inv2h, tauQ = AK.du * inv2h;
+            const double tA = __fma_rn(tauQ, (double)m + ax, tau0);
+            const double tB = __fma_rn(tauQ, (double)m + bx, tau0);
+            H.b[k] = b;
+            H.t0[k] = (float)fmin(tA, tB);
+            H.dt[k] = (float)fabs(tB - tA);
+            H.L[k] = (float)(AK.L * (bx - ax));
+            H.ck[k] = ck0 * (float)inv2h;
+            H.v[k] = true;
+        }
+    }
+    ++n;
+}
+
+// The first two candidates of b0..b1 (of at most four when ds covers half a
+// pixel's radial extent) load h and 1 / (2 h) together, clamped into the
+// table so that the loads need no guard; the others follow one by one (two
+// at once keep the register count at three waves per SIMD).
 __device__ __forceinline__ int col_hits(const GeoK& g, const AngleK& AK, int m, int mc, int b0, int b1, int first,
                                         float ck0, Hits& H) {
 #pragma unroll
     for (int k = 0; k < BP3_HMAX; ++k) {
         H.b[k] = 0;
-        H.tA[k] = H.tB[k] = 0.0;
+        H.t0[k] = H.dt[k] = 0.0f;
         H.L[k] = H.ck[k] = 0.0f;
         H.v[k] = false;
     }
-    int n = 0;
-    for (int b = b0; b <= b1; ++b) {
-        const TxRay tx = tx_ray(g, AK, b);
-        const double gm = __fma_rn(tx.Q, (double)m, tx.P);
-        double ax, bx;
-        cell_interval(gm, tx.Q, tx.invQ, mc, ax, bx);
-        if (!(bx > ax)) continue;
-        const int slot = n - first;
+    constexpr int CMAX = 2;
+    const int last = g.n_radial - 1;
+    double h[CMAX], i2h[CMAX];
 #pragma unroll
-        for (int k = 0; k < BP3_HMAX; ++k) {
-            if (slot == k) {
-                const ZBin zbk = z_bin(g, AK, b);
-                H.b[k] = b;
-                H.tA[k] = __fma_rn(zbk.tauQ, (double)m + ax, zbk.tau0);
-                H.tB[k] = __fma_rn(zbk.tauQ, (double)m + bx, zbk.tau0);
-                H.L[k] = (float)(tx.L * (bx - ax));
-                H.ck[k] = ck0 * (float)g.bin[b].inv2h;
-                H.v[k] = true;
-            }
-        }
-        ++n;
+    for (int c = 0; c < CMAX; ++c) {
+        const BinK& B = g.bin[min(max(b0 + c, 0), last)];
+        h[c] = B.h;
+        i2h[c] = B.inv2h;
     }
+    int n = 0;
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c)
+        if (b0 + c <= b1) col_hit_one(g, AK, h[c], i2h[c], m, mc, b0 + c, first, ck0, n, H);
+    for (int b = b0 + CMAX; b <= b1; ++b) col_hit_one(g, AK, g.bin[b].h, g.bin[b].inv2h, m, mc, b, first, ck0, n, H);
     return n;
 }
 
@@ -528,14 +554,14 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared&
             if (pass > 0) (void)col_hits(g, AK, m, mc, b0, b1, pass * BP3_HMAX, ck0, H);
             // (5) stage w of ring differences in groups of dpg, double buffered:
             // the loads of group k+1 run while group k is gathered
+            // Each wave stages and gathers its own slots: only the
+            // wave's own loads are waited for, no block barrier per group.
             const int ngr = (ND + dpg - 1) / dpg;
-            __syncthreads();
             bp3_stage<NBS>(g, A, sh, s_w, 0, z0, aidx, blo, nbv);
             for (int gi = 0; gi < ngr; ++gi) {
                 const int dg = gi * dpg;
                 float* buf = s_w + (gi & 1) * A.half;
-                __builtin_amdgcn_s_waitcnt(0);      // this thread's loads into buf have landed
-                __syncthreads();                    // ... everyone's; the other buffer is free
+                __builtin_amdgcn_s_waitcnt(0);      // this wave's loads (and zeros) into buf have landed
                 if (gi + 1 < ngr)
                     bp3_stage<NBS>(g, A, sh, s_w + ((gi + 1) & 1) * A.half, dg + dpg, z0, aidx, blo, nbv);
                 // (6) gather: wave v takes the group's ring differences v, v+4, ...
@@ -543,30 +569,42 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared&
                     const int di = dg + ds;
                     if (di >= ND) break;
                     const int d = di - D;
-                    const double dd = (double)d;
+                    const float fd = (float)d, ad = fabsf(fd);
                     const int omin = sh.omin[di], omax = sh.omax[di];
+                    const bool fits = omax - omin + ZB + 1 <= rw;
 #pragma unroll
                     for (int k = 0; k < BP3_HMAX; ++k) {
-                        if (!H.v[k]) continue;
-                        const double zA = __fma_rn(dd, H.tA[k], 0.5), zB = __fma_rn(dd, H.tB[k], 0.5);
-                        const double zlo = fmin(zA, zB), zhi = fmax(zA, zB);
-                        const int o1 = (int)floor(zlo), o2 = (int)floor(zhi);
+                        // the piece's axial range [zlo, zhi] in slice units (FP32:
+                        // |zeta| <= 1/2 + D, its rounding far below a slice); it
+                        // meets slice offsets o1 and, across boundary o2 = o1 + 1,
+                        // o2 (the host bounds the span below one slice)
+                        const float zref = fmaf(fd, H.t0[k], 0.5f), span = ad * H.dt[k];
+                        const float zlo = d >= 0 ? zref : zref - span;
+                        const float zhi = d >= 0 ? zref + span : zref;
+                        const float flo = floorf(zlo), fhi = floorf(zhi);
+                        const int o1 = (int)flo, o2 = (int)fhi;
                         // 3D length per transaxial length of this (bin, d)
-                        const float x = (float)d * H.ck[k];
-                        const float LK = H.L[k] * sqrtf(fmaf(x, x, 1.0f));
-                        float a1 = LK, a2 = 0.0f;
-                        if (o2 != o1) {
-                            // the piece crosses slice boundary o2: split in proportion
-                            a1 = LK * ((float)((double)o2 - zlo) / (float)(zhi - zlo));
-                            a2 = LK - a1;
-                        }
+                        const float x = fd * H.ck[k];
+                        const float LK = H.L[k] * __builtin_amdgcn_sqrtf(fmaf(x, x, 1.0f));
+                        const bool split = fhi != flo;
+                        // split in proportion to the axial lengths on either side
+                        const float frac = fminf(1.0f, fmaxf(0.0f, (fhi - zlo) * __builtin_amdgcn_rcpf(span)));
+                        const float a1 = split ? LK * frac : LK;
+                        const float a2 = LK - a1;
                         // inside the staged footprint by construction: the tile's bin
                         // window and tau range contain every hit of its columns, and
                         // the host-side bounds on bins and slice-offset span hold; the
                         // test only keeps LDS reads in range
                         const int bcol = H.b[k] - blo;
-                        if (bcol >= 0 && bcol < nbv && o1 >= omin && o2 <= omax && omax - omin + ZB + 1 <= rw)
-                            bp3_apply<ZB, NBS>(acc, buf + (ds * rw + (omax - o1)) * NBS + bcol, a1, a2);
+                        const bool use = H.v[k] && bcol >= 0 && bcol < nbv && o1 >= omin && o2 <= omax && fits;
+                        const bool any_split = __ballot(use && a2 != 0.0f) != 0;   // wave-uniform
+                        if (use) {
+                            const float* sp = buf + (ds * rw + (omax - o1)) * NBS + bcol;
+                            // offset o1 with a1; where some lane of the wave splits,
+                            // offset o2 = o1 + 1 (one row up in the staging) with a2
+                            bp3_apply<ZB, NBS>(acc, sp, a1);
+                            if (any_split) bp3_apply<ZB, NBS>(acc, sp - NBS, a2);
+                        }
                     }
                 }
             }
