@@ -269,14 +269,24 @@ __host__ __device__ inline int bp3_nbs(int nb) { return nb <= 20 ? 20 : 40; }
 
 // LDS shared by the back-projector's phases (declared once per kernel); the
 // staging area is separate (dynamic in the single-request kernel, sized to
-// the geometry's footprint)
+// the geometry's footprint).  Angles are taken in chunks of BP3_AMAX whose
+// tile windows are found together, one thread per angle.
+constexpr int BP3_AMAX = 16;
 struct BP3Shared {
-    double tau[2];
-    int blo, nb, npass;
-    int omin[BP3_MAXND], omax[BP3_MAXND];
     int pbase[BP3_MAXND];    // plane of ring r1 = 0 of ring difference index di (plane_base - first ring)
+    int ang[BP3_AMAX];       // the chunk's angles
+    int blo[BP3_AMAX], nb[BP3_AMAX];    // the tile's staged bins of each angle
+    double tau[BP3_AMAX][2];            // the tile's tau range of each angle
     double red[NT / 64];
 };
+
+// Slice-offset range (+1 margin) over the tile of ring difference d, from the
+// tile's tau range of the angle.
+__device__ __forceinline__ void bp3_orange(double tau0, double tau1, int d, int& omin, int& omax) {
+    const double za = 0.5 + (double)d * tau0, zc = 0.5 + (double)d * tau1;
+    omin = (int)floor(fmin(za, zc)) - 1;
+    omax = (int)floor(fmax(za, zc)) + 1;
+}
 
 // acc[i] += a w(r1 = iz - o) for the ZB slices of the block, with
 // sp[(i + 1) * NBS] holding w(r1 = z0 + i - o).  Loads go in batches of 16
@@ -342,7 +352,7 @@ __device__ void bp3_finish(const GeoK& g, const BP3Args& A, float (&acc)[BP3_ZMA
 // waiting.
 template <int NBS>
 __device__ __forceinline__ void bp3_stage(const GeoK& g, const BP3Args& A, const BP3Shared& sh, float* buf, int dg,
-                                          int z0, int aidx, int blo, int nbv) {
+                                          int z0, int aidx, int blo, int nbv, const double* tk) {
     constexpr int LPI = 64 / NBS;                   // rows per wave instruction
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -357,7 +367,8 @@ __device__ __forceinline__ void bp3_stage(const GeoK& g, const BP3Args& A, const
         if (di >= ND) break;
         const int d = di - D;
         const int lo = max(0, -d), hi = min(R - 1, R - 1 - d);
-        const int om = __builtin_amdgcn_readfirstlane(sh.omax[di]);
+        int omn, om;
+        bp3_orange(tk[0], tk[1], d, omn, om);
         const int r1_row0 = z0 - om - 1;            // ring r1 of row 0
         // rows of valid rings (row 0 stays zero): [rlo, rhi], possibly empty
         const int rlo = max(1, lo - r1_row0), rhi = min(rw - 1, hi - r1_row0);
@@ -475,31 +486,30 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared&
     const int rw = A.rw, dpg = A.dpg;
     const float ck0 = (float)g.vz;      // ring pitch (== vz)
 
-    // tile box in mm
-    const double X0 = ((double)tx0 - 0.5 * g.nx) * g.vx, X1 = X0 + BP3_T * g.vx;
-    const double Y0 = ((double)ty0 - 0.5 * g.ny) * g.vy, Y1 = Y0 + BP3_T * g.vy;
-
-
     float acc[BP3_ZMAX];
 #pragma unroll
     for (int i = 0; i < BP3_ZMAX; ++i) acc[i] = 0.0f;
     // plane of ring 0 per ring difference, read by the staging (published by
-    // the first barrier of the angle loop)
+    // the first barrier of the chunk loop)
     if ((int)threadIdx.x < ND) {
         const int d = (int)threadIdx.x - D;
         sh.pbase[threadIdx.x] = g.plane_base[threadIdx.x] - max(0, -d);
     }
 
-    for (int al = 0; al < A.n_al; ++al) {
-        const int a = A.angles[al];
-        const AngleK& AK = g.ang[a];
-        const int aidx = A.w_natural ? a : al;
-        // (1) the tile's bins [blo, blo + nb) (+1 bin margin) and tau range
-        if (threadIdx.x == 0) {
-            sh.npass = 0;
+    for (int c0 = 0; c0 < A.n_al; c0 += BP3_AMAX) {
+        const int na = min(BP3_AMAX, A.n_al - c0);
+        __syncthreads();    // the previous chunk's windows are read no more
+        // (1) per angle of the chunk (one thread each): the tile's bins
+        // [blo, blo + nb) (+1 bin margin) and tau range
+        if ((int)threadIdx.x < na) {
+            const int k = threadIdx.x;
+            const int a = A.angles[c0 + k];
+            const AngleK& AK = g.ang[a];
+            const double X0 = ((double)tx0 - 0.5 * g.nx) * g.vx, X1 = X0 + BP3_T * g.vx;
+            const double Y0 = ((double)ty0 - 0.5 * g.ny) * g.vy, Y1 = Y0 + BP3_T * g.vy;
             double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
-            for (int k = 0; k < 4; ++k) {
-                const double x = (k & 1) ? X1 : X0, y = (k & 2) ? Y1 : Y0;
+            for (int q = 0; q < 4; ++q) {
+                const double x = (q & 1) ? X1 : X0, y = (q & 2) ? Y1 : Y0;
                 const double u = x * AK.c + y * AK.s;      // radial position
                 const double v = -x * AK.s + y * AK.c;     // position along the ray
                 umin = fmin(umin, u);
@@ -510,106 +520,116 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared&
             const int blo = max((int)floor(umin / g.ds + g.h0) - 1, 0);
             const int bhi = min((int)ceil(umax / g.ds + g.h0) + 1, Nr - 1);
             const int nb = max(0, min(bhi - blo + 1, min(A.nb, NBS)));
-            sh.blo = blo;
-            sh.nb = nb;
             double hmin = g.det_radius, hmax = g.det_radius;
             if (nb > 0) {
                 const int bl = blo + nb - 1;
                 hmin = fmin(g.bin[blo].h, g.bin[bl].h);
                 hmax = ((double)blo <= g.h0 && (double)bl >= g.h0) ? g.det_radius : fmax(g.bin[blo].h, g.bin[bl].h);
             }
-            sh.tau[0] = 0.5 + vmin / (2.0 * (vmin < 0.0 ? hmin : hmax)) - 1e-9;
-            sh.tau[1] = 0.5 + vmax / (2.0 * (vmax > 0.0 ? hmin : hmax)) + 1e-9;
+            sh.ang[k] = a;
+            sh.blo[k] = blo;
+            sh.nb[k] = nb;
+            sh.tau[k][0] = 0.5 + vmin / (2.0 * (vmin < 0.0 ? hmin : hmax)) - 1e-9;
+            sh.tau[k][1] = 0.5 + vmax / (2.0 * (vmax > 0.0 ? hmin : hmax)) + 1e-9;
         }
         __syncthreads();
-        // (2) slice-offset range of every ring difference over the tile (+1 margin)
-        if ((int)threadIdx.x < ND) {
-            const double dd = (double)((int)threadIdx.x - D);
-            const double za = 0.5 + dd * sh.tau[0], zc = 0.5 + dd * sh.tau[1];
-            sh.omin[threadIdx.x] = (int)floor(fmin(za, zc)) - 1;
-            sh.omax[threadIdx.x] = (int)floor(fmax(za, zc)) + 1;
-        }
-        // (3) candidate bins of the column: g(m) in [mc - max(Q,0), mc + 1 - min(Q,0)]
-        const int m = AK.row_major ? iy : ix;
-        const int mc = AK.row_major ? ix : iy;
-        int b0 = 0, b1 = -1;
-        if (col_in) {
-            const double base = __fma_rn(AK.Q, (double)m, AK.wC);
-            const double glo = (double)mc - fmax(AK.Q, 0.0) - 1e-7;
-            const double ghi = (double)mc + 1.0 - fmin(AK.Q, 0.0) + 1e-7;
-            const double bA = (glo - base) * AK.inv_wslope, bB = (ghi - base) * AK.inv_wslope;
-            b0 = (int)fmax(floor(fmin(bA, bB)), 0.0);
-            b1 = (int)fmin(ceil(fmax(bA, bB)), (double)(Nr - 1));
-        }
-        // (4) the column's hits: bins whose ray crosses its cell, in bin order.
-        // A pass takes BP3_HMAX of them; one pass covers any column when ds is
-        // at least half the pixel's radial extent (e.g. ds == vx == vy).
-        Hits H;
-        const int nh = col_hits(g, AK, m, mc, b0, b1, 0, ck0, H);
-        if (nh > 0) atomicMax(&sh.npass, (nh + BP3_HMAX - 1) / BP3_HMAX);
-        __syncthreads();
-        const int npass = sh.npass;
-        const int blo = sh.blo, nbv = sh.nb;
-        for (int pass = 0; pass < npass; ++pass) {
-            if (pass > 0) (void)col_hits(g, AK, m, mc, b0, b1, pass * BP3_HMAX, ck0, H);
-            // (5) stage w of ring differences in groups of dpg, double buffered:
-            // the loads of group k+1 run while group k is gathered
-            // Each wave stages and gathers its own slots: only the
-            // wave's own loads are waited for, no block barrier per group.
+        // (2) each wave goes through the chunk's angles on its own: the
+        // staging slots it fills are the ones it gathers, so no barrier
+        // orders the waves until the chunk ends
+        for (int k = 0; k < na; ++k) {
+            const int al = c0 + k;
+            const int a = sh.ang[k];
+            const AngleK& AK = g.ang[a];
+            const int aidx = A.w_natural ? a : al;
+            const int blo = sh.blo[k], nbv = sh.nb[k];
+            const double* tk = sh.tau[k];    // read where used (registers are scarce)
             const int ngr = (ND + dpg - 1) / dpg;
-            bp3_stage<NBS>(g, A, sh, s_w, 0, z0, aidx, blo, nbv);
-            for (int gi = 0; gi < ngr; ++gi) {
-                const int dg = gi * dpg;
-                float* buf = s_w + (gi & 1) * A.half;
-                __builtin_amdgcn_s_waitcnt(0);      // this wave's loads (and zeros) into buf have landed
-                if (gi + 1 < ngr)
-                    bp3_stage<NBS>(g, A, sh, s_w + ((gi + 1) & 1) * A.half, dg + dpg, z0, aidx, blo, nbv);
-                // (6) gather: wave v takes the group's ring differences v, v+4, ...
-                for (int ds = wave; ds < dpg; ds += 4) {
-                    const int di = dg + ds;
-                    if (di >= ND) break;
-                    const int d = di - D;
-                    const float fd = (float)d, ad = fabsf(fd);
-                    const int omin = sh.omin[di], omax = sh.omax[di];
-                    const bool fits = omax - omin + ZB + 1 <= rw;
+            // the first group's loads run while the column's hits are found
+            bp3_stage<NBS>(g, A, sh, s_w, 0, z0, aidx, blo, nbv, tk);
+            // (3) candidate bins of the column: g(m) in [mc - max(Q,0), mc + 1 - min(Q,0)]
+            const int m = AK.row_major ? iy : ix;
+            const int mc = AK.row_major ? ix : iy;
+            int b0 = 0, b1 = -1;
+            if (col_in) {
+                const double base = __fma_rn(AK.Q, (double)m, AK.wC);
+                const double glo = (double)mc - fmax(AK.Q, 0.0) - 1e-7;
+                const double ghi = (double)mc + 1.0 - fmin(AK.Q, 0.0) + 1e-7;
+                const double bA = (glo - base) * AK.inv_wslope, bB = (ghi - base) * AK.inv_wslope;
+                b0 = (int)fmax(floor(fmin(bA, bB)), 0.0);
+                b1 = (int)fmin(ceil(fmax(bA, bB)), (double)(Nr - 1));
+            }
+            // (4) the column's hits: bins whose ray crosses its cell, in bin
+            // order.  A pass takes BP3_HMAX of them; one pass covers any
+            // column when ds is at least half the pixel's radial extent (e.g.
+            // ds == vx == vy).  Every wave holds all the tile's columns, so
+            // the passes (the wave's maximum) are the same in every wave.
+            Hits H;
+            const int nh = col_hits(g, AK, m, mc, b0, b1, 0, ck0, H);
+            int npass = (nh + BP3_HMAX - 1) / BP3_HMAX;
 #pragma unroll
-                    for (int k = 0; k < BP3_HMAX; ++k) {
-                        // the piece's axial range [zlo, zhi] in slice units (FP32:
-                        // |zeta| <= 1/2 + D, its rounding far below a slice); it
-                        // meets slice offsets o1 and, across boundary o2 = o1 + 1,
-                        // o2 (the host bounds the span below one slice)
-                        const float zref = fmaf(fd, H.t0[k], 0.5f), span = ad * H.dt[k];
-                        const float zlo = d >= 0 ? zref : zref - span;
-                        const float zhi = d >= 0 ? zref + span : zref;
-                        const float flo = floorf(zlo), fhi = floorf(zhi);
-                        const int o1 = (int)flo, o2 = (int)fhi;
-                        // 3D length per transaxial length of this (bin, d)
-                        const float x = fd * H.ck[k];
-                        const float LK = H.L[k] * __builtin_amdgcn_sqrtf(fmaf(x, x, 1.0f));
-                        const bool split = fhi != flo;
-                        // split in proportion to the axial lengths on either side
-                        const float frac = fminf(1.0f, fmaxf(0.0f, (fhi - zlo) * __builtin_amdgcn_rcpf(span)));
-                        const float a1 = split ? LK * frac : LK;
-                        const float a2 = LK - a1;
-                        // inside the staged footprint by construction: the tile's bin
-                        // window and tau range contain every hit of its columns, and
-                        // the host-side bounds on bins and slice-offset span hold; the
-                        // test only keeps LDS reads in range
-                        const int bcol = H.b[k] - blo;
-                        const bool use = H.v[k] && bcol >= 0 && bcol < nbv && o1 >= omin && o2 <= omax && fits;
-                        const bool any_split = __ballot(use && a2 != 0.0f) != 0;   // wave-uniform
-                        if (use) {
-                            const float* sp = buf + (ds * rw + (omax - o1)) * NBS + bcol;
-                            // offset o1 with a1; where some lane of the wave splits,
-                            // offset o2 = o1 + 1 (one row up in the staging) with a2
-                            bp3_apply<ZB, NBS>(acc, sp, a1);
-                            if (any_split) bp3_apply<ZB, NBS>(acc, sp - NBS, a2);
+            for (int sft = 1; sft < 64; sft <<= 1) npass = max(npass, __shfl_xor(npass, sft));
+            npass = __builtin_amdgcn_readfirstlane(npass);
+            for (int pass = 0; pass < npass; ++pass) {
+                if (pass > 0) {
+                    (void)col_hits(g, AK, m, mc, b0, b1, pass * BP3_HMAX, ck0, H);
+                    bp3_stage<NBS>(g, A, sh, s_w, 0, z0, aidx, blo, nbv, tk);
+                }
+                // (5) w of ring differences in groups of dpg, double buffered:
+                // the loads of group k+1 run while group k is gathered
+                for (int gi = 0; gi < ngr; ++gi) {
+                    const int dg = gi * dpg;
+                    float* buf = s_w + (gi & 1) * A.half;
+                    __builtin_amdgcn_s_waitcnt(0);      // this wave's loads (and zeros) into buf have landed
+                    if (gi + 1 < ngr)
+                        bp3_stage<NBS>(g, A, sh, s_w + ((gi + 1) & 1) * A.half, dg + dpg, z0, aidx, blo, nbv, tk);
+                    // (6) gather: wave v takes the group's ring differences v, v+4, ...
+                    for (int ds = wave; ds < dpg; ds += 4) {
+                        const int di = dg + ds;
+                        if (di >= ND) break;
+                        const int d = di - D;
+                        const float fd = (float)d, ad = fabsf(fd);
+                        int omin, omax;
+                        bp3_orange(tk[0], tk[1], d, omin, omax);
+                        const bool fits = omax - omin + ZB + 1 <= rw;
+#pragma unroll
+                        for (int kk = 0; kk < BP3_HMAX; ++kk) {
+                            // the piece's axial range [zlo, zhi] in slice units (FP32:
+                            // |zeta| <= 1/2 + D, its rounding far below a slice); it
+                            // meets slice offsets o1 and, across boundary o2 = o1 + 1,
+                            // o2 (the host bounds the span below one slice)
+                            const float zref = fmaf(fd, H.t0[kk], 0.5f), span = ad * H.dt[kk];
+                            const float zlo = d >= 0 ? zref : zref - span;
+                            const float zhi = d >= 0 ? zref + span : zref;
+                            const float flo = floorf(zlo), fhi = floorf(zhi);
+                            const int o1 = (int)flo, o2 = (int)fhi;
+                            // 3D length per transaxial length of this (bin, d)
+                            const float x = fd * H.ck[kk];
+                            const float LK = H.L[kk] * __builtin_amdgcn_sqrtf(fmaf(x, x, 1.0f));
+                            const bool split = fhi != flo;
+                            // split in proportion to the axial lengths on either side
+                            const float frac = fminf(1.0f, fmaxf(0.0f, (fhi - zlo) * __builtin_amdgcn_rcpf(span)));
+                            const float a1 = split ? LK * frac : LK;
+                            const float a2 = LK - a1;
+                            // inside the staged footprint by construction: the tile's bin
+                            // window and tau range contain every hit of its columns, and
+                            // the host-side bounds on bins and slice-offset span hold; the
+                            // test only keeps LDS reads in range
+                            const int bcol = H.b[kk] - blo;
+                            const bool use = H.v[kk] && bcol >= 0 && bcol < nbv && o1 >= omin && o2 <= omax && fits;
+                            const bool any_split = __ballot(use && a2 != 0.0f) != 0;   // wave-uniform
+                            if (use) {
+                                const float* sp = buf + (ds * rw + (omax - o1)) * NBS + bcol;
+                                // offset o1 with a1; where some lane of the wave splits,
+                                // offset o2 = o1 + 1 (one row up in the staging) with a2
+                                bp3_apply<ZB, NBS>(acc, sp, a1);
+                                if (any_split) bp3_apply<ZB, NBS>(acc, sp - NBS, a2);
+                            }
                         }
                     }
                 }
             }
+            __builtin_amdgcn_s_waitcnt(0);      // no load of this angle is left in flight
         }
-        __syncthreads();    // the angle's shared values are read no more
     }
     bp3_finish<ZB>(g, A, acc, s_w, tx0, ty0, z0);
 }
@@ -617,7 +637,7 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared&
 // dynamic LDS: the staging area, A.lds floats.  Up to 32 slices per block the
 // register budget is held to four waves per SIMD.
 template <int ZB, int NBS>
-__global__ __launch_bounds__(NT, ZB <= 32 ? 4 : 1) void k_bp3(GeoK g, BP3Args A, int n_tiles) {
+__global__ __launch_bounds__(NT, ZB <= 32 ? 4 : 3) void k_bp3(GeoK g, BP3Args A, int n_tiles) {
     __shared__ BP3Shared sh;
     extern __shared__ float bp3_stage_area[];
     const int tile = (int)xcd_block(blockIdx.x, n_tiles);
