@@ -535,9 +535,11 @@ static int autotune3(pet_os_geom* g, GeomExtra* ex, int32_t flags, hipStream_t s
             return PET_OS_OK;
         }
     }
+    // + 4 floats: the 3D back-projector's 16-byte staging loads may read up to
+    // three bins past the last row
     const size_t nw = (size_t)g->max_sub_angles * g->n_planes * g->d.n_radial;
     float *w = nullptr, *img = nullptr;
-    if (hipMalloc(&w, nw * sizeof(float)) != hipSuccess || hipMalloc(&img, (size_t)g->n_vox * sizeof(float)) != hipSuccess) {
+    if (hipMalloc(&w, (nw + 4) * sizeof(float)) != hipSuccess || hipMalloc(&img, (size_t)g->n_vox * sizeof(float)) != hipSuccess) {
         if (w) (void)hipFree(w);
         return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc failed in autotune");
     }
@@ -600,7 +602,7 @@ extern "C" int pet_os_autotune(pet_os_geom* g, int32_t flags, pet_os_stream stre
     const size_t nw = (size_t)g->max_sub_angles * g->n_planes * g->d.n_radial;
     float *f = nullptr, *w = nullptr, *img = nullptr;
     if (hipMalloc(&f, (size_t)g->n_vox * sizeof(float)) != hipSuccess ||
-        hipMalloc(&w, nw * sizeof(float)) != hipSuccess || hipMalloc(&img, (size_t)g->n_vox * sizeof(float)) != hipSuccess) {
+        hipMalloc(&w, (nw + 4) * sizeof(float)) != hipSuccess || hipMalloc(&img, (size_t)g->n_vox * sizeof(float)) != hipSuccess) {
         if (f) (void)hipFree(f);
         if (w) (void)hipFree(w);
         return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc failed in autotune");

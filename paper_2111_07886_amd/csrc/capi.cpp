@@ -464,7 +464,9 @@ static WorkLayout work_layout(const pet_os_geom* g, bool need_nu) {
     L.need_nu = need_nu;
     L.d3 = g->d.dim == 3;
     L.psf = g->k.psf_kx > 0;
-    L.o_w = cv.take<float>((size_t)g->max_sub_angles * g->n_planes * g->d.n_radial);
+    // + 4 floats: the 3D back-projector's 16-byte staging loads may read up to
+    // three bins past the last row
+    L.o_w = cv.take<float>((size_t)g->max_sub_angles * g->n_planes * g->d.n_radial + 4);
     L.o_G = cv.take<float>(nv);
     L.o_mu = cv.take<float>(nv);
     L.o_nu = need_nu ? cv.take<float>(nv) : 0;
@@ -1089,7 +1091,8 @@ int pet_os_subset_gradient(const pet_os_geom* g, const pet_os_params* p, const f
     float* wsino = w.w;
     float* big = nullptr;
     if (n_al > g->max_sub_angles) {
-        if (hipMalloc(&big, sizeof(float) * (size_t)n_al * g->n_planes * g->d.n_radial) != hipSuccess) {
+        // + 4 floats of padding for the 3D back-projector's 16-byte staging loads
+        if (hipMalloc(&big, sizeof(float) * ((size_t)n_al * g->n_planes * g->d.n_radial + 4)) != hipSuccess) {
             work_free(&w);
             return fail(PET_OS_ERR_OUT_OF_MEMORY, "hipMalloc of the ratio sinogram failed");
         }

@@ -342,25 +342,30 @@ __device__ void bp3_finish(const GeoK& g, const BP3Args& A, float (&acc)[BP3_ZMA
 // Stage w of the calling wave's ring differences of group dg (slots ds =
 // wave, wave + 4, ... < dpg: the ones it gathers) into buf as [ds][row][bin],
 // row r of slot ds holding r1 = z0 - omax(d) + r - 1 (row 0 and invalid
-// rings: zeros; unit weights: ones).  NBS is the row stride; one wave
-// instruction copies 64/NBS consecutive rows straight from device memory into
-// LDS.  Per ring difference the rows of valid rings form one range [rlo,
-// rhi]: the rows outside it are zero-filled by the wave, the range is copied
-// in chunks of 64/NBS rows whose only per-lane work is the range test and the
-// address.  A slot's rows are written and read by the same wave, so no block
-// barrier orders them: the wave waits for its own loads.  Returns without
-// waiting.
+// rings: zeros; unit weights: ones).  NBS is the row stride.  Per ring
+// difference the rows of valid rings form one range [rlo, rhi]: the rows
+// outside it are zero-filled by the wave, the range is copied straight from
+// device memory into LDS, each lane moving four consecutive bins (16 bytes),
+// 64 / (NBS / 4) rows per wave instruction; a caller's natural-layout w
+// (whose last row may end at its allocation) moves one bin per lane.  A
+// slot's rows are written and read by the same wave, so no block barrier
+// orders them: the wave waits for its own loads.  Returns without waiting.
 template <int NBS>
 __device__ __forceinline__ void bp3_stage(const GeoK& g, const BP3Args& A, const BP3Shared& sh, float* buf, int dg,
                                           int z0, int aidx, int blo, int nbv, const double* tk) {
-    constexpr int LPI = 64 / NBS;                   // rows per wave instruction
+    constexpr int CPR = NBS / 4;                    // 16-byte chunks per row
+    constexpr int RPI4 = 64 / CPR;                  // rows per wave instruction, 16-byte lanes
+    constexpr int RPI1 = 64 / NBS;                  // rows per wave instruction, 4-byte lanes
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int sub = lane / NBS, col = lane - sub * NBS;
     const int D = g.max_rd, ND = 2 * D + 1, R = g.n_rings, rw = A.rw, dpg = A.dpg;
-    const bool lane_ok = sub < LPI && col < nbv;
-    // a lane's element of a chunk: row (chunk start + sub), bin (blo + col);
-    // its offset from the chunk's first element is the same in every chunk
+    const bool wide = !A.w_natural;
+    // a lane's element of a chunk: row (chunk start + sub), bins from blo +
+    // col; its offset from the chunk's first element is the same in every chunk
+    const int sub = wide ? lane / CPR : lane / NBS;
+    const int col = wide ? 4 * (lane - sub * CPR) : lane - sub * NBS;
+    const int rpi = wide ? RPI4 : RPI1;
+    const bool lane_ok = sub < rpi && col < nbv;
     const long long lane_off = (long long)sub * A.w_sp + col;
     for (int ds = wave; ds < dpg; ds += 4) {
         const int di = dg + ds;
@@ -373,12 +378,12 @@ __device__ __forceinline__ void bp3_stage(const GeoK& g, const BP3Args& A, const
         // rows of valid rings (row 0 stays zero): [rlo, rhi], possibly empty
         const int rlo = max(1, lo - r1_row0), rhi = min(rw - 1, hi - r1_row0);
         float* bd = buf + ds * rw * NBS;
-        // zeros below the range ([0, nzlo)) and above it ([top0, rw))
+        // zeros below the range ([0, nzlo)) and above it ([top0, rw)), 16 bytes a lane
         const int nzlo = min(rlo, rw), top0 = max(rhi, rlo - 1) + 1, nzhi = max(rw - top0, 0);
-        for (int e = lane; e < (nzlo + nzhi) * NBS; e += 64) {
-            const int rr = e / NBS, cc = e - rr * NBS;
+        for (int e = lane; e < (nzlo + nzhi) * CPR; e += 64) {
+            const int rr = e / CPR, cc = e - rr * CPR;
             const int row = rr < nzlo ? rr : top0 + (rr - nzlo);
-            bd[row * NBS + cc] = 0.0f;
+            *reinterpret_cast<float4*>(bd + row * NBS + 4 * cc) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
         if (rhi < rlo) continue;
         if (A.w == nullptr) {
@@ -387,11 +392,21 @@ __device__ __forceinline__ void bp3_stage(const GeoK& g, const BP3Args& A, const
         }
         // (uniform) element of row rlo, bin blo: plane pbase[di] + r1
         const float* wr = A.w + ((long long)sh.pbase[di] + r1_row0 + rlo) * A.w_sp + (long long)aidx * A.w_sa + blo;
-        const long long wstep = (long long)LPI * A.w_sp;
-        for (int r0 = rlo; r0 <= rhi; r0 += LPI, wr += wstep) {
-            if (lane_ok && r0 + sub <= rhi)
-                __builtin_amdgcn_global_load_lds(wr + lane_off, (__attribute__((address_space(3))) void*)(bd + r0 * NBS),
-                                                 4, 0, 0);
+        const long long wstep = (long long)rpi * A.w_sp;
+        if (wide) {
+            // bins past the window (up to blo + nbv + 2) may be read: they lie
+            // in the next row or in the scratch's padding, and are never gathered
+            for (int r0 = rlo; r0 <= rhi; r0 += RPI4, wr += wstep) {
+                if (lane_ok && r0 + sub <= rhi)
+                    __builtin_amdgcn_global_load_lds(wr + lane_off, (__attribute__((address_space(3))) void*)(bd + r0 * NBS),
+                                                     16, 0, 0);
+            }
+        } else {
+            for (int r0 = rlo; r0 <= rhi; r0 += RPI1, wr += wstep) {
+                if (lane_ok && r0 + sub <= rhi)
+                    __builtin_amdgcn_global_load_lds(wr + lane_off, (__attribute__((address_space(3))) void*)(bd + r0 * NBS),
+                                                     4, 0, 0);
+            }
         }
     }
 }
@@ -409,6 +424,7 @@ struct Hits {
     float L[BP3_HMAX], ck[BP3_HMAX];
     bool v[BP3_HMAX];
 };
+
 
 // One candidate bin b of col_hits, with h and 1 / (2 h) of its table row
 // already loaded.
@@ -639,7 +655,7 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared&
 template <int ZB, int NBS>
 __global__ __launch_bounds__(NT, ZB <= 32 ? 4 : 3) void k_bp3(GeoK g, BP3Args A, int n_tiles) {
     __shared__ BP3Shared sh;
-    extern __shared__ float bp3_stage_area[];
+    extern __shared__ __attribute__((aligned(16))) float bp3_stage_area[];
     const int tile = (int)xcd_block(blockIdx.x, n_tiles);
     if (tile >= n_tiles) return;
     bp3_body<ZB, NBS>(g, A, tile, sh, bp3_stage_area);
@@ -1039,7 +1055,7 @@ __global__ __launch_bounds__(NT) void k_fp3_batch(const SlotDev* __restrict__ S,
 template <int ZB, int NBS>
 __global__ __launch_bounds__(NT) void k_bp3_batch(const SlotDev* __restrict__ S, const Item* __restrict__ items, const int* __restrict__ count) {
     __shared__ BP3Shared sh;
-    __shared__ float s_w[BP3_LDS];
+    __shared__ __attribute__((aligned(16))) float s_w[BP3_LDS];
     const int n = *count;
     for (int it = xcd_item(blockIdx.x, gridDim.x); it < n; it += gridDim.x) {
         const Item I = items[it];
