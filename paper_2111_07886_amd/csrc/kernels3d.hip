@@ -194,7 +194,9 @@ __device__ void fp3_body(const GeoK& g, const FP3Args& A, long long vblock) {
                 if (counting) {
                     for (int j = 0; j < total; ++j) acc += s_pc[wave][j].len;
                 } else {
-#pragma unroll 4
+                    // eight pieces' image loads in flight per lane (sixteen cost
+                    // more in occupancy than they hide in latency)
+#pragma unroll 8
                     for (int j = 0; j < total; ++j) {
                         const Piece p = s_pc[wave][j];
                         acc = fmaf(p.len, img_at(A.fz, p.off + r1), acc);
