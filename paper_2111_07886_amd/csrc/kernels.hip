@@ -373,15 +373,20 @@ constexpr int ANG_W = (int)(sizeof(AngleK) / sizeof(double));   // 8-byte words 
 static_assert(sizeof(AngleK) % sizeof(double) == 0, "angle records are copied in 8-byte words");
 
 // LEAN (the batched kernel, whose occupancy is register-bound) reads the
-// angle records from the geometry table in the gather and the pixel's update
-// inputs after it; otherwise both are fetched before the gather.
+// angle records from the geometry table in the gather (only the axis-parallel
+// and many-bin windows need them) and the pixel's update inputs after it;
+// otherwise both are fetched before the gather.
 template <class T, bool SUB = false, bool ATT = false, bool LEAN = false>
 __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
     constexpr int NV = T::X * T::Y;                 // pixels per tile
     constexpr int HX = T::X + 2, HY = T::Y + 2;
     extern __shared__ float s_w[];
     __shared__ float s_f[HX * HY];
-    __shared__ int s_blo[MAXCH], s_nb[MAXCH], s_a[MAXCH];
+    __shared__ int s_blo[MAXCH], s_nb[MAXCH], s_a[MAXCH], s_two[MAXCH];
+    // oblique angles, per angle of the chunk: the tile's pixel (0, 0) centre
+    // in bin units relative to blo, the steps per pixel in x and y, e_out in
+    // bins, and the trapezoid's e_out, 1 / (e_out - e_in) and Lmax
+    __shared__ float s_p0[MAXCH], s_dpx[MAXCH], s_dpy[MAXCH], s_E[MAXCH], s_eo[MAXCH], s_ide[MAXCH], s_lm[MAXCH];
     __shared__ AngleK s_ang[MAXCH];
     __shared__ double s_red[NT / 64];
     __shared__ float s_acc[T::AG > 1 ? T::AG * NV : 1];
@@ -465,7 +470,7 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
             const int j = threadIdx.x;
             const int a = A.angles[c0 + j];
             const AngleK& AK = g.ang[a];
-            if (!LEAN) s_a[j] = a;
+            s_a[j] = a;
             if (A.w != nullptr) {
                 double umin = 1e300, umax = -1e300;
                 for (int k = 0; k < 4; ++k) {
@@ -478,6 +483,20 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
                 int bhi = min((int)ceil(umax / g.ds + g.h0) + 1, Nr - 1);
                 s_blo[j] = blo;
                 s_nb[j] = max(0, min(bhi - blo + 1, nb_max));
+                // a pixel's window holds at most two bins when e_out <= ds
+                s_two[j] = (AK.Q != 0.0 && AK.e_out <= g.ds) ? 1 : 0;
+                if (AK.Q != 0.0) {
+                    const double xc0 = ((double)tx0 - 0.5 * (double)(g.nx - 1)) * g.vx;
+                    const double yc0 = ((double)ty0 - 0.5 * (double)(g.ny - 1)) * g.vy;
+                    const double u00 = __fma_rn(xc0, AK.c, yc0 * AK.s);
+                    s_p0[j] = (float)(__fma_rn(u00, inv_ds, g.h0) - (double)blo);
+                    s_dpx[j] = (float)(g.vx * AK.c * inv_ds);
+                    s_dpy[j] = (float)(g.vy * AK.s * inv_ds);
+                    s_E[j] = (float)(AK.e_out * inv_ds);
+                    s_eo[j] = (float)AK.e_out;
+                    s_ide[j] = (float)AK.inv_de;
+                    s_lm[j] = (float)AK.Lmax;
+                }
             }
         }
         if (!LEAN && c0 == 0 && A.f != nullptr) {
@@ -495,7 +514,7 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
                 const int j = e / nb_max, col = e - j * nb_max;
                 if (col < s_nb[j]) {
                     const int al = c0 + j;
-                    const int aidx = A.w_natural ? (LEAN ? A.angles[al] : s_a[j]) : al;
+                    const int aidx = A.w_natural ? s_a[j] : al;
                     const long long idx = (long long)aidx * A.w_sa + s_blo[j] + col;
                     s_w[e] = ATT ? A.w[idx] * A.att[idx] : A.w[idx];
                 }
@@ -511,7 +530,7 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
         if (inside) {
             for (int j = grp; j < nch; j += T::AG) {
                 const int al = c0 + j;
-                const int a = LEAN ? A.angles[al] : s_a[j];
+                const int a = s_a[j];     // from LDS: a global load per angle would stall the gather
                 const AngleK& AK = LEAN ? g.ang[a] : s_ang[j];
                 const int aidx = A.w_natural ? a : al;
                 const int bst = s_blo[j], nbs = s_nb[j];
@@ -543,6 +562,26 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
                         for (int b = b0; b <= b1; ++b) {
                             const int cnt = subray_axis_count(g, b, mc, n, v);
                             if (cnt > 0) acc = fmaf(subray_axis_weight(g, AK, cnt), wval(b), acc);
+                        }
+                    }
+                } else if (A.w != nullptr && s_two[j]) {
+                    // oblique, at most two bins per pixel: the pixel centre's
+                    // position p in the staged window's bin units, in FP32 from
+                    // the tile's reference (|p| within the window, its rounding
+                    // near 1e-6 bins); bins k0 = the first above p - e_out/ds
+                    // and k0 + 1, each weighted by the trapezoid of its radial
+                    // offset (0 outside the window's reach)
+                    const float p = fmaf((float)ly, s_dpy[j], fmaf((float)lx, s_dpx[j], s_p0[j]));
+                    const int k0 = (int)floorf(p - s_E[j]) + 1;
+                    const float dsf = (float)g.ds, eo = s_eo[j], ide = s_ide[j], lmax = s_lm[j];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const int k = k0 + u;
+                        const float tt = fabsf((p - (float)k) * dsf);
+                        const float len = lmax * fminf(1.0f, (eo - tt) * ide);
+                        if (len > 0.0f) {
+                            if (k >= 0 && k < nbs) acc = fmaf(len, s_w[j * nb_max + k], acc);
+                            else if (bst + k >= 0 && bst + k < Nr) acc = fmaf(len, wval(bst + k), acc);
                         }
                     }
                 } else if (AK.Q != 0.0) {
@@ -1295,7 +1334,7 @@ __global__ __launch_bounds__(NT) void k_fp_batch(const SlotDev* __restrict__ S, 
 // at most 72 VGPRs (7 waves per SIMD): measured 2 % faster than the
 // unbounded 77, and 6 % faster than 64 with its spills
 template <class T>
-__global__ __launch_bounds__(NT, 7) void k_bp_batch(const SlotDev* __restrict__ S, const Item* __restrict__ items, const int* __restrict__ count) {
+__global__ __launch_bounds__(NT, 6) void k_bp_batch(const SlotDev* __restrict__ S, const Item* __restrict__ items, const int* __restrict__ count) {
     const int n = *count;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const Item I = items[it];
