@@ -1331,10 +1331,11 @@ __global__ __launch_bounds__(NT) void k_fp_batch(const SlotDev* __restrict__ S, 
     }
 }
 
-// at most 72 VGPRs (7 waves per SIMD): measured 2 % faster than the
-// unbounded 77, and 6 % faster than 64 with its spills
+// at most 96 VGPRs (5 waves per SIMD): the gather's per-angle tile
+// references need more than 72 without spilling to scratch (6 waves: 80
+// VGPRs and 7 spilled; 5 waves measured 1 % faster, with no scratch traffic)
 template <class T>
-__global__ __launch_bounds__(NT, 6) void k_bp_batch(const SlotDev* __restrict__ S, const Item* __restrict__ items, const int* __restrict__ count) {
+__global__ __launch_bounds__(NT, 5) void k_bp_batch(const SlotDev* __restrict__ S, const Item* __restrict__ items, const int* __restrict__ count) {
     const int n = *count;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const Item I = items[it];
