@@ -268,6 +268,9 @@ constexpr int BP3_MAXND = 63;    // ring differences -31..31
 
 // LDS row stride of the staged footprint: 20 bins (3 rows per wave load) or 40
 __host__ __device__ inline int bp3_nbs(int nb) { return nb <= 20 ? 20 : 40; }
+// The single-request kernel also has a 16-bin stride (one wave instruction
+// then stages 16 rows, every lane used)
+__host__ __device__ inline int bp3_nbs_single(int nb) { return nb <= 16 ? 16 : bp3_nbs(nb); }
 
 // LDS shared by the back-projector's phases (declared once per kernel); the
 // staging area is separate (dynamic in the single-request kernel, sized to
@@ -864,7 +867,10 @@ int upd3_grid(const pet_os_geom* G) {
 // (ring difference, bin) for zb slices: zb + slice-offset span + 1 pad row.
 static int bp3_rows(const pet_os_geom* G, int zb, int& nb, int& rw) {
     const auto& d = G->d;
-    nb = (int)std::ceil(BP3_T * (d.vx + d.vy) / d.ds) + 4;
+    // an 8x8 tile's projection onto the detector axis is at most
+    // BP3_T sqrt(vx^2 + vy^2) wide; the window adds a bin of margin each side
+    // and up to one for rounding at each end
+    nb = (int)std::ceil(BP3_T * std::sqrt(d.vx * d.vx + d.vy * d.vy) / d.ds + 1e-6) + 4;
     if (nb > d.n_radial) nb = d.n_radial;
     if (nb > 40) return fail(PET_OS_ERR_INVALID_ARG, "3D geometry: more than 40 bins per 8x8 voxel tile (ds too small)");
     const double smax = 0.5 * (d.n_radial - 1) * d.ds;
@@ -900,7 +906,7 @@ int bp3_shape(const pet_os_geom* G, int& nb, int& zb, int& rw, int& dpg) {
 int bp3_shape_single(const pet_os_geom* G, int zb, int dpg_req, int& nb, int& rw, int& dpg, int& half, int& lds) {
     int rc = bp3_rows(G, zb, nb, rw);
     if (rc) return rc;
-    const long long nbs = bp3_nbs(nb);
+    const long long nbs = bp3_nbs_single(nb);
     dpg = dpg_req > 0 ? dpg_req : ((8LL * nbs * rw <= BP3_LDS / 2) ? 8 : 4);
     const long long h = (long long)dpg * nbs * rw;
     const long long fin = 2LL * zb * 64;     // the finish: the waves' partial sums and their total
@@ -956,21 +962,24 @@ int launch_bp3(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
     if (rc) return rc;
     if (L.f != nullptr) return fail(PET_OS_ERR_DEVICE, "the 3D penalty gradient is k_pen3's (launch_pen3)");
     const int grid = bp3_grid(G);
-    const bool wide = bp3_nbs(a.nb) == 40;
+    const int nbs = bp3_nbs_single(a.nb);
     const dim3 blocks(8 * ((grid + 7) / 8));
     const size_t lds = (size_t)a.lds * sizeof(float);
     switch (a.zb) {
         case 16:
-            if (wide) petos_launch(k_bp3<16, 40>, blocks, dim3(NT), lds, s, G->k, a, grid);
-            else petos_launch(k_bp3<16, 20>, blocks, dim3(NT), lds, s, G->k, a, grid);
+            if (nbs == 40) petos_launch(k_bp3<16, 40>, blocks, dim3(NT), lds, s, G->k, a, grid);
+            else if (nbs == 20) petos_launch(k_bp3<16, 20>, blocks, dim3(NT), lds, s, G->k, a, grid);
+            else petos_launch(k_bp3<16, 16>, blocks, dim3(NT), lds, s, G->k, a, grid);
             break;
         case 32:
-            if (wide) petos_launch(k_bp3<32, 40>, blocks, dim3(NT), lds, s, G->k, a, grid);
-            else petos_launch(k_bp3<32, 20>, blocks, dim3(NT), lds, s, G->k, a, grid);
+            if (nbs == 40) petos_launch(k_bp3<32, 40>, blocks, dim3(NT), lds, s, G->k, a, grid);
+            else if (nbs == 20) petos_launch(k_bp3<32, 20>, blocks, dim3(NT), lds, s, G->k, a, grid);
+            else petos_launch(k_bp3<32, 16>, blocks, dim3(NT), lds, s, G->k, a, grid);
             break;
         case 64:
-            if (wide) petos_launch(k_bp3<64, 40>, blocks, dim3(NT), lds, s, G->k, a, grid);
-            else petos_launch(k_bp3<64, 20>, blocks, dim3(NT), lds, s, G->k, a, grid);
+            if (nbs == 40) petos_launch(k_bp3<64, 40>, blocks, dim3(NT), lds, s, G->k, a, grid);
+            else if (nbs == 20) petos_launch(k_bp3<64, 20>, blocks, dim3(NT), lds, s, G->k, a, grid);
+            else petos_launch(k_bp3<64, 16>, blocks, dim3(NT), lds, s, G->k, a, grid);
             break;
         default:
             return fail(PET_OS_ERR_DEVICE, "3D back-projector: slices per block must be 16, 32 or 64");
