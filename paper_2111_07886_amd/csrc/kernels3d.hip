@@ -127,6 +127,10 @@ __device__ void fp3_body(const GeoK& g, const FP3Args& A, long long vblock) {
         const float Lkf = (float)Lk, invQf = (float)tx.invQ, invQzf = (float)invQz;
         // a LOR between rings r1 and r1 + d stays in slices r1 + [min(0,d), max(0,d)]
         const int olo = min(0, d), ohi = max(0, d);
+        // offset of voxel (minor cell c, major cell m, slice o) in the
+        // z-fastest copy: m ms + c cs + o
+        const int cs = tx.row_major ? g.nz : g.nx * g.nz;
+        const int ms = tx.row_major ? g.nx * g.nz : g.nz;
         for (int mb = m0; mb <= m1; mb += 64) {
             // (1) the lane's major cell: up to three pieces.  Over the cell
             // the ray's transaxial minor coordinate runs from gm to gm + Q
@@ -155,19 +159,21 @@ __device__ void fp3_body(const GeoK& g, const FP3Args& A, long long vblock) {
                 const bool x_first = tX <= tZ;
                 const float t1 = fminf(tX, tZ), t2 = fmaxf(tX, tZ);
                 const int c1 = c0 + qstep, o1 = o0 + zstep;
-                const float frac[3] = {t1, t2 - t1, 1.0f - t2};
-                const int pc[3] = {c0, x_first ? c1 : c0, c1};
-                const int po[3] = {o0, x_first ? o0 : o1, o1};
-                const bool exists[3] = {true, xc || zc, xc && zc};
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const int c = pc[k], o = po[k];
-                    if (!exists[k] || !(frac[k] > 0.0f) || c < 0 || c >= n_minor || o < olo || o > ohi) continue;
-                    const int ix = tx.row_major ? c : m, iy = tx.row_major ? m : c;
-                    off[k] = (iy * g.nx + ix) * g.nz + o;
-                    len[k] = counting ? 1.0f : Lkf * frac[k];
-                    present |= 1 << k;
-                }
+                const int pc1 = x_first ? c1 : c0, po1 = x_first ? o0 : o1;
+                const float f0 = t1, f1 = t2 - t1, f2 = 1.0f - t2;
+                // a piece is kept when it exists, has a length and lies in the
+                // image and in the LOR's slices; offset = m ms + c cs + o
+                const bool v0 = f0 > 0.0f && c0 >= 0 && c0 < n_minor && o0 >= olo && o0 <= ohi;
+                const bool v1 = (xc || zc) && f1 > 0.0f && pc1 >= 0 && pc1 < n_minor && po1 >= olo && po1 <= ohi;
+                const bool v2 = xc && zc && f2 > 0.0f && c1 >= 0 && c1 < n_minor && o1 >= olo && o1 <= ohi;
+                const int offm = m * ms;
+                off[0] = offm + c0 * cs + o0;
+                off[1] = offm + pc1 * cs + po1;
+                off[2] = offm + c1 * cs + o1;
+                len[0] = counting ? 1.0f : Lkf * f0;
+                len[1] = counting ? 1.0f : Lkf * f1;
+                len[2] = counting ? 1.0f : Lkf * f2;
+                present = (v0 ? 1 : 0) | (v1 ? 2 : 0) | (v2 ? 4 : 0);
             }
             // (2) compact the pieces of the 64 cells, in cell order, into LDS
             // (each lane has 0..3 pieces: the exclusive prefix of the counts
