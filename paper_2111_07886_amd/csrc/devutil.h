@@ -178,6 +178,38 @@ __device__ inline double partials_total(double v, double* sh) {
     return s_tot;
 }
 
+// One neighbour pair's term of the RDP gradient (eqn:gradRD) at f_j, without
+// the factor 2: (f_j - f_k)(gamma |f_j - f_k| + f_j + 3 f_k + 2 eps) /
+// (f_j + f_k + gamma |f_j - f_k| + eps)^2, as numerator and 1 / denominator
+// (the hardware reciprocal, 1 ulp, in place of a correctly rounded division:
+// one instruction instead of about ten per pair).  fje = f_j + eps and fj2e =
+// f_j + 2 eps are formed once per voxel.
+struct RdpPair {
+    float num, rden;
+};
+__device__ __forceinline__ RdpPair rdp_pair(float fj, float fje, float fj2e, float fk, float gR) {
+    const float d = fj - fk;
+    const float ad = fabsf(d);
+    const float den = fmaf(gR, ad, fje + fk);
+    RdpPair t;
+    t.num = d * fmaf(3.0f, fk, fmaf(gR, ad, fj2e));
+    t.rden = __builtin_amdgcn_rcpf(den * den);
+    return t;
+}
+__device__ __forceinline__ float rdp_term(float fj, float fk, float gR, float eps) {
+    const RdpPair t = rdp_pair(fj, fj + eps, fj + 2.0f * eps, fk, gR);
+    return t.num * t.rden;
+}
+
+// Matlab-style derivative along one axis at index i of n (Sec. III-B):
+// one-sided at the ends, central inside, 0 on an axis of length 1.
+__device__ __forceinline__ float mat_der(int i, int n, float fp, float fj, float fm) {
+    if (n < 2) return 0.0f;
+    if (i == 0) return fp - fj;
+    if (i == n - 1) return fj - fm;
+    return 0.5f * (fp - fm);
+}
+
 // RDP gradient (eqn:gradRD; in-image 8/26 neighbours, unit weights) and the
 // Matlab-style gradient magnitude of Sec. III-B at one voxel of the halo tile.
 template <int DIM>
@@ -199,24 +231,14 @@ __device__ __forceinline__ void stencil_at(const float* sf, int HX, int HY, int 
             for (int dx = -1; dx <= 1; ++dx) {
                 const int x = ix + dx;
                 if ((dx | dy | dz) == 0 || x < 0 || x >= g.nx) continue;
-                const float fk = at(dx, dy, dz);
-                const float d = fj - fk;
-                const float ad = fabsf(d);
-                const float den = fj + fk + gR * ad + eps;
-                const float num = d * (gR * ad + fj + 3.0f * fk + 2.0f * eps);
-                // the hardware reciprocal (1 ulp) in place of a correctly
-                // rounded division: one instruction instead of about ten, per
-                // neighbour pair
-                acc += num * __builtin_amdgcn_rcpf(den * den);
+                acc += rdp_term(fj, at(dx, dy, dz), gR, eps);
             }
         }
     }
     gradR = 2.0f * acc;
     auto der = [&](int i, int n, int dx, int dy, int dz) -> float {
         if (n < 2) return 0.0f;
-        if (i == 0) return at(dx, dy, dz) - fj;
-        if (i == n - 1) return fj - at(-dx, -dy, -dz);
-        return 0.5f * (at(dx, dy, dz) - at(-dx, -dy, -dz));
+        return mat_der(i, n, at(dx, dy, dz), fj, at(-dx, -dy, -dz));
     };
     const float gx = der(ix, g.nx, 1, 0, 0);
     const float gy = der(iy, g.ny, 0, 1, 0);

@@ -716,11 +716,47 @@ __device__ void pen3_body(const GeoK& g, const Pen3Args& A, int vblock) {
     const int ix = x0 + lx, iy = y0 + ly;
     double mu_part = 0.0;
     if (ix < g.nx && iy < g.ny) {
+        // The thread's column, slice by slice, with the 3x3 neighbourhood of
+        // three slices in registers (one new slice read from LDS per step)
+        // and the out-of-image neighbours masked instead of branched around
+        // (the 26 in-image neighbours of eqn:gradRD, in stencil_at's order).
+        const bool okx[3] = {ix > 0, true, ix < g.nx - 1};
+        const bool oky[3] = {iy > 0, true, iy < g.ny - 1};
+        const float gR = A.gamma_R, eps = A.eps;
+        float pl[3][9];     // slices lz - 1, lz, lz + 1 of the halo tile (hz = lz .. lz + 2)
+        auto load = [&](float (&p)[9], int hz) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) p[q] = s_f[(hz * HY + ly + q / 3) * HX + lx + q % 3];
+        };
+        load(pl[0], 0);
+        load(pl[1], 1);
+#pragma unroll
         for (int lz = 0; lz < PEN3_Z; ++lz) {
             const int iz = z0 + lz;
             if (iz >= g.nz) break;
-            float gradR, gmag;
-            stencil_at<3>(s_f, HX, HY, lx + 1, ly + 1, lz + 1, ix, iy, iz, g, A.gamma_R, A.eps, gradR, gmag);
+            float (&pm)[9] = pl[lz % 3];
+            float (&pc)[9] = pl[(lz + 1) % 3];
+            float (&pp)[9] = pl[(lz + 2) % 3];
+            load(pp, lz + 2);
+            const bool okz[3] = {iz > 0, true, iz < g.nz - 1};
+            const float fj = pc[4], fje = fj + eps, fj2e = fj + 2.0f * eps;
+            float acc = 0.0f;
+#pragma unroll
+            for (int dz = 0; dz < 3; ++dz) {
+                const float* p = dz == 0 ? pm : (dz == 1 ? pc : pp);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    if (dz == 1 && q == 4) continue;
+                    const RdpPair t = rdp_pair(fj, fje, fj2e, p[q], gR);
+                    // an out-of-image neighbour adds 0
+                    acc = fmaf(t.num, (okz[dz] && oky[q / 3] && okx[q % 3]) ? t.rden : 0.0f, acc);
+                }
+            }
+            const float gradR = 2.0f * acc;
+            const float gx = mat_der(ix, g.nx, pc[5], fj, pc[3]);
+            const float gy = mat_der(iy, g.ny, pc[7], fj, pc[1]);
+            const float gz = mat_der(iz, g.nz, pp[4], fj, pm[4]);
+            const float gmag = sqrtf(gx * gx + gy * gy + gz * gz);
             const long long j = ((long long)iz * g.ny + iy) * g.nx + ix;
             A.G[j] = fmaf(A.beta_over_M, gradR, A.G[j]);
             if (A.want_mu) {
