@@ -299,18 +299,27 @@ __device__ __forceinline__ void bp3_orange(double tau0, double tau1, int d, int&
     omax = (int)floor(fmax(za, zc)) + 1;
 }
 
-// acc[i] += a w(r1 = iz - o) for the ZB slices of the block, with
-// sp[(i + 1) * NBS] holding w(r1 = z0 + i - o).  Loads go in batches of 16
-// to bound the live registers.
+// acc[i] += a1 w(r1 = iz - o1) + a2 w(r1 = iz - o1 - 1) for the ZB slices
+// of the block, with sp[(i + 1) * NBS] holding w(r1 = z0 + i - o1): the row
+// of offset o1 + 1 for slice i is the row of offset o1 for slice i - 1, so
+// the second term reuses the value loaded for the slice below and a column
+// whose piece crosses a slice boundary costs one FMA more per slice, no LDS
+// read (a2 = 0 elsewhere).  Loads go in batches of 16 to bound the live
+// registers.
 template <int ZB, int NBS>
-__device__ __forceinline__ void bp3_apply(float (&acc)[BP3_ZMAX], const float* sp, float a) {
+__device__ __forceinline__ void bp3_apply(float (&acc)[BP3_ZMAX], const float* sp, float a1, float a2) {
+    float below = sp[0];
 #pragma unroll
     for (int c = 0; c < ZB; c += 16) {
         float v[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) v[i] = sp[(c + i + 1) * NBS];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) acc[c + i] = fmaf(a, v[i], acc[c + i]);
+        for (int i = 0; i < 16; ++i) {
+            acc[c + i] = fmaf(a1, v[i], acc[c + i]);
+            acc[c + i] = fmaf(a2, i == 0 ? below : v[i - 1], acc[c + i]);
+        }
+        below = v[15];
         __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -643,13 +652,11 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared&
                             // test only keeps LDS reads in range
                             const int bcol = H.b[kk] - blo;
                             const bool use = H.v[kk] && bcol >= 0 && bcol < nbv && o1 >= omin && o2 <= omax && fits;
-                            const bool any_split = __ballot(use && a2 != 0.0f) != 0;   // wave-uniform
                             if (use) {
+                                // offset o1 with a1 and offset o2 = o1 + 1 (one row up
+                                // in the staging) with a2
                                 const float* sp = buf + (ds * rw + (omax - o1)) * NBS + bcol;
-                                // offset o1 with a1; where some lane of the wave splits,
-                                // offset o2 = o1 + 1 (one row up in the staging) with a2
-                                bp3_apply<ZB, NBS>(acc, sp, a1);
-                                if (any_split) bp3_apply<ZB, NBS>(acc, sp - NBS, a2);
+                                bp3_apply<ZB, NBS>(acc, sp, a1, a2);
                             }
                         }
                     }
