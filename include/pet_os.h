@@ -139,6 +139,10 @@ const char* pet_os_version(void);
 /* Geometry: validates the descriptor (Sec. IV-A conventions above), builds the
  * FP64 angle/bin/plane tables on the device and computes the sensitivity
  * s = A^T 1 and the normaliser p_j = s_j/M (or 1/M where s_j = 0) of eq:pj.
+ * Size limits (PET_OS_ERR_INVALID_ARG beyond them): at most 2^30 voxels; one
+ * pass of rays (3D: angle, bin, ring difference, 64-ring chunk items) below
+ * 2^31; in 3D, max_ring_diff <= min(nz - 1, 31), nx nz and ny nz below 2^23,
+ * and LORs no more oblique than one slice per transaxial voxel.
  * Synchronous.  The library owns *out until pet_os_destroy_geometry. */
 int pet_os_create_geometry(const pet_os_geom_desc* desc, pet_os_geom** out);
 

@@ -68,6 +68,9 @@ int validate_desc(const pet_os_geom_desc* d) {
             return fail(PET_OS_ERR_INVALID_ARG, "rings must sit at slice centres: n_rings == nz, ring_pitch == vz");
         if (d->max_ring_diff < 0 || d->max_ring_diff > std::min(d->nz - 1, 31))
             return fail(PET_OS_ERR_INVALID_ARG, "max_ring_diff must be in [0, min(nz-1, 31)]");
+        // the forward projector forms voxel offsets with 24-bit multiplies
+        if ((int64_t)std::max(d->nx, d->ny) * d->nz >= ((int64_t)1 << 23))
+            return fail(PET_OS_ERR_INVALID_ARG, "3D: nx*nz and ny*nz must be below 2^23");
         double half_diag = 0.5 * std::sqrt((double)d->nx * d->nx * d->vx * d->vx + (double)d->ny * d->ny * d->vy * d->vy);
         double smax = 0.5 * (d->n_radial - 1) * d->ds;
         if (!finite_pos(d->det_radius) || d->det_radius <= half_diag || d->det_radius <= smax)

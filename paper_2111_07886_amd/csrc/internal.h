@@ -252,6 +252,7 @@ int launch_sum_f(const pet_os_geom* g, const float* f, float* fz, Reduction red,
 
 // 3D projectors and update (kernels3d.hip)
 int fp3_grid(const pet_os_geom* g, int n_al);
+int fp3_launch_grid(const pet_os_geom* g, int n_al);
 int bp3_grid(const pet_os_geom* g);          // single-request launch (autotuned shape)
 int bp3_grid_batch(const pet_os_geom* g);    // batched launch (default shape)
 int bp3_grid_zb(const pet_os_geom* g, int zb);

@@ -937,7 +937,7 @@ int fp_grid_seg(const pet_os_geom* G, int n_al, int seg) {
 }
 
 int fp_grid(const pet_os_geom* G, int n_al) {
-    if (G->d.dim == 3) return fp3_grid(G, n_al);
+    if (G->d.dim == 3) return fp3_launch_grid(G, n_al);
     long long nrays = (long long)n_al * G->n_planes * G->d.n_radial;
     return fp_grid_seg(G, n_al, fp_seg_heuristic(nrays));
 }

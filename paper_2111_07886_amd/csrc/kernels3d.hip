@@ -8,14 +8,18 @@
 // slice r1 + o is crossed exactly where zeta lies in [o, o + 1).  Both
 // projectors are built on that:
 //
-//   k_fp3    one wave per (angle, bin, ring difference); the lanes are the
-//            first rings r1.  The 64 lanes first walk 64 major cells in
-//            parallel and list the (transaxial cell, slice offset o, length)
-//            pieces of that stretch in LDS; then every lane adds
-//            length * f[cell, slice r1 + o] for every piece, from a copy of
-//            the image with z fastest, so that one wave load reads 64
-//            consecutive slices.  The Poisson ratio (or the FP64
-//            log-likelihood term) is the epilogue, as in 2D.
+//   k_fp3    one block per (angle, bin), a wave per ring difference in
+//            turn; the lanes are the first rings r1.  The 64 lanes first walk
+//            64 major cells in parallel and list the (transaxial cell, slice
+//            offset o, length) pieces of that stretch in LDS; then every lane
+//            adds length * f[cell, slice r1 + o] for every piece.  The image
+//            columns of the stretch (a copy of the image with z fastest) are
+//            staged in LDS once for all ring differences, so a piece costs
+//            one conflict-free LDS read of 64 consecutive slices.  The
+//            Poisson ratio (or the FP64 log-likelihood term) is the
+//            epilogue, as in 2D.  k_fp3_wave (one wave per (angle, bin, ring
+//            difference), the same pieces read from device memory) covers
+//            more than 64 rings or 32 ring differences, and the batched path.
 //   k_bp3    one block per 8x8 column tile and z-range.  A lane owns one
 //            column; wave v takes ring differences v, v+4, ... of each
 //            staged group.  Per angle a lane finds the bins whose ray crosses
@@ -65,8 +69,8 @@ constexpr int FP3_W = NT / 64;      // waves per block: one (angle, bin, ring di
 constexpr int FP3_CAP = 3 * 64;     // pieces of a stretch of 64 major cells (<= 3 per cell)
 
 struct Piece {
-    int off;      // (iy * nx + ix) * nz + o
-    float len;    // 3D length (1 when counting)
+    int off;      // slice o of the voxel's column: in the z-fastest copy, or in the staged columns
+    float len;    // 3D length
 };
 
 __host__ __device__ inline long long fp3_items(int n_al, int n_radial, int max_rd, int n_rings) {
@@ -131,6 +135,7 @@ __device__ void fp3_body(const GeoK& g, const FP3Args& A, long long vblock) {
         // z-fastest copy: m ms + c cs + o
         const int cs = tx.row_major ? g.nz : g.nx * g.nz;
         const int ms = tx.row_major ? g.nx * g.nz : g.nz;
+        const int qcs = qstep * cs;
         for (int mb = m0; mb <= m1; mb += 64) {
             // (1) the lane's major cell: up to three pieces.  Over the cell
             // the ray's transaxial minor coordinate runs from gm to gm + Q
@@ -140,11 +145,12 @@ __device__ void fp3_body(const GeoK& g, const FP3Args& A, long long vblock) {
             // distances).  The pieces, in order along the ray: up to the
             // first crossing in (c0, o0), then up to the second in the cell
             // the first crossing leads to, then in (c0 + qstep, o0 + zstep).
-            const int m = mb + lane;
-            int off[3] = {0, 0, 0};
-            float len[3] = {0.0f, 0.0f, 0.0f};
-            int present = 0;
-            if (m <= m1) {
+            // (lanes past the last cell repeat it and keep no piece: no branch)
+            const int m = min(mb + lane, m1);
+            int off[3];
+            float len[3];
+            int present;
+            {
                 const double gm = __fma_rn(tx.Q, (double)m, tx.P);
                 const double zm = __fma_rn(Qz, (double)m, zeta0);
                 const double cf = floor(gm), of = floor(zm);
@@ -163,17 +169,22 @@ __device__ void fp3_body(const GeoK& g, const FP3Args& A, long long vblock) {
                 const float f0 = t1, f1 = t2 - t1, f2 = 1.0f - t2;
                 // a piece is kept when it exists, has a length and lies in the
                 // image and in the LOR's slices; offset = m ms + c cs + o
-                const bool v0 = f0 > 0.0f && c0 >= 0 && c0 < n_minor && o0 >= olo && o0 <= ohi;
-                const bool v1 = (xc || zc) && f1 > 0.0f && pc1 >= 0 && pc1 < n_minor && po1 >= olo && po1 <= ohi;
-                const bool v2 = xc && zc && f2 > 0.0f && c1 >= 0 && c1 < n_minor && o1 >= olo && o1 <= ohi;
-                const int offm = m * ms;
-                off[0] = offm + c0 * cs + o0;
-                off[1] = offm + pc1 * cs + po1;
-                off[2] = offm + c1 * cs + o1;
-                len[0] = counting ? 1.0f : Lkf * f0;
-                len[1] = counting ? 1.0f : Lkf * f1;
-                len[2] = counting ? 1.0f : Lkf * f2;
-                present = (v0 ? 1 : 0) | (v1 ? 2 : 0) | (v2 ? 4 : 0);
+                // (a cell index is in [0, n_minor) when it is below n_minor as unsigned)
+                const bool v0 = f0 > 0.0f && (unsigned)c0 < (unsigned)n_minor && o0 >= olo && o0 <= ohi;
+                const bool v1 = (xc || zc) && f1 > 0.0f && (unsigned)pc1 < (unsigned)n_minor && po1 >= olo && po1 <= ohi;
+                const bool v2 = xc && zc && f2 > 0.0f && (unsigned)c1 < (unsigned)n_minor && o1 >= olo && o1 <= ohi;
+                // 24-bit signed products (full-rate multiplies): the descriptor
+                // check keeps the strides nx nz and ny nz below 2^23, and the
+                // cell indices lie within a cell or two of the image
+                const int offm = __mul24(m, ms);
+                const int c0s = __mul24(c0, cs), c1s = c0s + qcs;
+                off[0] = offm + c0s + o0;
+                off[1] = offm + (x_first ? c1s : c0s) + po1;
+                off[2] = offm + c1s + o1;
+                len[0] = Lkf * f0;
+                len[1] = Lkf * f1;
+                len[2] = Lkf * f2;
+                present = mb + lane <= m1 ? (v0 ? 1 : 0) | (v1 ? 2 : 0) | (v2 ? 4 : 0) : 0;
             }
             // (2) compact the pieces of the 64 cells, in cell order, into LDS
             // (each lane has 0..3 pieces: the exclusive prefix of the counts
@@ -198,7 +209,7 @@ __device__ void fp3_body(const GeoK& g, const FP3Args& A, long long vblock) {
             // (3) every lane (first ring r1) applies every piece
             if (lane_ok) {
                 if (counting) {
-                    for (int j = 0; j < total; ++j) acc += s_pc[wave][j].len;
+                    acc += (float)total;    // pieces of the LOR
                 } else {
                     // eight pieces' image loads in flight per lane (sixteen cost
                     // more in occupancy than they hide in latency)
@@ -243,10 +254,214 @@ __device__ __forceinline__ long long xcd_block(long long block, long long n) {
     return (block % 8) * per + block / 8;
 }
 
-__global__ __launch_bounds__(NT) void k_fp3(GeoK g, FP3Args A, long long n_blocks) {
+// per-wave items (any ring count and ring difference range)
+__global__ __launch_bounds__(NT) void k_fp3_wave(GeoK g, FP3Args A, long long n_blocks) {
     const long long vb = xcd_block(blockIdx.x, n_blocks);
     if (vb >= n_blocks) return;
     fp3_body(g, A, vb);
+}
+
+// Forward projection with the ray's image columns staged in LDS, used when
+// the rings fit one chunk (nz <= 64) and there are at most 32 ring
+// differences.  One block takes one (angle, bin); its eight waves take the
+// ring differences w, w + 8, w + 16, w + 24.  The transaxial path of the ray
+// is the same for every ring difference, so for each stretch of 64 major
+// cells the columns it can enter (minor cells c0 and c0 + qstep of each major
+// cell, all nz slices) are copied to LDS once, and every ring difference
+// reads its pieces there instead of from device memory, where each piece
+// cost a 256-byte wave load through the vector L1.  Pieces, their order and
+// their arithmetic are those of fp3_body, so the results agree bit for bit.
+constexpr int FPS_NT = 512;
+constexpr int FPS_W = FPS_NT / 64;      // waves per block
+constexpr int FPS_DPW = 4;              // ring differences per wave at most
+constexpr int FPS_ZS = 64;              // floats per staged column (nz <= 64)
+constexpr int FPS_SLOTS = 128;          // staged columns of a stretch: slot 2k (c0) and 2k + 1 (c0 + qstep) of cell mb + k
+
+__host__ __device__ inline bool fp3_staged(int nz, int max_rd) {
+    return nz <= FPS_ZS && 2 * max_rd + 1 <= FPS_W * FPS_DPW;
+}
+
+__device__ void fp3s_body(const GeoK& g, const FP3Args& A, long long vblock) {
+    __shared__ __attribute__((aligned(16))) float s_col[FPS_SLOTS * FPS_ZS];
+    __shared__ Piece s_pc[FPS_W][FP3_CAP];
+    __shared__ double s_red[FPS_W];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int D = g.max_rd, ND = 2 * D + 1, Nr = g.n_radial, R = g.n_rings, nz = g.nz;
+    const int b = (int)(vblock % Nr), al = (int)(vblock / Nr);
+    const bool counting = A.mode == FP_COUNT;
+    const int a = A.angles[al];
+    const AngleK& AK = g.ang[a];
+    const TxRay tx = tx_ray(g, AK, b);
+    const int n_major = tx.row_major ? g.ny : g.nx;
+    const int n_minor = tx.row_major ? g.nx : g.ny;
+    int m0, m1;
+    major_range(tx, n_major, n_minor, m0, m1);
+    const ZBin zb = z_bin(g, AK, b);
+    const int qstep = (tx.Q >= 0.0) ? 1 : -1;
+    const float invQf = (float)tx.invQ;
+    // offset of voxel (minor cell c, major cell m, slice o) in the z-fastest
+    // copy: m ms + c cs + o (24-bit products, as in fp3_body)
+    const int cs = tx.row_major ? nz : g.nx * nz;
+    const int ms = tx.row_major ? g.nx * nz : nz;
+    const bool wide = (nz & 3) == 0;    // 16-byte copies (column starts 16-byte aligned)
+
+    float acc[FPS_DPW];
+#pragma unroll
+    for (int j = 0; j < FPS_DPW; ++j) acc[j] = 0.0f;
+
+    for (int mb = m0; mb <= m1; mb += 64) {
+        // (1) stage the stretch's columns (the ones outside the image or past
+        // m1 are left unwritten: no piece refers to them).  Counting reads
+        // no image (and is given none).
+        __syncthreads();    // the previous stretch's columns are read no more
+        if (counting) {
+        } else if (wide) {
+            // one wave instruction copies four columns, sixteen lanes each
+            const int sub = lane >> 4, q = (lane & 15) * 4;
+            for (int s0 = wave * 4; s0 < FPS_SLOTS; s0 += FPS_W * 4) {
+                const int slot = s0 + sub, m = mb + (slot >> 1);
+                bool ok = m <= m1 && q < nz;
+                int src = 0;
+                if (ok) {
+                    const int c = (int)floor(__fma_rn(tx.Q, (double)m, tx.P)) + ((slot & 1) ? qstep : 0);
+                    ok = (unsigned)c < (unsigned)n_minor;
+                    src = __mul24(m, ms) + __mul24(c, cs) + q;
+                }
+                if (ok)
+                    __builtin_amdgcn_global_load_lds(A.fz + src, (__attribute__((address_space(3))) void*)(s_col + s0 * FPS_ZS),
+                                                     16, 0, 0);
+            }
+        } else {
+            // one slice a lane, one column per wave instruction
+            for (int slot = wave; slot < FPS_SLOTS; slot += FPS_W) {
+                const int m = mb + (slot >> 1);
+                bool ok = m <= m1 && lane < nz;
+                int src = 0;
+                if (ok) {
+                    const int c = (int)floor(__fma_rn(tx.Q, (double)m, tx.P)) + ((slot & 1) ? qstep : 0);
+                    ok = (unsigned)c < (unsigned)n_minor;
+                    src = __mul24(m, ms) + __mul24(c, cs) + lane;
+                }
+                if (ok)
+                    __builtin_amdgcn_global_load_lds(A.fz + src, (__attribute__((address_space(3))) void*)(s_col + slot * FPS_ZS),
+                                                     4, 0, 0);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);      // this wave's copies have landed
+        __syncthreads();                    // and every other wave's
+
+        // (2) the transaxial part of the lane's major cell, shared by the
+        // wave's ring differences (lanes past the last cell repeat it and
+        // keep no piece)
+        const int mraw = mb + lane;
+        const int m = min(mraw, m1);
+        const double gm = __fma_rn(tx.Q, (double)m, tx.P);
+        const double cf = floor(gm);
+        const int c0 = (int)cf, c1 = c0 + qstep;
+        const double ce = (tx.Q >= 0.0) ? cf + 1.0 : cf;
+        const double ge = gm + tx.Q;
+        const bool xc = (tx.Q >= 0.0) ? (ge > ce) : (ge < ce);
+        const float tX = xc ? (float)(ce - gm) * invQf : 1.0f;
+        const bool in0 = (unsigned)c0 < (unsigned)n_minor, in1 = (unsigned)c1 < (unsigned)n_minor;
+        const int sl0 = 2 * (m - mb) * FPS_ZS, sl1 = sl0 + FPS_ZS;    // LDS offsets of the two columns
+
+#pragma unroll
+        for (int j = 0; j < FPS_DPW; ++j) {
+            const int di = wave + FPS_W * j;
+            if (di >= ND) break;
+            const int d = di - D;
+            // (3) the axial part and the pieces, as in fp3_body
+            const double zeta0 = __fma_rn((double)d, zb.tau0, 0.5);
+            const double Qz = (double)d * zb.tauQ;
+            const double invQz = (d == 0) ? 0.0 : g.inv_d[di] * zb.inv_tauQ;
+            const float Lkf = (float)(tx.L * g.kappa[(long long)b * ND + di]), invQzf = (float)invQz;
+            const int zstep = (Qz >= 0.0) ? 1 : -1;
+            const int olo = min(0, d), ohi = max(0, d);
+            const double zm = __fma_rn(Qz, (double)m, zeta0);
+            const double of = floor(zm);
+            const int o0 = (int)of, o1 = o0 + zstep;
+            const double oe = (Qz >= 0.0) ? of + 1.0 : of;
+            const double ze = zm + Qz;
+            const bool zc = (Qz >= 0.0) ? (ze > oe) : (ze < oe);
+            const float tZ = zc ? (float)(oe - zm) * invQzf : 1.0f;
+            const bool x_first = tX <= tZ;
+            const float t1 = fminf(tX, tZ), t2 = fmaxf(tX, tZ);
+            const int po1 = x_first ? o0 : o1;
+            const bool pin1 = x_first ? in1 : in0;
+            const float f0 = t1, f1 = t2 - t1, f2 = 1.0f - t2;
+            const bool v0 = f0 > 0.0f && in0 && o0 >= olo && o0 <= ohi;
+            const bool v1 = (xc || zc) && f1 > 0.0f && pin1 && po1 >= olo && po1 <= ohi;
+            const bool v2 = xc && zc && f2 > 0.0f && in1 && o1 >= olo && o1 <= ohi;
+            const int off[3] = {sl0 + o0, (x_first ? sl1 : sl0) + po1, sl1 + o1};
+            const float len[3] = {Lkf * f0, Lkf * f1, Lkf * f2};
+            const int present = mraw <= m1 ? (v0 ? 1 : 0) | (v1 ? 2 : 0) | (v2 ? 4 : 0) : 0;
+            // (4) compact the pieces in cell order (as in fp3_body)
+            const int cnt = __popc(present);
+            int pos = 0, total = 0;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const unsigned long long bm = __ballot((cnt >> k) & 1);
+                pos += __builtin_amdgcn_mbcnt_hi((unsigned)(bm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bm, 0u)) << k;
+                total += __popcll(bm) << k;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (present & (1 << k)) {
+                    s_pc[wave][pos] = Piece{off[k], len[k]};
+                    ++pos;
+                }
+            }
+            wave_lds_sync();
+            // (5) every lane (first ring r1) applies every piece from LDS
+            const int r1 = max(0, -d) + lane;
+            if (r1 <= min(R - 1, R - 1 - d)) {
+                if (counting) {
+                    acc[j] += (float)total;
+                } else {
+#pragma unroll 8
+                    for (int k = 0; k < total; ++k) {
+                        const Piece p = s_pc[wave][k];
+                        acc[j] = fmaf(p.len, s_col[p.off + r1], acc[j]);
+                    }
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+
+    // (6) the rays' outputs, as in fp3_body
+    double term = 0.0;
+#pragma unroll
+    for (int j = 0; j < FPS_DPW; ++j) {
+        const int di = wave + FPS_W * j;
+        if (di >= ND) break;
+        const int d = di - D;
+        const int r1lo = max(0, -d), r1 = r1lo + lane;
+        if (r1 > min(R - 1, R - 1 - d)) continue;
+        const int plane = g.plane_base[di] + (r1 - r1lo);
+        const long long nat = ((long long)plane * g.n_angles + a) * Nr + b;
+        const long long ray = ((long long)al * g.n_planes + plane) * Nr + b;
+        if (A.mode == FP_RATIO) {
+            A.out[ray] = 1.0f - A.y[nat] / (acc[j] + A.r[nat]);
+        } else if (A.mode == FP_EM) {
+            A.out[ray] = A.y[nat] / (acc[j] + A.r[nat]);
+        } else if (A.mode == FP_COUNT || A.mode == FP_COMPACT) {
+            A.out[ray] = acc[j];
+        } else if (A.mode == FP_PLAIN) {
+            A.out[nat] = acc[j];
+        } else {
+            const double q = (double)acc[j];
+            term += q - (double)A.y[nat] * log(q + (double)A.r[nat]);
+        }
+    }
+    if (A.mode == FP_OBJECTIVE) write_partial(term, A.red, s_red, vblock);
+}
+
+// six waves per SIMD: 44 KB of LDS per block lets three blocks share a CU
+__global__ __launch_bounds__(FPS_NT, 6) void k_fp3(GeoK g, FP3Args A, long long n_blocks) {
+    const long long vb = xcd_block(blockIdx.x, n_blocks);
+    if (vb >= n_blocks) return;
+    fp3s_body(g, A, vb);
 }
 
 // ------------------------------------------------------------------ back projection
@@ -893,6 +1108,13 @@ int fp3_grid(const pet_os_geom* G, int n_al) {
     return (int)((n + FP3_W - 1) / FP3_W);
 }
 
+// blocks of the single-request forward projection: one per (angle, bin) with
+// staged columns, else the per-wave items of fp3_body
+int fp3_launch_grid(const pet_os_geom* G, int n_al) {
+    if (fp3_staged(G->d.nz, G->d.max_ring_diff)) return n_al * G->d.n_radial;
+    return fp3_grid(G, n_al);
+}
+
 // Slices per block of the batched back-projector, and the default of the
 // single-request one: the smallest of 16, 32, 64 that holds the volume's depth.
 int bp3_zb(const pet_os_geom* G) { return G->d.nz <= 16 ? 16 : (G->d.nz <= 32 ? 32 : 64); }
@@ -979,9 +1201,12 @@ int launch_fp3(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
     a.red = L.red;
     if (L.n_al == 0) return PET_OS_OK;
     if (L.mode != FP_COUNT && L.fz == nullptr) return fail(PET_OS_ERR_DEVICE, "3D forward projection without z copy");
-    const int grid = fp3_grid(G, L.n_al);
+    const int grid = fp3_launch_grid(G, L.n_al);
     if (L.mode == FP_OBJECTIVE && grid > L.red.cap) return fail(PET_OS_ERR_DEVICE, "objective partials too small");
-    petos_launch(k_fp3, dim3(8 * ((grid + 7) / 8)), dim3(NT), 0, s, G->k, a, (long long)grid);
+    if (fp3_staged(G->d.nz, G->d.max_ring_diff))
+        petos_launch(k_fp3, dim3(8 * ((grid + 7) / 8)), dim3(FPS_NT), 0, s, G->k, a, (long long)grid);
+    else
+        petos_launch(k_fp3_wave, dim3(8 * ((grid + 7) / 8)), dim3(NT), 0, s, G->k, a, (long long)grid);
     PETOS_HIP(hipGetLastError());
     return PET_OS_OK;
 }

@@ -63,6 +63,16 @@ def test_invalid_geometry_rejected_before_device(pet, bad):
     assert pet.last_error()
 
 
+def test_3d_strides_limited_to_24_bit_products(pet):
+    # the forward projector multiplies voxel strides in 24-bit integers
+    d = pet.desc_struct(_desc(dim=3, nx=1 << 17, ny=1, nz=64, vz=3.0, n_rings=64, ring_pitch=3.0,
+                              max_ring_diff=2, det_radius=3e5))
+    h = C.c_void_p()
+    assert pet.lib().pet_os_create_geometry(C.byref(d), C.byref(h)) == -1
+    assert h.value is None
+    assert "2^23" in pet.last_error()
+
+
 def test_null_arguments(pet):
     L = pet.lib()
     assert L.pet_os_create_geometry(None, None) == -1

@@ -55,6 +55,10 @@ GEOMS = {
                      n_rings=8, max_ring_diff=3, ring_pitch=3.0, det_radius=120.0, n_subsets=4),
     "3d_ragged": dict(dim=3, nx=35, ny=35, nz=13, vx=2.0, vy=2.0, vz=2.5, n_angles=24, n_radial=49, ds=2.0,
                       n_rings=13, max_ring_diff=5, ring_pitch=2.5, det_radius=150.0, n_subsets=6),
+    # 33 ring differences: more than the column-staging forward projector
+    # takes, so the per-wave one runs
+    "3d_many_d": dict(dim=3, nx=20, ny=18, nz=40, vx=2.0, vy=2.0, vz=2.5, n_angles=12, n_radial=31, ds=2.0,
+                      n_rings=40, max_ring_diff=16, ring_pitch=2.5, det_radius=150.0, n_subsets=4),
 }
 
 
@@ -103,6 +107,30 @@ def test_forward_projection(geoms, orc, name):
             if subset == 0 or a % g.n_subsets == subset - 1:
                 mask[:, a] = True
         assert rel(q[mask], qo[mask]) <= 1e-5, (subset, rel(q[mask], qo[mask]))
+
+
+@pytest.mark.parametrize("name", ["3d_small", "3d_ragged", "3d_many_d"])
+def test_nnz_3d(geoms, orc, name):
+    """Nonzeros of A (counting pieces, no image read) against the oracle's
+    traces over every ray of subset 1, and the subsets adding up to the whole.
+    Crossings through a cell corner leave the FP64 trace pieces of length
+    ~1e-14 mm; the FP32 fractions keep some of them, so the count lies
+    between the oracle's pieces longer than 1e-9 mm and its pieces of any
+    positive length (plus a margin for corners the FP32 fractions split)."""
+    G, g, d = geoms[name]
+    say(f"nnz {name}")
+    total = G.nnz(0)
+    parts = [G.nnz(s) for s in range(1, d["n_subsets"] + 1)]
+    assert sum(parts) == total
+    n_pos = n_real = 0
+    for a in range(0, d["n_angles"], d["n_subsets"]):
+        for plane in range(orc.n_planes(g)):
+            for b in range(d["n_radial"]):
+                _, ln = orc.trace(g, plane, a, b)
+                n_pos += int(np.count_nonzero(ln > 0.0))
+                n_real += int(np.count_nonzero(ln > 1e-9))
+    say(f"nnz {name}: {parts[0]} against {n_real} .. {n_pos}")
+    assert n_real <= parts[0] <= n_pos + 1e-3 * n_real, (parts[0], n_real, n_pos)
 
 
 @pytest.mark.parametrize("name", list(GEOMS))
