@@ -474,7 +474,7 @@ static WorkLayout work_layout(const pet_os_geom* g, bool need_nu) {
     L.o_mu = cv.take<float>(nv);
     L.o_nu = need_nu ? cv.take<float>(nv) : 0;
     L.o_fz = L.d3 ? cv.take<float>(nv) : 0;
-    L.o_snap = L.d3 ? 0 : cv.take<float>(nv);
+    L.o_snap = cv.take<float>(nv);     // 2D: snapshot of f; 3D: penalty gradient
     L.o_fb = L.psf ? cv.take<float>(nv) : 0;
     L.caps[RED_SUMF] = std::max(std::max(sumf_grid(g), bp_grid_max(g)), elem_grid(g->n_vox));
     L.caps[RED_SUMMU] = std::max(std::max(bp_grid_max(g), elem_grid(g->n_vox)), g->d.dim == 3 ? pen3_grid(g) : 0);
@@ -502,6 +502,7 @@ static void work_carve(const WorkLayout& L, char* blk, Work* w) {
     w->nu_frozen = L.need_nu ? (float*)(blk + L.o_nu) : nullptr;
     w->fz = L.d3 ? (float*)(blk + L.o_fz) : nullptr;
     w->fsnap = L.d3 ? nullptr : (float*)(blk + L.o_snap);
+    w->gradR = L.d3 ? (float*)(blk + L.o_snap) : nullptr;
     w->fb = L.psf ? (float*)(blk + L.o_fb) : nullptr;
     w->check_part = (unsigned*)(blk + L.o_chk);
     w->check_total = (unsigned long long*)(blk + L.o_chkt);
@@ -790,23 +791,25 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
         }
         if (rc || (rc = prof_end(ev, s))) return rc;
     } else {
-        // 3D: the back-projection into G, then (SDP-BSREM) the penalty
-        // gradient added to it and mu, then the update
+        // 3D: the back-projection into G and (SDP-BSREM) in the same launch
+        // the penalty gradient of f and mu, then the update, which adds the
+        // penalty gradient to the back-projection
         B.out = st->w.G;
+        if (!osem) {
+            B.f = f; B.mu = st->w.mu; B.want_mu = want_mu ? 1 : 0;
+            B.part_f = st->w.red[RED_SUMF].part;
+            B.n_part_f = sumf_grid(g);
+            B.red_mu = st->w.red[RED_SUMMU];
+            B.gradR = st->w.gradR;
+        }
         if ((rc = prof_begin(st, 1, s, &ev, true))) return rc;
         rc = launch_bp(g, B, s);
         if (rc || (rc = prof_end(ev, s))) return rc;
-        if (!osem) {
-            BPLaunch P = B;
-            P.f = f; P.mu = st->w.mu; P.want_mu = want_mu ? 1 : 0;
-            P.part_f = st->w.red[RED_SUMF].part;
-            P.n_part_f = sumf_grid(g);
-            P.red_mu = st->w.red[RED_SUMMU];
-            if ((rc = prof_begin(st, 3, s, &ev, true))) return rc;
-            rc = launch_pen3(g, P, s);
-            if (rc || (rc = prof_end(ev, s))) return rc;
-        }
         UpdLaunch U{};
+        if (!osem) {
+            U.gradR = st->w.gradR;
+            U.beta_over_M = B.beta_over_M;
+        }
         U.osem_sens = sens_i;
         U.f = f; U.fz = st->w.fz; U.G = st->w.G; U.mu = st->w.mu; U.pnorm = g->pnorm; U.nu_frozen = st->w.nu_frozen;
         U.nu_mode = sc.nu_mode;

@@ -89,6 +89,7 @@ struct Work {
     float* nu_frozen = nullptr;
     float* fz = nullptr;       // 3D: copy of the iterate with z fastest [(iy*nx+ix)*nz+iz]
     float* fsnap = nullptr;    // 2D: snapshot of the iterate entering the subiteration
+    float* gradR = nullptr;    // 3D: penalty gradient of the entering iterate (same storage as fsnap in 2D)
     float* fb = nullptr;       // 2D PSF: the blurred iterate, then the blurred back-projection
     double* red_block = nullptr;   // reductions' storage
     Reduction red[RED_COUNT];
@@ -181,6 +182,10 @@ struct BPLaunch {
     int n_part_mu = 0;
     Reduction red_f{};                 // partials of sum of the new iterate
     const float* osem_sens = nullptr;  // 2D fused OSEM update: subset sensitivity of this subset
+    // 3D: the penalty gradient of f computed by extra blocks of the
+    // back-projector's launch into gradR (with f, mu, want_mu, the penalty
+    // constants, part_f and red_mu); the update then adds it to b
+    float* gradR = nullptr;
 };
 int launch_bp(const pet_os_geom* g, const BPLaunch& L, hipStream_t s);
 // 2D full model: out = B in (PSF), and the image-space part of a subiteration
@@ -205,6 +210,8 @@ struct UpdLaunch {
     int n_part_mu;
     Reduction red_f;         // sum of the new iterate
     const float* osem_sens = nullptr;   // OSEM: subset sensitivity; G = A_i^T (y/(q+r))
+    const float* gradR = nullptr;       // 3D: penalty gradient to add, G = b + beta_over_M gradR
+    float beta_over_M = 0.0f;
 };
 int launch_update(const pet_os_geom* g, const UpdLaunch& L, hipStream_t s);
 

@@ -466,6 +466,34 @@ __global__ __launch_bounds__(FPS_NT, 6) void k_fp3(GeoK g, FP3Args A, long long 
 
 // ------------------------------------------------------------------ back projection
 
+// The image-space part of a 3D subiteration: grad R(f) (eqn:gradRD, 26
+// in-image neighbours), either added after the back-projection b = A_i^T w
+// as G = b + (beta/M) grad R(f) in place over b, or (gradR given) stored on
+// its own for the update to add, so that it can run in the back-projector's
+// launch; with want_mu the smoothness measure mu = max(0.01, |grad f| /
+// mean f) (Sec. III-B) with the block's FP64 partial of sum mu.  One block
+// per 32 (x) x 8 (y) x 8 (z) voxels (a thread per (x, y), eight slices
+// each); f with a one-voxel halo in LDS.
+constexpr int PEN3_X = 32, PEN3_Y = 8, PEN3_Z = 8;
+constexpr int PEN3_HALO = (PEN3_X + 2) * (PEN3_Y + 2) * (PEN3_Z + 2);   // floats of the halo tile
+
+struct Pen3Args {
+    const float* f;
+    float* G;                // in: b, out: G (gradR null)
+    float* gradR;            // non-null: grad R(f) goes here and G is left alone
+    float* mu;
+    int want_mu;
+    float beta_over_M, gamma_R, eps;
+    const double* part_f;    // partials of sum f of the entering iterate (mean f)
+    int n_part_f;
+    Reduction red_mu;
+};
+
+__host__ __device__ inline int pen3_tiles(int n, int t) { return (n + t - 1) / t; }
+
+__device__ void pen3_body(const GeoK& g, const Pen3Args& A, int vblock, float* s_f, double* s_red);
+
+
 struct BP3Args {
     const float* w;          // null => unit weights (sensitivity)
     long long w_sp, w_sa;    // w index = plane * w_sp + angle_index * w_sa + b
@@ -479,6 +507,8 @@ struct BP3Args {
     int dpg;                 // ring differences staged together: 4 or 8
     int half;                // floats of one staging buffer (>= dpg * row stride * rw)
     int lds;                 // floats of the staging area (two buffers; the finish reuses it)
+    Pen3Args pen;            // the penalty blocks' arguments (gradR set) when n_pen > 0
+    int n_pen;
 };
 
 constexpr int BP3_T = 8;         // columns per tile side
@@ -884,11 +914,19 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared&
 }
 
 // dynamic LDS: the staging area, A.lds floats.  Up to 32 slices per block the
-// register budget is held to four waves per SIMD.
+// register budget is held to four waves per SIMD.  The first bp_blocks
+// blocks back-project; A.n_pen more compute the penalty gradient and mu of
+// the entering iterate (pen3_body, halo tile in the staging area): they need
+// neither w nor b, and fill the CUs' spare slots and issue cycles while the
+// latency-bound back-projection runs.
 template <int ZB, int NBS>
-__global__ __launch_bounds__(NT, ZB <= 32 ? 4 : 3) void k_bp3(GeoK g, BP3Args A, int n_tiles) {
+__global__ __launch_bounds__(NT, ZB <= 32 ? 4 : 3) void k_bp3(GeoK g, BP3Args A, int n_tiles, int bp_blocks) {
     __shared__ BP3Shared sh;
     extern __shared__ __attribute__((aligned(16))) float bp3_stage_area[];
+    if ((int)blockIdx.x >= bp_blocks) {
+        pen3_body(g, A.pen, (int)blockIdx.x - bp_blocks, bp3_stage_area, sh.red);
+        return;
+    }
     const int tile = (int)xcd_block(blockIdx.x, n_tiles);
     if (tile >= n_tiles) return;
     bp3_body<ZB, NBS>(g, A, tile, sh, bp3_stage_area);
@@ -896,31 +934,10 @@ __global__ __launch_bounds__(NT, ZB <= 32 ? 4 : 3) void k_bp3(GeoK g, BP3Args A,
 
 // ------------------------------------------------------------------ penalty gradient and mu
 
-// The image-space part of a 3D subiteration after the back-projection b =
-// A_i^T w: G = b + (beta/M) grad R(f) (eqn:gradRD, 26 in-image neighbours)
-// in place over b, and with want_mu the smoothness measure mu = max(0.01,
-// |grad f| / mean f) (Sec. III-B) with the block's FP64 partial of sum mu.
-// One block per 32 (x) x 8 (y) x 8 (z) voxels (a thread per (x, y), eight
-// slices each); f with a one-voxel halo in LDS.
-constexpr int PEN3_X = 32, PEN3_Y = 8, PEN3_Z = 8;
 
-struct Pen3Args {
-    const float* f;
-    float* G;                // in: b, out: G
-    float* mu;
-    int want_mu;
-    float beta_over_M, gamma_R, eps;
-    const double* part_f;    // partials of sum f of the entering iterate (mean f)
-    int n_part_f;
-    Reduction red_mu;
-};
-
-__host__ __device__ inline int pen3_tiles(int n, int t) { return (n + t - 1) / t; }
-
-__device__ void pen3_body(const GeoK& g, const Pen3Args& A, int vblock) {
+// s_f: PEN3_HALO floats of LDS, s_red: NT / 64 doubles
+__device__ void pen3_body(const GeoK& g, const Pen3Args& A, int vblock, float* s_f, double* s_red) {
     constexpr int HX = PEN3_X + 2, HY = PEN3_Y + 2, HZ = PEN3_Z + 2;
-    __shared__ float s_f[HX * HY * HZ];
-    __shared__ double s_red[NT / 64];
     const int tx = pen3_tiles(g.nx, PEN3_X), ty = pen3_tiles(g.ny, PEN3_Y);
     const int x0 = (vblock % tx) * PEN3_X, y0 = ((vblock / tx) % ty) * PEN3_Y, z0 = (vblock / (tx * ty)) * PEN3_Z;
     for (int e = threadIdx.x; e < HX * HY * HZ; e += NT) {
@@ -980,7 +997,8 @@ __device__ void pen3_body(const GeoK& g, const Pen3Args& A, int vblock) {
             const float gz = mat_der(iz, g.nz, pp[4], fj, pm[4]);
             const float gmag = sqrtf(gx * gx + gy * gy + gz * gz);
             const long long j = ((long long)iz * g.ny + iy) * g.nx + ix;
-            A.G[j] = fmaf(A.beta_over_M, gradR, A.G[j]);
+            if (A.gradR != nullptr) A.gradR[j] = gradR;
+            else A.G[j] = fmaf(A.beta_over_M, gradR, A.G[j]);
             if (A.want_mu) {
                 const float mu = fmaxf(0.01f, gmag / meanf);
                 A.mu[j] = mu;
@@ -991,7 +1009,11 @@ __device__ void pen3_body(const GeoK& g, const Pen3Args& A, int vblock) {
     if (A.want_mu) write_partial(mu_part, A.red_mu, s_red, vblock);
 }
 
-__global__ __launch_bounds__(NT) void k_pen3(GeoK g, Pen3Args A) { pen3_body(g, A, blockIdx.x); }
+__global__ __launch_bounds__(NT) void k_pen3(GeoK g, Pen3Args A) {
+    __shared__ float s_f[PEN3_HALO];
+    __shared__ double s_red[NT / 64];
+    pen3_body(g, A, blockIdx.x, s_f, s_red);
+}
 
 int pen3_grid(const pet_os_geom* G) {
     return pen3_tiles(G->d.nx, PEN3_X) * pen3_tiles(G->d.ny, PEN3_Y) * pen3_tiles(G->d.nz, PEN3_Z);
@@ -1022,6 +1044,8 @@ struct Upd3Args {
     float* f;
     float* fz;
     const float* G;
+    const float* gradR;      // non-null: G = b + (beta/M) gradR, with b in G
+    float beta_over_M;
     const float* mu;
     const float* pnorm;
     float* nu_frozen;
@@ -1068,7 +1092,7 @@ __device__ void upd3_body(const Upd3Args& A, long long vblock, bool update) {
                 A.f[j] = fn;
                 v = fn;
             } else if (update) {
-                const float Gj = A.G[j];
+                const float Gj = A.gradR != nullptr ? fmaf(A.beta_over_M, A.gradR[j], A.G[j]) : A.G[j];
                 const float pj = A.pnorm[j];
                 float nu = 1.0f;
                 if (want_mu) {
@@ -1234,26 +1258,48 @@ int launch_bp3(const pet_os_geom* G, const BPLaunch& L, hipStream_t s) {
     a.zb = bp3_zb_single(G);
     int rc = bp3_shape_single(G, a.zb, G->tuned_dpg, a.nb, a.rw, a.dpg, a.half, a.lds);
     if (rc) return rc;
-    if (L.f != nullptr) return fail(PET_OS_ERR_DEVICE, "the 3D penalty gradient is k_pen3's (launch_pen3)");
+    // penalty blocks in the same launch when gradR is given (the penalty
+    // gradient then goes there, and the update adds it to b)
+    if ((L.f != nullptr) != (L.gradR != nullptr))
+        return fail(PET_OS_ERR_DEVICE, "3D back-projection: the penalty blocks need both f and gradR");
+    a.pen = Pen3Args{};
+    a.n_pen = 0;
+    if (L.gradR != nullptr) {
+        a.pen.f = L.f;
+        a.pen.G = nullptr;
+        a.pen.gradR = L.gradR;
+        a.pen.mu = L.mu;
+        a.pen.want_mu = L.want_mu;
+        a.pen.beta_over_M = L.beta_over_M;
+        a.pen.gamma_R = L.gamma_R;
+        a.pen.eps = L.eps;
+        a.pen.part_f = L.part_f;
+        a.pen.n_part_f = L.n_part_f;
+        a.pen.red_mu = L.red_mu;
+        a.n_pen = pen3_grid(G);
+        if (L.want_mu && a.n_pen > L.red_mu.cap) return fail(PET_OS_ERR_DEVICE, "mu partials too small");
+        a.lds = std::max(a.lds, PEN3_HALO);
+    }
     const int grid = bp3_grid(G);
     const int nbs = bp3_nbs_single(a.nb);
-    const dim3 blocks(8 * ((grid + 7) / 8));
+    const int bp_blocks = 8 * ((grid + 7) / 8);
+    const dim3 blocks(bp_blocks + a.n_pen);
     const size_t lds = (size_t)a.lds * sizeof(float);
     switch (a.zb) {
         case 16:
-            if (nbs == 40) petos_launch(k_bp3<16, 40>, blocks, dim3(NT), lds, s, G->k, a, grid);
-            else if (nbs == 20) petos_launch(k_bp3<16, 20>, blocks, dim3(NT), lds, s, G->k, a, grid);
-            else petos_launch(k_bp3<16, 16>, blocks, dim3(NT), lds, s, G->k, a, grid);
+            if (nbs == 40) petos_launch(k_bp3<16, 40>, blocks, dim3(NT), lds, s, G->k, a, grid, bp_blocks);
+            else if (nbs == 20) petos_launch(k_bp3<16, 20>, blocks, dim3(NT), lds, s, G->k, a, grid, bp_blocks);
+            else petos_launch(k_bp3<16, 16>, blocks, dim3(NT), lds, s, G->k, a, grid, bp_blocks);
             break;
         case 32:
-            if (nbs == 40) petos_launch(k_bp3<32, 40>, blocks, dim3(NT), lds, s, G->k, a, grid);
-            else if (nbs == 20) petos_launch(k_bp3<32, 20>, blocks, dim3(NT), lds, s, G->k, a, grid);
-            else petos_launch(k_bp3<32, 16>, blocks, dim3(NT), lds, s, G->k, a, grid);
+            if (nbs == 40) petos_launch(k_bp3<32, 40>, blocks, dim3(NT), lds, s, G->k, a, grid, bp_blocks);
+            else if (nbs == 20) petos_launch(k_bp3<32, 20>, blocks, dim3(NT), lds, s, G->k, a, grid, bp_blocks);
+            else petos_launch(k_bp3<32, 16>, blocks, dim3(NT), lds, s, G->k, a, grid, bp_blocks);
             break;
         case 64:
-            if (nbs == 40) petos_launch(k_bp3<64, 40>, blocks, dim3(NT), lds, s, G->k, a, grid);
-            else if (nbs == 20) petos_launch(k_bp3<64, 20>, blocks, dim3(NT), lds, s, G->k, a, grid);
-            else petos_launch(k_bp3<64, 16>, blocks, dim3(NT), lds, s, G->k, a, grid);
+            if (nbs == 40) petos_launch(k_bp3<64, 40>, blocks, dim3(NT), lds, s, G->k, a, grid, bp_blocks);
+            else if (nbs == 20) petos_launch(k_bp3<64, 20>, blocks, dim3(NT), lds, s, G->k, a, grid, bp_blocks);
+            else petos_launch(k_bp3<64, 16>, blocks, dim3(NT), lds, s, G->k, a, grid, bp_blocks);
             break;
         default:
             return fail(PET_OS_ERR_DEVICE, "3D back-projector: slices per block must be 16, 32 or 64");
@@ -1266,6 +1312,8 @@ static void fill_upd3(const pet_os_geom* G, const UpdLaunch& L, Upd3Args& a) {
     a.f = L.f;
     a.fz = L.fz;
     a.G = L.G;
+    a.gradR = L.gradR;
+    a.beta_over_M = L.beta_over_M;
     a.mu = L.mu;
     a.pnorm = L.pnorm;
     a.nu_frozen = L.nu_frozen;
@@ -1367,6 +1415,8 @@ __global__ __launch_bounds__(NT) void k_bp3_batch(const SlotDev* __restrict__ S,
 }
 
 __global__ __launch_bounds__(NT) void k_pen3_batch(const SlotDev* __restrict__ S, const Item* __restrict__ items, const int* __restrict__ count) {
+    __shared__ float s_f[PEN3_HALO];
+    __shared__ double s_red[NT / 64];
     const int n = *count;
     for (int it = xcd_item(blockIdx.x, gridDim.x); it < n; it += gridDim.x) {
         const Item I = items[it];
@@ -1386,7 +1436,7 @@ __global__ __launch_bounds__(NT) void k_pen3_batch(const SlotDev* __restrict__ S
         A.red_mu.part = d.part_mu;
         A.red_mu.total = nullptr;
         A.red_mu.cap = d.n_part_mu;
-        pen3_body(d.g, A, I.block);
+        pen3_body(d.g, A, I.block, s_f, s_red);
         __syncthreads();
     }
 }
