@@ -50,10 +50,11 @@ WORKLOADS = {
           "(64 rings, |d| <= 15), 28 subsets, 5e8 counts, 30% background; step = 1 iteration "
           "(28 subiterations); the FP64 objective is timed on its own",
 }
+# 3D: three launches per subiteration (the penalty gradient and mu run as
+# extra blocks of the back-projector's launch)
 KERNELS = {0: "k_fp3 (forward projection + Poisson ratio)",
-           1: "k_bp3 (back-projection)",
-           2: "k_upd3 (nu, S, relaxed step, P_t; z-fastest copy)",
-           3: "k_pen3 (RDP gradient, G, mu)"}
+           1: "k_bp3 (back-projection; RDP gradient and mu blocks in the same launch)",
+           2: "k_upd3 (G = b + (beta/M) grad R, nu, S, relaxed step, P_t; z-fastest copy)"}
 # 2D: two launches per subiteration (the update is fused into the back-projection)
 KERNELS_2D = {0: "k_fp_px (forward projection + Poisson ratio; snapshot of f and mu)",
               1: "k_bp (back-projection + RDP gradient + nu, S, relaxed step, P_t)"}
@@ -78,7 +79,7 @@ def kernel_source_hash():
 
 # kernel-name prefixes of the per-subiteration launches, by kernel index
 TRAFFIC_KERNELS = {2: {0: "void petos::k_fp_px<", 1: "void petos::k_bp<"},
-                   3: {0: "petos::k_fp3(", 1: "void petos::k_bp3<", 2: "petos::k_upd3(", 3: "petos::k_pen3("}}
+                   3: {0: "petos::k_fp3(", 1: "void petos::k_bp3<", 2: "petos::k_upd3("}}
 COPY_BYTES = 64 * 1024 * 1024 * 4      # the --calibrate-copy transfer
 
 
@@ -210,28 +211,27 @@ FP32_VECTOR_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2 * CLOCK_HZ / 1e12
 FP32_UNPACKED_PEAK_TFLOPS = FP32_VECTOR_PEAK_TFLOPS / 2
 
 
-def algorithmic_flops(kernel, nnz_sub, rays_sub, q):
+def algorithmic_flops(kernel, nnz_sub, rays_sub, q, osem=False):
     """Floating-point work one 3D launch must do: one FMA (2 flops) per
     nonzero in either projector; the Poisson ratio (add, divide, subtract)
-    per ray; the penalty (kernel 3) 26 neighbour terms of 10 flops plus the
-    gradient magnitude and mu (about 280 per voxel); the update (kernel 2)
-    about 12 per voxel (nu, S, step, P_t)."""
+    per ray; the penalty blocks of the back-projector's launch (not in OSEM)
+    26 neighbour terms of 10 flops plus the gradient magnitude and mu (about
+    280 per voxel); the update (kernel 2) about 14 per voxel (G, nu, S,
+    step, P_t)."""
     if kernel == 0:
         return 2.0 * nnz_sub + 3.0 * rays_sub
     if kernel == 1:
-        return 2.0 * nnz_sub
-    if kernel == 3:
-        return 280.0 * q
-    return 12.0 * q
+        return 2.0 * nnz_sub + (0.0 if osem else 280.0 * q)
+    return 14.0 * q
 
 
 def algorithmic_bytes(kernel, nnz_sub, rays_sub, q, dim=3, osem=False, psf=False):
     """Bytes one launch must move (A is computed on the fly, never stored).
-    3D, four launches: forward: 4 B image gather per nonzero + read y, r and
-    write w per ray; back: 4 B w gather per nonzero + stage w once per ray +
-    write A_i^T w per voxel; penalty (kernel 3): read A_i^T w and f, write G
-    and mu; update: read f, G, mu, p and write f: 8 nnz + 16 rays + 40 q per
-    subiteration.  2D, two launches: forward + pixel pass (read f, write its
+    3D, three launches: forward: 4 B image gather per nonzero + read y, r
+    and write w per ray; back: 4 B w gather per nonzero + stage w once per
+    ray + write A_i^T w per voxel, and its penalty blocks read f and write
+    grad R and mu; update: read f, A_i^T w, grad R, mu, p and write f:
+    8 nnz + 16 rays + 40 q per subiteration.  2D, two launches: forward + pixel pass (read f, write its
     snapshot and mu), and back-projection + update (read the snapshot, mu, p,
     write f): 8 nnz + 16 rays + 32 q.  OSEM has no mu, p or penalty but reads
     the subset sensitivity: 2D forward + pixel pass 8 q, back + update 12 q;
@@ -255,10 +255,8 @@ def algorithmic_bytes(kernel, nnz_sub, rays_sub, q, dim=3, osem=False, psf=False
     if kernel == 0:
         return 4.0 * nnz_sub + 12.0 * rays_sub
     if kernel == 1:
-        return 4.0 * nnz_sub + 4.0 * rays_sub + 4.0 * q
-    if kernel == 3:
-        return 16.0 * q
-    return 20.0 * q
+        return 4.0 * nnz_sub + 4.0 * rays_sub + 16.0 * q
+    return 24.0 * q
 
 
 def cpu_baseline_osem(w, budget_s=12.0):
@@ -837,7 +835,8 @@ def main():
         dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"])
         roofline = roofline_of(per_kernel, dom, names, dim, nnz_sub, rays_sub, q,
                                stored_traffic(args.workload, p["mode"], shapes, dom),
-                               stored_counters(args.workload, p["mode"], shapes, dom))
+                               stored_counters(args.workload, p["mode"], shapes, dom),
+                               osem=p["mode"] == "OSEM")
 
     del state
     cpu, parity = None, None
@@ -886,7 +885,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def roofline_of(per_kernel, dom, names, dim, nnz_sub, rays_sub, q, traffic, counters):
+def roofline_of(per_kernel, dom, names, dim, nnz_sub, rays_sub, q, traffic, counters, osem=False):
     """The roofline record of the dominant kernel `dom`.  2D: HBM-bound,
     achieved = its algorithmic bytes over its average launch.  3D: the
     projectors' gathers are served by LDS and L2, not HBM (their algorithmic
@@ -903,7 +902,7 @@ def roofline_of(per_kernel, dom, names, dim, nnz_sub, rays_sub, q, traffic, coun
               "per_kernel_us": {names[k].split(" (")[0]: round(v["avg_us"], 3) for k, v in per_kernel.items()},
               "ceilings": onchip_ceilings(counters, K["avg_us"], traffic)}
     if dim == 3:
-        fl = algorithmic_flops(dom, nnz_sub, rays_sub, q)
+        fl = algorithmic_flops(dom, nnz_sub, rays_sub, q, osem=osem)
         achieved = fl / t / 1e12
         out = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(FP32_VECTOR_PEAK_TFLOPS, 1),
                "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5),

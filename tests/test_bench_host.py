@@ -35,13 +35,13 @@ def test_more_than_one_gpu_is_refused():
 @pytest.mark.parametrize("osem", [False, True])
 def test_byte_model_totals(bench, osem):
     """Per subiteration the launches move 8 nnz + 16 rays + 32 q bytes in 2D
-    and 8 nnz + 16 rays + 40 q in 3D, whose penalty kernel reads the
-    back-projection and f and writes G and mu (OSEM: no mu, p or penalty,
-    but the subset sensitivity; 2D 8 nnz + 16 rays + 20 q, 3D
-    8 nnz + 16 rays + 24 q)."""
+    and 8 nnz + 16 rays + 40 q in 3D, whose back-projector's penalty blocks
+    read f and write grad R and mu, and whose update reads the back-projection
+    and grad R (OSEM: no mu, p or penalty, but the subset sensitivity; 2D
+    8 nnz + 16 rays + 20 q, 3D 8 nnz + 16 rays + 24 q)."""
     nnz, rays, q = 1_001_276.0, 4404.0, 65536.0
     two = sum(bench.algorithmic_bytes(k, nnz, rays, q, dim=2, osem=osem) for k in (0, 1))
-    three = sum(bench.algorithmic_bytes(k, nnz, rays, q, dim=3, osem=osem) for k in ((0, 1, 2) if osem else (0, 1, 2, 3)))
+    three = sum(bench.algorithmic_bytes(k, nnz, rays, q, dim=3, osem=osem) for k in (0, 1, 2))
     if not osem:
         assert two == 8 * nnz + 16 * rays + 32 * q
         assert three == 8 * nnz + 16 * rays + 40 * q
@@ -168,20 +168,23 @@ def test_counters_and_onchip_ceilings(bench, tmp_path):
 def test_roofline_bound_by_dimension(bench):
     """2D: the dominant kernel's algorithmic bytes over its launch against
     8 TB/s.  3D: the gathers are served on chip, so the record is the VALU
-    bound: 2 flops per nonzero over the launch against the published FP32
-    vector peak (157.3 TFLOP/s; 78.6 without packed FP32), with the byte
-    rate under its own key."""
+    bound: 2 flops per nonzero (and, in the back-projector's launch, ~280
+    per voxel for its penalty blocks, none in OSEM) over the launch against
+    the published FP32 vector peak (157.3 TFLOP/s; 78.6 without packed
+    FP32), with the byte rate under its own key."""
     assert abs(bench.FP32_VECTOR_PEAK_TFLOPS - 157.2864) < 1e-9
     assert abs(bench.FP32_UNPACKED_PEAK_TFLOPS - 78.6432) < 1e-9
     names = {0: "k_fp3 (x)", 1: "k_bp3 (y)"}
     nnz, rays, q = 1e9, 4e6, 2.5e6
     per = {0: {"avg_us": 100.0, "bytes": bench.algorithmic_bytes(0, nnz, rays, q, 3)},
            1: {"avg_us": 400.0, "bytes": bench.algorithmic_bytes(1, nnz, rays, q, 3)}}
-    r3 = bench.roofline_of(per, 1, names, 3, nnz, rays, q, None, None)
+    r3 = bench.roofline_of(per, 1, names, 3, nnz, rays, q, None, None, osem=True)
     assert r3["bound"] == "alu" and r3["unit"] == "TFLOP/s"
     assert abs(r3["achieved"] - 2e9 / 400e-6 / 1e12) < 1e-3            # 5 TFLOP/s
     assert abs(r3["frac"] - 5.0 / 157.2864) < 1e-5
-    assert abs(r3["algorithmic_bytes_GBs"] - (4 * nnz + 4 * rays + 4 * q) / 400e-6 / 1e9) < 0.1
+    assert abs(r3["algorithmic_bytes_GBs"] - (4 * nnz + 4 * rays + 16 * q) / 400e-6 / 1e9) < 0.1
+    r3p = bench.roofline_of(per, 1, names, 3, nnz, rays, q, None, None)
+    assert abs(r3p["algorithmic_flops_per_launch"] - (2 * nnz + 280 * q)) < 1.0
     assert r3["kernel"] == "k_bp3 (y)" and r3["traffic"] is None
     per2 = {1: {"avg_us": 10.0, "bytes": 5e6}}
     r2 = bench.roofline_of(per2, 1, {1: "k_bp (z)"}, 2, nnz, rays, q, 4e6, None)
