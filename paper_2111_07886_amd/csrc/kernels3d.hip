@@ -291,12 +291,23 @@ __device__ void fp3s_body(const GeoK& g, const FP3Args& A, long long vblock) {
     const bool counting = A.mode == FP_COUNT;
     const int a = A.angles[al];
     const AngleK& AK = g.ang[a];
-    const TxRay tx = tx_ray(g, AK, b);
+    // the ray's FP64 constants live in LDS (read where used) rather than in
+    // registers across the loops
+    __shared__ double s_ray[5];    // P, L, tau0, tauQ, inv_tauQ
+    const TxRay tx0 = tx_ray(g, AK, b);
+    const ZBin zb0 = z_bin(g, AK, b);
+    if (threadIdx.x == 0) {
+        s_ray[0] = tx0.P;
+        s_ray[1] = tx0.L;
+        s_ray[2] = zb0.tau0;
+        s_ray[3] = zb0.tauQ;
+        s_ray[4] = zb0.inv_tauQ;
+    }
+    TxRay tx = tx0;
     const int n_major = tx.row_major ? g.ny : g.nx;
     const int n_minor = tx.row_major ? g.nx : g.ny;
     int m0, m1;
     major_range(tx, n_major, n_minor, m0, m1);
-    const ZBin zb = z_bin(g, AK, b);
     const int qstep = (tx.Q >= 0.0) ? 1 : -1;
     const float invQf = (float)tx.invQ;
     // offset of voxel (minor cell c, major cell m, slice o) in the z-fastest
@@ -313,7 +324,8 @@ __device__ void fp3s_body(const GeoK& g, const FP3Args& A, long long vblock) {
         // (1) stage the stretch's columns (the ones outside the image or past
         // m1 are left unwritten: no piece refers to them).  Counting reads
         // no image (and is given none).
-        __syncthreads();    // the previous stretch's columns are read no more
+        __syncthreads();    // the previous stretch's columns are read no more (and s_ray is written)
+        tx.P = s_ray[0];
         if (counting) {
         } else if (wide) {
             // one wave instruction copies four columns, sixteen lanes each
@@ -371,10 +383,10 @@ __device__ void fp3s_body(const GeoK& g, const FP3Args& A, long long vblock) {
             if (di >= ND) break;
             const int d = di - D;
             // (3) the axial part and the pieces, as in fp3_body
-            const double zeta0 = __fma_rn((double)d, zb.tau0, 0.5);
-            const double Qz = (double)d * zb.tauQ;
-            const double invQz = (d == 0) ? 0.0 : g.inv_d[di] * zb.inv_tauQ;
-            const float Lkf = (float)(tx.L * g.kappa[(long long)b * ND + di]), invQzf = (float)invQz;
+            const double zeta0 = __fma_rn((double)d, s_ray[2], 0.5);
+            const double Qz = (double)d * s_ray[3];
+            const double invQz = (d == 0) ? 0.0 : g.inv_d[di] * s_ray[4];
+            const float Lkf = (float)(s_ray[1] * g.kappa[(long long)b * ND + di]), invQzf = (float)invQz;
             const int zstep = (Qz >= 0.0) ? 1 : -1;
             const int olo = min(0, d), ohi = max(0, d);
             const double zm = __fma_rn(Qz, (double)m, zeta0);
