@@ -283,7 +283,11 @@ __host__ __device__ inline bool fp3_staged(int nz, int max_rd) {
 
 __device__ void fp3s_body(const GeoK& g, const FP3Args& A, long long vblock) {
     __shared__ __attribute__((aligned(16))) float s_col[FPS_SLOTS * FPS_ZS];
-    __shared__ Piece s_pc[FPS_W][FP3_CAP];
+    // the pieces as two arrays: length, and the byte offset (off + 16) * 4 of
+    // slice o of the staged column, which fits 16 bits (o >= -15 here), so
+    // that the broadcast reads of a batch of pieces move 6 bytes a piece
+    __shared__ __attribute__((aligned(16))) unsigned short s_po[FPS_W][FP3_CAP];
+    __shared__ __attribute__((aligned(16))) float s_pl[FPS_W][FP3_CAP];
     __shared__ double s_red[FPS_W];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int D = g.max_rd, ND = 2 * D + 1, Nr = g.n_radial, R = g.n_rings, nz = g.nz;
@@ -419,7 +423,8 @@ __device__ void fp3s_body(const GeoK& g, const FP3Args& A, long long vblock) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 if (present & (1 << k)) {
-                    s_pc[wave][pos] = Piece{off[k], len[k]};
+                    s_po[wave][pos] = (unsigned short)((off[k] + 16) * 4);
+                    s_pl[wave][pos] = len[k];
                     ++pos;
                 }
             }
@@ -430,11 +435,29 @@ __device__ void fp3s_body(const GeoK& g, const FP3Args& A, long long vblock) {
                 if (counting) {
                     acc[j] += (float)total;
                 } else {
-#pragma unroll 8
-                    for (int k = 0; k < total; ++k) {
-                        const Piece p = s_pc[wave][k];
-                        acc[j] = fmaf(p.len, s_col[p.off + r1], acc[j]);
+                    // byte address of slice o of a piece's column for this
+                    // lane: colb + (o + 16) * 4 with colb at ring r1 - 16
+                    const char* colb = reinterpret_cast<const char*>(s_col) + 4 * r1 - 64;
+                    int k = 0;
+                    for (; k + 8 <= total; k += 8) {
+                        // eight pieces: offsets in one 16-byte read, lengths in
+                        // two, the eight column reads in flight together
+                        const uint4 po4 = *reinterpret_cast<const uint4*>(&s_po[wave][k]);
+                        const float4 l0 = *reinterpret_cast<const float4*>(&s_pl[wave][k]);
+                        const float4 l1 = *reinterpret_cast<const float4*>(&s_pl[wave][k + 4]);
+                        const unsigned po[4] = {po4.x, po4.y, po4.z, po4.w};
+                        const float ln[8] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w};
+                        float x[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const unsigned ob = (u & 1) ? (po[u >> 1] >> 16) : (po[u >> 1] & 0xffffu);
+                            x[u] = *reinterpret_cast<const float*>(colb + ob);
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) acc[j] = fmaf(ln[u], x[u], acc[j]);
                     }
+                    for (; k < total; ++k)
+                        acc[j] = fmaf(s_pl[wave][k], *reinterpret_cast<const float*>(colb + s_po[wave][k]), acc[j]);
                 }
             }
             wave_lds_sync();
