@@ -37,6 +37,8 @@ int validate_desc(const pet_os_geom_desc* d) {
     if (!d) return fail(PET_OS_ERR_INVALID_ARG, "desc is NULL");
     if (d->dim != 2 && d->dim != 3) return fail(PET_OS_ERR_INVALID_ARG, "dim must be 2 or 3");
     if (d->nx < 1 || d->ny < 1) return fail(PET_OS_ERR_INVALID_ARG, "nx, ny must be >= 1");
+    // the projectors form pixel offsets with 24-bit multiplies
+    if (d->nx >= (1 << 23) || d->ny >= (1 << 23)) return fail(PET_OS_ERR_INVALID_ARG, "nx, ny must be below 2^23");
     if (!finite_pos(d->vx) || !finite_pos(d->vy) || !finite_pos(d->ds))
         return fail(PET_OS_ERR_INVALID_ARG, "vx, vy, ds must be finite and > 0");
     if (d->n_angles < 1 || d->n_radial < 1) return fail(PET_OS_ERR_INVALID_ARG, "n_angles, n_radial must be >= 1");

@@ -107,7 +107,10 @@ __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
     static_assert(SEG == 1 || (64 % SEG == 0), "segments of a ray stay in one wave");
     constexpr int RPB = NT / SEG;
     __shared__ double s_red[NT / 64];
-    const int lr = (SEG == 1) ? threadIdx.x : threadIdx.x / SEG;
+    int lr = (SEG == 1) ? threadIdx.x : threadIdx.x / SEG;
+    // one ray per wave: its index is wave-uniform, so that its decode, its
+    // angle and bin records and its major range run once on the scalar unit
+    if (SEG == 64) lr = __builtin_amdgcn_readfirstlane(lr);
     const int seg = (SEG == 1) ? 0 : threadIdx.x % SEG;
     const int P = g.n_planes, Nr = g.n_radial;
     const long long nrays = (long long)A.n_al * P * Nr;
@@ -207,9 +210,11 @@ __device__ void fp_body(const GeoK& g, const FPArgs& A, long long vblock) {
                         leaf += (in0 ? 1.0f : 0.0f) + (in1 ? 1.0f : 0.0f);
                         continue;
                     }
-                    const int base = m * sm;
-                    if (in0) leaf = fmaf(a1, img_at(A.f, base + c0 * sx), leaf);
-                    if (in1) leaf = fmaf(a2, img_at(A.f, base + c1 * sx), leaf);
+                    // 24-bit signed products (full-rate multiplies; the
+                    // descriptor check keeps nx, ny below 2^23)
+                    const int base = __mul24(m, sm);
+                    if (in0) leaf = fmaf(a1, img_at(A.f, base + __mul24(c0, sx)), leaf);
+                    if (in1) leaf = fmaf(a2, img_at(A.f, base + __mul24(c1, sx)), leaf);
                 }
             }
             tree.add(k, leaf);
@@ -395,7 +400,11 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
     const int tx0 = (vblock % tiles_x) * T::X;
     const int ty0 = (vblock / tiles_x) * T::Y;
     const int vox = threadIdx.x % NV;               // pixel of the tile
-    const int grp = threadIdx.x / NV;               // angle group
+    // angle group: a whole number of waves each, so the group index (and
+    // with it the gather's angle loop) is wave-uniform and its index
+    // arithmetic runs on the scalar unit
+    static_assert(NV % 64 == 0, "angle groups of whole waves");
+    const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / NV);
     const int lx = vox % T::X, ly = vox / T::X;
     const int ix = tx0 + lx, iy = ty0 + ly;
     const bool inside = ix < g.nx && iy < g.ny;
@@ -530,7 +539,9 @@ __device__ void bp_body(const GeoK& g, const BPArgs& A, int vblock) {
         if (inside) {
             for (int j = grp; j < nch; j += T::AG) {
                 const int al = c0 + j;
-                const int a = s_a[j];     // from LDS: a global load per angle would stall the gather
+                // from LDS (a global load per angle would stall the gather),
+                // wave-uniform as j is
+                const int a = __builtin_amdgcn_readfirstlane(s_a[j]);
                 const AngleK& AK = LEAN ? g.ang[a] : s_ang[j];
                 const int aidx = A.w_natural ? a : al;
                 const int bst = s_blo[j], nbs = s_nb[j];
@@ -854,7 +865,9 @@ __device__ void px_body(const GeoK& g, const PxArgs& P, long long pblock) {
     for (int k = 0; k < K; ++k) {
         const long long j = pblock * PX_PER_BLOCK + k * NT + threadIdx.x;
         if (j < g.nvox) {
-            const float mu = fmaxf(0.01f, gmag2(P.f, g, (int)(j % g.nx), (int)(j / g.nx), fv[k]) / meanf);
+            // (an image holds at most 2^30 pixels: 32-bit division)
+            const int j32 = (int)j, iy = j32 / g.nx;
+            const float mu = fmaxf(0.01f, gmag2(P.f, g, j32 - iy * g.nx, iy, fv[k]) / meanf);
             P.mu[j] = mu;
             part += (double)mu;
         }

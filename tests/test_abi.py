@@ -46,7 +46,7 @@ def _desc(**kw):
     return d
 
 
-@pytest.mark.parametrize("bad", [dict(dim=4), dict(nx=0), dict(vx=-1.0), dict(ds=float("nan")),
+@pytest.mark.parametrize("bad", [dict(dim=4), dict(nx=0), dict(nx=1 << 23, ny=1), dict(vx=-1.0), dict(ds=float("nan")),
                                  dict(n_subsets=0), dict(n_subsets=13), dict(n_angles=0),
                                  dict(dim=3, nz=8, vz=3.0, n_rings=7, ring_pitch=3.0, max_ring_diff=2,
                                       det_radius=300.0),
