@@ -55,6 +55,9 @@ GEOMS = {
                      n_rings=8, max_ring_diff=3, ring_pitch=3.0, det_radius=120.0, n_subsets=4),
     "3d_ragged": dict(dim=3, nx=35, ny=35, nz=13, vx=2.0, vy=2.0, vz=2.5, n_angles=24, n_radial=49, ds=2.0,
                       n_rings=13, max_ring_diff=5, ring_pitch=2.5, det_radius=150.0, n_subsets=6),
+    # direct planes only (one ring difference), an odd depth
+    "3d_d0": dict(dim=3, nx=17, ny=12, nz=5, vx=2.0, vy=2.0, vz=2.5, n_angles=10, n_radial=25, ds=2.0,
+                  n_rings=5, max_ring_diff=0, ring_pitch=2.5, det_radius=120.0, n_subsets=2),
     # 33 ring differences: more than the column-staging forward projector
     # takes, so the per-wave one runs
     "3d_many_d": dict(dim=3, nx=20, ny=18, nz=40, vx=2.0, vy=2.0, vz=2.5, n_angles=12, n_radial=31, ds=2.0,
@@ -109,7 +112,7 @@ def test_forward_projection(geoms, orc, name):
         assert rel(q[mask], qo[mask]) <= 1e-5, (subset, rel(q[mask], qo[mask]))
 
 
-@pytest.mark.parametrize("name", ["3d_small", "3d_ragged", "3d_many_d"])
+@pytest.mark.parametrize("name", ["3d_small", "3d_ragged", "3d_d0", "3d_many_d"])
 def test_nnz_3d(geoms, orc, name):
     """Nonzeros of A (counting pieces, no image read) against the oracle's
     traces over every ray of subset 1, and the subsets adding up to the whole.
