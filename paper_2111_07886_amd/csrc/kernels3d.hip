@@ -281,6 +281,46 @@ __host__ __device__ inline bool fp3_staged(int nz, int max_rd) {
     return nz <= FPS_ZS && 2 * max_rd + 1 <= FPS_W * FPS_DPW;
 }
 
+// Copy a stretch's columns into s_col: slot 2k holds minor cell c0 of major
+// cell mb + k, slot 2k + 1 its neighbour c0 + qstep, all nz slices; columns
+// outside the image or past m1 stay unwritten (no piece refers to them).
+// With nz a multiple of 4 (column starts 16-byte aligned) a wave instruction
+// copies four columns, sixteen lanes of 16 bytes each; else one column, a
+// slice per lane.  Returns without waiting.
+__device__ __forceinline__ void fp3s_stage(const float* fz, float* s_col, const TxRay& tx, int mb, int m1, int n_minor,
+                                           int qstep, int ms, int cs, int nz, int wave, int lane) {
+    if ((nz & 3) == 0) {
+        const int sub = lane >> 4, q = (lane & 15) * 4;
+        for (int s0 = wave * 4; s0 < FPS_SLOTS; s0 += FPS_W * 4) {
+            const int slot = s0 + sub, m = mb + (slot >> 1);
+            bool ok = m <= m1 && q < nz;
+            int src = 0;
+            if (ok) {
+                const int c = (int)floor(__fma_rn(tx.Q, (double)m, tx.P)) + ((slot & 1) ? qstep : 0);
+                ok = (unsigned)c < (unsigned)n_minor;
+                src = __mul24(m, ms) + __mul24(c, cs) + q;
+            }
+            if (ok)
+                __builtin_amdgcn_global_load_lds(fz + src, (__attribute__((address_space(3))) void*)(s_col + s0 * FPS_ZS),
+                                                 16, 0, 0);
+        }
+    } else {
+        for (int slot = wave; slot < FPS_SLOTS; slot += FPS_W) {
+            const int m = mb + (slot >> 1);
+            bool ok = m <= m1 && lane < nz;
+            int src = 0;
+            if (ok) {
+                const int c = (int)floor(__fma_rn(tx.Q, (double)m, tx.P)) + ((slot & 1) ? qstep : 0);
+                ok = (unsigned)c < (unsigned)n_minor;
+                src = __mul24(m, ms) + __mul24(c, cs) + lane;
+            }
+            if (ok)
+                __builtin_amdgcn_global_load_lds(fz + src, (__attribute__((address_space(3))) void*)(s_col + slot * FPS_ZS),
+                                                 4, 0, 0);
+        }
+    }
+}
+
 __device__ void fp3s_body(const GeoK& g, const FP3Args& A, long long vblock) {
     __shared__ __attribute__((aligned(16))) float s_col[FPS_SLOTS * FPS_ZS];
     // the pieces as two arrays: length, and the byte offset (off + 16) * 4 of
@@ -318,51 +358,17 @@ __device__ void fp3s_body(const GeoK& g, const FP3Args& A, long long vblock) {
     // copy: m ms + c cs + o (24-bit products, as in fp3_body)
     const int cs = tx.row_major ? nz : g.nx * nz;
     const int ms = tx.row_major ? g.nx * nz : nz;
-    const bool wide = (nz & 3) == 0;    // 16-byte copies (column starts 16-byte aligned)
 
     float acc[FPS_DPW];
 #pragma unroll
     for (int j = 0; j < FPS_DPW; ++j) acc[j] = 0.0f;
 
     for (int mb = m0; mb <= m1; mb += 64) {
-        // (1) stage the stretch's columns (the ones outside the image or past
-        // m1 are left unwritten: no piece refers to them).  Counting reads
-        // no image (and is given none).
+        // (1) stage the stretch's columns (counting reads no image, and is
+        // given none)
         __syncthreads();    // the previous stretch's columns are read no more (and s_ray is written)
         tx.P = s_ray[0];
-        if (counting) {
-        } else if (wide) {
-            // one wave instruction copies four columns, sixteen lanes each
-            const int sub = lane >> 4, q = (lane & 15) * 4;
-            for (int s0 = wave * 4; s0 < FPS_SLOTS; s0 += FPS_W * 4) {
-                const int slot = s0 + sub, m = mb + (slot >> 1);
-                bool ok = m <= m1 && q < nz;
-                int src = 0;
-                if (ok) {
-                    const int c = (int)floor(__fma_rn(tx.Q, (double)m, tx.P)) + ((slot & 1) ? qstep : 0);
-                    ok = (unsigned)c < (unsigned)n_minor;
-                    src = __mul24(m, ms) + __mul24(c, cs) + q;
-                }
-                if (ok)
-                    __builtin_amdgcn_global_load_lds(A.fz + src, (__attribute__((address_space(3))) void*)(s_col + s0 * FPS_ZS),
-                                                     16, 0, 0);
-            }
-        } else {
-            // one slice a lane, one column per wave instruction
-            for (int slot = wave; slot < FPS_SLOTS; slot += FPS_W) {
-                const int m = mb + (slot >> 1);
-                bool ok = m <= m1 && lane < nz;
-                int src = 0;
-                if (ok) {
-                    const int c = (int)floor(__fma_rn(tx.Q, (double)m, tx.P)) + ((slot & 1) ? qstep : 0);
-                    ok = (unsigned)c < (unsigned)n_minor;
-                    src = __mul24(m, ms) + __mul24(c, cs) + lane;
-                }
-                if (ok)
-                    __builtin_amdgcn_global_load_lds(A.fz + src, (__attribute__((address_space(3))) void*)(s_col + slot * FPS_ZS),
-                                                     4, 0, 0);
-            }
-        }
+        if (!counting) fp3s_stage(A.fz, s_col, tx, mb, m1, n_minor, qstep, ms, cs, nz, wave, lane);
         __builtin_amdgcn_s_waitcnt(0);      // this wave's copies have landed
         __syncthreads();                    // and every other wave's
 
