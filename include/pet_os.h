@@ -46,6 +46,12 @@
  *     one device pass over y, r and f followed by a synchronisation of
  *     `stream`; a state makes it when it first sees a (f, y, r) triple of
  *     buffers, not again while the same buffers come back.
+ *   - A 3D state (up to 64 rings and 15 ring differences) also copies y and r
+ *     into a bin-major layout of its own (8 bytes per bin, allocated at the
+ *     first subiteration) when it first sees a (y, r) pair of buffers, and
+ *     reads the copy while the same pair comes back: new contents in the
+ *     same buffers need a state of their own.  If that allocation fails, or
+ *     for pet_os_reconstruct_noalloc, y and r are read where they are.
  *   - Calls are asynchronous on `stream` unless stated otherwise.
  */
 #ifndef PET_OS_H
@@ -274,7 +280,10 @@ int pet_os_run(pet_os_state* state, float* f, const float* y, const float* r, in
 /* Kernel timing with HIP events on the state's stream (tracing, Sec. IV
  * reports CPU time; this reports device time).  kernel: 0 = forward
  * projection + ratio, 1 = back-projection (2D: with the RDP/mu stencil and
- * the update), 2 = 3D update, 3 = 3D RDP gradient and mu, -1 = off.  Events bracket every launch of that kernel until switched off.
+ * the update; 3D: with the RDP gradient and mu blocks in the same launch),
+ * 2 = 3D update, 3 = accepted and brackets nothing (the 3D RDP gradient has
+ * no launch of its own in a subiteration), -1 = off.  Events bracket every
+ * launch of that kernel until switched off.
  * read: synchronises, returns the summed milliseconds and launch count since
  * the last read, and resets them. */
 int pet_os_state_profile(pet_os_state* state, int32_t kernel);

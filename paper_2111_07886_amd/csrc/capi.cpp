@@ -719,6 +719,31 @@ static int prof_end(hipEvent_t end, hipStream_t s) {
     return PET_OS_OK;
 }
 
+// 3D: the bin-major copy of (y, r) that the staged forward projector reads
+// (its y and r loads are then coalesced), made when the state first sees the
+// pair of buffers, as the data check is.  A state that may not allocate (the
+// static-scratch entry point), or whose allocation fails, reads y and r in
+// their natural layout instead.
+static int ensure_yr(pet_os_state* st, const float* y, const float* r, hipStream_t s) {
+    const pet_os_geom* g = st->g;
+    if (!st->may_allocate || !fp3_reads_yr(g)) return PET_OS_OK;
+    if (st->yr != nullptr && st->yr_y == y && st->yr_r == r) return PET_OS_OK;
+    if (st->yr == nullptr) {
+        void* p = nullptr;
+        if (hipMalloc(&p, (size_t)g->n_bins * sizeof(float2)) != hipSuccess) {
+            (void)hipGetLastError();    // the natural layout serves
+            return PET_OS_OK;
+        }
+        st->yr = (float2*)p;
+    }
+    st->yr_y = st->yr_r = nullptr;
+    int rc = launch_yr3(g, y, r, st->yr, s);
+    if (rc) return rc;
+    st->yr_y = y;
+    st->yr_r = r;
+    return PET_OS_OK;
+}
+
 static int run_subiteration(pet_os_state* st, float* f, const float* y, const float* r, hipStream_t s,
                             bool sumf_current) {
     const pet_os_geom* g = st->g;
@@ -739,6 +764,8 @@ static int run_subiteration(pet_os_state* st, float* f, const float* y, const fl
     const bool d3 = g->d.dim == 3;
     FPLaunch F{};
     F.f = f; F.fz = st->w.fz; F.y = y; F.r = r; F.out = st->w.w; F.angles = angles; F.n_al = n_al;
+    if (d3 && (rc = ensure_yr(st, y, r, s))) return rc;
+    F.yr = (d3 && st->yr != nullptr && st->yr_y == y && st->yr_r == r) ? st->yr : nullptr;
     const bool osem = st->p.mode == PET_OS_OSEM;
     const float* sens_i = osem ? st->osem_sens + (size_t)(st->i - 1) * g->n_vox : nullptr;
     F.mode = osem ? FP_EM : FP_RATIO;
@@ -912,6 +939,7 @@ int pet_os_state_destroy(pet_os_state* st) {
     work_free(&st->w);
     if (st->osem_sens) (void)hipFree(st->osem_sens);
     if (st->obj_dev) (void)hipFree(st->obj_dev);
+    if (st->yr) (void)hipFree(st->yr);
     for (auto& pr : st->prof_ev) {
         (void)hipEventDestroy(pr.first);
         (void)hipEventDestroy(pr.second);

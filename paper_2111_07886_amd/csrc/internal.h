@@ -137,6 +137,9 @@ struct FPLaunch {
     const float* fz = nullptr;   // 3D: the image with z fastest (the 3D projector reads this, not f)
     const float* y;
     const float* r;
+    // 3D: (y, r) pairs bin-major, [(angle * n_radial + bin) * n_planes + plane]
+    // (launch_yr3), read instead of y and r by the staged forward projector
+    const float2* yr = nullptr;
     float* out;              // FP_RATIO, FP_EM, FP_COUNT, FP_COMPACT: compact [al][plane][b]; FP_PLAIN: natural q
     const int* angles;       // device list of natural angle indices for this pass
     int n_al;                // number of angles
@@ -154,6 +157,10 @@ struct FPLaunch {
     Reduction px_red_mu{};
 };
 int launch_fp(const pet_os_geom* g, const FPLaunch& L, hipStream_t s);
+// 3D: the bin-major copy of y and r that the staged forward projector reads
+// (yr: n_bins pairs); whether the geometry's forward projector uses it
+int launch_yr3(const pet_os_geom* g, const float* y, const float* r, float2* yr, hipStream_t s);
+bool fp3_reads_yr(const pet_os_geom* g);
 
 enum NuMode { NU_ONE = 0, NU_COMPUTE = 1, NU_COMPUTE_FREEZE = 2, NU_FROZEN = 3 };
 
@@ -362,5 +369,11 @@ struct pet_os_state {
     const float* checked_f = nullptr;
     const float* checked_y = nullptr;
     const float* checked_r = nullptr;
+    // 3D: bin-major copy of the (y, r) buffers yr_y, yr_r (made with the data
+    // check, when the state may allocate)
+    float2* yr = nullptr;
+    const float* yr_y = nullptr;
+    const float* yr_r = nullptr;
+    bool may_allocate = true;
 };
 

@@ -58,6 +58,7 @@ struct FP3Args {
     const float* fz;        // image with z fastest: fz[(iy * nx + ix) * nz + iz]
     const float* y;
     const float* r;
+    const float2* yr;       // null, or (y, r) bin-major (read by the staged kernel instead)
     float* out;
     const int* angles;
     int n_al;
@@ -482,10 +483,20 @@ __device__ void fp3s_body(const GeoK& g, const FP3Args& A, long long vblock) {
         const int plane = g.plane_base[di] + (r1 - r1lo);
         const long long nat = ((long long)plane * g.n_angles + a) * Nr + b;
         const long long ray = ((long long)al * g.n_planes + plane) * Nr + b;
-        if (A.mode == FP_RATIO) {
-            A.out[ray] = 1.0f - A.y[nat] / (acc[j] + A.r[nat]);
-        } else if (A.mode == FP_EM) {
-            A.out[ray] = A.y[nat] / (acc[j] + A.r[nat]);
+        if (A.mode == FP_RATIO || A.mode == FP_EM) {
+            // y and r of the ray: from the bin-major copy the lanes' planes
+            // are consecutive (one 512-byte wave load), in the natural layout
+            // they lie n_angles * n_radial apart
+            float yv, rv;
+            if (A.yr != nullptr) {
+                const float2 v = A.yr[((long long)a * Nr + b) * g.n_planes + plane];
+                yv = v.x;
+                rv = v.y;
+            } else {
+                yv = A.y[nat];
+                rv = A.r[nat];
+            }
+            A.out[ray] = A.mode == FP_RATIO ? 1.0f - yv / (acc[j] + rv) : yv / (acc[j] + rv);
         } else if (A.mode == FP_COUNT || A.mode == FP_COMPACT) {
             A.out[ray] = acc[j];
         } else if (A.mode == FP_PLAIN) {
@@ -1254,11 +1265,45 @@ int bp3_shape_single(const pet_os_geom* G, int zb, int dpg_req, int& nb, int& rw
     return PET_OS_OK;
 }
 
+bool fp3_reads_yr(const pet_os_geom* G) { return G->d.dim == 3 && fp3_staged(G->d.nz, G->d.max_ring_diff); }
+
+// yr[(a * n_radial + b) * n_planes + plane] = (y, r)[(plane * n_angles + a) *
+// n_radial + b]: a transpose of [plane][angle-bin] by 64 x 64 tiles through
+// LDS, both sides coalesced
+__global__ __launch_bounds__(NT) void k_yr3(const float* __restrict__ y, const float* __restrict__ r,
+                                            float2* __restrict__ yr, int n_ab, int n_planes) {
+    __shared__ float2 t[64][65];
+    const int ab0 = blockIdx.x * 64, p0 = blockIdx.y * 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int k = w; k < 64; k += NT / 64) {
+        const int p = p0 + k, ab = ab0 + lane;
+        if (p < n_planes && ab < n_ab) {
+            const long long i = (long long)p * n_ab + ab;
+            t[k][lane] = make_float2(y[i], r[i]);
+        }
+    }
+    __syncthreads();
+    for (int k = w; k < 64; k += NT / 64) {
+        const int ab = ab0 + k, p = p0 + lane;
+        if (p < n_planes && ab < n_ab) yr[(long long)ab * n_planes + p] = t[lane][k];
+    }
+}
+
+int launch_yr3(const pet_os_geom* G, const float* y, const float* r, float2* yr, hipStream_t s) {
+    const int n_ab = G->d.n_angles * G->d.n_radial;
+    const dim3 grid((n_ab + 63) / 64, (G->n_planes + 63) / 64);
+    if (grid.y > 65535) return fail(PET_OS_ERR_INVALID_ARG, "too many planes for the bin-major copy");
+    petos_launch(k_yr3, grid, dim3(NT), 0, s, y, r, yr, n_ab, G->n_planes);
+    PETOS_HIP(hipGetLastError());
+    return PET_OS_OK;
+}
+
 int launch_fp3(const pet_os_geom* G, const FPLaunch& L, hipStream_t s) {
     FP3Args a;
     a.fz = L.fz;
     a.y = L.y;
     a.r = L.r;
+    a.yr = L.yr;
     a.out = L.out;
     a.angles = L.angles;
     a.n_al = L.n_al;

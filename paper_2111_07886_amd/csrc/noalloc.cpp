@@ -73,6 +73,7 @@ extern "C" int pet_os_reconstruct_noalloc(const pet_os_geom* g, const pet_os_par
     st.i = 1;
     st.t_nest = 1.0;
     st.have_frozen = 0;
+    st.may_allocate = false;    // y and r read in their natural layout
     const bool need_nu = p->mode == PET_OS_P1 || p->mode == PET_OS_P2;
     if ((rc = work_place(g, need_nu, base, SCRATCH_BYTES, &st.w, s))) return rc;
     // the data check of Sec. II-A before anything of the iterations is queued

@@ -102,6 +102,35 @@ def test_state_checks_each_new_triple(pet):
     assert st.position() == (0, 2)
 
 
+def test_3d_state_follows_new_data_buffers(pet):
+    """A 3D state reads y and r from a bin-major copy made when it first sees
+    a (y, r) pair of buffers: a new pair mid-reconstruction is copied and
+    used.  The second subiteration with new counts equals, bit for bit, that
+    of a state sought to the same position from the same image, and differs
+    from a second subiteration with the old counts."""
+    w, p = small_3d()
+    G = pet.Geometry(w.desc)
+    y, r, f0 = dev(w.y), dev(w.r), dev(w.f0)
+    y2 = dev(2.0 * w.y)
+    st = pet.State(G, p)
+    f = f0.clone()
+    st.subiteration(f, y, r)
+    f1 = f.clone()
+    st.subiteration(f, y2, r)                  # new counts, new buffer
+    fa = f.clone()
+    old = pet.State(G, p)
+    g = f0.clone()
+    old.subiteration(g, y, r)
+    old.subiteration(g, y, r)                  # the old counts again
+    fresh = pet.State(G, p)
+    fresh.seek(0, 2)
+    h = f1.clone()
+    fresh.subiteration(h, y2, r)
+    say(f"3D new data buffers: |a - fresh| = {float((fa - h).abs().max())}, |a - old| = {float((fa - g).abs().max())}")
+    assert torch.equal(fa, h)
+    assert not torch.equal(fa, g)
+
+
 def test_batch_add_rejects_bad_data(pet):
     w, p = small_2d(43)
     G = pet.Geometry(w.desc)
