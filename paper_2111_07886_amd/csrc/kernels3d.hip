@@ -669,7 +669,7 @@ __device__ void bp3_finish(const GeoK& g, const BP3Args& A, float (&acc)[BP3_ZMA
 // orders them: the wave waits for its own loads.  Returns without waiting.
 template <int NBS>
 __device__ __forceinline__ void bp3_stage(const GeoK& g, const BP3Args& A, const BP3Shared& sh, float* buf, int dg,
-                                          int z0, int aidx, int blo, int nbv, const double* tk) {
+                                          int z0, int aidx, int blo, int nbv, double tau0, double tau1) {
     constexpr int CPR = NBS / 4;                    // 16-byte chunks per row
     constexpr int RPI4 = 64 / CPR;                  // rows per wave instruction, 16-byte lanes
     constexpr int RPI1 = 64 / NBS;                  // rows per wave instruction, 4-byte lanes
@@ -690,7 +690,7 @@ __device__ __forceinline__ void bp3_stage(const GeoK& g, const BP3Args& A, const
         const int d = di - D;
         const int lo = max(0, -d), hi = min(R - 1, R - 1 - d);
         int omn, om;
-        bp3_orange(tk[0], tk[1], d, omn, om);
+        bp3_orange(tau0, tau1, d, omn, om);
         const int r1_row0 = z0 - om - 1;            // ring r1 of row 0
         // rows of valid rings (row 0 stays zero): [rlo, rhi], possibly empty
         const int rlo = max(1, lo - r1_row0), rhi = min(rw - 1, hi - r1_row0);
@@ -804,6 +804,67 @@ __device__ __forceinline__ int col_hits(const GeoK& g, const AngleK& AK, int m, 
     return n;
 }
 
+// One staging group of an angle: wait for this wave's copies into buf,
+// issue the next group's copies into nxt, gather buf.  buf and nxt are
+// distinct halves of the staging area; as restrict parameters they tell the
+// compiler so, which lets the next group's copies stay in flight while buf
+// is read (the compiler otherwise waits for every copy to LDS before an LDS
+// read it cannot tell apart from their targets).
+template <int ZB, int NBS>
+__device__ __forceinline__ void bp3_group(const GeoK& g, const BP3Args& A, const BP3Shared& sh,
+                                          float (&acc)[BP3_ZMAX], const Hits& H, const float* __restrict__ buf,
+                                          float* __restrict__ nxt, bool stage_next, int dg, int z0, int aidx,
+                                          int blo, int nbv, const double* tk) {
+    const int wave = threadIdx.x >> 6;
+    const int D = g.max_rd, ND = 2 * D + 1, rw = A.rw, dpg = A.dpg;
+    // the angle's tau range in registers before any copy is in flight
+    const double tau0 = tk[0], tau1 = tk[1];
+    __builtin_amdgcn_s_waitcnt(0);      // this wave's copies (and zeros) into buf have landed
+    if (stage_next) bp3_stage<NBS>(g, A, sh, nxt, dg + dpg, z0, aidx, blo, nbv, tau0, tau1);
+    // (6) gather: wave v takes the group's ring differences v, v+4, ...
+    for (int ds = wave; ds < dpg; ds += 4) {
+        const int di = dg + ds;
+        if (di >= ND) break;
+        const int d = di - D;
+        const float fd = (float)d, ad = fabsf(fd);
+        int omin, omax;
+        bp3_orange(tau0, tau1, d, omin, omax);
+        const bool fits = omax - omin + ZB + 1 <= rw;
+#pragma unroll
+        for (int kk = 0; kk < BP3_HMAX; ++kk) {
+            // the piece's axial range [zlo, zhi] in slice units (FP32:
+            // |zeta| <= 1/2 + D, its rounding far below a slice); it
+            // meets slice offsets o1 and, across boundary o2 = o1 + 1,
+            // o2 (the host bounds the span below one slice)
+            const float zref = fmaf(fd, H.t0[kk], 0.5f), span = ad * H.dt[kk];
+            const float zlo = d >= 0 ? zref : zref - span;
+            const float zhi = d >= 0 ? zref + span : zref;
+            const float flo = floorf(zlo), fhi = floorf(zhi);
+            const int o1 = (int)flo, o2 = (int)fhi;
+            // 3D length per transaxial length of this (bin, d)
+            const float x = fd * H.ck[kk];
+            const float LK = H.L[kk] * __builtin_amdgcn_sqrtf(fmaf(x, x, 1.0f));
+            const bool split = fhi != flo;
+            // split in proportion to the axial lengths on either side
+            const float frac = fminf(1.0f, fmaxf(0.0f, (fhi - zlo) * __builtin_amdgcn_rcpf(span)));
+            const float a1 = split ? LK * frac : LK;
+            const float a2 = LK - a1;
+            // inside the staged footprint by construction: the tile's bin
+            // window and tau range contain every hit of its columns, and
+            // the host-side bounds on bins and slice-offset span hold; the
+            // test only keeps LDS reads in range
+            const int bcol = H.b[kk] - blo;
+            const bool use = H.v[kk] && bcol >= 0 && bcol < nbv && o1 >= omin && o2 <= omax && fits;
+            if (use) {
+                // offset o1 with a1 and offset o2 = o1 + 1 (one row up
+                // in the staging) with a2
+                const float* sp = buf + (ds * rw + (omax - o1)) * NBS + bcol;
+                bp3_apply<ZB, NBS>(acc, sp, a1, a2);
+            }
+        }
+    }
+}
+
 template <int ZB, int NBS>
 __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared& sh, float* s_w) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -878,7 +939,7 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared&
             const double* tk = sh.tau[k];    // read where used (registers are scarce)
             const int ngr = (ND + dpg - 1) / dpg;
             // the first group's loads run while the column's hits are found
-            bp3_stage<NBS>(g, A, sh, s_w, 0, z0, aidx, blo, nbv, tk);
+            bp3_stage<NBS>(g, A, sh, s_w, 0, z0, aidx, blo, nbv, tk[0], tk[1]);
             // (3) candidate bins of the column: g(m) in [mc - max(Q,0), mc + 1 - min(Q,0)]
             const int m = AK.row_major ? iy : ix;
             const int mc = AK.row_major ? ix : iy;
@@ -905,59 +966,13 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared&
             for (int pass = 0; pass < npass; ++pass) {
                 if (pass > 0) {
                     (void)col_hits(g, AK, m, mc, b0, b1, pass * BP3_HMAX, ck0, H);
-                    bp3_stage<NBS>(g, A, sh, s_w, 0, z0, aidx, blo, nbv, tk);
+                    bp3_stage<NBS>(g, A, sh, s_w, 0, z0, aidx, blo, nbv, tk[0], tk[1]);
                 }
                 // (5) w of ring differences in groups of dpg, double buffered:
                 // the loads of group k+1 run while group k is gathered
-                for (int gi = 0; gi < ngr; ++gi) {
-                    const int dg = gi * dpg;
-                    float* buf = s_w + (gi & 1) * A.half;
-                    __builtin_amdgcn_s_waitcnt(0);      // this wave's loads (and zeros) into buf have landed
-                    if (gi + 1 < ngr)
-                        bp3_stage<NBS>(g, A, sh, s_w + ((gi + 1) & 1) * A.half, dg + dpg, z0, aidx, blo, nbv, tk);
-                    // (6) gather: wave v takes the group's ring differences v, v+4, ...
-                    for (int ds = wave; ds < dpg; ds += 4) {
-                        const int di = dg + ds;
-                        if (di >= ND) break;
-                        const int d = di - D;
-                        const float fd = (float)d, ad = fabsf(fd);
-                        int omin, omax;
-                        bp3_orange(tk[0], tk[1], d, omin, omax);
-                        const bool fits = omax - omin + ZB + 1 <= rw;
-#pragma unroll
-                        for (int kk = 0; kk < BP3_HMAX; ++kk) {
-                            // the piece's axial range [zlo, zhi] in slice units (FP32:
-                            // |zeta| <= 1/2 + D, its rounding far below a slice); it
-                            // meets slice offsets o1 and, across boundary o2 = o1 + 1,
-                            // o2 (the host bounds the span below one slice)
-                            const float zref = fmaf(fd, H.t0[kk], 0.5f), span = ad * H.dt[kk];
-                            const float zlo = d >= 0 ? zref : zref - span;
-                            const float zhi = d >= 0 ? zref + span : zref;
-                            const float flo = floorf(zlo), fhi = floorf(zhi);
-                            const int o1 = (int)flo, o2 = (int)fhi;
-                            // 3D length per transaxial length of this (bin, d)
-                            const float x = fd * H.ck[kk];
-                            const float LK = H.L[kk] * __builtin_amdgcn_sqrtf(fmaf(x, x, 1.0f));
-                            const bool split = fhi != flo;
-                            // split in proportion to the axial lengths on either side
-                            const float frac = fminf(1.0f, fmaxf(0.0f, (fhi - zlo) * __builtin_amdgcn_rcpf(span)));
-                            const float a1 = split ? LK * frac : LK;
-                            const float a2 = LK - a1;
-                            // inside the staged footprint by construction: the tile's bin
-                            // window and tau range contain every hit of its columns, and
-                            // the host-side bounds on bins and slice-offset span hold; the
-                            // test only keeps LDS reads in range
-                            const int bcol = H.b[kk] - blo;
-                            const bool use = H.v[kk] && bcol >= 0 && bcol < nbv && o1 >= omin && o2 <= omax && fits;
-                            if (use) {
-                                // offset o1 with a1 and offset o2 = o1 + 1 (one row up
-                                // in the staging) with a2
-                                const float* sp = buf + (ds * rw + (omax - o1)) * NBS + bcol;
-                                bp3_apply<ZB, NBS>(acc, sp, a1, a2);
-                            }
-                        }
-                    }
-                }
+                for (int gi = 0; gi < ngr; ++gi)
+                    bp3_group<ZB, NBS>(g, A, sh, acc, H, s_w + (gi & 1) * A.half, s_w + ((gi + 1) & 1) * A.half,
+                                       gi + 1 < ngr, gi * dpg, z0, aidx, blo, nbv, tk);
             }
             __builtin_amdgcn_s_waitcnt(0);      // no load of this angle is left in flight
         }
