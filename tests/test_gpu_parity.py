@@ -487,15 +487,18 @@ def test_checkpoint_resume_bitwise(pet):
     assert e.value.code == -7
 
 
-def test_objective_and_default_U(pet, orc):
-    from synth import configs
-    w, p, _ = configs.c1()
+@pytest.mark.parametrize("name", ["c1", "3d_ragged"])
+def test_objective_and_default_U(pet, orc, name):
+    """The FP64 objective (eq:ObjectiveFunction: the forward projector's
+    log-likelihood epilogue and the RDP sum) and the default U, in 2D and
+    with the 3D forward projector's staged columns."""
+    w, p, _ = workload(name, orc)
     G = pet.Geometry(full_desc(w.desc))
     g = orc.geom(w.desc)
     rng = np.random.default_rng(4)
     f = f32(rng.uniform(0.2, 3.0, G.img_shape))
     y, r = dev(w.y), dev(w.r)
-    say("objective/default U")
+    say(f"objective/default U {name}")
     phi = G.objective(p, dev(f), y, r)
     phio = orc.objective(g, f, host(y), host(r), p["beta"], p["gamma_R"], p["eps"])
     assert abs(phi - phio) <= 1e-6 * abs(phio)
