@@ -867,7 +867,7 @@ __device__ __forceinline__ void bp3_group(const GeoK& g, const BP3Args& A, const
 
 template <int ZB, int NBS>
 __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared& sh, float* s_w) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63;
     const int tiles_x = (g.nx + BP3_T - 1) / BP3_T, tiles_y = (g.ny + BP3_T - 1) / BP3_T;
     int t = vblock;
     const int tx0 = (t % tiles_x) * BP3_T;
@@ -877,7 +877,7 @@ __device__ void bp3_body(const GeoK& g, const BP3Args& A, int vblock, BP3Shared&
     const int ix = tx0 + (lane & 7), iy = ty0 + (lane >> 3);
     const bool col_in = ix < g.nx && iy < g.ny;
     const int D = g.max_rd, ND = 2 * D + 1, Nr = g.n_radial;
-    const int rw = A.rw, dpg = A.dpg;
+    const int dpg = A.dpg;
     const float ck0 = (float)g.vz;      // ring pitch (== vz)
 
     float acc[BP3_ZMAX];
