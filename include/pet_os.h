@@ -259,13 +259,13 @@ int pet_os_reconstruct(const pet_os_geom* geom, const pet_os_params* params, flo
  * the geometry must belong to the current device.  Errors: INVALID_ARG also
  * when the request's scratch exceeds the array (the message states both
  * sizes; a 200x200x64 volume with 224 x 281 x 1744 bins and 28 subsets needs
- * about 57 MB) and for PET_OS_OSEM (its subset sensitivities need a state).
+ * about 75 MB) and for PET_OS_OSEM (its subset sensitivities need a state).
  * The data check (conventions) waits for `stream` before the iterations are
  * queued; the iterations run asynchronously.  Every call on a GPU shares that
  * GPU's array and overwrites what the previous call left there: calls queued
  * on one stream run one after the other, calls that overlap on one GPU
  * (different streams or threads) race and must not be made. */
-#define PET_OS_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define PET_OS_NOALLOC_SCRATCH_BYTES (96u << 20)
 int pet_os_reconstruct_noalloc(const pet_os_geom* geom, const pet_os_params* params, float* f,
                                const float* y, const float* r, int32_t n_iter, pet_os_stream stream);
 

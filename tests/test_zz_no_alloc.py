@@ -57,9 +57,24 @@ def test_noalloc_equals_reconstruct(pet):
             assert not torch.equal(f, dev(w.f0)), label    # the iterations ran
 
 
+def test_noalloc_fits_the_3d_workload(pet):
+    """The static area holds a 200x200x64 request with 224 x 281 x 1744 bins
+    and 28 subsets (synthetic data: one iteration runs)."""
+    from synth import configs
+    d = configs.desc_3d(200, 64, 224, 281, 1.5, 3.0, 64, 15, 28)
+    G = pet.Geometry(d)
+    p = configs.params_3d(U=1e6)
+    f = torch.ones(G.img_shape, device="cuda")
+    y = torch.ones(G.sino_shape, device="cuda")
+    r = torch.ones(G.sino_shape, device="cuda")
+    pet.reconstruct_noalloc(G, p, f, y, r, 1)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(f).all()) and not bool((f == 1.0).all())
+
+
 def test_noalloc_rejects_what_does_not_fit(pet):
     from synth import configs
-    # three 4096^2 images of scratch (gradient, mu, snapshot): 192 MiB > 64 MiB
+    # three 4096^2 images of scratch (gradient, mu, snapshot): 192 MiB > 96 MiB
     d = configs.desc_2d(4096, 4, 9, 0.1, 2)
     G = pet.Geometry(d)
     p = configs.params_2d(2, 1e5, mode="BSREM")
